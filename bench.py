@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Benchmark: effective TFLOP/s (2mnk/t) of Strassen-Winograd against the
+plain MFMA GEMM of the same library, on one MI355X, with the relative error
+against the float64 oracle and p50/p99 step latency.
+
+Workload (one "step" = one whole product, every kernel of the path):
+square float32 C = A x B, n = 4096, entries i.i.d. U[-1, 1] from a fixed
+seed, Strassen-Winograd with the grouped schedule.  The plain MFMA GEMM
+(mm_naive) runs the same product for comparison.  Inputs are resident in HBM
+before timing starts.
+
+Printed: one JSON line (rank 0).  ``roofline`` is for the dominant kernel,
+the grouped MFMA leaf GEMM launch: algorithmic flops of one launch
+(7^L leaf products of 2 (n/2^L)^3 flops) over that launch's average duration,
+measured with HIP events recorded around each launch on the stream the
+kernels run on, during the timed steps.  ``cpu_baseline`` is the oracle (the
+double-precision triple loop) timed on the host on a sample of output rows.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--levels", type=int, default=None, help="recursion levels (default: tuned)")
+    ap.add_argument("--sched", default="grouped")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline and error check")
+    ap.add_argument("--no-extra", action="store_true", help="skip the n=3000 / n=8192 side runs")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def _events(torch, n, stream):
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    for e in evs:              # create the underlying HIP events
+        e.record(stream)
+    return evs
+
+
+def time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup):
+    """Run warm-up steps, then exactly ``steps`` timed steps with per-launch
+    events.  Returns (wall ms per step, per-step ms list, per-launch ms lists)."""
+    import ctypes
+    lib = L.load()
+    s = torch.cuda.current_stream()
+    nops = plan.info["launches"]
+    evsets = [_events(torch, nops + 1, s) for _ in range(steps)]
+    ptrs = [(ctypes.c_void_p * (nops + 1))(*[e.cuda_event for e in evs]) for evs in evsets]
+    wsp, wsb = (ws.data_ptr(), ws.numel()) if ws is not None else (None, 0)
+    for _ in range(warmup):
+        L.check(lib.mm_plan_execute(plan._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), wsp, wsb,
+                                    s.cuda_stream))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        L.check(lib.mm_plan_execute_timed(plan._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), wsp,
+                                          wsb, s.cuda_stream, ptrs[i], nops + 1))
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    step_ms = [evs[0].elapsed_time(evs[-1]) for evs in evsets]
+    per_op = [[evs[j].elapsed_time(evs[j + 1]) for evs in evsets] for j in range(nops)]
+    kinds = [lib.mm_plan_op_kind(plan._ptr, j) for j in range(nops)]
+    return wall_ms, step_ms, per_op, kinds
+
+
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtype="f32"):
+    plan = api.Plan(algo, sched, n, n, n, cutoff=1, levels=levels, dtype=dtype)
+    ws = torch.empty(max(plan.ws_bytes, 256), dtype=torch.uint8, device=A.device)
+    C = torch.empty((n, n), dtype=A.dtype, device=A.device)
+    wall, step_ms, per_op, kinds = time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup)
+    return dict(plan=plan, C=C, wall_ms=wall, p50=pct(step_ms, 50), p99=pct(step_ms, 99),
+                per_op=per_op, kinds=kinds, tflops=2.0 * n ** 3 / (wall * 1e-3) / 1e12)
+
+
+def gemm_roofline(res, n):
+    """Roofline of the leaf GEMM launch (the dominant kernel)."""
+    info = res["plan"].info
+    Lv = info["levels"]
+    leaf_flops = 2.0 * (info["M"] >> Lv) * (info["N"] >> Lv) * (info["K"] >> Lv)
+    flops = leaf_flops * 7 ** Lv
+    durs = [sum(d) / len(d) for d, k in zip(res["per_op"], res["kinds"]) if k == 1]
+    avg_ms = durs[0] if durs else float("nan")
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    return dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=None,
+                kernel="gemm_kernel<float> (grouped leaf products)",
+                flops_per_launch=flops, avg_launch_ms=round(avg_ms, 4))
+
+
+def ew_bandwidth(res, n):
+    """Achieved HBM rate of the element-wise launches (algorithmic bytes)."""
+    info = res["plan"].info
+    Lv = info["levels"]
+    out = []
+    ew = [sum(d) / len(d) for d, k in zip(res["per_op"], res["kinds"]) if k == 0]
+    # S/T launch of level l: reads A and B blocks (4+4 quarters), writes 8
+    # quarters; U launch: reads 7 quarters, writes 4 (float32, per block).
+    for l in range(Lv):
+        q = (n >> (l + 1)) ** 2 * 4.0 * 7 ** l
+        out.append(("ST", l, 16 * q))
+    for l in reversed(range(Lv)):
+        q = (n >> (l + 1)) ** 2 * 4.0 * 7 ** l
+        out.append(("U", l, 11 * q))
+    res_list = []
+    for (kind, l, bytes_), ms in zip(out, ew):
+        res_list.append(dict(kind=kind, level=l, bytes=bytes_, ms=round(ms, 4),
+                             gbs=round(bytes_ / (ms * 1e-3) / 1e9, 1)))
+    return res_list
+
+
+def cpu_baseline(A_np, B_np, seconds):
+    """The oracle (double triple loop, all host cores) on a sample of rows."""
+    import numpy as np
+    from oracle import naive
+    n = A_np.shape[0]
+    rows = 8
+    t0 = time.perf_counter()
+    naive.gemm_rows(A_np, B_np, np.arange(rows))
+    dt = time.perf_counter() - t0
+    rows = int(max(8, min(n, rows * seconds / max(dt, 1e-3))))
+    sample = np.linspace(0, n - 1, rows).astype(np.int64)
+    t0 = time.perf_counter()
+    ref = naive.gemm_rows(A_np, B_np, sample)
+    dt = time.perf_counter() - t0
+    flops = 2.0 * rows * n * n
+    return dict(value=round(flops / dt / 1e12, 6), unit="TFLOP/s", cores=naive.max_threads(),
+                kind="oracle",
+                sample=f"{rows} of {n} output rows of the same product ({dt:.1f} s, float64 triple loop)"), \
+        sample, ref
+
+
+def rel_err(C, rows, ref):
+    import numpy as np
+    import torch
+    got = C[torch.from_numpy(rows).to(C.device)].double().cpu().numpy()
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2309_00628_amd import _lib as L
+    from paper_2309_00628_amd import api, inputs
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    n = args.n
+    A_np, B_np = inputs.pair("uniform", n, n, n, 0, np.float32)
+    A = torch.from_numpy(A_np).cuda()
+    B = torch.from_numpy(B_np).cuda()
+    print(f"# bench n={n} fp32, steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+
+    # level choice: time L = 1..3 briefly (the tuned choice) unless given
+    if args.levels is None:
+        best = None
+        for lv in (1, 2, 3):
+            r = run_product(torch, api, L, "winograd", args.sched, n, lv, A, B, 5, 2)
+            print(f"# tune L={lv}: {r['tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+            if best is None or r["tflops"] > best[1]:
+                best = (lv, r["tflops"])
+        levels = best[0]
+    else:
+        levels = args.levels
+
+    win = run_product(torch, api, L, "winograd", args.sched, n, levels, A, B, args.steps, args.warmup)
+    print(f"# winograd L={levels}: {win['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    plain = run_product(torch, api, L, "naive", "auto", n, 0, A, B, args.steps, args.warmup)
+    print(f"# plain mfma gemm: {plain['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
+
+    # vendor GEMM (hipBLASLt through torch.matmul) as context only
+    torch.backends.cuda.matmul.allow_tf32 = False
+    for _ in range(3):
+        torch.matmul(A, B)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        torch.matmul(A, B)
+    torch.cuda.synchronize()
+    vendor_tflops = 2.0 * n ** 3 / ((time.perf_counter() - t0) / args.steps) / 1e12
+
+    out = {
+        "metric": "effective TFLOP/s (2mnk/t) Winograd vs plain GEMM at stated rel. err; p99 ms",
+        "value": round(win["tflops"], 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(win["wall_ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (uniform[-1,1], seeded)",
+        "config": {"workload": f"square fp32 matmul n={n}, Strassen-Winograd {args.sched} "
+                               f"L={levels} vs plain MFMA GEMM",
+                   "n": n, "levels": levels, "schedule": args.sched},
+        "p50_ms": round(win["p50"], 4),
+        "p99_ms": round(win["p99"], 4),
+        "plain_gemm": {"tflops": round(plain["tflops"], 3), "p50_ms": round(plain["p50"], 4),
+                       "p99_ms": round(plain["p99"], 4)},
+        "speedup_vs_plain": round(win["tflops"] / plain["tflops"], 4),
+        "vendor_hipblaslt_tflops": round(vendor_tflops, 3),
+        "roofline": gemm_roofline(win, n),
+        "plain_gemm_roofline": gemm_roofline(plain, n),
+        "addition_kernels": ew_bandwidth(win, n),
+    }
+
+    if not args.no_cpu:
+        cb, rows, ref = cpu_baseline(A_np, B_np, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["rel_err"] = rel_err(win["C"], rows, ref)
+        out["plain_rel_err"] = rel_err(plain["C"], rows, ref)
+        out["rel_err_note"] = "relative Frobenius error vs the float64 oracle on the sampled rows"
+
+    if not args.no_extra:
+        extra = {}
+        for n2, lvls in ((3000, (1, 2)), (8192, (1, 2))):
+            A2_np, B2_np = inputs.pair("uniform", n2, n2, n2, 1, np.float32)
+            A2, B2 = torch.from_numpy(A2_np).cuda(), torch.from_numpy(B2_np).cuda()
+            p2 = run_product(torch, api, L, "naive", "auto", n2, 0, A2, B2, 5, 2)
+            e = {"plain_tflops": round(p2["tflops"], 3)}
+            for lv in lvls:
+                w2 = run_product(torch, api, L, "winograd", args.sched, n2, lv, A2, B2, 5, 2)
+                e[f"winograd_L{lv}_tflops"] = round(w2["tflops"], 3)
+                e[f"winograd_L{lv}_p99_ms"] = round(w2["p99"], 4)
+            extra[str(n2)] = e
+            print(f"# extra n={n2}: {e}", file=sys.stderr, flush=True)
+            del A2, B2
+        out["extra"] = extra
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * mm.h -- C ABI of libmm: C = A x B by the naive method, by Strassen's
+ * recursion and by Strassen-Winograd, on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Section 2.1): given A (m x k) and B (k x n), compute
+ * C (m x n) with c_ij = sum_p a_ip b_pj.  Strassen (Section 2.2) and
+ * Strassen-Winograd (Section 2.3) reach the same C in exact arithmetic with
+ * seven block products per level instead of eight; in floating point they
+ * round differently, so results are compared by tolerance.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * Layout     Row-major.  The short forms take contiguous matrices
+ *            (lda = k, ldb = n, ldc = n); the _ex forms take leading
+ *            dimensions in elements (ld >= row length).
+ * Pointers   A, B, C and workspaces are DEVICE pointers on the current HIP
+ *            device, owned by the caller, and must stay valid until the work
+ *            enqueued on `stream` has completed.  Host pointers are never
+ *            accepted.
+ * dtype      MM_F64: double in, double out, double arithmetic.
+ *            MM_F32: float in, float out, float MFMA products, float sums.
+ *            MM_BF16X3_REFINED: float in and out; block sums in float; every
+ *            leaf product splits each float operand x into bfloat16 parts
+ *            x = hi + lo + res (res formed in double), multiplies the parts
+ *            with bfloat16 MFMA into a float accumulator: three main
+ *            products hi*hi + hi*lo + lo*hi plus one correction
+ *            lo*lo + res*hi + hi*res.  Relative Frobenius error is about
+ *            1e-6 on well-scaled inputs (float32 level).
+ * Asynchrony Every call only enqueues work on `stream` (a hipStream_t; NULL
+ *            is the legacy default stream) and returns.  Faults inside
+ *            kernels surface at the caller's synchronisation.
+ * Errors     Every call returns an mm_status; no exception crosses the ABI.
+ *            mm_last_error() gives a message for the last non-OK status of
+ *            the calling thread.
+ * Sizes      m == 0 or n == 0: no-op, MM_OK.  k == 0: C is set to zero.
+ *
+ * Recursion control (cutoff, levels)
+ * ---------------------------------
+ * Section 3.4: the recursion stops and the naive method runs once the order
+ * is at most the cutoff.  Here a level is added while (levels < 0 or the
+ * number of levels so far < levels) and the smallest of ceil(m / 2^l),
+ * ceil(n / 2^l), ceil(k / 2^l) is greater than max(cutoff, 1).  cutoff <= 1
+ * is Algorithm 2's 1x1 base case.  At most MM_MAX_LEVELS levels are
+ * allowed (MM_E_UNSUPPORTED beyond).  Dimensions that are not multiples of
+ * 2^levels are zero-padded (Section 3.1): the grouped schedule pads virtually
+ * (out-of-range reads are zero, no copy); the depth-first schedules copy A
+ * and B into padded workspace buffers and copy the result back.
+ */
+#ifndef MM_H_
+#define MM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MM_MAX_LEVELS 6
+
+typedef enum { MM_F64 = 0, MM_F32 = 1, MM_BF16X3_REFINED = 2 } mm_dtype;
+
+/* Algorithms: Section 2.1 (naive), Section 2.2 (Strassen), Section 2.3
+ * (Strassen-Winograd, the 22-operation block form). */
+typedef enum { MM_ALGO_NAIVE = 0, MM_ALGO_STRASSEN = 1, MM_ALGO_WINOGRAD = 2 } mm_algo;
+
+/* Schedules (the order of block operations and where each result lives).
+ *  MM_SCHED_TWO_TEMP  Section 3.3, Table 2: depth-first, two temporaries
+ *                     X ((m/2) x max(k,n)/2) and Y ((k/2) x (n/2)) per
+ *                     level.  Winograd only.
+ *  MM_SCHED_IN_PLACE  Section 3.3, Table 3: depth-first, no temporaries;
+ *                     A and B are OVERWRITTEN (their contents are undefined
+ *                     afterwards).  Winograd only; needs k == n <= m.
+ *  MM_SCHED_GROUPED   Breadth-first (not in the paper): per level one fused
+ *                     launch forms all S and T blocks, the 7^L leaf products
+ *                     run as one grouped MFMA launch, and one fused launch per
+ *                     level forms the U blocks.  More workspace, far fewer
+ *                     launches, leaves fill the GPU.  Winograd only.
+ *  MM_SCHED_DFS3      Strassen, depth-first with three temporaries (the paper
+ *                     gives no reduced-memory schedule for Strassen): X and Y
+ *                     hold the operand sums, Z the product of a non-leaf level;
+ *                     leaf products add themselves into their C quadrants.
+ *  MM_SCHED_AUTO      GROUPED for Winograd, DFS3 for Strassen.
+ * For MM_ALGO_NAIVE the schedule is ignored. */
+typedef enum {
+  MM_SCHED_TWO_TEMP = 0,
+  MM_SCHED_IN_PLACE = 1,
+  MM_SCHED_GROUPED = 2,
+  MM_SCHED_DFS3 = 3,
+  MM_SCHED_AUTO = 4
+} mm_sched;
+
+typedef enum {
+  MM_OK = 0,
+  MM_E_INVALID = 1,     /* bad argument: negative size, NULL pointer with nonzero size,
+                           ld shorter than a row, unknown enum value */
+  MM_E_UNSUPPORTED = 2, /* valid but not supported: schedule/algorithm mismatch, in-place
+                           shape rule, too many levels, no GPU / wrong architecture */
+  MM_E_WORKSPACE = 3,   /* workspace smaller than the plan needs */
+  MM_E_ALIAS = 4,       /* C overlaps A or B */
+  MM_E_HIP = 5,         /* a HIP runtime call failed at enqueue time */
+  MM_E_NOMEM = 6        /* device allocation for plan metadata or a cached workspace failed */
+} mm_status;
+
+typedef struct mm_plan_s* mm_plan_t;
+
+/* ---- short forms (contiguous operands) --------------------------------- */
+
+/* The naive method (Section 2.1) as one MFMA GEMM.  Needs no workspace. */
+int mm_naive(int64_t m, int64_t n, int64_t k, const void* A, const void* B, void* C, int dtype,
+             hipStream_t stream);
+
+/* Strassen (Section 2.2, Algorithm 2 with the cutoff of Section 3.4),
+ * schedule MM_SCHED_DFS3.  Uses the workspace registered for `stream` with
+ * mm_set_workspace, else a workspace the library allocates once per
+ * (device, stream) and keeps (first call only; later calls allocate nothing
+ * unless a larger size is needed). */
+int mm_strassen(int64_t m, int64_t n, int64_t k, const void* A, const void* B, void* C, int cutoff,
+                int levels, int dtype, hipStream_t stream);
+
+/* Strassen-Winograd (Section 2.3 with Section 3.4's cutoff), schedule
+ * MM_SCHED_AUTO.  Workspace as for mm_strassen. */
+int mm_winograd(int64_t m, int64_t n, int64_t k, const void* A, const void* B, void* C, int cutoff,
+                int levels, int dtype, hipStream_t stream);
+
+/* ---- extended form ---------------------------------------------------- */
+
+/* Any algorithm and schedule, leading dimensions, caller-provided workspace
+ * (ws may be NULL when mm_workspace_size returns 0).  A and B are written
+ * only by MM_SCHED_IN_PLACE. */
+int mm_gemm_ex(int algo, int sched, int64_t m, int64_t n, int64_t k, void* A, int64_t lda, void* B,
+               int64_t ldb, void* C, int64_t ldc, int cutoff, int levels, int dtype, void* ws,
+               size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes mm_gemm_ex needs for these arguments (0 on invalid
+ * arguments; see mm_last_error). */
+size_t mm_workspace_size(int algo, int sched, int64_t m, int64_t n, int64_t k, int cutoff,
+                         int levels, int dtype);
+
+/* Register a caller-owned workspace for the short forms on `stream` (bytes 0
+ * or ws NULL unregisters).  The library never frees it. */
+int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
+
+/* ---- plans ------------------------------------------------------------ */
+
+/* Flags for mm_plan_create. */
+#define MM_PLAN_GRAPH 1u /* capture the launch sequence in a hipGraph per distinct
+                            (A, B, C, workspace) address tuple and replay it */
+
+/* Build (once) the launch sequence and device descriptor table of one
+ * product shape on the current device.  The plan owns a small device table
+ * (freed by mm_plan_destroy) and, with MM_PLAN_GRAPH, its graphs. */
+int mm_plan_create(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb,
+                   int64_t ldc, int cutoff, int levels, int dtype, unsigned flags, mm_plan_t* plan);
+
+/* Enqueue the plan on `stream` for these operands.  No allocation. */
+int mm_plan_execute(mm_plan_t plan, void* A, void* B, void* C, void* ws, size_t ws_bytes,
+                    hipStream_t stream);
+
+/* mm_plan_execute with timing: events[i] (created by the caller with
+ * hipEventCreate, i = 0 .. launches) is recorded on `stream` before launch i,
+ * and events[launches] after the last one, so the caller can read each
+ * launch's duration with hipEventElapsedTime after synchronising.  Graph
+ * capture is not used on this path. */
+int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, size_t ws_bytes,
+                          hipStream_t stream, hipEvent_t* events, int nevents);
+
+/* Kind of launch i of a plan: 0 element-wise block operations, 1 MFMA GEMM
+ * group (leaf products); -1 if i is out of range. */
+int mm_plan_op_kind(mm_plan_t plan, int i);
+
+/* Plan facts: info[0] workspace bytes, [1] levels L, [2..4] padded m, n, k,
+ * [5] kernel launches per execution, [6] leaf products, [7] schedule used,
+ * [8] leaf edge (rows of a leaf block).  Returns the number of entries written. */
+int mm_plan_info(mm_plan_t plan, int64_t* info, int ninfo);
+
+/* Human-readable listing of the launch sequence (one line per block
+ * operation, "kind dst <- srcs" with block coordinates).  Returns the length
+ * of the full text; writes at most len-1 characters and a NUL. */
+size_t mm_plan_describe(mm_plan_t plan, char* buf, size_t len);
+
+int mm_plan_destroy(mm_plan_t plan);
+
+/* ---- batches ---------------------------------------------------------- */
+
+/* A batch of independent products C_i = A_i x B_i (contiguous, one dtype),
+ * each with its own cutoff and levels (NULL arrays: cutoff 1 and levels 0,
+ * i.e. the naive method, for every problem).  Problems are executed
+ * level-synchronously: one launch per recursion stage for the whole batch
+ * and one grouped MFMA launch for every leaf of every problem.  The plan
+ * binds the operand addresses. */
+int mm_batched_plan_create(int count, const int64_t* mnk, void* const* A, void* const* B,
+                           void* const* C, int dtype, const int* cutoff, const int* levels,
+                           unsigned flags, mm_plan_t* plan);
+
+/* One-shot batch: builds (or fetches from a cache keyed by all arguments)
+ * the batched plan and executes it with the workspace given. */
+int mm_batched(int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C,
+               int dtype, const int* cutoff, const int* levels, void* ws, size_t ws_bytes,
+               hipStream_t stream);
+
+/* ---- diagnostics ------------------------------------------------------ */
+
+/* Host-only: build the plan mm_plan_create would build, without touching a
+ * device, and return its listing as mm_plan_describe does (and its facts as
+ * mm_plan_info does, when info is not NULL).  Returns 0 when the arguments
+ * are rejected (see mm_last_error).  Lets the launch sequence be inspected
+ * and checked on a machine with no GPU. */
+size_t mm_describe(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb,
+                   int64_t ldc, int cutoff, int levels, int dtype, char* buf, size_t len, int64_t* info,
+                   int ninfo);
+
+/* Host-only counterpart for mm_batched_plan_create.  The addresses are only
+ * recorded (never dereferenced), so any values may be passed. */
+size_t mm_batched_describe(int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C,
+                           int dtype, const int* cutoff, const int* levels, char* buf, size_t len,
+                           int64_t* info, int ninfo);
+
+const char* mm_last_error(void);
+int mm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H_ */

@@ -1,0 +1,85 @@
+// Descriptors shared by the planner (host) and the kernels (device).
+//
+// A plan is a list of operations.  Each operation is one kernel launch that
+// processes an array of descriptors stored in a device-resident table owned by
+// the plan.  Descriptors address memory relative to the buffers of a call
+// (A, B, C, workspace), so one plan serves every call with the same shape and
+// the table is uploaded once, when the plan is built.
+#pragma once
+#include <stdint.h>
+
+namespace mm {
+
+enum Base : int32_t { MB_A = 0, MB_B = 1, MB_C = 2, MB_WS = 3, MB_ABS = 4, MB_NONE = 5 };
+constexpr int kNumBases = 5;
+
+// A rows x cols block of a row-major matrix.  Element (r, c) lives at
+// base + off + r * ld + c.  Reads outside [0, vrows) x [0, vcols) return zero
+// and writes there are dropped: this is how zero padding is applied without
+// copying (the block is a quadrant of a conceptually padded matrix).
+struct MView {
+  int64_t off;
+  int64_t ld;
+  int32_t rows, cols;
+  int32_t vrows, vcols;
+  int32_t base;
+  int32_t vec;  // off and ld are multiples of the 16-byte vector width
+};
+
+// Element-wise block recipes.  Each names the formulas of one fused step.
+enum EwKind : int32_t {
+  EW_COPY = 0,     // o0 = i0 (with zero fill where i0 is outside its valid extent)
+  EW_ADD = 1,      // o0 = i0 + i1
+  EW_SUB = 2,      // o0 = i0 - i1
+  EW_WINO_S = 3,   // i = A11 A12 A21 A22 ; o = S1 S2 S3 S4        (Section 2.3)
+  EW_WINO_T = 4,   // i = B11 B12 B21 B22 ; o = T1 T2 T3 T4        (Section 2.3)
+  EW_WINO_U = 5,   // i = P1..P7 ; o = C11 C12 C21 C22 = U1 U5 U6 U7 (Section 2.3)
+  EW_TT_U = 6,     // Table 2 operations 13-17: i = X(P1) C11(P3) C12(P6) C21(P7) C22(P5)
+                   //                        o = C12(U5) C21(U3) C22(U7)
+  EW_IP_A = 7,     // Table 3 operations 1-2: i = A11 A21 A22 ; o = C11(S3) A21(S1)
+  EW_IP_B = 8,     // Table 3 operations 3-4: i = B11 B12 B22 ; o = C22(T1) B12(T3)
+  EW_IP_U = 9,     // Table 3 operations 16-20: i = C11(P1) C12(P2) C22(U2) A11(P5) C21(P7) A21(P4)
+                   //                          o = C11(U1) C12(U4) C21(U6) C22(U7)
+  EW_DIST = 10,    // o_j = mode_j(d_j, z): i = Z D0 D1 ; mode 1: z, 2: d + z, 3: d - z
+  EW_ZERO = 11,    // o0 = 0
+};
+
+constexpr int kEwMaxIn = 7;
+constexpr int kEwMaxOut = 4;
+
+struct EwPart {
+  int32_t kind;
+  int32_t nin, nout;
+  int32_t rows, cols;
+  int32_t blk_start;   // first block of this part in the launch
+  int32_t mode[2];     // EW_DIST output modes
+  MView in[kEwMaxIn];
+  MView out[kEwMaxOut];
+};
+
+// GEMM epilogue: out = sign * acc (store) or out = d + sign * acc (add).
+enum GemmMode : int32_t { GM_NONE = 0, GM_STORE = 1, GM_ADD = 2 };
+
+struct GemmOut {
+  MView c;
+  MView d;
+  int32_t mode;
+  int32_t sign;  // +1 or -1
+};
+
+struct GemmDesc {
+  MView a, b;
+  int32_t m, n, k;
+  int32_t tiles_m, tiles_n;
+  int32_t tile_start;  // first tile of this problem in the launch
+  int32_t nout;
+  int32_t pad_;
+  GemmOut out[2];
+};
+
+struct KernelBases {
+  void* p[kNumBases];
+  int32_t aligned;  // bit b set: base b is 16-byte aligned
+};
+
+}  // namespace mm

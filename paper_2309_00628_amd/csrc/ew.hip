@@ -1,0 +1,205 @@
+// Element-wise block kernels: the pre-additions (S, T), post-additions (U, C)
+// and the copies of the recursion levels.  These kernels move data and do one
+// add or subtract per output element, so they are bound by HBM bandwidth:
+// every thread handles 16-byte chunks of each operand with one vector load or
+// store (4 floats or 2 doubles), rows of a block map to consecutive threads,
+// and all outputs of a fused step are produced from one read of its inputs.
+//
+// One launch processes an array of parts (blocks of possibly different shape
+// and recipe); the block index selects the part.
+#include <hip/hip_runtime.h>
+
+#include "desc.h"
+#include "kernels.h"
+
+namespace mm {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 2;  // chunks per thread
+
+template <typename T>
+struct VecT;
+template <>
+struct VecT<float> {
+  static constexpr int N = 4;
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct VecT<double> {
+  static constexpr int N = 2;
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+
+template <typename T>
+__device__ inline T* resolve(const KernelBases& kb, const MView& v) {
+  char* b = v.base == MB_ABS ? nullptr : reinterpret_cast<char*>(kb.p[v.base]);
+  return reinterpret_cast<T*>(b) + v.off;
+}
+
+template <typename T, int V>
+__device__ inline void load_chunk(const KernelBases& kb, const MView& v, int r, int c0, bool vec,
+                                  T (&x)[V]) {
+  if (r >= v.vrows || c0 >= v.vcols) {
+#pragma unroll
+    for (int e = 0; e < V; ++e) x[e] = T(0);
+    return;
+  }
+  const T* p = resolve<T>(kb, v) + (int64_t)r * v.ld + c0;
+  if (vec && c0 + V <= v.vcols) {
+    typename VecT<T>::type t = *reinterpret_cast<const typename VecT<T>::type*>(p);
+#pragma unroll
+    for (int e = 0; e < V; ++e) x[e] = t[e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < V; ++e) x[e] = (c0 + e < v.vcols) ? p[e] : T(0);
+  }
+}
+
+template <typename T, int V>
+__device__ inline void store_chunk(const KernelBases& kb, const MView& v, int r, int c0, bool vec,
+                                   const T (&x)[V]) {
+  if (r >= v.vrows || c0 >= v.vcols) return;
+  T* p = resolve<T>(kb, v) + (int64_t)r * v.ld + c0;
+  if (vec && c0 + V <= v.vcols) {
+    typename VecT<T>::type t;
+#pragma unroll
+    for (int e = 0; e < V; ++e) t[e] = x[e];
+    *reinterpret_cast<typename VecT<T>::type*>(p) = t;
+  } else {
+#pragma unroll
+    for (int e = 0; e < V; ++e)
+      if (c0 + e < v.vcols) p[e] = x[e];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void ew_kernel(KernelBases kb, const EwPart* __restrict__ parts,
+                                                      int nparts) {
+  constexpr int V = VecT<T>::N;
+  const int b = blockIdx.x;
+  int lo = 0, hi = nparts - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (parts[mid].blk_start <= b) lo = mid; else hi = mid - 1;
+  }
+  const EwPart& P = parts[lo];
+  const int kind = P.kind, nin = P.nin, nout = P.nout;
+  bool vec = true;
+  for (int i = 0; i < nin; ++i)
+    vec = vec && (P.in[i].base == MB_NONE ||
+                  (P.in[i].vec && (P.in[i].base == MB_ABS || ((kb.aligned >> P.in[i].base) & 1))));
+  for (int o = 0; o < nout; ++o)
+    vec = vec && P.out[o].vec && (P.out[o].base == MB_ABS || ((kb.aligned >> P.out[o].base) & 1));
+  const int cpr = (P.cols + V - 1) / V;
+  const int64_t total = (int64_t)P.rows * cpr;
+  const int64_t first = (int64_t)(b - P.blk_start) * (kThreads * kItems) + threadIdx.x;
+
+  for (int it = 0; it < kItems; ++it) {
+    const int64_t q = first + (int64_t)it * kThreads;
+    if (q >= total) break;
+    const int r = (int)(q / cpr);
+    const int c0 = (int)(q - (int64_t)r * cpr) * V;
+    T x[kEwMaxIn][V];
+    T y[kEwMaxOut][V];
+#pragma unroll
+    for (int i = 0; i < kEwMaxIn; ++i)
+      if (i < nin) load_chunk<T, V>(kb, P.in[i], r, c0, vec, x[i]);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      switch (kind) {
+        case EW_COPY: y[0][e] = x[0][e]; break;
+        case EW_ADD: y[0][e] = x[0][e] + x[1][e]; break;
+        case EW_SUB: y[0][e] = x[0][e] - x[1][e]; break;
+        case EW_WINO_S: {  // x = A11 A12 A21 A22
+          const T s1 = x[2][e] + x[3][e];
+          const T s2 = s1 - x[0][e];
+          const T s3 = x[0][e] - x[2][e];
+          const T s4 = x[1][e] - s2;
+          y[0][e] = s1; y[1][e] = s2; y[2][e] = s3; y[3][e] = s4;
+          break;
+        }
+        case EW_WINO_T: {  // x = B11 B12 B21 B22
+          const T t1 = x[1][e] - x[0][e];
+          const T t2 = x[3][e] - t1;
+          const T t3 = x[3][e] - x[1][e];
+          const T t4 = t2 - x[2][e];
+          y[0][e] = t1; y[1][e] = t2; y[2][e] = t3; y[3][e] = t4;
+          break;
+        }
+        case EW_WINO_U: {  // x = P1..P7
+          const T u1 = x[0][e] + x[1][e];
+          const T u2 = x[0][e] + x[5][e];
+          const T u3 = u2 + x[6][e];
+          const T u4 = u2 + x[4][e];
+          const T u5 = u4 + x[2][e];
+          const T u6 = u3 - x[3][e];
+          const T u7 = u3 + x[4][e];
+          y[0][e] = u1; y[1][e] = u5; y[2][e] = u6; y[3][e] = u7;
+          break;
+        }
+        case EW_TT_U: {  // x = X(P1) C11(P3) C12(P6) C21(P7) C22(P5)
+          const T u2 = x[0][e] + x[2][e];
+          const T u3 = u2 + x[3][e];
+          const T u4 = u2 + x[4][e];
+          const T u7 = u3 + x[4][e];
+          const T u5 = u4 + x[1][e];
+          y[0][e] = u5; y[1][e] = u3; y[2][e] = u7;
+          break;
+        }
+        case EW_IP_A: {  // x = A11 A21 A22 ; y = S3 S1
+          y[0][e] = x[0][e] - x[1][e];
+          y[1][e] = x[1][e] + x[2][e];
+          break;
+        }
+        case EW_IP_B: {  // x = B11 B12 B22 ; y = T1 T3
+          y[0][e] = x[1][e] - x[0][e];
+          y[1][e] = x[2][e] - x[1][e];
+          break;
+        }
+        case EW_IP_U: {  // x = P1 P2 U2 P5 P7 P4 ; y = U1 U4 U6 U7
+          const T u1 = x[0][e] + x[1][e];
+          const T u4 = x[2][e] + x[3][e];
+          const T u3 = x[2][e] + x[4][e];
+          const T u6 = u3 - x[5][e];
+          const T u7 = u3 + x[3][e];
+          y[0][e] = u1; y[1][e] = u4; y[2][e] = u6; y[3][e] = u7;
+          break;
+        }
+        case EW_DIST: {  // x = Z D0 D1
+          for (int o = 0; o < 2; ++o) {
+            const int md = P.mode[o];
+            y[o][e] = md == 1 ? x[0][e] : (md == 2 ? x[1 + o][e] + x[0][e] : x[1 + o][e] - x[0][e]);
+          }
+          break;
+        }
+        default: y[0][e] = T(0); break;  // EW_ZERO
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < kEwMaxOut; ++o)
+      if (o < nout) store_chunk<T, V>(kb, P.out[o], r, c0, vec, y[o]);
+  }
+}
+
+}  // namespace
+
+int ew_blocks(int rows, int cols, int dtype) {
+  const int V = dtype == DT_F64 ? 2 : 4;
+  const int64_t cpr = (cols + V - 1) / V;
+  const int64_t chunks = (int64_t)rows * cpr;
+  return (int)((chunks + kThreads * kItems - 1) / (kThreads * kItems));
+}
+
+hipError_t launch_ew(int dtype, const KernelBases& kb, const EwPart* dparts, int nparts, int blocks,
+                     hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (dtype == DT_F64)
+    hipLaunchKernelGGL(ew_kernel<double>, dim3(blocks), dim3(kThreads), 0, s, kb, dparts, nparts);
+  else
+    hipLaunchKernelGGL(ew_kernel<float>, dim3(blocks), dim3(kThreads), 0, s, kb, dparts, nparts);
+  return hipGetLastError();
+}
+
+}  // namespace mm

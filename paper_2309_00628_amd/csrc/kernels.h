@@ -1,0 +1,25 @@
+// Host-side launch functions of the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "desc.h"
+
+namespace mm {
+
+// Element types the kernels compute in (the public dtype codes of mm.h map
+// onto these; the split-bfloat16 path keeps float32 buffers).
+enum KDtype : int { DT_F64 = 0, DT_F32 = 1, DT_BF16X3 = 2 };
+
+// Block-tile geometry of the MFMA GEMM kernels (rows x cols of C per
+// workgroup).  The planner needs it to count tiles.
+constexpr int kGemmBM = 128;
+constexpr int kGemmBN = 128;
+
+int ew_blocks(int rows, int cols, int dtype);
+hipError_t launch_ew(int dtype, const KernelBases& kb, const EwPart* dparts, int nparts, int blocks,
+                     hipStream_t s);
+bool gemm_bf16x3_available();
+hipError_t launch_gemm(int dtype, const KernelBases& kb, const GemmDesc* ddescs, int ndesc, int tiles,
+                       hipStream_t s);
+
+}  // namespace mm

@@ -1,0 +1,1232 @@
+// libmm host side: argument checking, the planner that turns a product
+// (algorithm, schedule, shape, cutoff, levels) into a launch sequence, the
+// executor, plan and workspace caches, hipGraph capture, and the C ABI.
+//
+// A plan is built once per shape.  The planner walks the recursion the way
+// the chosen schedule orders it and records each block operation as a
+// descriptor (element-wise parts for the additions, GEMM descriptors for the
+// leaf products).  Descriptors address memory relative to the call's buffers
+// (A, B, C, workspace) so the table is uploaded to the device once and every
+// later execution is kernel launches only.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "mm.h"
+#include "desc.h"
+#include "kernels.h"
+
+struct mm_plan_s;
+
+namespace mm {
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+size_t elem_size(int dtype) { return dtype == MM_F64 ? 8 : 4; }
+int kernel_dtype(int dtype) { return dtype == MM_F64 ? DT_F64 : (dtype == MM_F32 ? DT_F32 : DT_BF16X3); }
+int ew_dtype(int dtype) { return dtype == MM_F64 ? DT_F64 : DT_F32; }
+
+enum OpType { OP_EW = 0, OP_GEMM = 1 };
+
+struct OpRec {
+  int type;
+  int kdtype;
+  size_t off;  // byte offset of the first descriptor in the table
+  int count;   // descriptors
+  int grid;    // workgroups
+};
+
+}  // namespace
+
+struct Plan {
+  int algo = 0, sched = 0, dtype = 0;
+  int64_t m = 0, n = 0, k = 0, lda = 0, ldb = 0, ldc = 0;
+  int64_t M = 0, N = 0, K = 0;  // padded sizes
+  int cutoff = 1, levels = 0, L = 0;
+  int64_t leaf_rows = 0;
+  int64_t leaves = 0;
+  size_t ws_bytes = 0;
+  bool batched = false;
+  unsigned flags = 0;
+  std::vector<OpRec> ops;
+  std::vector<uint8_t> table;
+  std::string text;
+  void* dtable = nullptr;
+  int device = -1;
+  struct Graph {
+    void *a, *b, *c, *ws;
+    hipStream_t stream;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+  std::mutex mu;
+  ~Plan() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    if (dtable) (void)hipFree(dtable);
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Builder: records block operations while a schedule walks its recursion.
+// ---------------------------------------------------------------------------
+struct Builder {
+  Plan& P;
+  size_t esz;
+  int64_t E;  // elements per 16-byte vector
+  int64_t ws_top = 0, ws_peak = 0;
+  std::vector<EwPart> ew;
+  int ew_grid = 0;
+  std::vector<GemmDesc> gm;
+  int gm_grid = 0;
+  std::ostringstream txt;
+
+  explicit Builder(Plan& p) : P(p), esz(elem_size(p.dtype)), E(16 / (int64_t)elem_size(p.dtype)) {}
+
+  MView view(int base, int64_t off, int64_t ld, int64_t rows, int64_t cols, int64_t vr, int64_t vc) {
+    MView v;
+    v.base = base;
+    v.off = off;
+    v.ld = ld;
+    v.rows = (int32_t)rows;
+    v.cols = (int32_t)cols;
+    v.vrows = (int32_t)std::max<int64_t>(0, std::min(vr, rows));
+    v.vcols = (int32_t)std::max<int64_t>(0, std::min(vc, cols));
+    if (v.vrows == 0 || v.vcols == 0) v.vrows = v.vcols = 0;
+    if (base == MB_ABS)
+      v.vec = ((off * (int64_t)esz) % 16 == 0) && (ld % E == 0);
+    else
+      v.vec = (off % E == 0) && (ld % E == 0);
+    return v;
+  }
+  MView none() {
+    MView v;
+    std::memset(&v, 0, sizeof v);
+    v.base = MB_NONE;
+    return v;
+  }
+  // Quadrant (qi, qj) of an even-sized block, with its valid extent clipped.
+  MView quad(const MView& v, int qi, int qj) {
+    const int64_t r = v.rows / 2, c = v.cols / 2;
+    return view(v.base, v.off + qi * r * v.ld + qj * c, v.ld, r, c, (int64_t)v.vrows - qi * r,
+                (int64_t)v.vcols - qj * c);
+  }
+  MView corner(const MView& v, int64_t rows, int64_t cols) {
+    return view(v.base, v.off, v.ld, rows, cols, std::min<int64_t>(v.vrows, rows),
+                std::min<int64_t>(v.vcols, cols));
+  }
+  MView temp(int64_t rows, int64_t cols) {
+    const int64_t ld = std::max<int64_t>(round_up(std::max<int64_t>(cols, 1), E), 1);
+    const int64_t off = ws_top;
+    ws_top += round_up(rows * ld, 64);  // 256-byte aligned slots
+    ws_peak = std::max(ws_peak, ws_top);
+    return view(MB_WS, off, ld, rows, cols, rows, cols);
+  }
+
+  static std::string vs(const MView& v) {
+    std::ostringstream o;
+    if (v.base == MB_NONE) return "-";
+    o << v.base << ":" << v.off << ":" << v.ld << ":" << v.rows << ":" << v.cols << ":" << v.vrows
+      << ":" << v.vcols;
+    return o.str();
+  }
+
+  // ---- element-wise parts ------------------------------------------------
+  void ew_part(int kind, int64_t rows, int64_t cols, std::initializer_list<MView> ins,
+               std::initializer_list<MView> outs, int mode0 = 0, int mode1 = 0) {
+    if (!gm.empty()) flush();
+    EwPart p;
+    std::memset(&p, 0, sizeof p);
+    p.kind = kind;
+    p.rows = (int32_t)rows;
+    p.cols = (int32_t)cols;
+    p.nin = (int32_t)ins.size();
+    p.nout = (int32_t)outs.size();
+    p.mode[0] = mode0;
+    p.mode[1] = mode1;
+    int i = 0;
+    for (const auto& v : ins) p.in[i++] = v;
+    for (; i < kEwMaxIn; ++i) p.in[i] = none();
+    i = 0;
+    for (const auto& v : outs) p.out[i++] = v;
+    for (; i < kEwMaxOut; ++i) p.out[i] = none();
+    const int blocks = ew_blocks((int)rows, (int)cols, ew_dtype(P.dtype));
+    if (blocks == 0) return;
+    p.blk_start = ew_grid;
+    ew_grid += blocks;
+    ew.push_back(p);
+    txt << "EW " << kind << " " << rows << " " << cols << " " << mode0 << " " << mode1 << " |";
+    for (const auto& v : ins) txt << " " << vs(v);
+    txt << " |";
+    for (const auto& v : outs) txt << " " << vs(v);
+    txt << "\n";
+  }
+
+  // ---- leaf products -------------------------------------------------------
+  struct Out {
+    MView c;
+    int mode;
+    int sign;
+    MView d;
+  };
+  static Out store(const MView& c, int sign = 1) { return Out{c, GM_STORE, sign, MView{}}; }
+  static Out add(const MView& c, const MView& d, int sign) { return Out{c, GM_ADD, sign, d}; }
+
+  void gemm(const MView& a, const MView& b, std::initializer_list<Out> outs) {
+    if (!ew.empty()) flush();
+    GemmDesc g;
+    std::memset(&g, 0, sizeof g);
+    g.a = a;
+    g.b = b;
+    g.m = a.rows;
+    g.k = a.cols;
+    g.n = b.cols;
+    g.nout = (int32_t)outs.size();
+    int i = 0;
+    for (const auto& o : outs) {
+      g.out[i].c = o.c;
+      g.out[i].mode = o.mode;
+      g.out[i].sign = o.sign;
+      g.out[i].d = o.mode == GM_ADD ? o.d : none();
+      ++i;
+    }
+    for (; i < 2; ++i) {
+      g.out[i].c = none();
+      g.out[i].d = none();
+      g.out[i].mode = GM_NONE;
+      g.out[i].sign = 1;
+    }
+    P.leaves += 1;
+    g.tiles_m = (int32_t)ceil_div(g.m, kGemmBM);
+    g.tiles_n = (int32_t)ceil_div(g.n, kGemmBN);
+    const int tiles = g.tiles_m * g.tiles_n;
+    txt << "GEMM " << g.m << " " << g.n << " " << g.k << " | " << vs(a) << " " << vs(b) << " |";
+    for (int j = 0; j < g.nout; ++j)
+      txt << " " << g.out[j].mode << ":" << g.out[j].sign << ":" << vs(g.out[j].c) << ":"
+          << vs(g.out[j].d);
+    txt << "\n";
+    if (tiles == 0) return;
+    g.tile_start = gm_grid;
+    gm_grid += tiles;
+    gm.push_back(g);
+  }
+
+  // Close the current launch.
+  void flush() {
+    if (!ew.empty()) {
+      OpRec r{OP_EW, ew_dtype(P.dtype), P.table.size(), (int)ew.size(), ew_grid};
+      const size_t bytes = ew.size() * sizeof(EwPart);
+      P.table.resize(round_up(P.table.size() + bytes, 256));
+      std::memcpy(P.table.data() + r.off, ew.data(), bytes);
+      P.ops.push_back(r);
+      txt << "LAUNCH EW " << ew.size() << " " << ew_grid << "\n";
+      ew.clear();
+      ew_grid = 0;
+    }
+    if (!gm.empty()) {
+      OpRec r{OP_GEMM, kernel_dtype(P.dtype), P.table.size(), (int)gm.size(), gm_grid};
+      const size_t bytes = gm.size() * sizeof(GemmDesc);
+      P.table.resize(round_up(P.table.size() + bytes, 256));
+      std::memcpy(P.table.data() + r.off, gm.data(), bytes);
+      P.ops.push_back(r);
+      txt << "LAUNCH GEMM " << gm.size() << " " << gm_grid << "\n";
+      gm.clear();
+      gm_grid = 0;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Schedules
+// ---------------------------------------------------------------------------
+
+// Section 3.3, Table 2 (Two Temp Winograd), depth first.  C = A B.
+void sched_two_temp(Builder& b, const MView& A, const MView& B, const MView& C, int depth) {
+  const int L = b.P.L;
+  if (depth == L) {
+    b.gemm(A, B, {Builder::store(C)});
+    b.flush();
+    return;
+  }
+  const int64_t hm = A.rows / 2, hk = A.cols / 2, hn = B.cols / 2;
+  const MView A11 = b.quad(A, 0, 0), A12 = b.quad(A, 0, 1), A21 = b.quad(A, 1, 0), A22 = b.quad(A, 1, 1);
+  const MView B11 = b.quad(B, 0, 0), B12 = b.quad(B, 0, 1), B21 = b.quad(B, 1, 0), B22 = b.quad(B, 1, 1);
+  const MView C11 = b.quad(C, 0, 0), C12 = b.quad(C, 0, 1), C21 = b.quad(C, 1, 0), C22 = b.quad(C, 1, 1);
+  const int64_t mark = b.ws_top;
+  const MView X = b.temp(hm, std::max(hk, hn));
+  const MView Y = b.temp(hk, hn);
+  const MView XS = b.corner(X, hm, hk), XP = b.corner(X, hm, hn);
+  const bool leaf = depth + 1 == L;
+  // 1, 2: S3 = A11 - A21 -> X ; T3 = B22 - B12 -> Y
+  b.ew_part(EW_SUB, hm, hk, {A11, A21}, {XS});
+  b.ew_part(EW_SUB, hk, hn, {B22, B12}, {Y});
+  b.flush();
+  // 3: P7 = S3 T3 -> C21
+  sched_two_temp(b, XS, Y, C21, depth + 1);
+  // 4, 5: S1 = A21 + A22 -> X ; T1 = B12 - B11 -> Y
+  b.ew_part(EW_ADD, hm, hk, {A21, A22}, {XS});
+  b.ew_part(EW_SUB, hk, hn, {B12, B11}, {Y});
+  b.flush();
+  // 6: P5 = S1 T1 -> C22
+  sched_two_temp(b, XS, Y, C22, depth + 1);
+  // 7, 8: S2 = S1 - A11 -> X ; T2 = B22 - T1 -> Y
+  b.ew_part(EW_SUB, hm, hk, {XS, A11}, {XS});
+  b.ew_part(EW_SUB, hk, hn, {B22, Y}, {Y});
+  b.flush();
+  // 9: P6 = S2 T2 -> C12
+  sched_two_temp(b, XS, Y, C12, depth + 1);
+  // 10: S4 = A12 - S2 -> X
+  b.ew_part(EW_SUB, hm, hk, {A12, XS}, {XS});
+  b.flush();
+  // 11: P3 = S4 B22 -> C11
+  sched_two_temp(b, XS, B22, C11, depth + 1);
+  // 12: P1 = A11 B11 -> X
+  sched_two_temp(b, A11, B11, XP, depth + 1);
+  // 13-17: U2, U3, U4, U7, U5 (fused; same per-element order) ; 18: T4 = T2 - B21 -> Y
+  b.ew_part(EW_TT_U, hm, hn, {XP, C11, C12, C21, C22}, {C12, C21, C22});
+  b.ew_part(EW_SUB, hk, hn, {Y, B21}, {Y});
+  b.flush();
+  // 19, 20: P4 = A22 T4 -> C11 ; U6 = U3 - P4 -> C21
+  if (leaf) {
+    b.gemm(A22, Y, {Builder::add(C21, C21, -1)});
+    b.flush();
+  } else {
+    sched_two_temp(b, A22, Y, C11, depth + 1);
+    b.ew_part(EW_SUB, hm, hn, {C21, C11}, {C21});
+    b.flush();
+  }
+  // 21, 22: P2 = A12 B21 -> C11 ; U1 = P1 + P2 -> C11
+  if (leaf) {
+    b.gemm(A12, B21, {Builder::add(C11, XP, +1)});
+    b.flush();
+  } else {
+    sched_two_temp(b, A12, B21, C11, depth + 1);
+    b.ew_part(EW_ADD, hm, hn, {XP, C11}, {C11});
+    b.flush();
+  }
+  b.flush();
+  b.ws_top = mark;
+}
+
+// Section 3.3, Table 3 (In-Place Winograd), depth first.  C = A B; A and B
+// are overwritten.  Needs k == n <= m (slot sizes).
+void sched_in_place(Builder& b, const MView& A, const MView& B, const MView& C, int depth) {
+  const int L = b.P.L;
+  if (depth == L) {
+    b.gemm(A, B, {Builder::store(C)});
+    b.flush();
+    return;
+  }
+  const int64_t hm = A.rows / 2, hk = A.cols / 2, hn = B.cols / 2;
+  const MView A11 = b.quad(A, 0, 0), A12 = b.quad(A, 0, 1), A21 = b.quad(A, 1, 0), A22 = b.quad(A, 1, 1);
+  const MView B11 = b.quad(B, 0, 0), B12 = b.quad(B, 0, 1), B21 = b.quad(B, 1, 0), B22 = b.quad(B, 1, 1);
+  const MView C11 = b.quad(C, 0, 0), C12 = b.quad(C, 0, 1), C21 = b.quad(C, 1, 0), C22 = b.quad(C, 1, 1);
+  const MView S3 = b.corner(C11, hm, hk), T1 = b.corner(C22, hk, hn), S2 = b.corner(C12, hm, hk);
+  const MView T4 = b.corner(C22, hk, hn);
+  const MView P5 = b.corner(A11, hm, hn), P4 = b.corner(A21, hm, hn), P3 = b.corner(A12, hm, hn);
+  const bool leaf = depth + 1 == L;
+  // 1-4: S3 -> C11, S1 -> A21, T1 -> C22, T3 -> B12
+  b.ew_part(EW_IP_A, hm, hk, {A11, A21, A22}, {S3, A21});
+  b.ew_part(EW_IP_B, hk, hn, {B11, B12, B22}, {T1, B12});
+  b.flush();
+  // 5: P7 = S3 T3 -> C21
+  sched_in_place(b, S3, B12, C21, depth + 1);
+  // 6: S2 = S1 - A11 -> C12
+  b.ew_part(EW_SUB, hm, hk, {A21, A11}, {S2});
+  b.flush();
+  // 7: P1 = A11 B11 -> C11
+  sched_in_place(b, A11, B11, C11, depth + 1);
+  // 8: T2 = B22 - T1 -> B11
+  b.ew_part(EW_SUB, hk, hn, {B22, T1}, {B11});
+  b.flush();
+  // 9: P5 = S1 T1 -> A11
+  sched_in_place(b, A21, T1, P5, depth + 1);
+  // 10: T4 = T2 - B21 -> C22
+  b.ew_part(EW_SUB, hk, hn, {B11, B21}, {T4});
+  b.flush();
+  // 11: P4 = A22 T4 -> A21
+  sched_in_place(b, A22, T4, P4, depth + 1);
+  // 12: S4 = A12 - S2 -> A22
+  b.ew_part(EW_SUB, hm, hk, {A12, S2}, {A22});
+  b.flush();
+  // 13, 14: P6 = S2 T2 -> C22 ; U2 = P1 + P6 -> C22
+  if (leaf) {
+    b.gemm(S2, B11, {Builder::add(C22, C11, +1)});
+    b.flush();
+  } else {
+    sched_in_place(b, S2, B11, C22, depth + 1);
+    b.ew_part(EW_ADD, hm, hn, {C11, C22}, {C22});
+    b.flush();
+  }
+  // 15: P2 = A12 B21 -> C12
+  sched_in_place(b, A12, B21, C12, depth + 1);
+  // 16-20: U1 -> C11, U4 -> C12, U3, U6 -> C21, U7 -> C22 (fused)
+  b.ew_part(EW_IP_U, hm, hn, {C11, C12, C22, P5, C21, P4}, {C11, C12, C21, C22});
+  b.flush();
+  // 21, 22: P3 = S4 B22 -> A12 ; U5 = U4 + P3 -> C12
+  if (leaf) {
+    b.gemm(A22, B22, {Builder::add(C12, C12, +1)});
+    b.flush();
+  } else {
+    sched_in_place(b, A22, B22, P3, depth + 1);
+    b.ew_part(EW_ADD, hm, hn, {C12, P3}, {C12});
+    b.flush();
+  }
+}
+
+// Strassen (Section 2.2), depth first with three temporaries.  The products
+// are taken in the order P1, P3, P2, P4, P5, P6, P7 so that every C quadrant
+// is accumulated left to right exactly as the paper writes it:
+// C11 = ((P1 + P4) - P5) + P7, C12 = P3 + P5, C21 = P2 + P4,
+// C22 = ((P1 + P3) - P2) + P6.
+void sched_strassen(Builder& b, const MView& A, const MView& B, const MView& C, int depth) {
+  const int L = b.P.L;
+  if (depth == L) {
+    b.gemm(A, B, {Builder::store(C)});
+    b.flush();
+    return;
+  }
+  const int64_t hm = A.rows / 2, hk = A.cols / 2, hn = B.cols / 2;
+  const MView A11 = b.quad(A, 0, 0), A12 = b.quad(A, 0, 1), A21 = b.quad(A, 1, 0), A22 = b.quad(A, 1, 1);
+  const MView B11 = b.quad(B, 0, 0), B12 = b.quad(B, 0, 1), B21 = b.quad(B, 1, 0), B22 = b.quad(B, 1, 1);
+  const MView C11 = b.quad(C, 0, 0), C12 = b.quad(C, 0, 1), C21 = b.quad(C, 1, 0), C22 = b.quad(C, 1, 1);
+  const int64_t mark = b.ws_top;
+  const MView X = b.temp(hm, hk);
+  const MView Y = b.temp(hk, hn);
+  const bool leaf = depth + 1 == L;
+  const MView Z = leaf ? b.none() : b.temp(hm, hn);
+  // mode: 1 = store, 2 = add, 3 = subtract
+  auto product = [&](const MView& Aop, const MView& Bop, const MView& D0, int m0, const MView* D1, int m1) {
+    if (leaf) {
+      auto out = [&](const MView& d, int md) {
+        return md == 1 ? Builder::store(d) : Builder::add(d, d, md == 2 ? +1 : -1);
+      };
+      if (D1)
+        b.gemm(Aop, Bop, {out(D0, m0), out(*D1, m1)});
+      else
+        b.gemm(Aop, Bop, {out(D0, m0)});
+      b.flush();
+    } else {
+      sched_strassen(b, Aop, Bop, Z, depth + 1);
+      if (D1)
+        b.ew_part(EW_DIST, hm, hn, {Z, D0, *D1}, {D0, *D1}, m0, m1);
+      else
+        b.ew_part(EW_DIST, hm, hn, {Z, D0, b.none()}, {D0}, m0, 0);
+      b.flush();
+    }
+  };
+  // P1 = (A11 + A22)(B11 + B22): C11 = P1, C22 = P1
+  b.ew_part(EW_ADD, hm, hk, {A11, A22}, {X});
+  b.ew_part(EW_ADD, hk, hn, {B11, B22}, {Y});
+  b.flush();
+  product(X, Y, C11, 1, &C22, 1);
+  // P3 = A11 (B12 - B22): C12 = P3, C22 += P3
+  b.ew_part(EW_SUB, hk, hn, {B12, B22}, {Y});
+  b.flush();
+  product(A11, Y, C12, 1, &C22, 2);
+  // P2 = (A21 + A22) B11: C21 = P2, C22 -= P2
+  b.ew_part(EW_ADD, hm, hk, {A21, A22}, {X});
+  b.flush();
+  product(X, B11, C21, 1, &C22, 3);
+  // P4 = A22 (-B11 + B21): C11 += P4, C21 += P4
+  b.ew_part(EW_SUB, hk, hn, {B21, B11}, {Y});
+  b.flush();
+  product(A22, Y, C11, 2, &C21, 2);
+  // P5 = (A11 + A12) B22: C11 -= P5, C12 += P5
+  b.ew_part(EW_ADD, hm, hk, {A11, A12}, {X});
+  b.flush();
+  product(X, B22, C11, 3, &C12, 2);
+  // P6 = (-A11 + A21)(B11 + B12): C22 += P6
+  b.ew_part(EW_SUB, hm, hk, {A21, A11}, {X});
+  b.ew_part(EW_ADD, hk, hn, {B11, B12}, {Y});
+  b.flush();
+  product(X, Y, C22, 2, nullptr, 0);
+  // P7 = (A12 - A22)(B21 + B22): C11 += P7
+  b.ew_part(EW_SUB, hm, hk, {A12, A22}, {X});
+  b.ew_part(EW_ADD, hk, hn, {B21, B22}, {Y});
+  b.flush();
+  product(X, Y, C11, 2, nullptr, 0);
+  b.ws_top = mark;
+}
+
+// Breadth-first Winograd (the 22-operation form of Section 2.3 evaluated
+// level by level): one launch forms S1..S4 and T1..T4 for every block of a
+// level, one grouped launch runs all 7^L leaf products, and one launch per
+// level forms U1, U5, U6, U7 into the C quadrants.  Per element the
+// operations and their order are those of the block form, so the result is
+// bitwise the same as the depth-first schedules with the same leaf kernel.
+struct Sub {
+  MView A, B, C;
+};
+
+void sched_grouped(Builder& b, std::vector<Sub> subs) {
+  const int L = b.P.L;
+  std::vector<std::vector<EwPart>> u_levels;  // recorded, emitted in reverse
+  std::vector<std::string> u_text;
+  for (int l = 0; l < L; ++l) {
+    std::vector<Sub> next;
+    next.reserve(subs.size() * 7);
+    std::vector<std::array<MView, 11>> uargs;
+    for (const Sub& s : subs) {
+      const int64_t hm = s.A.rows / 2, hk = s.A.cols / 2, hn = s.B.cols / 2;
+      const MView A11 = b.quad(s.A, 0, 0), A12 = b.quad(s.A, 0, 1), A21 = b.quad(s.A, 1, 0),
+                  A22 = b.quad(s.A, 1, 1);
+      const MView B11 = b.quad(s.B, 0, 0), B12 = b.quad(s.B, 0, 1), B21 = b.quad(s.B, 1, 0),
+                  B22 = b.quad(s.B, 1, 1);
+      MView S[4], T[4], Pt[7];
+      for (auto& v : S) v = b.temp(hm, hk);
+      for (auto& v : T) v = b.temp(hk, hn);
+      for (auto& v : Pt) v = b.temp(hm, hn);
+      b.ew_part(EW_WINO_S, hm, hk, {A11, A12, A21, A22}, {S[0], S[1], S[2], S[3]});
+      b.ew_part(EW_WINO_T, hk, hn, {B11, B12, B21, B22}, {T[0], T[1], T[2], T[3]});
+      next.push_back({A11, B11, Pt[0]});
+      next.push_back({A12, B21, Pt[1]});
+      next.push_back({S[3], B22, Pt[2]});
+      next.push_back({A22, T[3], Pt[3]});
+      next.push_back({S[0], T[0], Pt[4]});
+      next.push_back({S[1], T[1], Pt[5]});
+      next.push_back({S[2], T[2], Pt[6]});
+      uargs.push_back({Pt[0], Pt[1], Pt[2], Pt[3], Pt[4], Pt[5], Pt[6], b.quad(s.C, 0, 0),
+                       b.quad(s.C, 0, 1), b.quad(s.C, 1, 0), b.quad(s.C, 1, 1)});
+    }
+    b.flush();
+    // U parts of this level are emitted after the deeper levels finish.
+    u_levels.emplace_back();
+    for (const auto& u : uargs) {
+      EwPart p;
+      std::memset(&p, 0, sizeof p);
+      p.kind = EW_WINO_U;
+      p.rows = u[7].rows;
+      p.cols = u[7].cols;
+      p.nin = 7;
+      p.nout = 4;
+      for (int i = 0; i < 7; ++i) p.in[i] = u[i];
+      for (int i = 0; i < 4; ++i) p.out[i] = u[7 + i];
+      u_levels.back().push_back(p);
+    }
+    subs.swap(next);
+  }
+  for (const Sub& s : subs) b.gemm(s.A, s.B, {Builder::store(s.C)});
+  b.flush();
+  for (int l = L - 1; l >= 0; --l) {
+    for (const EwPart& p : u_levels[l])
+      b.ew_part(EW_WINO_U, p.rows, p.cols, {p.in[0], p.in[1], p.in[2], p.in[3], p.in[4], p.in[5], p.in[6]},
+                {p.out[0], p.out[1], p.out[2], p.out[3]});
+    b.flush();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Planning
+// ---------------------------------------------------------------------------
+int count_levels(int64_t m, int64_t n, int64_t k, int cutoff, int levels) {
+  const int64_t c = std::max(cutoff, 1);
+  int L = 0;
+  while (levels < 0 || L < levels) {
+    const int64_t d = (int64_t)1 << L;
+    const int64_t mn = std::min(std::min(ceil_div(m, d), ceil_div(n, d)), ceil_div(k, d));
+    if (mn <= c) break;
+    ++L;
+    if (L > 62) break;
+  }
+  return L;
+}
+
+bool bf16x3_available() { return gemm_bf16x3_available(); }
+
+int check_enums(int algo, int sched, int dtype) {
+  if (dtype < MM_F64 || dtype > MM_BF16X3_REFINED) return fail(MM_E_INVALID, "unknown dtype");
+  if (algo < MM_ALGO_NAIVE || algo > MM_ALGO_WINOGRAD) return fail(MM_E_INVALID, "unknown algorithm");
+  if (sched < MM_SCHED_TWO_TEMP || sched > MM_SCHED_AUTO) return fail(MM_E_INVALID, "unknown schedule");
+  return MM_OK;
+}
+
+int resolve_sched(int algo, int sched) {
+  if (algo == MM_ALGO_NAIVE) return MM_SCHED_AUTO;
+  if (sched == MM_SCHED_AUTO) return algo == MM_ALGO_STRASSEN ? MM_SCHED_DFS3 : MM_SCHED_GROUPED;
+  return sched;
+}
+
+// Build the launch sequence of one product into P (host side only).
+int build_plan(Plan& P) {
+  P.sched = resolve_sched(P.algo, P.sched);
+  if (P.dtype == MM_BF16X3_REFINED && !bf16x3_available())
+    return fail(MM_E_UNSUPPORTED, "split-bfloat16 leaves are not built into this library");
+  if (P.algo == MM_ALGO_STRASSEN && P.sched != MM_SCHED_DFS3)
+    return fail(MM_E_UNSUPPORTED, "Strassen supports the DFS3 schedule only");
+  if (P.algo == MM_ALGO_WINOGRAD && P.sched == MM_SCHED_DFS3)
+    return fail(MM_E_UNSUPPORTED, "DFS3 is a Strassen schedule");
+  const int64_t m = P.m, n = P.n, k = P.k;
+  P.L = (P.algo == MM_ALGO_NAIVE || m == 0 || n == 0 || k == 0)
+            ? 0
+            : count_levels(m, n, k, P.cutoff, P.levels);
+  if (P.L > MM_MAX_LEVELS)
+    return fail(MM_E_UNSUPPORTED, "recursion would need " + std::to_string(P.L) + " levels (max " +
+                                      std::to_string(MM_MAX_LEVELS) + "); raise cutoff or set levels");
+  Builder b(P);
+  const int64_t step = (int64_t)1 << P.L;
+  int64_t g = 1;
+  if (P.sched == MM_SCHED_GROUPED && P.L > 0 && std::min(std::min(m, n), k) / step >= 32) g = b.E;
+  P.M = round_up(m, step * g);
+  P.N = round_up(n, step * g);
+  P.K = round_up(k, step * g);
+  if (P.L == 0) {
+    P.M = m;
+    P.N = n;
+    P.K = k;
+  }
+  P.leaf_rows = P.M >> P.L;
+  if (P.sched == MM_SCHED_IN_PLACE && P.L > 0 && !(P.K == P.N && P.N <= P.M))
+    return fail(MM_E_UNSUPPORTED, "in-place schedule needs k == n <= m");
+
+  if (m == 0 || n == 0) {
+    // nothing to do
+  } else if (P.L == 0) {
+    const MView A = b.view(MB_A, 0, P.lda, m, k, m, k);
+    const MView B = b.view(MB_B, 0, P.ldb, k, n, k, n);
+    const MView C = b.view(MB_C, 0, P.ldc, m, n, m, n);
+    if (k == 0)
+      b.ew_part(EW_ZERO, m, n, {}, {C});
+    else
+      b.gemm(A, B, {Builder::store(C)});
+    b.flush();
+  } else if (P.sched == MM_SCHED_GROUPED) {
+    const MView A = b.view(MB_A, 0, P.lda, P.M, P.K, m, k);
+    const MView B = b.view(MB_B, 0, P.ldb, P.K, P.N, k, n);
+    const MView C = b.view(MB_C, 0, P.ldc, P.M, P.N, m, n);
+    sched_grouped(b, {Sub{A, B, C}});
+  } else {
+    // Depth-first schedules work on real buffers: pad by copying when needed.
+    const bool pad = P.M != m || P.N != n || P.K != k;
+    MView A = b.view(MB_A, 0, P.lda, m, k, m, k);
+    MView B = b.view(MB_B, 0, P.ldb, k, n, k, n);
+    MView C = b.view(MB_C, 0, P.ldc, m, n, m, n);
+    MView Cw = C;
+    if (pad) {
+      const MView Ap = b.temp(P.M, P.K), Bp = b.temp(P.K, P.N), Cp = b.temp(P.M, P.N);
+      b.ew_part(EW_COPY, P.M, P.K, {b.view(MB_A, 0, P.lda, P.M, P.K, m, k)}, {Ap});
+      b.ew_part(EW_COPY, P.K, P.N, {b.view(MB_B, 0, P.ldb, P.K, P.N, k, n)}, {Bp});
+      b.flush();
+      A = Ap;
+      B = Bp;
+      Cw = Cp;
+    }
+    if (P.sched == MM_SCHED_TWO_TEMP)
+      sched_two_temp(b, A, B, Cw, 0);
+    else if (P.sched == MM_SCHED_IN_PLACE)
+      sched_in_place(b, A, B, Cw, 0);
+    else
+      sched_strassen(b, A, B, Cw, 0);
+    if (pad) {
+      b.ew_part(EW_COPY, m, n, {b.corner(Cw, m, n)}, {C});
+      b.flush();
+    }
+  }
+  b.flush();
+  P.ws_bytes = (size_t)b.ws_peak * b.esz;
+  P.text = b.txt.str();
+  return MM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Devices, upload, execution
+// ---------------------------------------------------------------------------
+std::mutex g_dev_mu;
+std::map<int, int> g_dev_ok;  // device -> MM_OK or error code
+
+int check_device(int* dev_out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(MM_E_UNSUPPORTED, "no HIP device available");
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_dev_ok.find(dev);
+  if (it == g_dev_ok.end()) {
+    hipDeviceProp_t prop;
+    int ok = MM_OK;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+      ok = MM_E_UNSUPPORTED;
+    else if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      ok = MM_E_UNSUPPORTED;
+    it = g_dev_ok.emplace(dev, ok).first;
+  }
+  if (it->second != MM_OK) return fail(MM_E_UNSUPPORTED, "device is not gfx950 (MI355X)");
+  *dev_out = dev;
+  return MM_OK;
+}
+
+int upload(Plan& P) {
+  int dev = 0;
+  int rc = check_device(&dev);
+  if (rc != MM_OK) return rc;
+  P.device = dev;
+  if (P.table.empty()) return MM_OK;
+  if (hipMalloc(&P.dtable, P.table.size()) != hipSuccess) {
+    P.dtable = nullptr;
+    (void)hipGetLastError();
+    return fail(MM_E_NOMEM, "hipMalloc of the plan's descriptor table failed");
+  }
+  if (hipMemcpy(P.dtable, P.table.data(), P.table.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(MM_E_HIP, "upload of the plan's descriptor table failed");
+  return MM_OK;
+}
+
+int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEvent_t* events = nullptr) {
+  KernelBases kb;
+  kb.p[MB_A] = A;
+  kb.p[MB_B] = B;
+  kb.p[MB_C] = C;
+  kb.p[MB_WS] = ws;
+  kb.p[MB_ABS] = nullptr;
+  kb.aligned = 0;
+  for (int i = 0; i < 4; ++i)
+    if (((uintptr_t)kb.p[i] & 15) == 0) kb.aligned |= 1 << i;
+  int i = 0;
+  for (const OpRec& op : P.ops) {
+    const void* d = (const char*)P.dtable + op.off;
+    hipError_t e;
+    if (events && hipEventRecord(events[i], s) != hipSuccess) return fail(MM_E_HIP, "hipEventRecord failed");
+    ++i;
+    if (op.type == OP_EW)
+      e = launch_ew(op.kdtype, kb, (const EwPart*)d, op.count, op.grid, s);
+    else
+      e = launch_gemm(op.kdtype, kb, (const GemmDesc*)d, op.count, op.grid, s);
+    if (e != hipSuccess) return fail(MM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  }
+  if (events && hipEventRecord(events[i], s) != hipSuccess) return fail(MM_E_HIP, "hipEventRecord failed");
+  return MM_OK;
+}
+
+int execute(Plan& P, void* A, void* B, void* C, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (ws_bytes < P.ws_bytes || (P.ws_bytes > 0 && ws == nullptr))
+    return fail(MM_E_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, plan needs " +
+                                    std::to_string(P.ws_bytes));
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != P.device)
+    return fail(MM_E_INVALID, "plan was built for another device");
+  if (P.ops.empty()) return MM_OK;
+  if (!(P.flags & MM_PLAN_GRAPH) || s == nullptr) return enqueue(P, A, B, C, ws, s);
+  std::lock_guard<std::mutex> lk(P.mu);
+  for (auto& g : P.graphs)
+    if (g.a == A && g.b == B && g.c == C && g.ws == ws) {
+      if (hipGraphLaunch(g.exec, s) != hipSuccess) return fail(MM_E_HIP, "hipGraphLaunch failed");
+      return MM_OK;
+    }
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return fail(MM_E_HIP, "hipStreamBeginCapture failed");
+  int rc = enqueue(P, A, B, C, ws, s);
+  hipError_t e = hipStreamEndCapture(s, &graph);
+  if (rc != MM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess || !graph) return fail(MM_E_HIP, "hipStreamEndCapture failed");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(MM_E_HIP, "hipGraphInstantiate failed");
+  if (P.graphs.size() >= 8) {
+    // Retire the oldest graph once the stream it last ran on has drained.
+    (void)hipStreamSynchronize(P.graphs.front().stream);
+    (void)hipGraphExecDestroy(P.graphs.front().exec);
+    P.graphs.erase(P.graphs.begin());
+  }
+  P.graphs.push_back({A, B, C, ws, s, exec});
+  if (hipGraphLaunch(exec, s) != hipSuccess) return fail(MM_E_HIP, "hipGraphLaunch failed");
+  return MM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Argument checks
+// ---------------------------------------------------------------------------
+bool overlaps(const void* p, size_t pb, const void* q, size_t qb) {
+  if (!p || !q || pb == 0 || qb == 0) return false;
+  const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
+  return a < b + qb && b < a + pb;
+}
+
+size_t span_bytes(int64_t rows, int64_t cols, int64_t ld, size_t esz) {
+  if (rows <= 0 || cols <= 0) return 0;
+  return (size_t)((rows - 1) * ld + cols) * esz;
+}
+
+int check_args(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B, int64_t ldb,
+               const void* C, int64_t ldc, int dtype) {
+  if (m < 0 || n < 0 || k < 0) return fail(MM_E_INVALID, "negative dimension");
+  if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX) return fail(MM_E_UNSUPPORTED, "dimension above 2^31-1");
+  if (m == 0 || n == 0) return MM_OK;
+  if (k > 0 && (!A || !B)) return fail(MM_E_INVALID, "NULL operand with nonzero size");
+  if (!C) return fail(MM_E_INVALID, "NULL output with nonzero size");
+  if ((k > 0 && lda < k) || (k > 0 && ldb < n) || ldc < n) return fail(MM_E_INVALID, "leading dimension shorter than a row");
+  const size_t esz = elem_size(dtype);
+  const size_t cb = span_bytes(m, n, ldc, esz);
+  if (k > 0 && (overlaps(C, cb, A, span_bytes(m, k, lda, esz)) || overlaps(C, cb, B, span_bytes(k, n, ldb, esz))))
+    return fail(MM_E_ALIAS, "C overlaps A or B");
+  return MM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Caches for the short forms and one-shot batches
+// ---------------------------------------------------------------------------
+std::mutex g_cache_mu;
+std::map<std::string, std::unique_ptr<Plan>> g_plans;
+struct WsEntry {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  bool owned = false;
+};
+std::map<std::pair<int, hipStream_t>, WsEntry> g_ws;
+
+int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, int64_t ldc,
+              int cutoff, int levels, int dtype, unsigned flags, std::unique_ptr<Plan>* out) {
+  int rc = check_enums(algo, sched, dtype);
+  if (rc != MM_OK) return rc;
+  if (m < 0 || n < 0 || k < 0) return fail(MM_E_INVALID, "negative dimension");
+  std::unique_ptr<Plan> P(new Plan);
+  P->algo = algo;
+  P->sched = sched;
+  P->dtype = dtype;
+  P->m = m;
+  P->n = n;
+  P->k = k;
+  P->lda = lda;
+  P->ldb = ldb;
+  P->ldc = ldc;
+  P->cutoff = cutoff;
+  P->levels = levels;
+  P->flags = flags;
+  rc = build_plan(*P);
+  if (rc != MM_OK) return rc;
+  *out = std::move(P);
+  return MM_OK;
+}
+
+int cached_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, int64_t ldc,
+                int cutoff, int levels, int dtype, Plan** out) {
+  int dev = 0;
+  int rc = check_device(&dev);
+  if (rc != MM_OK) return rc;
+  char key[256];
+  std::snprintf(key, sizeof key, "%d|%d|%d|%lld|%lld|%lld|%lld|%lld|%lld|%d|%d|%d", dev, algo, sched,
+                (long long)m, (long long)n, (long long)k, (long long)lda, (long long)ldb, (long long)ldc,
+                cutoff, levels, dtype);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_plans.find(key);
+  if (it == g_plans.end()) {
+    std::unique_ptr<Plan> P;
+    rc = make_plan(algo, sched, m, n, k, lda, ldb, ldc, cutoff, levels, dtype, 0, &P);
+    if (rc != MM_OK) return rc;
+    rc = upload(*P);
+    if (rc != MM_OK) return rc;
+    it = g_plans.emplace(key, std::move(P)).first;
+  }
+  *out = it->second.get();
+  return MM_OK;
+}
+
+int stream_workspace(size_t need, hipStream_t s, void** ws) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(MM_E_HIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  WsEntry& w = g_ws[{dev, s}];
+  if (need == 0) {
+    *ws = w.ptr;
+    return MM_OK;
+  }
+  if (w.bytes < need) {
+    if (!w.owned && w.ptr) return fail(MM_E_WORKSPACE, "registered workspace is smaller than the product needs");
+    if (w.ptr) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(w.ptr);
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    if (hipMalloc(&w.ptr, need) != hipSuccess) {
+      w.ptr = nullptr;
+      (void)hipGetLastError();
+      return fail(MM_E_NOMEM, "could not allocate a workspace of " + std::to_string(need) + " bytes");
+    }
+    w.bytes = need;
+    w.owned = true;
+  }
+  *ws = w.ptr;
+  return MM_OK;
+}
+
+int short_form(int algo, int64_t m, int64_t n, int64_t k, const void* A, const void* B, void* C, int cutoff,
+               int levels, int dtype, hipStream_t s) {
+  int rc = check_enums(algo, MM_SCHED_AUTO, dtype);
+  if (rc != MM_OK) return rc;
+  rc = check_args(m, n, k, A, std::max<int64_t>(k, 1), B, std::max<int64_t>(n, 1), C, std::max<int64_t>(n, 1), dtype);
+  if (rc != MM_OK) return rc;
+  if (m == 0 || n == 0) return MM_OK;
+  Plan* P = nullptr;
+  rc = cached_plan(algo, MM_SCHED_AUTO, m, n, k, std::max<int64_t>(k, 1), std::max<int64_t>(n, 1),
+                   std::max<int64_t>(n, 1), cutoff, levels, dtype, &P);
+  if (rc != MM_OK) return rc;
+  void* ws = nullptr;
+  rc = stream_workspace(P->ws_bytes, s, &ws);
+  if (rc != MM_OK) return rc;
+  return execute(*P, (void*)A, (void*)B, C, ws, P->ws_bytes, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batches: every problem planned with the grouped schedule on absolute
+// addresses, then merged stage by stage across problems.
+// ---------------------------------------------------------------------------
+int build_batched(Plan& P, int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C,
+                  const int* cutoff, const int* levels) {
+  Builder b(P);
+  const size_t esz = b.esz;
+  struct Prob {
+    int L;
+    std::vector<std::vector<Sub>> subs;  // per level
+    std::vector<std::vector<EwPart>> st, u;
+  };
+  std::vector<Prob> probs(count);
+  int Lmax = 0;
+  for (int i = 0; i < count; ++i) {
+    const int64_t m = mnk[3 * i], n = mnk[3 * i + 1], k = mnk[3 * i + 2];
+    if (m < 0 || n < 0 || k < 0) return fail(MM_E_INVALID, "negative dimension in batch");
+    const int c = cutoff ? cutoff[i] : 1;
+    const int lv = levels ? levels[i] : 0;
+    int rc = check_args(m, n, k, A[i], std::max<int64_t>(k, 1), B[i], std::max<int64_t>(n, 1), C[i],
+                        std::max<int64_t>(n, 1), P.dtype);
+    if (rc != MM_OK) return rc;
+    const int L = (m == 0 || n == 0 || k == 0) ? 0 : count_levels(m, n, k, c, lv);
+    if (L > MM_MAX_LEVELS) return fail(MM_E_UNSUPPORTED, "too many levels in batch problem");
+    probs[i].L = L;
+    Lmax = std::max(Lmax, L);
+  }
+  // Stage l: S/T parts of every problem with more than l levels.
+  std::vector<std::vector<Sub>> cur(count);
+  std::vector<std::vector<std::array<MView, 11>>> uargs_by_level_prob;
+  std::vector<std::vector<EwPart>> u_stage(Lmax);
+  for (int i = 0; i < count; ++i) {
+    const int64_t m = mnk[3 * i], n = mnk[3 * i + 1], k = mnk[3 * i + 2];
+    if (m == 0 || n == 0) continue;
+    const int L = probs[i].L;
+    const int64_t step = (int64_t)1 << L;
+    int64_t g = (L > 0 && std::min(std::min(m, n), k) / step >= 32) ? b.E : 1;
+    const int64_t M = L ? round_up(m, step * g) : m, N = L ? round_up(n, step * g) : n,
+                  K = L ? round_up(k, step * g) : k;
+    const int64_t ka = std::max<int64_t>(k, 1), na = std::max<int64_t>(n, 1);
+    cur[i].push_back({b.view(MB_ABS, (int64_t)((uintptr_t)A[i] / esz), ka, M, K, m, k),
+                      b.view(MB_ABS, (int64_t)((uintptr_t)B[i] / esz), na, K, N, k, n),
+                      b.view(MB_ABS, (int64_t)((uintptr_t)C[i] / esz), na, M, N, m, n)});
+  }
+  for (int l = 0; l < Lmax; ++l) {
+    for (int i = 0; i < count; ++i) {
+      if (probs[i].L <= l) continue;
+      std::vector<Sub> next;
+      for (const Sub& s : cur[i]) {
+        const int64_t hm = s.A.rows / 2, hk = s.A.cols / 2, hn = s.B.cols / 2;
+        const MView A11 = b.quad(s.A, 0, 0), A12 = b.quad(s.A, 0, 1), A21 = b.quad(s.A, 1, 0),
+                    A22 = b.quad(s.A, 1, 1);
+        const MView B11 = b.quad(s.B, 0, 0), B12 = b.quad(s.B, 0, 1), B21 = b.quad(s.B, 1, 0),
+                    B22 = b.quad(s.B, 1, 1);
+        MView S[4], T[4], Pt[7];
+        for (auto& v : S) v = b.temp(hm, hk);
+        for (auto& v : T) v = b.temp(hk, hn);
+        for (auto& v : Pt) v = b.temp(hm, hn);
+        b.ew_part(EW_WINO_S, hm, hk, {A11, A12, A21, A22}, {S[0], S[1], S[2], S[3]});
+        b.ew_part(EW_WINO_T, hk, hn, {B11, B12, B21, B22}, {T[0], T[1], T[2], T[3]});
+        next.push_back({A11, B11, Pt[0]});
+        next.push_back({A12, B21, Pt[1]});
+        next.push_back({S[3], B22, Pt[2]});
+        next.push_back({A22, T[3], Pt[3]});
+        next.push_back({S[0], T[0], Pt[4]});
+        next.push_back({S[1], T[1], Pt[5]});
+        next.push_back({S[2], T[2], Pt[6]});
+        EwPart p;
+        std::memset(&p, 0, sizeof p);
+        p.kind = EW_WINO_U;
+        p.rows = (int32_t)hm;
+        p.cols = (int32_t)hn;
+        p.nin = 7;
+        p.nout = 4;
+        for (int j = 0; j < 7; ++j) p.in[j] = Pt[j];
+        p.out[0] = b.quad(s.C, 0, 0);
+        p.out[1] = b.quad(s.C, 0, 1);
+        p.out[2] = b.quad(s.C, 1, 0);
+        p.out[3] = b.quad(s.C, 1, 1);
+        u_stage[l].push_back(p);
+      }
+      cur[i].swap(next);
+    }
+    b.flush();
+  }
+  for (int i = 0; i < count; ++i) {
+    const int64_t m = mnk[3 * i], n = mnk[3 * i + 1], k = mnk[3 * i + 2];
+    if (m == 0 || n == 0) continue;
+    for (const Sub& s : cur[i]) {
+      if (k == 0)
+        continue;
+      b.gemm(s.A, s.B, {Builder::store(s.C)});
+    }
+  }
+  b.flush();
+  for (int i = 0; i < count; ++i) {
+    const int64_t m = mnk[3 * i], n = mnk[3 * i + 1], k = mnk[3 * i + 2];
+    if (m > 0 && n > 0 && k == 0) b.ew_part(EW_ZERO, m, n, {}, {cur[i][0].C});
+  }
+  b.flush();
+  for (int l = Lmax - 1; l >= 0; --l) {
+    for (const EwPart& p : u_stage[l])
+      b.ew_part(EW_WINO_U, p.rows, p.cols, {p.in[0], p.in[1], p.in[2], p.in[3], p.in[4], p.in[5], p.in[6]},
+                {p.out[0], p.out[1], p.out[2], p.out[3]});
+    b.flush();
+  }
+  P.ws_bytes = (size_t)b.ws_peak * esz;
+  P.text = b.txt.str();
+  int64_t lmax = 0;
+  for (auto& pr : probs) lmax = std::max<int64_t>(lmax, pr.L);
+  P.L = (int)lmax;
+  return MM_OK;
+}
+
+}  // namespace
+}  // namespace mm
+
+struct mm_plan_s {
+  std::unique_ptr<mm::Plan> p;
+};
+
+using namespace mm;
+
+extern "C" {
+
+const char* mm_last_error(void) { return g_err.c_str(); }
+
+int mm_version(void) { return 1; }
+
+int mm_naive(int64_t m, int64_t n, int64_t k, const void* A, const void* B, void* C, int dtype,
+             hipStream_t stream) {
+  return short_form(MM_ALGO_NAIVE, m, n, k, A, B, C, 1, 0, dtype, stream);
+}
+
+int mm_strassen(int64_t m, int64_t n, int64_t k, const void* A, const void* B, void* C, int cutoff,
+                int levels, int dtype, hipStream_t stream) {
+  return short_form(MM_ALGO_STRASSEN, m, n, k, A, B, C, cutoff, levels, dtype, stream);
+}
+
+int mm_winograd(int64_t m, int64_t n, int64_t k, const void* A, const void* B, void* C, int cutoff,
+                int levels, int dtype, hipStream_t stream) {
+  return short_form(MM_ALGO_WINOGRAD, m, n, k, A, B, C, cutoff, levels, dtype, stream);
+}
+
+int mm_gemm_ex(int algo, int sched, int64_t m, int64_t n, int64_t k, void* A, int64_t lda, void* B,
+               int64_t ldb, void* C, int64_t ldc, int cutoff, int levels, int dtype, void* ws,
+               size_t ws_bytes, hipStream_t stream) {
+  int rc = check_enums(algo, sched, dtype);
+  if (rc != MM_OK) return rc;
+  rc = check_args(m, n, k, A, lda, B, ldb, C, ldc, dtype);
+  if (rc != MM_OK) return rc;
+  if (m == 0 || n == 0) return MM_OK;
+  Plan* P = nullptr;
+  rc = cached_plan(algo, sched, m, n, k, lda, ldb, ldc, cutoff, levels, dtype, &P);
+  if (rc != MM_OK) return rc;
+  return execute(*P, A, B, C, ws, ws_bytes, stream);
+}
+
+size_t mm_workspace_size(int algo, int sched, int64_t m, int64_t n, int64_t k, int cutoff, int levels,
+                         int dtype) {
+  std::unique_ptr<Plan> P;
+  const int64_t lda = std::max<int64_t>(k, 1), ldb = std::max<int64_t>(n, 1);
+  if (make_plan(algo, sched, m, n, k, lda, ldb, ldb, cutoff, levels, dtype, 0, &P) != MM_OK) return 0;
+  return P->ws_bytes;
+}
+
+int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(MM_E_HIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  WsEntry& w = g_ws[{dev, stream}];
+  if (w.owned && w.ptr) {
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(w.ptr);
+  }
+  w.ptr = (ws && bytes) ? ws : nullptr;
+  w.bytes = (ws && bytes) ? bytes : 0;
+  w.owned = false;
+  return MM_OK;
+}
+
+int mm_plan_create(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb,
+                   int64_t ldc, int cutoff, int levels, int dtype, unsigned flags, mm_plan_t* plan) {
+  if (!plan) return fail(MM_E_INVALID, "NULL plan pointer");
+  *plan = nullptr;
+  if ((m > 0 && k > 0 && lda < k) || (k > 0 && n > 0 && ldb < n) || (m > 0 && n > 0 && ldc < n))
+    return fail(MM_E_INVALID, "leading dimension shorter than a row");
+  std::unique_ptr<Plan> P;
+  int rc = make_plan(algo, sched, m, n, k, lda, ldb, ldc, cutoff, levels, dtype, flags, &P);
+  if (rc != MM_OK) return rc;
+  rc = upload(*P);
+  if (rc != MM_OK) return rc;
+  *plan = new mm_plan_s{std::move(P)};
+  return MM_OK;
+}
+
+int mm_plan_execute(mm_plan_t plan, void* A, void* B, void* C, void* ws, size_t ws_bytes,
+                    hipStream_t stream) {
+  if (!plan || !plan->p) return fail(MM_E_INVALID, "NULL plan");
+  Plan& P = *plan->p;
+  if (!P.batched) {
+    int rc = check_args(P.m, P.n, P.k, A, P.lda, B, P.ldb, C, P.ldc, P.dtype);
+    if (rc != MM_OK) return rc;
+  }
+  return execute(P, A, B, C, ws, ws_bytes, stream);
+}
+
+int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, size_t ws_bytes,
+                          hipStream_t stream, hipEvent_t* events, int nevents) {
+  if (!plan || !plan->p) return fail(MM_E_INVALID, "NULL plan");
+  Plan& P = *plan->p;
+  if (!events || nevents < (int)P.ops.size() + 1)
+    return fail(MM_E_INVALID, "need one event per launch plus one");
+  if (!P.batched) {
+    int rc = check_args(P.m, P.n, P.k, A, P.lda, B, P.ldb, C, P.ldc, P.dtype);
+    if (rc != MM_OK) return rc;
+  }
+  if (ws_bytes < P.ws_bytes || (P.ws_bytes > 0 && ws == nullptr))
+    return fail(MM_E_WORKSPACE, "workspace smaller than the plan needs");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != P.device)
+    return fail(MM_E_INVALID, "plan was built for another device");
+  return enqueue(P, A, B, C, ws, stream, events);
+}
+
+int mm_plan_op_kind(mm_plan_t plan, int i) {
+  if (!plan || !plan->p || i < 0 || i >= (int)plan->p->ops.size()) return -1;
+  return plan->p->ops[i].type;
+}
+
+int mm_plan_info(mm_plan_t plan, int64_t* info, int ninfo) {
+  if (!plan || !plan->p || !info) return 0;
+  const Plan& P = *plan->p;
+  const int64_t v[9] = {(int64_t)P.ws_bytes, P.L, P.M, P.N, P.K, (int64_t)P.ops.size(), P.leaves, P.sched,
+                        P.leaf_rows};
+  const int cnt = std::min(ninfo, 9);
+  for (int i = 0; i < cnt; ++i) info[i] = v[i];
+  return cnt;
+}
+
+size_t mm_plan_describe(mm_plan_t plan, char* buf, size_t len) {
+  if (!plan || !plan->p) return 0;
+  const std::string& t = plan->p->text;
+  if (buf && len) {
+    const size_t c = std::min(len - 1, t.size());
+    std::memcpy(buf, t.data(), c);
+    buf[c] = 0;
+  }
+  return t.size();
+}
+
+int mm_plan_destroy(mm_plan_t plan) {
+  delete plan;
+  return MM_OK;
+}
+
+size_t mm_describe(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb,
+                   int64_t ldc, int cutoff, int levels, int dtype, char* buf, size_t len, int64_t* info,
+                   int ninfo) {
+  std::unique_ptr<Plan> P;
+  if (make_plan(algo, sched, m, n, k, lda, ldb, ldc, cutoff, levels, dtype, 0, &P) != MM_OK) return 0;
+  mm_plan_s tmp{std::move(P)};
+  if (info) mm_plan_info(&tmp, info, ninfo);
+  const size_t r = mm_plan_describe(&tmp, buf, len);
+  return r ? r : 1;
+}
+
+size_t mm_batched_describe(int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C,
+                           int dtype, const int* cutoff, const int* levels, char* buf, size_t len,
+                           int64_t* info, int ninfo) {
+  if (count < 0 || (count > 0 && (!mnk || !A || !B || !C))) return 0;
+  if (check_enums(MM_ALGO_WINOGRAD, MM_SCHED_GROUPED, dtype) != MM_OK) return 0;
+  std::unique_ptr<Plan> P(new Plan);
+  P->algo = MM_ALGO_WINOGRAD;
+  P->sched = MM_SCHED_GROUPED;
+  P->dtype = dtype;
+  P->batched = true;
+  if (build_batched(*P, count, mnk, A, B, C, cutoff, levels) != MM_OK) return 0;
+  mm_plan_s tmp{std::move(P)};
+  if (info) mm_plan_info(&tmp, info, ninfo);
+  const size_t r = mm_plan_describe(&tmp, buf, len);
+  return r ? r : 1;
+}
+
+int mm_batched_plan_create(int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C,
+                           int dtype, const int* cutoff, const int* levels, unsigned flags, mm_plan_t* plan) {
+  if (!plan) return fail(MM_E_INVALID, "NULL plan pointer");
+  *plan = nullptr;
+  if (count < 0 || (count > 0 && (!mnk || !A || !B || !C))) return fail(MM_E_INVALID, "bad batch arrays");
+  int rc = check_enums(MM_ALGO_WINOGRAD, MM_SCHED_GROUPED, dtype);
+  if (rc != MM_OK) return rc;
+  std::unique_ptr<Plan> P(new Plan);
+  P->algo = MM_ALGO_WINOGRAD;
+  P->sched = MM_SCHED_GROUPED;
+  P->dtype = dtype;
+  P->batched = true;
+  P->flags = flags;
+  rc = build_batched(*P, count, mnk, A, B, C, cutoff, levels);
+  if (rc != MM_OK) return rc;
+  rc = upload(*P);
+  if (rc != MM_OK) return rc;
+  *plan = new mm_plan_s{std::move(P)};
+  return MM_OK;
+}
+
+int mm_batched(int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C, int dtype,
+               const int* cutoff, const int* levels, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (count < 0 || (count > 0 && (!mnk || !A || !B || !C))) return fail(MM_E_INVALID, "bad batch arrays");
+  int dev = 0;
+  int rc = check_device(&dev);
+  if (rc != MM_OK) return rc;
+  std::ostringstream key;
+  key << "B|" << dev << "|" << dtype << "|" << count;
+  for (int i = 0; i < count; ++i)
+    key << "|" << mnk[3 * i] << "," << mnk[3 * i + 1] << "," << mnk[3 * i + 2] << "," << A[i] << "," << B[i]
+        << "," << C[i] << "," << (cutoff ? cutoff[i] : 1) << "," << (levels ? levels[i] : 0);
+  Plan* P = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_plans.find(key.str());
+    if (it == g_plans.end()) {
+      std::unique_ptr<Plan> np(new Plan);
+      np->algo = MM_ALGO_WINOGRAD;
+      np->sched = MM_SCHED_GROUPED;
+      np->dtype = dtype;
+      np->batched = true;
+      rc = check_enums(MM_ALGO_WINOGRAD, MM_SCHED_GROUPED, dtype);
+      if (rc != MM_OK) return rc;
+      rc = build_batched(*np, count, mnk, A, B, C, cutoff, levels);
+      if (rc != MM_OK) return rc;
+      rc = upload(*np);
+      if (rc != MM_OK) return rc;
+      it = g_plans.emplace(key.str(), std::move(np)).first;
+    }
+    P = it->second.get();
+  }
+  return execute(*P, nullptr, nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,235 @@
+"""Test-side simulator of libmm launch sequences (not the oracle).
+
+``mm_describe`` lists a plan as text, one line per block operation and one
+``LAUNCH`` line closing each kernel launch.  This module parses that listing
+and executes it on numpy buffers, doing per block what the kernels do per
+element: reads outside a view's valid extent give zero, writes there are
+dropped, element-wise recipes combine their inputs, GEMM descriptors form
+a @ b and apply their epilogues.  It also checks that no two operations of
+one launch touch memory in a conflicting way (the kernels of one launch run
+concurrently), so a planner bug shows up as a hazard even when the numbers
+happen to come out right.
+
+Run on integer matrices, the simulated product must equal the oracle's
+exactly.
+"""
+import numpy as np
+
+EW_COPY, EW_ADD, EW_SUB, EW_WINO_S, EW_WINO_T, EW_WINO_U, EW_TT_U = range(7)
+EW_IP_A, EW_IP_B, EW_IP_U, EW_DIST, EW_ZERO = 7, 8, 9, 10, 11
+GM_STORE, GM_ADD = 1, 2
+MB_A, MB_B, MB_C, MB_WS, MB_ABS = 0, 1, 2, 3, 4
+
+
+class View:
+    __slots__ = ("base", "off", "ld", "rows", "cols", "vrows", "vcols")
+
+    def __init__(self, fields):
+        (self.base, self.off, self.ld, self.rows, self.cols, self.vrows, self.vcols) = fields
+
+    def index(self, valid_only=True):
+        r = self.vrows if valid_only else self.rows
+        c = self.vcols if valid_only else self.cols
+        return (self.off + np.arange(r, dtype=np.int64)[:, None] * self.ld
+                + np.arange(c, dtype=np.int64)[None, :])
+
+
+def _view(tok):
+    if tok == "-":
+        return None
+    return View([int(x) for x in tok.split(":")])
+
+
+def parse(text):
+    """List of launches; each launch is ("EW"|"GEMM", [items])."""
+    launches, cur = [], []
+    for line in text.splitlines():
+        if not line.strip():
+            continue
+        if line.startswith("LAUNCH"):
+            _, kind, cnt, _grid = line.split()
+            assert len(cur) == int(cnt), (line, len(cur))
+            assert all(it[0] == kind for it in cur)
+            launches.append((kind, cur))
+            cur = []
+            continue
+        head, *rest = [s.strip() for s in line.split("|")]
+        h = head.split()
+        if h[0] == "EW":
+            kind, rows, cols, m0, m1 = map(int, h[1:])
+            ins = [_view(t) for t in rest[0].split()] if rest[0] else []
+            outs = [_view(t) for t in rest[1].split()] if rest[1] else []
+            cur.append(("EW", dict(kind=kind, rows=rows, cols=cols, mode=(m0, m1), ins=ins, outs=outs)))
+        else:
+            m, n, k = map(int, h[1:])
+            a, b = [_view(t) for t in rest[0].split()]
+            outs = []
+            for tok in rest[1].split():
+                f = tok.split(":")
+                mode, sign = int(f[0]), int(f[1])
+                c = View([int(x) for x in f[2:9]])
+                d = None if f[9] == "-" else View([int(x) for x in f[9:16]])
+                outs.append((mode, sign, c, d))
+            cur.append(("GEMM", dict(m=m, n=n, k=k, a=a, b=b, outs=outs)))
+    assert not cur, "listing ends inside a launch"
+    return launches
+
+
+class Memory:
+    def __init__(self, bufs):
+        self.bufs = bufs  # base -> flat numpy array
+
+    def read(self, v, shape=None):
+        rows, cols = (v.rows, v.cols) if shape is None else shape
+        out = np.zeros((rows, cols), dtype=self.dtype)
+        r, c = min(v.vrows, rows), min(v.vcols, cols)
+        if r and c:
+            out[:r, :c] = self.bufs[v.base][v.index()[:r, :c]]
+        return out
+
+    def write(self, v, val):
+        if v.vrows and v.vcols:
+            self.bufs[v.base][v.index()] = val[:v.vrows, :v.vcols]
+
+    @property
+    def dtype(self):
+        return next(iter(self.bufs.values())).dtype
+
+
+def _recipe(kind, x, mode):
+    if kind == EW_COPY:
+        return [x[0]]
+    if kind == EW_ADD:
+        return [x[0] + x[1]]
+    if kind == EW_SUB:
+        return [x[0] - x[1]]
+    if kind == EW_WINO_S:
+        a11, a12, a21, a22 = x
+        s1 = a21 + a22
+        s2 = s1 - a11
+        return [s1, s2, a11 - a21, a12 - s2]
+    if kind == EW_WINO_T:
+        b11, b12, b21, b22 = x
+        t1 = b12 - b11
+        t2 = b22 - t1
+        return [t1, t2, b22 - b12, t2 - b21]
+    if kind == EW_WINO_U:
+        p1, p2, p3, p4, p5, p6, p7 = x
+        u2 = p1 + p6
+        u3 = u2 + p7
+        return [p1 + p2, u2 + p5 + p3, u3 - p4, u3 + p5]
+    if kind == EW_TT_U:
+        xp, c11, c12, c21, c22 = x
+        u2 = xp + c12
+        u3 = u2 + c21
+        return [u2 + c22 + c11, u3, u3 + c22]
+    if kind == EW_IP_A:
+        a11, a21, a22 = x
+        return [a11 - a21, a21 + a22]
+    if kind == EW_IP_B:
+        b11, b12, b22 = x
+        return [b12 - b11, b22 - b12]
+    if kind == EW_IP_U:
+        p1, p2, u2, p5, p7, p4 = x
+        u3 = u2 + p7
+        return [p1 + p2, u2 + p5, u3 - p4, u3 + p5]
+    if kind == EW_DIST:
+        z, d0, d1 = x
+        out = []
+        for md, d in zip(mode, (d0, d1)):
+            if d is None:
+                break
+            out.append(z if md == 1 else (d + z if md == 2 else d - z))
+        return out
+    if kind == EW_ZERO:
+        return [np.zeros_like(x[0]) if x else None]
+    raise ValueError(kind)
+
+
+def _footprint(v):
+    if v is None or not (v.vrows and v.vcols):
+        return set()
+    return set(zip([v.base] * (v.vrows * v.vcols), v.index().ravel().tolist()))
+
+
+def check_hazards(launch):
+    """No operation of a launch writes what another one reads or writes, and
+    a GEMM never writes its own operands (element-wise parts may read and
+    write the same element in place)."""
+    kind, items = launch
+    reads, writes = [], []
+    for _, it in items:
+        if kind == "EW":
+            r = set().union(*[_footprint(v) for v in it["ins"]]) if it["ins"] else set()
+            w = set().union(*[_footprint(v) for v in it["outs"]])
+            # in-place element-wise: an input element may be rewritten only at
+            # the same (row, col) position of the block
+            for v_in in it["ins"]:
+                if v_in is None:
+                    continue
+                for v_out in it["outs"]:
+                    if v_in.base != v_out.base:
+                        continue
+                    ii = v_in.index()
+                    oi = v_out.index()
+                    common = np.intersect1d(ii, oi)
+                    if common.size:
+                        pos_in = {int(x): p for p, x in enumerate(ii.ravel().tolist())}
+                        pos_out = {int(x): p for p, x in enumerate(oi.ravel().tolist())}
+                        ci = ii.shape[1]
+                        co = oi.shape[1]
+                        for x in common.tolist():
+                            pi, po = pos_in[x], pos_out[x]
+                            assert (pi // ci, pi % ci) == (po // co, po % co), "EW cross-element alias"
+        else:
+            r = _footprint(it["a"]) | _footprint(it["b"])
+            w = set()
+            for mode, sign, c, d in it["outs"]:
+                fc = _footprint(c)
+                assert not (fc & r), "GEMM writes its own operand"
+                assert not (fc & w), "GEMM outputs overlap"
+                w |= fc
+                if d is not None and mode == GM_ADD:
+                    fd = _footprint(d)
+                    if fd & fc:
+                        assert d.off == c.off and d.ld == c.ld and d.base == c.base, \
+                            "GEMM epilogue reads C elsewhere than it writes"
+                    r |= fd - fc
+        reads.append(r)
+        writes.append(w)
+    for i in range(len(items)):
+        for j in range(len(items)):
+            if i != j:
+                assert not (writes[i] & writes[j]), f"{kind}: two operations write the same memory"
+                assert not (writes[i] & reads[j]), f"{kind}: one operation writes what another reads"
+
+
+def run(text, bufs, hazards=True):
+    mem = Memory(bufs)
+    for launch in parse(text):
+        if hazards:
+            check_hazards(launch)
+        kind, items = launch
+        results = []
+        for _, it in items:
+            if kind == "EW":
+                x = [mem.read(v, (it["rows"], it["cols"])) if v is not None else None
+                     for v in it["ins"]]
+                if it["kind"] == EW_ZERO:
+                    y = [np.zeros((it["rows"], it["cols"]), dtype=mem.dtype)]
+                else:
+                    y = _recipe(it["kind"], x, it["mode"])
+                results.append(list(zip(it["outs"], y)))
+            else:
+                a = mem.read(it["a"])
+                b = mem.read(it["b"])
+                acc = a @ b
+                outs = []
+                for mode, sign, c, d in it["outs"]:
+                    val = sign * acc if mode == GM_STORE else mem.read(d) + sign * acc
+                    outs.append((c, val))
+                results.append(outs)
+        for outs in results:
+            for v, val in outs:
+                mem.write(v, val)
+    return mem

@@ -1,0 +1,274 @@
+"""Parity of the HIP path with the oracle, through the C ABI (needs a GPU).
+
+Every product is compared element by element with the oracle's double
+triple loop on the same seeded inputs: exactly on integer inputs (where
+every method is exact), within 1e-12 relative Frobenius error in float64 and
+within 1e-5 in float32 (the stated target).  At the full sizes the oracle
+computes a sample of rows, which it does exactly as it would in the full
+product.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2309_00628_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_00628_amd import api as a
+    return a
+
+
+@pytest.fixture(scope="module")
+def naive(oracle_built):
+    from oracle import naive
+    return naive
+
+
+def rel_fro(got, ref):
+    ref = np.asarray(ref, dtype=np.float64)
+    d = np.linalg.norm(np.asarray(got, dtype=np.float64) - ref)
+    nr = np.linalg.norm(ref)
+    return d / nr if nr else d
+
+
+def gpu_mm(api, A, B, **kw):
+    At = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    Bt = torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    C = api.mm(At, Bt, **kw)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()
+
+
+SHAPES = [(1, 1, 1), (15, 16, 17), (64, 64, 64), (127, 129, 128), (375, 511, 512),
+          (129, 257, 33), (1000, 1, 300), (1, 700, 2000), (257, 129, 1025), (130, 300, 7)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("m,n,k", SHAPES)
+def test_naive_gemm_shapes(api, naive, dtype, m, n, k):
+    A, B = inputs.pair("uniform", m, n, k, 3, dtype)
+    print(f"naive {dtype.__name__} {m}x{n}x{k}", flush=True)
+    got = gpu_mm(api, A, B, algo="naive")
+    ref = naive.gemm(A, B)
+    tol = 1e-13 if dtype == np.float64 else 2e-6
+    assert rel_fro(got, ref) < tol
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_naive_gemm_exact_on_integers(api, naive, dtype):
+    A, B = inputs.pair("int", 300, 200, 250, 4, dtype)
+    assert np.array_equal(gpu_mm(api, A, B, algo="naive").astype(np.float64), naive.gemm(A, B))
+
+
+VARIANTS = [("naive", "auto"), ("strassen", "dfs3"), ("winograd", "two_temp"),
+            ("winograd", "in_place"), ("winograd", "grouped")]
+
+
+@pytest.mark.parametrize("n", [4, 8])
+@pytest.mark.parametrize("cutoff", [1, 2, 4])
+def test_integer_exact_small_fp64(api, naive, n, cutoff):
+    for seed in range(3):
+        A, B = inputs.pair("int", n, n, n, seed, np.float64)
+        ref = naive.gemm(A, B)
+        for algo, sched in VARIANTS:
+            got = gpu_mm(api, A, B, algo=algo, sched=sched, cutoff=cutoff)
+            assert np.array_equal(got, ref), (algo, sched, n, cutoff, seed)
+
+
+def test_fp64_512_cutoff_64(api, naive):
+    A, B = inputs.pair("uniform", 512, 512, 512, 0, np.float64)
+    ref = naive.gemm(A, B)
+    res = {}
+    for algo, sched in VARIANTS:
+        got = gpu_mm(api, A, B, algo=algo, sched=sched, cutoff=64)
+        err = rel_fro(got, ref)
+        print(f"fp64 512 {algo}/{sched}: {err:.3e}", flush=True)
+        assert err < 1e-12, (algo, sched, err)
+        res[(algo, sched)] = got
+    # the three Winograd schedules do the same operations in the same order
+    assert np.array_equal(res[("winograd", "two_temp")], res[("winograd", "in_place")])
+    assert np.array_equal(res[("winograd", "two_temp")], res[("winograd", "grouped")])
+
+
+def test_fp64_512_integer_exact(api, naive):
+    A, B = inputs.pair("int", 512, 512, 512, 5, np.float64)
+    ref = naive.gemm(A, B)
+    for algo, sched in VARIANTS:
+        assert np.array_equal(gpu_mm(api, A, B, algo=algo, sched=sched, cutoff=64), ref), (algo, sched)
+
+
+def test_fp32_integer_exact(api, naive):
+    # entries in {-1, 0, 1}, 256 with two levels: every intermediate is an
+    # integer below 2^24, so float32 arithmetic is exact
+    A, B = inputs.pair("int", 256, 256, 256, 6, np.float32)
+    A = np.clip(A, -1, 1)
+    B = np.clip(B, -1, 1)
+    ref = naive.gemm(A, B)
+    for algo, sched in VARIANTS:
+        got = gpu_mm(api, A, B, algo=algo, sched=sched, cutoff=1, levels=2)
+        assert np.array_equal(got.astype(np.float64), ref), (algo, sched)
+
+
+def test_fp32_schedules_bitwise(api):
+    A, B = inputs.pair("uniform", 1024, 1024, 1024, 7, np.float32)
+    outs = [gpu_mm(api, A, B, algo="winograd", sched=s, cutoff=1, levels=2)
+            for s in ("two_temp", "in_place", "grouped")]
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("m,n,k,cutoff,levels", [(100, 60, 80, 8, -1), (1000, 777, 555, 1, 2),
+                                                 (333, 333, 333, 1, 3), (96, 2000, 48, 1, 1)])
+def test_padding_shapes_fp32(api, naive, m, n, k, cutoff, levels):
+    A, B = inputs.pair("uniform", m, n, k, 8, np.float32)
+    ref = naive.gemm(A, B)
+    for algo, sched in [("winograd", "grouped"), ("winograd", "two_temp"), ("strassen", "dfs3")]:
+        got = gpu_mm(api, A, B, algo=algo, sched=sched, cutoff=cutoff, levels=levels)
+        err = rel_fro(got, ref)
+        assert err < 1e-5, (algo, sched, err)
+
+
+def test_in_place_square_padded(api, naive):
+    A, B = inputs.pair("uniform", 200, 200, 200, 9, np.float64)
+    got = gpu_mm(api, A, B, algo="winograd", sched="in_place", cutoff=1, levels=3)
+    assert rel_fro(got, naive.gemm(A, B)) < 1e-12
+
+
+def test_leading_dimensions(api, naive):
+    A, B = inputs.pair("uniform", 300, 260, 200, 10, np.float32)
+    Aw = torch.zeros((300, 211), dtype=torch.float32, device="cuda")
+    Bw = torch.zeros((200, 301), dtype=torch.float32, device="cuda")
+    Cw = torch.full((300, 263), 7.0, dtype=torch.float32, device="cuda")
+    Aw[:, :200] = torch.from_numpy(A)
+    Bw[:, :260] = torch.from_numpy(B)
+    for algo, sched in [("naive", "auto"), ("winograd", "grouped"), ("winograd", "two_temp")]:
+        api.mm(Aw[:, :200], Bw[:, :260], algo=algo, sched=sched, cutoff=1, levels=2,
+               out=Cw[:, :260])
+        torch.cuda.synchronize()
+        got = Cw.cpu().numpy()
+        assert rel_fro(got[:, :260], naive.gemm(A, B)) < 1e-5
+        assert np.all(got[:, 260:] == 7.0)   # nothing written outside C
+
+
+@pytest.mark.parametrize("n", [4096, 3000])
+def test_fp32_full_size_sampled_rows(api, naive, n):
+    A, B = inputs.pair("uniform", n, n, n, 11, np.float32)
+    rows = inputs.rng(12).choice(n, size=48, replace=False)
+    rows = np.sort(np.concatenate([rows, [0, n - 1]]))
+    ref = naive.gemm_rows(A, B, rows)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    for algo, sched, lv in [("naive", "auto", 0), ("winograd", "grouped", 1), ("winograd", "grouped", 2),
+                            ("winograd", "grouped", 3), ("winograd", "two_temp", 2),
+                            ("strassen", "dfs3", 1)]:
+        print(f"fp32 {n} {algo}/{sched} L={lv}", flush=True)
+        C = api.mm(At, Bt, algo=algo, sched=sched, cutoff=1, levels=lv)
+        torch.cuda.synchronize()
+        err = rel_fro(C[torch.from_numpy(rows).cuda()].cpu().numpy(), ref)
+        print(f"   rel err {err:.3e}", flush=True)
+        assert err < 1e-5, (algo, sched, lv, err)
+
+
+def test_degenerate_sizes(api):
+    z = torch.zeros((0, 5), device="cuda")
+    assert api.mm(z, torch.zeros((5, 3), device="cuda")).shape == (0, 3)
+    A = torch.zeros((6, 0), device="cuda")
+    B = torch.zeros((0, 4), device="cuda")
+    C = torch.full((6, 4), 3.0, device="cuda")
+    for algo in ("naive", "winograd", "strassen"):
+        C.fill_(3.0)
+        api.mm(A, B, algo=algo, out=C)
+        torch.cuda.synchronize()
+        assert torch.all(C == 0)
+
+
+def test_error_paths(api):
+    from paper_2309_00628_amd import _lib as L
+    lib = L.load()
+    A = torch.ones((64, 64), device="cuda")
+    with pytest.raises(L.MMError) as e:
+        api.mm(A, A, algo="winograd", out=A)
+    assert e.value.name == "MM_E_ALIAS"
+    with pytest.raises(L.MMError) as e:
+        api.mm(torch.ones((64, 32), device="cuda"), torch.ones((32, 64), device="cuda"),
+               algo="winograd", sched="in_place", cutoff=1, levels=1)
+    assert e.value.name == "MM_E_UNSUPPORTED"
+    B = torch.ones((64, 64), device="cuda")
+    C = torch.empty((64, 64), device="cuda")
+    need = lib.mm_workspace_size(2, 0, 64, 64, 64, 1, 2, 1)
+    assert need > 0
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    st = lib.mm_gemm_ex(2, 0, 64, 64, 64, A.data_ptr(), 64, B.data_ptr(), 64, C.data_ptr(), 64, 1, 2, 1,
+                        ws.data_ptr(), need - 4, s)
+    assert L.STATUS[st] == "MM_E_WORKSPACE"
+    st = lib.mm_gemm_ex(2, 0, 64, 64, 64, A.data_ptr(), 64, B.data_ptr(), 64, C.data_ptr(), 64, 1, 2, 1,
+                        ws.data_ptr(), need, s)
+    assert st == 0
+    torch.cuda.synchronize()
+    assert torch.all(C == 64)
+    st = lib.mm_naive(-1, 4, 4, A.data_ptr(), B.data_ptr(), C.data_ptr(), 1, s)
+    assert L.STATUS[st] == "MM_E_INVALID"
+
+
+def test_short_forms_through_the_abi(api, naive):
+    from paper_2309_00628_amd import _lib as L
+    lib = L.load()
+    A, B = inputs.pair("uniform", 384, 384, 384, 13, np.float32)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C = torch.empty((384, 384), device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    ref = naive.gemm(A, B)
+    for fn, args in [(lib.mm_naive, ()), (lib.mm_strassen, (64, -1)), (lib.mm_winograd, (64, -1))]:
+        C.zero_()
+        st = fn(384, 384, 384, At.data_ptr(), Bt.data_ptr(), C.data_ptr(), *args, L.MM_F32, s)
+        assert st == 0, L.last_error()
+        torch.cuda.synchronize()
+        assert rel_fro(C.cpu().numpy(), ref) < 1e-5
+
+
+def test_batched_matches_single(api, naive):
+    shapes = inputs.batched_shapes(12, 14, lo=64, hi=512)
+    As, Bs, Cs, refs = [], [], [], []
+    for i, (m, n, k) in enumerate(shapes):
+        A, B = inputs.pair("uniform", m, n, k, 20 + i, np.float32)
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+        Cs.append(torch.empty((m, n), device="cuda"))
+        refs.append(naive.gemm(A, B))
+    levels = [i % 3 for i in range(len(shapes))]
+    plan = api.BatchedPlan(As, Bs, Cs, cutoff=[1] * len(shapes), levels=levels, graph=False)
+    plan()
+    torch.cuda.synchronize()
+    for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+        single = api.mm(A, B, algo="winograd", sched="grouped", cutoff=1, levels=levels[i])
+        torch.cuda.synchronize()
+        assert torch.equal(C, single), i
+        assert rel_fro(C.cpu().numpy(), refs[i]) < 1e-5
+
+
+def test_graph_replay_matches_eager(api):
+    A, B = inputs.pair("uniform", 512, 512, 512, 15, np.float32)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    eager = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=2)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        C = torch.empty_like(At)
+        for rep in range(4):
+            C.fill_(float("nan"))
+            api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=2, out=C, graph=True,
+                   stream=s)
+            s.synchronize()
+            junk = At @ Bt  # unrelated eager work between replays
+            s.synchronize()
+            assert torch.equal(C, eager), rep
+            del junk

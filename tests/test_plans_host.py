@@ -1,0 +1,183 @@
+"""Host-side checks of libmm's planner (no GPU needed).
+
+The library lists the launch sequence it would run (mm_describe); the
+simulator in plan_sim executes that listing on integer numpy buffers.  Every
+schedule must reproduce the oracle's product exactly, with no two operations
+of one launch conflicting, and the plan facts (levels, padding, workspace,
+launches) must follow the paper's formulas.
+"""
+import numpy as np
+import pytest
+
+import plan_sim
+from paper_2309_00628_amd import inputs
+
+L = pytest.importorskip("paper_2309_00628_amd._lib")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    try:
+        return L.load()
+    except RuntimeError as e:
+        pytest.skip(str(e))
+
+
+@pytest.fixture(scope="module")
+def naive(oracle_built):
+    from oracle import naive
+    return naive
+
+
+ESZ = {"f64": 8, "f32": 4}
+
+
+def simulate(algo, sched, m, n, k, cutoff, levels=-1, dtype="f64", seed=0, lo=-9, hi=9):
+    text, info = L.describe(algo, sched, m, n, k, cutoff=cutoff, levels=levels, dtype=dtype)
+    A = inputs.integers((m, k), seed, lo, hi, dtype=np.int64)
+    B = inputs.integers((k, n), seed + 1, lo, hi, dtype=np.int64)
+    ws = np.full(max(info["ws_bytes"] // ESZ[dtype], 1), 10**9, dtype=np.int64)  # poison
+    C = np.full(m * n, -(10**9), dtype=np.int64)
+    mem = plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
+    return A, B, mem.bufs[2].reshape(m, n), info, text
+
+
+CASES = [
+    # algo, sched, m, n, k, cutoff
+    ("naive", "auto", 7, 5, 3, 1),
+    ("winograd", "two_temp", 4, 4, 4, 1),
+    ("winograd", "two_temp", 8, 8, 8, 2),
+    ("winograd", "two_temp", 16, 32, 8, 2),
+    ("winograd", "two_temp", 13, 7, 5, 1),      # padded (copies)
+    ("winograd", "two_temp", 100, 60, 80, 8),
+    ("winograd", "in_place", 4, 4, 4, 1),
+    ("winograd", "in_place", 8, 8, 8, 2),
+    ("winograd", "in_place", 32, 16, 16, 2),
+    ("winograd", "in_place", 12, 12, 12, 1),    # padded to 16
+    ("winograd", "grouped", 4, 4, 4, 1),
+    ("winograd", "grouped", 8, 8, 8, 1),
+    ("winograd", "grouped", 13, 7, 5, 1),       # virtual padding
+    ("winograd", "grouped", 100, 60, 80, 8),
+    ("winograd", "grouped", 200, 136, 72, 16),
+    ("winograd", "grouped", 128, 128, 128, 16),
+    ("strassen", "dfs3", 4, 4, 4, 1),
+    ("strassen", "dfs3", 8, 8, 8, 1),
+    ("strassen", "dfs3", 16, 8, 32, 2),
+    ("strassen", "dfs3", 13, 7, 5, 1),
+    ("strassen", "dfs3", 64, 64, 64, 4),
+]
+
+
+@pytest.mark.parametrize("algo,sched,m,n,k,cutoff", CASES)
+def test_schedule_exact_on_integers(lib, algo, sched, m, n, k, cutoff):
+    A, B, C, info, _ = simulate(algo, sched, m, n, k, cutoff)
+    assert np.array_equal(C, A @ B)
+
+
+def test_oracle_agrees_with_simulated_plan(lib, naive):
+    A, B, C, _, _ = simulate("winograd", "grouped", 24, 40, 16, 2)
+    assert np.array_equal(C.astype(np.float64), naive.gemm(A, B))
+
+
+def test_zero_inner_dimension_gives_zeros(lib):
+    for algo, sched in [("naive", "auto"), ("winograd", "grouped"), ("winograd", "two_temp"),
+                        ("strassen", "dfs3")]:
+        A, B, C, info, _ = simulate(algo, sched, 6, 5, 0, 1)
+        assert np.array_equal(C, np.zeros((6, 5), dtype=np.int64))
+        assert info["levels"] == 0
+
+
+def test_levels_rule_matches_oracle(lib):
+    from oracle import recursions
+    for (m, n, k, cutoff, levels) in [(512, 512, 512, 64, -1), (512, 512, 512, 64, 2),
+                                      (8, 8, 8, 1, -1), (8, 8, 8, 2, -1), (4096, 4096, 4096, 2048, -1),
+                                      (64, 32, 128, 4, -1), (16, 16, 16, 12, -1)]:
+        _, info = L.describe("winograd", "two_temp", m, n, k, cutoff=cutoff, levels=levels)
+        assert info["levels"] == recursions.levels_planned(m, k, n, cutoff, levels)
+
+
+def test_two_temp_workspace_formula(lib):
+    # Section 3.3: two temporaries per level, (n/2^l)^2 elements each
+    for n, cutoff, dtype in [(512, 64, "f64"), (256, 32, "f32"), (64, 8, "f64")]:
+        _, info = L.describe("winograd", "two_temp", n, n, n, cutoff=cutoff, dtype=dtype)
+        Lv = info["levels"]
+        assert info["ws_bytes"] == sum(2 * (n >> l) ** 2 for l in range(1, Lv + 1)) * ESZ[dtype]
+
+
+def test_in_place_needs_no_workspace(lib):
+    _, info = L.describe("winograd", "in_place", 512, 512, 512, cutoff=64, dtype="f64")
+    assert info["ws_bytes"] == 0 and info["levels"] == 3
+
+
+def test_grouped_launch_count_and_leaves(lib):
+    for L_ in (1, 2, 3):
+        _, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_)
+        assert info["levels"] == L_
+        assert info["launches"] == 2 * L_ + 1
+        assert info["leaves"] == 7 ** L_
+
+
+def test_depth_first_leaf_count(lib):
+    _, info = L.describe("winograd", "two_temp", 512, 512, 512, cutoff=64, dtype="f64")
+    assert info["leaves"] == 343
+    _, info = L.describe("strassen", "dfs3", 512, 512, 512, cutoff=64, dtype="f64")
+    assert info["leaves"] == 343
+
+
+def test_grouped_pads_virtually_to_vector_multiple(lib):
+    # 3000 = 8 * 375: three levels need no padding for the recursion itself;
+    # the grouped schedule still rounds to a multiple of 2^L * 4 floats so
+    # that every quadrant starts on a 16-byte boundary (no copy is made).
+    _, info = L.describe("winograd", "grouped", 3000, 3000, 3000, cutoff=1, levels=3)
+    assert (info["M"], info["N"], info["K"]) == (3008, 3008, 3008)
+    _, info = L.describe("winograd", "two_temp", 3000, 3000, 3000, cutoff=1, levels=3)
+    assert (info["M"], info["N"], info["K"]) == (3000, 3000, 3000)
+
+
+def test_plan_listing_follows_table2_order(lib):
+    text, _ = L.describe("winograd", "two_temp", 4, 4, 4, cutoff=2)
+    kinds = [l.split()[0] + (" " + l.split()[1] if l.startswith("EW") else "")
+             for l in text.splitlines() if not l.startswith("LAUNCH")]
+    # ops 1-2, 3, 4-5, 6, 7-8, 9, 10, 11, 12, 13-17 + 18, 19+20, 21+22
+    assert kinds == ["EW 2", "EW 2", "GEMM", "EW 1", "EW 2", "GEMM", "EW 2", "EW 2", "GEMM",
+                     "EW 2", "GEMM", "GEMM", "EW 6", "EW 2", "GEMM", "GEMM"]
+
+
+@pytest.mark.parametrize("args,msg", [
+    (("winograd", "in_place", 8, 16, 8, 1), "in-place"),
+    (("winograd", "two_temp", 4096, 4096, 4096, 1), "levels"),
+    (("strassen", "two_temp", 8, 8, 8, 1), "Strassen"),
+])
+def test_rejected_plans(lib, args, msg):
+    algo, sched, m, n, k, cutoff = args
+    with pytest.raises(L.MMError) as e:
+        L.describe(algo, sched, m, n, k, cutoff=cutoff)
+    assert msg in str(e.value)
+
+
+def test_batched_plan_exact(lib):
+    shapes = [(16, 32, 8), (40, 24, 56), (7, 9, 11), (64, 64, 64), (0, 5, 3), (6, 4, 0)]
+    cut = [2, 4, 1, 8, 1, 1]
+    lev = [-1, 2, 1, -1, 1, 1]
+    mem = []
+    addrs = []
+    mats = []
+    pos = 0
+    esz = 4
+    for i, (m, n, k) in enumerate(shapes):
+        A = inputs.integers((m, k), 100 + i, dtype=np.int64)
+        B = inputs.integers((k, n), 200 + i, dtype=np.int64)
+        a, b, c = pos, pos + A.size + 8, pos + A.size + B.size + 16
+        pos = c + m * n + 8
+        addrs.append(((a + 1024) * esz, (b + 1024) * esz, (c + 1024) * esz))
+        mats.append((A, B, a, b, c))
+    flat = np.full(pos + 2048, -(10**9), dtype=np.int64)
+    for A, B, a, b, c in mats:
+        flat[1024 + a:1024 + a + A.size] = A.ravel()
+        flat[1024 + b:1024 + b + B.size] = B.ravel()
+    text, info = L.batched_describe(shapes, addrs, dtype="f32", cutoff=cut, levels=lev)
+    ws = np.full(max(info["ws_bytes"] // esz, 1), 10**9, dtype=np.int64)
+    plan_sim.run(text, {plan_sim.MB_ABS: flat, plan_sim.MB_WS: ws})
+    for (m, n, k), (A, B, a, b, c) in zip(shapes, mats):
+        got = flat[1024 + c:1024 + c + m * n].reshape(m, n)
+        assert np.array_equal(got, A @ B), (m, n, k)
