@@ -62,7 +62,8 @@ struct MT<float> {
 };
 
 // v_mfma_f64_16x16x4_f64: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16];
-// result register r of lane l is C[4 (l / 16) + r][l % 16].
+// result register r of lane l is C[4 r + l / 16][l % 16] (rows interleaved
+// across the four lane groups, unlike the float32 16x16 form).
 template <>
 struct MT<double> {
   static constexpr int TM = 16;
@@ -74,7 +75,7 @@ struct MT<double> {
   static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
 };
 
 constexpr int BM = kGemmBM;
