@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline and error check")
     ap.add_argument("--no-extra", action="store_true", help="skip the n=3000 / n=8192 side runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run only the timed Winograd steps (for rocprofv3 runs)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB float32 buffer 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -176,6 +180,14 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4}), flush=True)
+        return
     n = args.n
     A_np, B_np = inputs.pair("uniform", n, n, n, 0, np.float32)
     A = torch.from_numpy(A_np).cuda()
@@ -196,6 +208,11 @@ def main():
 
     win = run_product(torch, api, L, "winograd", args.sched, n, levels, A, B, args.steps, args.warmup)
     print(f"# winograd L={levels}: {win['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    if args.profile_only:
+        print(json.dumps({"profile_only": True, "n": n, "levels": levels,
+                          "tflops": round(win["tflops"], 3),
+                          "roofline": gemm_roofline(win, n)}), flush=True)
+        return
     plain = run_product(torch, api, L, "naive", "auto", n, 0, A, B, args.steps, args.warmup)
     print(f"# plain mfma gemm: {plain['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
 

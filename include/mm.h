@@ -148,6 +148,12 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
 /* Flags for mm_plan_create. */
 #define MM_PLAN_GRAPH 1u /* capture the launch sequence in a hipGraph per distinct
                             (A, B, C, workspace) address tuple and replay it */
+/* Force the MFMA GEMM tile configuration c (0 .. 7) for every leaf launch
+ * instead of the planner's choice.  float32: 0 128x128 (BK 32), 1 256x128,
+ * 2 128x256, 3 256x256 (BK 16), 4 64x128, 5 128x64, 6 256x128 (BK 16),
+ * 7 128x128 (BK 16); float64: 0 128x128,
+ * 5 128x64 (others fall back to 0). */
+#define MM_PLAN_TILE(c) ((unsigned)((c) + 1) << 8)
 
 /* Build (once) the launch sequence and device descriptor table of one
  * product shape on the current device.  The plan owns a small device table

@@ -21,6 +21,12 @@ MM_F64, MM_F32, MM_BF16X3_REFINED = 0, 1, 2
 MM_ALGO_NAIVE, MM_ALGO_STRASSEN, MM_ALGO_WINOGRAD = 0, 1, 2
 MM_SCHED_TWO_TEMP, MM_SCHED_IN_PLACE, MM_SCHED_GROUPED, MM_SCHED_DFS3, MM_SCHED_AUTO = 0, 1, 2, 3, 4
 MM_PLAN_GRAPH = 1
+
+
+def plan_tile(c):
+    """MM_PLAN_TILE(c) flag bits (0 when c is None: planner's choice)."""
+    return 0 if c is None else ((int(c) + 1) << 8)
+
 STATUS = {0: "MM_OK", 1: "MM_E_INVALID", 2: "MM_E_UNSUPPORTED", 3: "MM_E_WORKSPACE",
           4: "MM_E_ALIAS", 5: "MM_E_HIP", 6: "MM_E_NOMEM"}
 

@@ -48,7 +48,7 @@ class Plan:
     """A built launch sequence for one product shape (mm_plan_create)."""
 
     def __init__(self, algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None,
-                 ldc=None, graph=False, device=None):
+                 ldc=None, graph=False, device=None, tile=None):
         lib = L.load()
         self.algo, self.sched, self.dtype = algo, sched, dtype
         self.m, self.n, self.k = m, n, k
@@ -61,7 +61,8 @@ class Plan:
         with torch.cuda.device(self.device):
             L.check(lib.mm_plan_create(L.ALGOS[algo], L.SCHEDS[sched], m, n, k, self.lda, self.ldb,
                                        self.ldc, cutoff, levels, L.DTYPES[dtype],
-                                       L.MM_PLAN_GRAPH if graph else 0, ctypes.byref(self._ptr)))
+                                       (L.MM_PLAN_GRAPH if graph else 0) | L.plan_tile(tile),
+                                       ctypes.byref(self._ptr)))
         info = (ctypes.c_int64 * 9)()
         lib.mm_plan_info(self._ptr, info, 9)
         self.info = L._info_dict(info)
@@ -110,18 +111,18 @@ def workspace(nbytes, device, stream):
     return cur
 
 
-def get_plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device):
-    key = (str(device), algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph)
+def get_plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile=None):
+    key = (str(device), algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, tile)
     with _plans_lock:
         p = _plans.get(key)
         if p is None:
-            p = Plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device)
+            p = Plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile)
             _plans[key] = p
     return p
 
 
 def mm(A, B, algo="winograd", sched="auto", cutoff=64, levels=-1, dtype=None, out=None,
-       graph=False, stream=None, clobber_inputs=False):
+       graph=False, stream=None, clobber_inputs=False, tile=None):
     """C = A @ B on the GPU by ``algo`` in {"naive", "strassen", "winograd"}.
 
     ``sched``: "auto", "grouped", "two_temp", "in_place" (Winograd) or
@@ -150,7 +151,7 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=64, levels=-1, dtype=None, ou
     ldc = _ld(C, "out")
     if m == 0 or n == 0:
         return C
-    p = get_plan(algo, sched, m, n, k, cutoff, levels, dt, lda, ldb, ldc, graph, A.device)
+    p = get_plan(algo, sched, m, n, k, cutoff, levels, dt, lda, ldb, ldc, graph, A.device, tile)
     with torch.cuda.device(A.device):
         p(A, B, C, stream=stream)
     return C
@@ -161,7 +162,7 @@ class BatchedPlan:
     (mm_batched_plan_create).  Run with ``plan()``; with ``graph=True`` the
     level-synchronous launch sequence is captured once and replayed."""
 
-    def __init__(self, As, Bs, Cs, cutoff=None, levels=None, dtype=None, graph=True):
+    def __init__(self, As, Bs, Cs, cutoff=None, levels=None, dtype=None, graph=True, tile=None):
         lib = L.load()
         if not (len(As) == len(Bs) == len(Cs)):
             raise ValueError("As, Bs, Cs differ in length")
@@ -188,7 +189,7 @@ class BatchedPlan:
         self._ptr = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             L.check(lib.mm_batched_plan_create(cnt, flat, Ap, Bp, Cp, L.DTYPES[dt], cp, lp,
-                                               L.MM_PLAN_GRAPH if graph else 0,
+                                               (L.MM_PLAN_GRAPH if graph else 0) | L.plan_tile(tile),
                                                ctypes.byref(self._ptr)))
         info = (ctypes.c_int64 * 9)()
         lib.mm_plan_info(self._ptr, info, 9)

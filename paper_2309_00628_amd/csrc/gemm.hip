@@ -5,10 +5,11 @@
 // a group of independent products (the seven products of a level, or many
 // problems of a batch), so small leaves still fill the 256 compute units.
 //
-// Workgroup: 256 threads = 4 wave64s in a 2 x 2 arrangement, a 128 x 128 tile
-// of C, each wave 64 x 64.  The K loop stages 128 x BK tiles of A and B in LDS
-// (BK = 32 floats or 16 doubles), double-buffered: the global loads of tile
-// t+1 are in flight while the MFMAs consume tile t, one barrier per step.
+// Workgroup: a BM x BN tile of C split among WGM x WGN wave64s (several tile
+// configurations are instantiated; the planner picks one per launch).  The K
+// loop stages BM x BK and BK x BN tiles of A and B in LDS, double-buffered:
+// the global loads of stage t+1 are in flight while the MFMAs consume stage
+// t, one barrier per stage.
 //
 // LDS layout ("k-chunked"): a 16-byte chunk holds E consecutive k values
 // (E = 4 floats / 2 doubles) of one row of A or one column of B, so every MFMA
@@ -26,6 +27,8 @@
 // folding a following block addition into the epilogue gives the same bits
 // as storing the product and adding it in a separate step.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "desc.h"
 #include "kernels.h"
@@ -78,11 +81,7 @@ struct MT<double> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
 };
 
-constexpr int BM = kGemmBM;
-constexpr int BN = kGemmBN;
-constexpr int BKC = 8;  // k-chunks per LDS tile
-constexpr int NT = 256;
-constexpr int WM = 64, WN = 64;  // wave tile
+constexpr int BKC_MAX = 8;
 
 template <typename T>
 __device__ __forceinline__ T* resolve(const KernelBases& kb, const MView& v) {
@@ -94,10 +93,16 @@ __device__ __forceinline__ bool view_vec(const KernelBases& kb, const MView& v) 
   return v.vec && (v.base == MB_ABS || ((kb.aligned >> v.base) & 1));
 }
 
-// Column swizzle of B's LDS tile (and of A's rows, below).
+// LDS swizzles.  A: the 16 lanes of a store phase cover 16/BKC consecutive
+// rows x BKC chunks; XOR-ing the row by (16/BKC) * kc spreads them over 16
+// bank groups.  B: 16 lanes store columns E*cb + c for 16 consecutive cb;
+// XOR-ing the low bits with (col / 16) mod E does the same.  Fragment reads
+// (16 consecutive rows or columns of one chunk plane) stay conflict-free
+// because both swizzles permute within aligned groups of 16.
+template <int BKC>
+__device__ __forceinline__ int swz_a(int row, int kc) { return row ^ ((16 / BKC) * kc); }
 template <int E>
 __device__ __forceinline__ int swz_b(int col) { return col ^ ((col >> 4) & (E - 1)); }
-__device__ __forceinline__ int swz_a(int row, int kc) { return row ^ (2 * kc); }
 
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
   // Workgroups are dealt to the 8 XCDs round-robin (b % 8).  Give each XCD a
@@ -108,17 +113,26 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + (x < r ? x : r) + j;
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void gemm_kernel(KernelBases kb, const GemmDesc* __restrict__ descs,
-                                                  int ndesc) {
+// BM x BN tile per workgroup, WGM x WGN waves (each (BM/WGM) x (BN/WGN)),
+// BKC 16-byte chunks of k per LDS stage.
+template <typename T, int BM, int BN, int BKC, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
+                                                              const GemmDesc* __restrict__ descs,
+                                                              int ndesc) {
   typedef MT<T> M;
   typedef typename M::chunk_t chunk_t;
+  constexpr int NT = 64 * WGM * WGN;
   constexpr int E = M::E;
   constexpr int TM = M::TM;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / TM, FN = WN / TM;
   constexpr int BK = BKC * E;
-  constexpr int NB = BKC * (BN / E) / NT;  // E x E blocks of B per thread
-  constexpr int NA = BM * BKC / NT;        // chunks of A per thread
+  constexpr int NBLK_B = BKC * (BN / E);      // E x E blocks of B per stage
+  constexpr int NB = (NBLK_B + NT - 1) / NT;  // ... per thread
+  constexpr int NCH_A = BM * BKC;             // chunks of A per stage
+  constexpr int NA = (NCH_A + NT - 1) / NT;
+  static_assert(FM >= 1 && FN >= 1 && WM % TM == 0 && WN % TM == 0, "wave tile");
+  static_assert(BKC % M::KG == 0 && BKC <= BKC_MAX && 16 % BKC == 0, "k chunks");
 
   __shared__ chunk_t As[2][BKC][BM];
   __shared__ chunk_t Bs[2][BKC][BN];
@@ -152,23 +166,26 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KernelBases kb, const GemmDesc
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
 
   // ---- global -> register staging ----------------------------------------
   chunk_t ra[NA];
   chunk_t rbk[NB][E];  // E rows (k) of E columns
 
-  auto load_tile = [&](int kt) {
+  // FULL: the whole stage is inside both operands' valid extents and every
+  // access is a 16-byte vector load (no masks, no branches, so the loads of
+  // the next stage stay in flight while the MFMAs of this one run).
+  auto load_tile = [&](auto full_tag, int kt) {
+    constexpr bool FULL = decltype(full_tag)::value;
     const int k0 = kt * BK;
-    const bool afull = avec && (i0 + BM <= av.vrows) && (k0 + BK <= av.vcols);
-    const bool bfull = bvec && (k0 + BK <= bv.vrows) && (j0 + BN <= bv.vcols);
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int q = tid + NT * i;
+      if (NCH_A % NT != 0 && q >= NCH_A) break;
       const int row = q / BKC, kc = q % BKC;
       const int gr = i0 + row, gc = k0 + kc * E;
       const T* p = Ap + (int64_t)gr * lda + gc;
-      if (afull) {
+      if (FULL) {
         ra[i] = *reinterpret_cast<const chunk_t*>(p);
       } else if (avec && gr < av.vrows && gc + E <= av.vcols) {
         ra[i] = *reinterpret_cast<const chunk_t*>(p);
@@ -181,13 +198,14 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KernelBases kb, const GemmDesc
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int q = tid + NT * i;
+      if (NBLK_B % NT != 0 && q >= NBLK_B) break;
       const int kc = q / (BN / E), cb = q % (BN / E);
       const int gc = j0 + cb * E;
 #pragma unroll
       for (int rr = 0; rr < E; ++rr) {
         const int gr = k0 + kc * E + rr;
         const T* p = Bp + (int64_t)gr * ldb + gc;
-        if (bfull) {
+        if (FULL) {
           rbk[i][rr] = *reinterpret_cast<const chunk_t*>(p);
         } else if (bvec && gr < bv.vrows && gc + E <= bv.vcols) {
           rbk[i][rr] = *reinterpret_cast<const chunk_t*>(p);
@@ -204,12 +222,14 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KernelBases kb, const GemmDesc
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int q = tid + NT * i;
+      if (NCH_A % NT != 0 && q >= NCH_A) break;
       const int row = q / BKC, kc = q % BKC;
-      As[buf][kc][swz_a(row, kc)] = ra[i];
+      As[buf][kc][swz_a<BKC>(row, kc)] = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int q = tid + NT * i;
+      if (NBLK_B % NT != 0 && q >= NBLK_B) break;
       const int kc = q / (BN / E), cb = q % (BN / E);
 #pragma unroll
       for (int c = 0; c < E; ++c) {
@@ -231,71 +251,127 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KernelBases kb, const GemmDesc
 
   const int g = lane / TM, t = lane % TM;
 
-  if (ktiles > 0) {
-    load_tile(0);
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int kb2 = 0; kb2 < BKC / M::KG; ++kb2) {
+      const int plane = kb2 * M::KG + g;
+      chunk_t fa[FM], fb[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) fa[a] = As[buf][plane][swz_a<BKC>(wm * WM + a * TM + t, plane)];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) fb[b] = Bs[buf][plane][swz_b<E>(wn * WN + b * TM + t)];
+#pragma unroll
+      for (int s = 0; s < E; ++s)
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) acc[a][b] = M::mfma(fa[a][s], fb[b][s], acc[a][b]);
+    }
+  };
+
+  auto main_loop = [&](auto full_tag) {
+    load_tile(full_tag, 0);
     store_tile(0);
     __syncthreads();
     for (int kt = 0; kt < ktiles; ++kt) {
       const int buf = kt & 1;
-      if (kt + 1 < ktiles) load_tile(kt + 1);
-#pragma unroll
-      for (int kb2 = 0; kb2 < BKC / M::KG; ++kb2) {
-        const int plane = kb2 * M::KG + g;
-        chunk_t fa[FM], fb[FN];
-#pragma unroll
-        for (int a = 0; a < FM; ++a) fa[a] = As[buf][plane][swz_a(wm * WM + a * TM + t, plane)];
-#pragma unroll
-        for (int b = 0; b < FN; ++b) fb[b] = Bs[buf][plane][swz_b<E>(wn * WN + b * TM + t)];
-#pragma unroll
-        for (int s = 0; s < E; ++s)
-#pragma unroll
-          for (int a = 0; a < FM; ++a)
-#pragma unroll
-            for (int b = 0; b < FN; ++b) acc[a][b] = M::mfma(fa[a][s], fb[b][s], acc[a][b]);
-      }
+      if (kt + 1 < ktiles) load_tile(full_tag, kt + 1);
+      compute(buf);
       if (kt + 1 < ktiles) store_tile(buf ^ 1);
       __syncthreads();
     }
+  };
+
+  if (ktiles > 0) {
+    const bool interior = avec && bvec && (i0 + BM <= av.vrows) && (j0 + BN <= bv.vcols) &&
+                          (K % BK == 0) && (K <= av.vcols) && (K <= bv.vrows);
+    if (interior)
+      main_loop(std::true_type{});
+    else
+      main_loop(std::false_type{});
   }
 
   // ---- epilogue --------------------------------------------------------------
-  for (int o = 0; o < D.nout; ++o) {
-    const GemmOut& O = D.out[o];
-    T* Cp = resolve<T>(kb, O.c);
-    const int64_t ldc = O.c.ld;
-    const bool add = O.mode == GM_ADD;
-    const T* Dp = add ? resolve<T>(kb, O.d) : nullptr;
-    const int64_t ldd = add ? O.d.ld : 0;
-    const T sg = T(O.sign);
+  const int nout = D.nout;
+  for (int o = 0; o < nout; ++o) {
+    const MView cv = D.out[o].c;
+    const MView dv = D.out[o].d;
+    const int mode = D.out[o].mode;
+    const T sg = T(D.out[o].sign);
+    T* __restrict__ Cp = resolve<T>(kb, cv);
+    const bool add = mode == GM_ADD;
+    const T* Dp = add ? resolve<T>(kb, dv) : nullptr;
+    const int64_t ldc = cv.ld, ldd = add ? dv.ld : 0;
+    const int crows = cv.vrows, ccols = cv.vcols;
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
       for (int b = 0; b < FN; ++b) {
         const int col = j0 + wn * WN + b * TM + t;
+        const int rbase = i0 + wm * WM + a * TM;
+        T* cpt = Cp + (int64_t)rbase * ldc + col;
+        const T* dpt = add ? Dp + (int64_t)rbase * ldd + col : nullptr;
 #pragma unroll
         for (int r = 0; r < M::NACC; ++r) {
-          const int row = i0 + wm * WM + a * TM + M::row(lane, r);
-          if (row < O.c.vrows && col < O.c.vcols) {
+          const int rr = M::row(lane, r);
+          if (rbase + rr < crows && col < ccols) {
             const T v = sg * acc[a][b][r];
-            Cp[(int64_t)row * ldc + col] = add ? Dp[(int64_t)row * ldd + col] + v : v;
+            cpt[(int64_t)rr * ldc] = add ? dpt[(int64_t)rr * ldd] + v : v;
           }
         }
       }
   }
 }
 
+template <typename T, int BM, int BN, int BKC, int WGM, int WGN>
+hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BKC, WGM, WGN>), dim3(tiles), dim3(64 * WGM * WGN), 0, s, kb,
+                     d, n);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 bool gemm_bf16x3_available() { return false; }
 
-hipError_t launch_gemm(int dtype, const KernelBases& kb, const GemmDesc* ddescs, int ndesc, int tiles,
+GemmCfg gemm_cfg(int dtype, int cfg) {
+  if (dtype == DT_F64) {
+    switch (cfg) {
+      case 5: return {128, 64};
+      default: return {128, 128};
+    }
+  }
+  switch (cfg) {
+    case 1: return {256, 128};
+    case 2: return {128, 256};
+    case 3: return {256, 256};
+    case 4: return {64, 128};
+    case 5: return {128, 64};
+    case 6: return {256, 128};
+    case 7: return {128, 128};
+    default: return {128, 128};
+  }
+}
+
+hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc* d, int n, int tiles,
                        hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  if (dtype == DT_F64)
-    hipLaunchKernelGGL(gemm_kernel<double>, dim3(tiles), dim3(NT), 0, s, kb, ddescs, ndesc);
-  else
-    hipLaunchKernelGGL(gemm_kernel<float>, dim3(tiles), dim3(NT), 0, s, kb, ddescs, ndesc);
-  return hipGetLastError();
+  if (dtype == DT_F64) {
+    switch (cfg) {
+      case 5: return launch_cfg<double, 128, 64, 8, 2, 2>(kb, d, n, tiles, s);
+      default: return launch_cfg<double, 128, 128, 8, 2, 2>(kb, d, n, tiles, s);
+    }
+  }
+  switch (cfg) {
+    case 1: return launch_cfg<float, 256, 128, 8, 4, 2>(kb, d, n, tiles, s);
+    case 2: return launch_cfg<float, 128, 256, 8, 2, 4>(kb, d, n, tiles, s);
+    case 3: return launch_cfg<float, 256, 256, 4, 2, 2>(kb, d, n, tiles, s);
+    case 4: return launch_cfg<float, 64, 128, 8, 2, 2>(kb, d, n, tiles, s);
+    case 5: return launch_cfg<float, 128, 64, 8, 2, 2>(kb, d, n, tiles, s);
+    case 6: return launch_cfg<float, 256, 128, 4, 2, 2>(kb, d, n, tiles, s);
+    case 7: return launch_cfg<float, 128, 128, 4, 2, 2>(kb, d, n, tiles, s);
+    default: return launch_cfg<float, 128, 128, 8, 2, 2>(kb, d, n, tiles, s);
+  }
 }
 
 }  // namespace mm

@@ -10,16 +10,19 @@ namespace mm {
 // onto these; the split-bfloat16 path keeps float32 buffers).
 enum KDtype : int { DT_F64 = 0, DT_F32 = 1, DT_BF16X3 = 2 };
 
-// Block-tile geometry of the MFMA GEMM kernels (rows x cols of C per
-// workgroup).  The planner needs it to count tiles.
-constexpr int kGemmBM = 128;
-constexpr int kGemmBN = 128;
+// Tile configurations of the MFMA GEMM kernel (rows x cols of C per
+// workgroup); the planner needs the geometry to count tiles.
+struct GemmCfg {
+  int bm, bn;
+};
+constexpr int kNumGemmCfg = 8;
+GemmCfg gemm_cfg(int dtype, int cfg);
 
 int ew_blocks(int rows, int cols, int dtype);
 hipError_t launch_ew(int dtype, const KernelBases& kb, const EwPart* dparts, int nparts, int blocks,
                      hipStream_t s);
 bool gemm_bf16x3_available();
-hipError_t launch_gemm(int dtype, const KernelBases& kb, const GemmDesc* ddescs, int ndesc, int tiles,
+hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc* ddescs, int ndesc, int tiles,
                        hipStream_t s);
 
 }  // namespace mm

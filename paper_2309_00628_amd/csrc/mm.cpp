@@ -53,6 +53,7 @@ struct OpRec {
   size_t off;  // byte offset of the first descriptor in the table
   int count;   // descriptors
   int grid;    // workgroups
+  int cfg;     // GEMM tile configuration
 };
 
 }  // namespace
@@ -67,6 +68,7 @@ struct Plan {
   size_t ws_bytes = 0;
   bool batched = false;
   unsigned flags = 0;
+  int tile_cfg = -1;  // forced GEMM tile configuration, -1: planner's choice
   std::vector<OpRec> ops;
   std::vector<uint8_t> table;
   std::string text;
@@ -86,6 +88,23 @@ struct Plan {
 };
 
 namespace {
+
+// Tile configuration for one GEMM launch (a group of independent products).
+// Measured on MI355X (float32): 256x256 tiles (one workgroup per CU) reach
+// the highest MFMA rate on large products but only when the launch fills
+// whole waves of 256 workgroups; 128x128 tiles (two per CU) lose less to a
+// partial last wave; 64x128 tiles keep small launches spread over more CUs.
+int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
+  if (kdtype == DT_F64) return 0;
+  int64_t t256 = 0, t128 = 0;
+  for (const GemmDesc& g : group) {
+    t256 += ceil_div(g.m, 256) * ceil_div(g.n, 256);
+    t128 += ceil_div(g.m, 128) * ceil_div(g.n, 128);
+  }
+  if (t256 >= 1024 || (t256 >= 256 && t256 % 256 == 0)) return 3;
+  if (t128 >= 256) return 0;
+  return 4;
+}
 
 // ---------------------------------------------------------------------------
 // Builder: records block operations while a schedule walks its recursion.
@@ -217,24 +236,19 @@ struct Builder {
       g.out[i].sign = 1;
     }
     P.leaves += 1;
-    g.tiles_m = (int32_t)ceil_div(g.m, kGemmBM);
-    g.tiles_n = (int32_t)ceil_div(g.n, kGemmBN);
-    const int tiles = g.tiles_m * g.tiles_n;
     txt << "GEMM " << g.m << " " << g.n << " " << g.k << " | " << vs(a) << " " << vs(b) << " |";
     for (int j = 0; j < g.nout; ++j)
       txt << " " << g.out[j].mode << ":" << g.out[j].sign << ":" << vs(g.out[j].c) << ":"
           << vs(g.out[j].d);
     txt << "\n";
-    if (tiles == 0) return;
-    g.tile_start = gm_grid;
-    gm_grid += tiles;
+    if (g.m == 0 || g.n == 0) return;
     gm.push_back(g);
   }
 
   // Close the current launch.
   void flush() {
     if (!ew.empty()) {
-      OpRec r{OP_EW, ew_dtype(P.dtype), P.table.size(), (int)ew.size(), ew_grid};
+      OpRec r{OP_EW, ew_dtype(P.dtype), P.table.size(), (int)ew.size(), ew_grid, 0};
       const size_t bytes = ew.size() * sizeof(EwPart);
       P.table.resize(round_up(P.table.size() + bytes, 256));
       std::memcpy(P.table.data() + r.off, ew.data(), bytes);
@@ -244,12 +258,22 @@ struct Builder {
       ew_grid = 0;
     }
     if (!gm.empty()) {
-      OpRec r{OP_GEMM, kernel_dtype(P.dtype), P.table.size(), (int)gm.size(), gm_grid};
+      const int kd = kernel_dtype(P.dtype);
+      const int cfg = P.tile_cfg >= 0 ? P.tile_cfg : choose_gemm_cfg(kd, gm);
+      const GemmCfg gc = gemm_cfg(kd, cfg);
+      gm_grid = 0;
+      for (GemmDesc& g : gm) {
+        g.tiles_m = (int32_t)ceil_div(g.m, gc.bm);
+        g.tiles_n = (int32_t)ceil_div(g.n, gc.bn);
+        g.tile_start = gm_grid;
+        gm_grid += g.tiles_m * g.tiles_n;
+      }
+      OpRec r{OP_GEMM, kd, P.table.size(), (int)gm.size(), gm_grid, cfg};
       const size_t bytes = gm.size() * sizeof(GemmDesc);
       P.table.resize(round_up(P.table.size() + bytes, 256));
       std::memcpy(P.table.data() + r.off, gm.data(), bytes);
       P.ops.push_back(r);
-      txt << "LAUNCH GEMM " << gm.size() << " " << gm_grid << "\n";
+      txt << "LAUNCH GEMM " << gm.size() << " " << gm_grid << " " << cfg << "\n";
       gm.clear();
       gm_grid = 0;
     }
@@ -708,7 +732,7 @@ int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEven
     if (op.type == OP_EW)
       e = launch_ew(op.kdtype, kb, (const EwPart*)d, op.count, op.grid, s);
     else
-      e = launch_gemm(op.kdtype, kb, (const GemmDesc*)d, op.count, op.grid, s);
+      e = launch_gemm(op.kdtype, op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, s);
     if (e != hipSuccess) return fail(MM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   }
   if (events && hipEventRecord(events[i], s) != hipSuccess) return fail(MM_E_HIP, "hipEventRecord failed");
@@ -814,6 +838,8 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   P->cutoff = cutoff;
   P->levels = levels;
   P->flags = flags;
+  P->tile_cfg = (int)((flags >> 8) & 0xff) - 1;
+  if (P->tile_cfg >= kNumGemmCfg) return fail(MM_E_INVALID, "unknown tile configuration");
   rc = build_plan(*P);
   if (rc != MM_OK) return rc;
   *out = std::move(P);
@@ -1187,6 +1213,8 @@ int mm_batched_plan_create(int count, const int64_t* mnk, void* const* A, void* 
   P->dtype = dtype;
   P->batched = true;
   P->flags = flags;
+  P->tile_cfg = (int)((flags >> 8) & 0xff) - 1;
+  if (P->tile_cfg >= kNumGemmCfg) return fail(MM_E_INVALID, "unknown tile configuration");
   rc = build_batched(*P, count, mnk, A, B, C, cutoff, levels);
   if (rc != MM_OK) return rc;
   rc = upload(*P);

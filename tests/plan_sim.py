@@ -47,7 +47,7 @@ def parse(text):
         if not line.strip():
             continue
         if line.startswith("LAUNCH"):
-            _, kind, cnt, _grid = line.split()
+            _, kind, cnt, _grid = line.split()[:4]
             assert len(cur) == int(cnt), (line, len(cur))
             assert all(it[0] == kind for it in cur)
             launches.append((kind, cur))
