@@ -31,14 +31,15 @@
 #include <type_traits>
 
 #include "desc.h"
+#include "gemm_common.h"
 #include "kernels.h"
 
 namespace mm {
 
 namespace {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+using namespace gemm_detail;
+
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
@@ -83,36 +84,6 @@ struct MT<double> {
 
 constexpr int BKC_MAX = 8;
 
-template <typename T>
-__device__ __forceinline__ T* resolve(const KernelBases& kb, const MView& v) {
-  char* b = v.base == MB_ABS ? nullptr : reinterpret_cast<char*>(kb.p[v.base]);
-  return reinterpret_cast<T*>(b) + v.off;
-}
-
-__device__ __forceinline__ bool view_vec(const KernelBases& kb, const MView& v) {
-  return v.vec && (v.base == MB_ABS || ((kb.aligned >> v.base) & 1));
-}
-
-// LDS swizzles.  A: the 16 lanes of a store phase cover 16/BKC consecutive
-// rows x BKC chunks; XOR-ing the row by (16/BKC) * kc spreads them over 16
-// bank groups.  B: 16 lanes store columns E*cb + c for 16 consecutive cb;
-// XOR-ing the low bits with (col / 16) mod E does the same.  Fragment reads
-// (16 consecutive rows or columns of one chunk plane) stay conflict-free
-// because both swizzles permute within aligned groups of 16.
-template <int BKC>
-__device__ __forceinline__ int swz_a(int row, int kc) { return row ^ ((16 / BKC) * kc); }
-template <int E>
-__device__ __forceinline__ int swz_b(int col) { return col ^ ((col >> 4) & (E - 1)); }
-
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  // Workgroups are dealt to the 8 XCDs round-robin (b % 8).  Give each XCD a
-  // contiguous range of tiles so that tiles sharing A rows / B columns share
-  // that XCD's L2.
-  const int q = nb >> 3, r = nb & 7;
-  const int x = b & 7, j = b >> 3;
-  return x * q + (x < r ? x : r) + j;
-}
-
 // BM x BN tile per workgroup, WGM x WGN waves (each (BM/WGM) x (BN/WGN)),
 // BKC 16-byte chunks of k per LDS stage.
 template <typename T, int BM, int BN, int BKC, int WGM, int WGN>
@@ -138,23 +109,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
   __shared__ chunk_t Bs[2][BKC][BN];
 
   // ---- which problem and which tile -------------------------------------
-  const int rb = xcd_remap(blockIdx.x, gridDim.x);
-  int lo = 0, hi = ndesc - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].tile_start <= rb) lo = mid; else hi = mid - 1;
-  }
-  const GemmDesc& D = descs[lo];
-  const int lt = rb - D.tile_start;
-  const int tiles_m = D.tiles_m, tiles_n = D.tiles_n;
-  constexpr int GROUP = 8;
-  const int per_group = GROUP * tiles_n;
-  const int gid = lt / per_group;
-  const int first_m = gid * GROUP;
-  const int gsz = min(tiles_m - first_m, GROUP);
-  const int tm = first_m + (lt - gid * per_group) % gsz;
-  const int tn = (lt - gid * per_group) / gsz;
-  const int i0 = tm * BM, j0 = tn * BN;
+  const TileRef tr = locate_tile<BM, BN>(descs, ndesc);
+  const GemmDesc& D = descs[tr.desc];
+  const int i0 = tr.i0, j0 = tr.j0;
 
   const MView av = D.a, bv = D.b;
   const T* __restrict__ Ap = resolve<T>(kb, av);
@@ -292,35 +249,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
   }
 
   // ---- epilogue --------------------------------------------------------------
-  const int nout = D.nout;
-  for (int o = 0; o < nout; ++o) {
-    const MView cv = D.out[o].c;
-    const MView dv = D.out[o].d;
-    const int mode = D.out[o].mode;
-    const T sg = T(D.out[o].sign);
-    T* __restrict__ Cp = resolve<T>(kb, cv);
-    const bool add = mode == GM_ADD;
-    const T* Dp = add ? resolve<T>(kb, dv) : nullptr;
-    const int64_t ldc = cv.ld, ldd = add ? dv.ld : 0;
-    const int crows = cv.vrows, ccols = cv.vcols;
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-      for (int b = 0; b < FN; ++b) {
-        const int col = j0 + wn * WN + b * TM + t;
-        const int rbase = i0 + wm * WM + a * TM;
-        T* cpt = Cp + (int64_t)rbase * ldc + col;
-        const T* dpt = add ? Dp + (int64_t)rbase * ldd + col : nullptr;
-#pragma unroll
-        for (int r = 0; r < M::NACC; ++r) {
-          const int rr = M::row(lane, r);
-          if (rbase + rr < crows && col < ccols) {
-            const T v = sg * acc[a][b][r];
-            cpt[(int64_t)rr * ldc] = add ? dpt[(int64_t)rr * ldd] + v : v;
-          }
-        }
-      }
-  }
+  store_outputs<T, TM, M::NACC, FM, FN, WM, WN>(kb, D, i0, j0, wm, wn, lane, acc,
+                                                 [](int l, int r) { return M::row(l, r); });
 }
 
 template <typename T, int BM, int BN, int BKC, int WGM, int WGN>
@@ -332,9 +262,8 @@ hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles
 
 }  // namespace
 
-bool gemm_bf16x3_available() { return false; }
-
 GemmCfg gemm_cfg(int dtype, int cfg) {
+  if (dtype == DT_BF16X3) return gemm_bf16x3_cfg(cfg);
   if (dtype == DT_F64) {
     switch (cfg) {
       case 5: return {128, 64};
@@ -356,6 +285,7 @@ GemmCfg gemm_cfg(int dtype, int cfg) {
 hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc* d, int n, int tiles,
                        hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
+  if (dtype == DT_BF16X3) return launch_gemm_bf16x3(cfg, kb, d, n, tiles, s);
   if (dtype == DT_F64) {
     switch (cfg) {
       case 5: return launch_cfg<double, 128, 64, 8, 2, 2>(kb, d, n, tiles, s);

@@ -1,0 +1,272 @@
+// Leaf products for float32 operands on bfloat16 matrix cores, with the
+// split-precision refinement of the MM_BF16X3_REFINED dtype.
+//
+// Every float32 operand element x is split once, when its tile is staged in
+// LDS, into three bfloat16 parts (round to nearest even at each step):
+//   hi  = bf16(x)
+//   lo  = bf16(x - hi)                      (x - hi is exact in float32)
+//   res = bf16(x - hi - lo), the residual formed in float64
+// so that x = hi + lo + res up to about 2^-25 |x|.  A product of two parts is
+// exact in float32 (8 x 8 significant bits), so v_mfma_f32_32x32x16_bf16
+// accumulates them in float32 without extra rounding.  Per 16-wide k step
+// each C tile receives the three leading products hi*hi + hi*lo + lo*hi and
+// the one-step correction lo*lo + res*hi + hi*res, smallest first; the
+// neglected terms (lo*res, res*lo, res*res) are below 2^-24 relative.  The
+// result therefore carries float32-level error while every multiply runs at
+// the bfloat16 MFMA rate.
+//
+// Structure as in the float32 kernel: grouped problems, XCD-aware tile order,
+// LDS double buffering (three planes per operand: hi, lo, res), masked edge
+// tiles and a branch-free interior loop.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "desc.h"
+#include "gemm_common.h"
+#include "kernels.h"
+
+namespace mm {
+
+namespace {
+
+using namespace gemm_detail;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// v_mfma_f32_32x32x16_bf16: lanes 0-31 and 32-63 supply the two 8-wide k
+// halves of a 32 x 16 by 16 x 32 product (lane l: row / column l % 32); the
+// result layout is that of the other 32 x 32 MFMAs:
+// register r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+__device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ int row32(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// Split 8 floats into their bfloat16 hi, lo and residual parts.
+__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo, bf16x8& rs) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    const float hf = (float)h;
+    const __bf16 l = (__bf16)(x[e] - hf);
+    const float lf = (float)l;
+    const double r = ((double)x[e] - (double)hf) - (double)lf;
+    hi[e] = h;
+    lo[e] = l;
+    rs[e] = (__bf16)(float)r;
+  }
+}
+
+constexpr int KC = 8;  // k values per 16-byte chunk (bfloat16)
+constexpr int EB = 2;  // B columns per staged block (one float2 per k row)
+
+template <int BM, int BN, int BKC, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases kb,
+                                                                     const GemmDesc* __restrict__ descs,
+                                                                     int ndesc) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int TM = 32;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / TM, FN = WN / TM;
+  constexpr int BK = BKC * KC;
+  constexpr int NCH_A = BM * BKC;  // 8-float chunks of A per stage
+  constexpr int NA = (NCH_A + NT - 1) / NT;
+  constexpr int NBLK_B = BKC * (BN / EB);  // 8 x 2 blocks of B per stage
+  constexpr int NB = (NBLK_B + NT - 1) / NT;
+  static_assert(BKC % 2 == 0 && 16 % BKC == 0 && FM >= 1 && FN >= 1, "tile shape");
+
+  __shared__ bf16x8 As[2][3][BKC][BM];
+  __shared__ bf16x8 Bs[2][3][BKC][BN];
+
+  const TileRef tr = locate_tile<BM, BN>(descs, ndesc);
+  const GemmDesc& D = descs[tr.desc];
+  const int i0 = tr.i0, j0 = tr.j0;
+  const MView av = D.a, bv = D.b;
+  const float* __restrict__ Ap = resolve<float>(kb, av);
+  const float* __restrict__ Bp = resolve<float>(kb, bv);
+  const int64_t lda = av.ld, ldb = bv.ld;
+  const bool avec = view_vec(kb, av), bvec = view_vec(kb, bv);
+  const int K = D.k;
+  const int ktiles = (K + BK - 1) / BK;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+
+  float ra[NA][8];
+  float rb[NB][8][EB];
+
+  auto load_tile = [&](auto full_tag, int kt) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + NT * i;
+      if (NCH_A % NT != 0 && q >= NCH_A) break;
+      const int row = q / BKC, kc = q % BKC;
+      const int gr = i0 + row, gc = k0 + kc * KC;
+      const float* p = Ap + (int64_t)gr * lda + gc;
+      if (FULL || (avec && gr < av.vrows && gc + KC <= av.vcols)) {
+        const f32x4 u = *reinterpret_cast<const f32x4*>(p);
+        const f32x4 w = *reinterpret_cast<const f32x4*>(p + 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          ra[i][e] = u[e];
+          ra[i][4 + e] = w[e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < KC; ++e) ra[i][e] = (gr < av.vrows && gc + e < av.vcols) ? p[e] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + NT * i;
+      if (NBLK_B % NT != 0 && q >= NBLK_B) break;
+      const int kc = q / (BN / EB), cb = q % (BN / EB);
+      const int gc = j0 + cb * EB;
+#pragma unroll
+      for (int rr = 0; rr < KC; ++rr) {
+        const int gr = k0 + kc * KC + rr;
+        const float* p = Bp + (int64_t)gr * ldb + gc;
+        if (FULL || (bvec && gr < bv.vrows && gc + EB <= bv.vcols)) {
+          const f32x2 u = *reinterpret_cast<const f32x2*>(p);
+          rb[i][rr][0] = u[0];
+          rb[i][rr][1] = u[1];
+        } else {
+#pragma unroll
+          for (int e = 0; e < EB; ++e) rb[i][rr][e] = (gr < bv.vrows && gc + e < bv.vcols) ? p[e] : 0.f;
+        }
+      }
+    }
+  };
+
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + NT * i;
+      if (NCH_A % NT != 0 && q >= NCH_A) break;
+      const int row = q / BKC, kc = q % BKC;
+      bf16x8 h, l, r;
+      split8(ra[i], h, l, r);
+      const int sr = swz_a<BKC>(row, kc);
+      As[buf][0][kc][sr] = h;
+      As[buf][1][kc][sr] = l;
+      As[buf][2][kc][sr] = r;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + NT * i;
+      if (NBLK_B % NT != 0 && q >= NBLK_B) break;
+      const int kc = q / (BN / EB), cb = q % (BN / EB);
+#pragma unroll
+      for (int c = 0; c < EB; ++c) {
+        float col[8];
+#pragma unroll
+        for (int rr = 0; rr < KC; ++rr) col[rr] = rb[i][rr][c];
+        bf16x8 h, l, r;
+        split8(col, h, l, r);
+        const int sc = swz_b<EB>(cb * EB + c);
+        Bs[buf][0][kc][sc] = h;
+        Bs[buf][1][kc][sc] = l;
+        Bs[buf][2][kc][sc] = r;
+      }
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  const int g = lane / TM, t = lane % TM;
+
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < BKC / 2; ++ks) {
+      const int plane = 2 * ks + g;
+      bf16x8 fa[3][FM], fb[3][FN];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+#pragma unroll
+        for (int a = 0; a < FM; ++a) fa[p][a] = As[buf][p][plane][swz_a<BKC>(wm * WM + a * TM + t, plane)];
+#pragma unroll
+        for (int b = 0; b < FN; ++b) fb[p][b] = Bs[buf][p][plane][swz_b<EB>(wn * WN + b * TM + t)];
+      }
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+          f32x16 c = acc[a][b];
+          c = mfma_bf16(fa[1][a], fb[1][b], c);  // lo  * lo
+          c = mfma_bf16(fa[2][a], fb[0][b], c);  // res * hi
+          c = mfma_bf16(fa[0][a], fb[2][b], c);  // hi  * res
+          c = mfma_bf16(fa[1][a], fb[0][b], c);  // lo  * hi
+          c = mfma_bf16(fa[0][a], fb[1][b], c);  // hi  * lo
+          c = mfma_bf16(fa[0][a], fb[0][b], c);  // hi  * hi
+          acc[a][b] = c;
+        }
+    }
+  };
+
+  auto main_loop = [&](auto full_tag) {
+    load_tile(full_tag, 0);
+    store_tile(0);
+    __syncthreads();
+    for (int kt = 0; kt < ktiles; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < ktiles) load_tile(full_tag, kt + 1);
+      compute(buf);
+      if (kt + 1 < ktiles) store_tile(buf ^ 1);
+      __syncthreads();
+    }
+  };
+
+  if (ktiles > 0) {
+    const bool interior = avec && bvec && (i0 + BM <= av.vrows) && (j0 + BN <= bv.vcols) &&
+                          (K % BK == 0) && (K <= av.vcols) && (K <= bv.vrows);
+    if (interior)
+      main_loop(std::true_type{});
+    else
+      main_loop(std::false_type{});
+  }
+
+  store_outputs<float, TM, 16, FM, FN, WM, WN>(kb, D, i0, j0, wm, wn, lane, acc,
+                                               [](int l, int r) { return row32(l, r); });
+}
+
+template <int BM, int BN, int BKC, int WGM, int WGN>
+hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN, BKC, WGM, WGN>), dim3(tiles), dim3(64 * WGM * WGN), 0, s,
+                     kb, d, n);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool gemm_bf16x3_available() { return true; }
+
+GemmCfg gemm_bf16x3_cfg(int cfg) {
+  switch (cfg) {
+    case 1: return {256, 128};
+    case 4: return {64, 128};
+    default: return {128, 128};
+  }
+}
+
+hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d, int n, int tiles,
+                              hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  switch (cfg) {
+    case 1: return launch_cfg<256, 128, 4, 4, 2>(kb, d, n, tiles, s);
+    case 4: return launch_cfg<64, 128, 4, 2, 2>(kb, d, n, tiles, s);
+    default: return launch_cfg<128, 128, 4, 2, 2>(kb, d, n, tiles, s);
+  }
+}
+
+}  // namespace mm

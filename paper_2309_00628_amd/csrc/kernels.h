@@ -22,6 +22,9 @@ int ew_blocks(int rows, int cols, int dtype);
 hipError_t launch_ew(int dtype, const KernelBases& kb, const EwPart* dparts, int nparts, int blocks,
                      hipStream_t s);
 bool gemm_bf16x3_available();
+GemmCfg gemm_bf16x3_cfg(int cfg);
+hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d, int n, int tiles,
+                              hipStream_t s);
 hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc* ddescs, int ndesc, int tiles,
                        hipStream_t s);
 

@@ -96,6 +96,17 @@ namespace {
 // partial last wave; 64x128 tiles keep small launches spread over more CUs.
 int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
   if (kdtype == DT_F64) return 0;
+  if (kdtype == DT_BF16X3) {
+    // 256x128 tiles with eight waves (two per SIMD) hide the split's VALU
+    // work behind the MFMAs; smaller launches keep more CUs busy with 64x128.
+    int64_t t256 = 0, t128 = 0;
+    for (const GemmDesc& g : group) {
+      t256 += ceil_div(g.m, 256) * ceil_div(g.n, 128);
+      t128 += ceil_div(g.m, 128) * ceil_div(g.n, 128);
+    }
+    if (t256 >= 256) return 1;
+    return t128 >= 256 ? 0 : 4;
+  }
   int64_t t256 = 0, t128 = 0;
   for (const GemmDesc& g : group) {
     t256 += ceil_div(g.m, 256) * ceil_div(g.n, 256);

@@ -1,0 +1,85 @@
+"""Parity of the split-bfloat16 dtype (MM_BF16X3_REFINED) with the oracle.
+
+Float32 inputs, float32 outputs, every leaf product on bfloat16 MFMA with
+the hi/lo/residual split.  Target: relative Frobenius error <= 1e-5 against
+the float64 oracle, also on the wide-range inputs of the precision workload
+(Gaussian rows scaled by 10^u, u ~ U[-3, 3]).  Small integers split exactly
+(hi = x), so on them the product must be exact.
+"""
+import numpy as np
+import pytest
+
+from paper_2309_00628_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_00628_amd import api as a
+    return a
+
+
+@pytest.fixture(scope="module")
+def naive(oracle_built):
+    from oracle import naive
+    return naive
+
+
+def rel_fro(got, ref):
+    ref = np.asarray(ref, dtype=np.float64)
+    return np.linalg.norm(np.asarray(got, dtype=np.float64) - ref) / np.linalg.norm(ref)
+
+
+def run(api, A, B, **kw):
+    C = api.mm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), dtype="bf16x3", **kw)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 33, 65), (128, 128, 128), (333, 517, 259),
+                                   (64, 1000, 31), (1024, 768, 512)])
+@pytest.mark.parametrize("kind", ["uniform", "gauss_rowscaled"])
+def test_naive_bf16x3_shapes(api, naive, m, n, k, kind):
+    A, B = inputs.pair(kind, m, n, k, 1, np.float32)
+    err = rel_fro(run(api, A, B, algo="naive"), naive.gemm(A, B))
+    print(f"bf16x3 naive {kind} {m}x{n}x{k}: {err:.3e}", flush=True)
+    assert err < 1e-5
+
+
+def test_bf16x3_integer_exact(api, naive):
+    A, B = inputs.pair("int", 256, 256, 256, 2, np.float32)
+    ref = naive.gemm(A, B)
+    for algo, sched, lv in [("naive", "auto", 0), ("winograd", "grouped", 2), ("winograd", "two_temp", 1),
+                            ("strassen", "dfs3", 1)]:
+        got = run(api, A, B, algo=algo, sched=sched, cutoff=1, levels=lv)
+        assert np.array_equal(got.astype(np.float64), ref), (algo, sched, lv)
+
+
+@pytest.mark.parametrize("n,levels", [(1024, 1), (2048, 2), (1000, 2)])
+def test_winograd_bf16x3_gauss_rowscaled(api, naive, n, levels):
+    A, B = inputs.pair("gauss_rowscaled", n, n, n, 3, np.float32)
+    ref = naive.gemm(A, B)
+    for sched in ("grouped", "two_temp"):
+        err = rel_fro(run(api, A, B, algo="winograd", sched=sched, cutoff=1, levels=levels), ref)
+        print(f"bf16x3 winograd {sched} n={n} L={levels}: {err:.3e}", flush=True)
+        assert err < 1e-5
+
+
+def test_precision_workload_8192_sampled(api, naive):
+    # the precision workload at full size: n = 8192, two Winograd levels;
+    # the oracle computes a sample of output rows exactly as in the full product
+    n = 8192
+    A, B = inputs.pair("gauss_rowscaled", n, n, n, 0, np.float32)
+    rows = np.sort(inputs.rng(4).choice(n, size=24, replace=False))
+    ref = naive.gemm_rows(A, B, rows)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=2, dtype="bf16x3")
+    torch.cuda.synchronize()
+    err = rel_fro(C[torch.from_numpy(rows).cuda()].cpu().numpy(), ref)
+    print(f"bf16x3 winograd n=8192 L=2 sampled rows: {err:.3e}", flush=True)
+    assert err < 1e-5
