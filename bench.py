@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--sched", default="grouped")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline and error check")
     ap.add_argument("--no-extra", action="store_true", help="skip the n=3000 / n=8192 side runs")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batch")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the timed Winograd steps (for rocprofv3 runs)")
@@ -86,8 +88,8 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtype="f32"):
-    plan = api.Plan(algo, sched, n, n, n, cutoff=1, levels=levels, dtype=dtype)
+def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtype="f32", tile=None):
+    plan = api.Plan(algo, sched, n, n, n, cutoff=1, levels=levels, dtype=dtype, tile=tile)
     ws = torch.empty(max(plan.ws_bytes, 256), dtype=torch.uint8, device=A.device)
     C = torch.empty((n, n), dtype=A.dtype, device=A.device)
     wall, step_ms, per_op, kinds = time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup)
@@ -165,6 +167,96 @@ def rel_err(C, rows, ref):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
+def bench_batched(torch, api, inputs, tuner, count=512, steps=10, warmup=3, seed=7):
+    """512 independent float32 products, m, n, k log-uniform in [64, 2048]
+    (multiples of 16), levels per size class from the tuner, run as one
+    level-synchronous batched plan replayed from a hipGraph."""
+    shapes = inputs.batched_shapes(count, seed)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    As, Bs, Cs, levels = [], [], [], []
+    for (m, n, k) in shapes:
+        As.append(torch.rand((m, k), generator=g, device="cuda") * 2 - 1)
+        Bs.append(torch.rand((k, n), generator=g, device="cuda") * 2 - 1)
+        Cs.append(torch.empty((m, n), device="cuda"))
+        levels.append(tuner.choose(m, n, k, "f32")["levels"])
+    flops = sum(2.0 * m * n * k for (m, n, k) in shapes)
+    plan = api.BatchedPlan(As, Bs, Cs, cutoff=[1] * count, levels=levels, graph=True)
+    s = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps, e0.elapsed_time(e1) / reps
+
+    wall, dev = timed(plan, steps)
+    naive_plans = [api.get_plan("naive", "auto", m, n, k, 1, 0, "f32", k, n, n, False, As[0].device)
+                   for (m, n, k) in shapes]
+
+    def loop_naive():
+        for p, a, b, c in zip(naive_plans, As, Bs, Cs):
+            p(a, b, c)
+
+    def loop_torch():
+        for a, b, c in zip(As, Bs, Cs):
+            torch.matmul(a, b, out=c)
+    wall_n, _ = timed(loop_naive, 3)
+    wall_t, _ = timed(loop_torch, 3)
+    return {"workload": f"{count} fp32 products, m,n,k log-uniform in [64,2048] (x16), uniform[-1,1]",
+            "tflops": round(flops / (wall * 1e-3) / 1e12, 3), "ms_per_batch": round(wall, 4),
+            "device_ms_per_batch": round(dev, 4), "launches_per_batch": plan.info["launches"],
+            "levels_histogram": {str(l): levels.count(l) for l in sorted(set(levels))},
+            "loop_of_mm_naive_tflops": round(flops / (wall_n * 1e-3) / 1e12, 3),
+            "loop_of_torch_matmul_tflops": round(flops / (wall_t * 1e-3) / 1e12, 3),
+            "graph": True}
+
+
+def bench_serving(torch, inputs, count=160, budget_gib=32, slots=4, seed=11):
+    """Poisson arrivals, square n: 70% in [256,1024], 25% in [1024,4096],
+    5% = 8192; dtype 50/50 float32 / split-bfloat16 refined; HBM-budget
+    admission, one stream and workspace per slot."""
+    from paper_2309_00628_amd import serving
+    dev = torch.device("cuda", 0)
+    base = inputs.serving_trace(count, seed, qps=1.0)
+    reqs = serving.make_requests(base, dev)
+    torch.cuda.synchronize()
+
+    def run(qps):
+        for r, t in zip(reqs, base):
+            r.arrival = 0.0 if qps is None else t["t"] / qps
+            r.t_admit = r.t_done = -1.0
+            r.error = ""
+            r.C = None
+        ex = serving.GpuExecutor(slots, keep_outputs=False)
+        srv = serving.Server(ex, budget_gib << 30, n_slots=slots)
+        done, wall = srv.run(reqs)
+        torch.cuda.synchronize()
+        st = serving.summarize(done, wall)
+        st["max_concurrent"] = srv.max_running
+        return st
+
+    run(None)                                   # warm-up: plans, workspaces
+    sat = run(None)
+    out = {"workload": f"{count} requests, n: 70% U[256,1024], 25% U[1024,4096], 5% 8192; "
+                       "dtype 50/50 f32 / bf16x3; Poisson arrivals",
+           "hbm_budget_gib": budget_gib, "slots": slots, "saturation": sat, "load": {}}
+    for f in (0.25, 0.5, 0.75, 0.9):
+        qps = f * sat["req_per_s"]
+        st = run(qps)
+        st["offered_qps"] = round(qps, 2)
+        out["load"][str(f)] = st
+        print(f"# serving load {f}: {st}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -174,7 +266,7 @@ def main():
     import torch
 
     from paper_2309_00628_amd import _lib as L
-    from paper_2309_00628_amd import api, inputs
+    from paper_2309_00628_amd import api, inputs, tuner
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
@@ -194,8 +286,12 @@ def main():
     B = torch.from_numpy(B_np).cuda()
     print(f"# bench n={n} fp32, steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
 
-    # level choice: time L = 1..3 briefly (the tuned choice) unless given
-    if args.levels is None:
+    # level choice: the tuner's cached choice for this size class; without one
+    # time L = 1..3 briefly and keep the fastest
+    ch = tuner.choose(n, n, n, "f32")
+    if args.levels is None and ch["source"] == "tuned" and ch["levels"] > 0:
+        levels = ch["levels"]
+    elif args.levels is None:
         best = None
         for lv in (1, 2, 3):
             r = run_product(torch, api, L, "winograd", args.sched, n, lv, A, B, 5, 2)
@@ -206,14 +302,21 @@ def main():
     else:
         levels = args.levels
 
-    win = run_product(torch, api, L, "winograd", args.sched, n, levels, A, B, args.steps, args.warmup)
+    tile = ch["tile"] if (ch["source"] == "tuned" and ch["levels"] == levels) else None
+    win = run_product(torch, api, L, "winograd", args.sched, n, levels, A, B, args.steps, args.warmup,
+                      tile=tile)
     print(f"# winograd L={levels}: {win['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
     if args.profile_only:
         print(json.dumps({"profile_only": True, "n": n, "levels": levels,
                           "tflops": round(win["tflops"], 3),
                           "roofline": gemm_roofline(win, n)}), flush=True)
         return
-    plain = run_product(torch, api, L, "naive", "auto", n, 0, A, B, args.steps, args.warmup)
+    pch = tuner.load_cache().get(tuner.class_key("f32", n, n, n), {})
+    plain_tile = None
+    if pch.get("levels") == 0:
+        plain_tile = pch.get("tile")
+    plain = run_product(torch, api, L, "naive", "auto", n, 0, A, B, args.steps, args.warmup,
+                        tile=plain_tile)
     print(f"# plain mfma gemm: {plain['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
 
     # vendor GEMM (hipBLASLt through torch.matmul) as context only
@@ -276,6 +379,12 @@ def main():
             print(f"# extra n={n2}: {e}", file=sys.stderr, flush=True)
             del A2, B2
         out["extra"] = extra
+
+    if not args.no_batched:
+        out["batched"] = bench_batched(torch, api, inputs, tuner)
+        print(f"# batched: {out['batched']}", file=sys.stderr, flush=True)
+    if not args.no_serving:
+        out["serving"] = bench_serving(torch, inputs)
 
     print(json.dumps(out), flush=True)
 

@@ -121,9 +121,13 @@ def get_plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, 
     return p
 
 
-def mm(A, B, algo="winograd", sched="auto", cutoff=64, levels=-1, dtype=None, out=None,
+def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None, out=None,
        graph=False, stream=None, clobber_inputs=False, tile=None):
     """C = A @ B on the GPU by ``algo`` in {"naive", "strassen", "winograd"}.
+
+    ``cutoff`` / ``levels`` control the recursion as in mm.h; when both are
+    None the autotuner's choice for this size class is used (levels and leaf
+    tile shape).
 
     ``sched``: "auto", "grouped", "two_temp", "in_place" (Winograd) or
     "dfs3" (Strassen).  ``dtype``: None (from the tensors), "f64", "f32" or
@@ -151,6 +155,19 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=64, levels=-1, dtype=None, ou
     ldc = _ld(C, "out")
     if m == 0 or n == 0:
         return C
+    if cutoff is None and levels is None:
+        if algo == "naive":
+            cutoff, levels = 1, 0
+        else:
+            from . import tuner
+            ch = tuner.choose(m, n, k, dt)
+            cutoff, levels = 1, ch["levels"]
+            if tile is None:
+                tile = ch["tile"]
+    elif cutoff is None:
+        cutoff = 1
+    elif levels is None:
+        levels = -1
     p = get_plan(algo, sched, m, n, k, cutoff, levels, dt, lda, ldb, ldc, graph, A.device, tile)
     with torch.cuda.device(A.device):
         p(A, B, C, stream=stream)

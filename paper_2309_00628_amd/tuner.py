@@ -1,0 +1,180 @@
+"""Autotuner: recursion depth (cutoff / levels) and MFMA tile shape per size class.
+
+Section 3.4 derives the cutoff from an operation-count model (the naive method
+wins below order 12 on the paper's CPU).  On MI355X the break-even is set by
+MFMA rate against HBM bandwidth instead, so it is measured: for a size class
+the tuner times each candidate (levels L = 0..Lmax of Strassen-Winograd with
+the grouped schedule, L = 0 being the plain MFMA GEMM, crossed with a few
+leaf tile shapes) on the GPU with HIP events and keeps the fastest.
+
+Choices are cached per (GPU architecture, dtype, size class) in a JSON file
+(``tuning/<arch>.json`` next to this module) so that a process, a batch or a
+server reuses them.  A size class is the (m, n, k) triple rounded to half
+octaves.  Without a cached entry ``choose`` falls back to a rule of thumb
+measured on MI355X: one level per halving while the leaf stays at or above
+2048 (float32) / 4096 (split bfloat16), at most two levels.
+"""
+import json
+import math
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE_DIR = os.path.join(HERE, "tuning")
+
+_lock = threading.Lock()
+_cache = {}
+
+
+def size_class(m, n, k):
+    def q(x):
+        return round(2 * math.log2(max(int(x), 1))) / 2
+    return (q(m), q(n), q(k))
+
+
+def class_key(dtype, m, n, k):
+    a, b, c = size_class(m, n, k)
+    return f"{dtype}|{a:.1f}|{b:.1f}|{c:.1f}"
+
+
+def _arch():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        pass
+    return "gfx950"
+
+
+def cache_path(arch=None):
+    return os.path.join(CACHE_DIR, f"{arch or _arch()}.json")
+
+
+def load_cache(arch=None):
+    arch = arch or _arch()
+    with _lock:
+        if arch not in _cache:
+            p = cache_path(arch)
+            _cache[arch] = json.load(open(p)) if os.path.exists(p) else {}
+        return _cache[arch]
+
+
+def save_cache(arch=None):
+    arch = arch or _arch()
+    with _lock:
+        os.makedirs(CACHE_DIR, exist_ok=True)
+        tmp = cache_path(arch) + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(_cache.get(arch, {}), f, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path(arch))
+
+
+def rule_of_thumb(m, n, k, dtype):
+    """Levels by the leaf-size rule; tile left to the planner."""
+    leaf = 2048 if dtype != "bf16x3" else 4096
+    L = 0
+    while L < 2 and min(m, n, k) >> (L + 1) >= leaf:
+        L += 1
+    return {"levels": L, "tile": None, "cutoff": 1, "source": "rule"}
+
+
+def choose(m, n, k, dtype="f32"):
+    """(levels, tile, cutoff) for C = A (m x k) B (k x n)."""
+    entry = load_cache().get(class_key(dtype, m, n, k))
+    if entry is not None:
+        return dict(entry, source="tuned")
+    return rule_of_thumb(m, n, k, dtype)
+
+
+def _time_plan(plan, A, B, C, reps, warmup):
+    import ctypes
+
+    import torch
+
+    from . import _lib as L
+    lib = L.load()
+    s = torch.cuda.current_stream()
+    ws = torch.empty(max(plan.ws_bytes, 256), dtype=torch.uint8, device=A.device)
+    for _ in range(warmup):
+        L.check(lib.mm_plan_execute(plan._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), ws.data_ptr(),
+                                    ws.numel(), s.cuda_stream))
+    e0 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    e1 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    for i in range(reps):
+        e0[i].record(s)
+        L.check(lib.mm_plan_execute(plan._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), ws.data_ptr(),
+                                    ws.numel(), s.cuda_stream))
+        e1[i].record(s)
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in zip(e0, e1))
+    return ts[len(ts) // 2]
+
+
+TILES = {"f32": (None, 0, 3, 4), "bf16x3": (None, 0, 1, 4), "f64": (None,)}
+
+
+def tune(m, n, k, dtype="f32", max_levels=3, reps=7, warmup=2, tiles=None, save=True, verbose=False):
+    """Measure the candidates for this size class and cache the fastest."""
+    import numpy as np
+    import torch
+
+    from . import api, inputs
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    ndt = np.float64 if dtype == "f64" else np.float32
+    A_np, B_np = inputs.pair("uniform", m, n, k, 0, ndt)
+    A = torch.from_numpy(A_np).cuda()
+    B = torch.from_numpy(B_np).cuda()
+    C = torch.empty((m, n), dtype=tdt, device="cuda")
+    results = []
+    for L_ in range(0, max_levels + 1):
+        if L_ > 0 and min(m, n, k) >> L_ < 64:
+            break
+        for tile in (tiles or TILES.get(dtype, (None,))):
+            try:
+                algo = "naive" if L_ == 0 else "winograd"
+                p = api.Plan(algo, "grouped" if L_ else "auto", m, n, k, cutoff=1, levels=L_, dtype=dtype,
+                             tile=tile)
+                t = _time_plan(p, A, B, C, reps, warmup)
+            except Exception as e:  # an unsupported candidate is skipped
+                if verbose:
+                    print(f"  skip L={L_} tile={tile}: {e}")
+                continue
+            results.append((t, L_, tile))
+            if verbose:
+                print(f"  {dtype} {m}x{n}x{k} L={L_} tile={tile}: {t:.3f} ms "
+                      f"{2.0 * m * n * k / t / 1e9:.1f} TFLOP/s", flush=True)
+    t, L_, tile = min(results, key=lambda r: r[0])
+    leaf = min(m, n, k) >> L_
+    # the cutoff that stops the recursion after L_ halvings: the leaf order
+    entry = {"levels": L_, "tile": tile, "cutoff": leaf if L_ else min(m, n, k),
+             "ms": round(t, 4), "tflops": round(2.0 * m * n * k / t / 1e9, 2),
+             "shape": [m, n, k]}
+    arch = _arch()
+    load_cache(arch)[class_key(dtype, m, n, k)] = entry
+    if save:
+        save_cache(arch)
+    return entry
+
+
+def main(argv=None):
+    """Tune square size classes: python -m paper_2309_00628_amd.tuner --n 1024,4096 --dtype f32"""
+    import argparse
+    import shutil
+    ap = argparse.ArgumentParser(description="measure and cache recursion levels / tile per size class")
+    ap.add_argument("--n", default="256,362,512,724,1024,1448,2048,2896,3000,4096,5793,8192")
+    ap.add_argument("--dtype", default="f32,bf16x3")
+    ap.add_argument("--max-levels", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=7)
+    ap.add_argument("--copy-to", default=None, help="also copy the cache file here")
+    args = ap.parse_args(argv)
+    for dt in args.dtype.split(","):
+        for n in [int(x) for x in args.n.split(",")]:
+            e = tune(n, n, n, dt, max_levels=args.max_levels, reps=args.reps, verbose=True)
+            print(f"{dt} n={n}: levels={e['levels']} tile={e['tile']} {e['tflops']} TFLOP/s", flush=True)
+    if args.copy_to:
+        shutil.copy(cache_path(), args.copy_to)
+
+
+if __name__ == "__main__":
+    main()
