@@ -89,7 +89,7 @@ constexpr int BKC_MAX = 8;
 template <typename T, int BM, int BN, int BKC, int WGM, int WGN>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
                                                               const GemmDesc* __restrict__ descs,
-                                                              int ndesc) {
+                                                              int ndesc, int remap) {
   typedef MT<T> M;
   typedef typename M::chunk_t chunk_t;
   constexpr int NT = 64 * WGM * WGN;
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
   __shared__ chunk_t Bs[2][BKC][BN];
 
   // ---- which problem and which tile -------------------------------------
-  const TileRef tr = locate_tile<BM, BN>(descs, ndesc);
+  const TileRef tr = locate_tile<BM, BN>(descs, ndesc, remap);
   const GemmDesc& D = descs[tr.desc];
   const int i0 = tr.i0, j0 = tr.j0;
 
@@ -129,11 +129,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
   chunk_t ra[NA];
   chunk_t rbk[NB][E];  // E rows (k) of E columns
 
-  // FULL: the whole stage is inside both operands' valid extents and every
-  // access is a 16-byte vector load (no masks, no branches, so the loads of
-  // the next stage stay in flight while the MFMAs of this one run).
-  auto load_tile = [&](auto full_tag, int kt) {
-    constexpr bool FULL = decltype(full_tag)::value;
+  // LOAD_FULL: the whole stage is inside both operands' valid extents and
+  // every access is a 16-byte vector load (no masks, no branches, so the
+  // loads of the next stage stay in flight while the MFMAs of this one run).
+  // LOAD_EDGE_VEC: edge tile of aligned operands whose valid widths are
+  // multiples of the chunk: whole chunks are in or out, selected without
+  // branches.  Otherwise per-element masked loads.
+  auto load_tile = [&](auto mode_tag, int kt) {
+    constexpr int MODE = decltype(mode_tag)::value;
     const int k0 = kt * BK;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
@@ -142,8 +145,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
       const int row = q / BKC, kc = q % BKC;
       const int gr = i0 + row, gc = k0 + kc * E;
       const T* p = Ap + (int64_t)gr * lda + gc;
-      if (FULL) {
+      if (MODE == LOAD_FULL) {
         ra[i] = *reinterpret_cast<const chunk_t*>(p);
+      } else if (MODE == LOAD_EDGE_VEC) {
+        // whole chunks are either valid or not: load from a valid address
+        // and select zero, so the loop has no data-dependent branches
+        const bool ok = gr < av.vrows && gc < av.vcols;
+        const chunk_t v = *reinterpret_cast<const chunk_t*>(ok ? p : Ap);
+        ra[i] = ok ? v : chunk_t{};
       } else if (avec && gr < av.vrows && gc + E <= av.vcols) {
         ra[i] = *reinterpret_cast<const chunk_t*>(p);
       } else {
@@ -162,8 +171,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
       for (int rr = 0; rr < E; ++rr) {
         const int gr = k0 + kc * E + rr;
         const T* p = Bp + (int64_t)gr * ldb + gc;
-        if (FULL) {
+        if (MODE == LOAD_FULL) {
           rbk[i][rr] = *reinterpret_cast<const chunk_t*>(p);
+        } else if (MODE == LOAD_EDGE_VEC) {
+          const bool ok = gr < bv.vrows && gc < bv.vcols;
+          const chunk_t v = *reinterpret_cast<const chunk_t*>(ok ? p : Bp);
+          rbk[i][rr] = ok ? v : chunk_t{};
         } else if (bvec && gr < bv.vrows && gc + E <= bv.vcols) {
           rbk[i][rr] = *reinterpret_cast<const chunk_t*>(p);
         } else {
@@ -226,13 +239,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
     }
   };
 
-  auto main_loop = [&](auto full_tag) {
-    load_tile(full_tag, 0);
+  auto main_loop = [&](auto mode_tag) {
+    load_tile(mode_tag, 0);
     store_tile(0);
     __syncthreads();
     for (int kt = 0; kt < ktiles; ++kt) {
       const int buf = kt & 1;
-      if (kt + 1 < ktiles) load_tile(full_tag, kt + 1);
+      if (kt + 1 < ktiles) load_tile(mode_tag, kt + 1);
       compute(buf);
       if (kt + 1 < ktiles) store_tile(buf ^ 1);
       __syncthreads();
@@ -242,10 +255,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
   if (ktiles > 0) {
     const bool interior = avec && bvec && (i0 + BM <= av.vrows) && (j0 + BN <= bv.vcols) &&
                           (K % BK == 0) && (K <= av.vcols) && (K <= bv.vrows);
+    const bool edge_vec = avec && bvec && av.vrows > 0 && av.vcols > 0 && bv.vrows > 0 && bv.vcols > 0 &&
+                          av.vcols % E == 0 && bv.vcols % E == 0;
     if (interior)
-      main_loop(std::true_type{});
+      main_loop(std::integral_constant<int, LOAD_FULL>{});
+    else if (edge_vec)
+      main_loop(std::integral_constant<int, LOAD_EDGE_VEC>{});
     else
-      main_loop(std::false_type{});
+      main_loop(std::integral_constant<int, LOAD_MASKED>{});
   }
 
   // ---- epilogue --------------------------------------------------------------
@@ -254,9 +271,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
 }
 
 template <typename T, int BM, int BN, int BKC, int WGM, int WGN>
-hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles, hipStream_t s) {
+hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap, hipStream_t s) {
   hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BKC, WGM, WGN>), dim3(tiles), dim3(64 * WGM * WGN), 0, s, kb,
-                     d, n);
+                     d, n, remap);
   return hipGetLastError();
 }
 
@@ -283,24 +300,24 @@ GemmCfg gemm_cfg(int dtype, int cfg) {
 }
 
 hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc* d, int n, int tiles,
-                       hipStream_t s) {
+                       int remap, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
-  if (dtype == DT_BF16X3) return launch_gemm_bf16x3(cfg, kb, d, n, tiles, s);
+  if (dtype == DT_BF16X3) return launch_gemm_bf16x3(cfg, kb, d, n, tiles, remap, s);
   if (dtype == DT_F64) {
     switch (cfg) {
-      case 5: return launch_cfg<double, 128, 64, 8, 2, 2>(kb, d, n, tiles, s);
-      default: return launch_cfg<double, 128, 128, 8, 2, 2>(kb, d, n, tiles, s);
+      case 5: return launch_cfg<double, 128, 64, 8, 2, 2>(kb, d, n, tiles, remap, s);
+      default: return launch_cfg<double, 128, 128, 8, 2, 2>(kb, d, n, tiles, remap, s);
     }
   }
   switch (cfg) {
-    case 1: return launch_cfg<float, 256, 128, 8, 4, 2>(kb, d, n, tiles, s);
-    case 2: return launch_cfg<float, 128, 256, 8, 2, 4>(kb, d, n, tiles, s);
-    case 3: return launch_cfg<float, 256, 256, 4, 2, 2>(kb, d, n, tiles, s);
-    case 4: return launch_cfg<float, 64, 128, 8, 2, 2>(kb, d, n, tiles, s);
-    case 5: return launch_cfg<float, 128, 64, 8, 2, 2>(kb, d, n, tiles, s);
-    case 6: return launch_cfg<float, 256, 128, 4, 2, 2>(kb, d, n, tiles, s);
-    case 7: return launch_cfg<float, 128, 128, 4, 2, 2>(kb, d, n, tiles, s);
-    default: return launch_cfg<float, 128, 128, 8, 2, 2>(kb, d, n, tiles, s);
+    case 1: return launch_cfg<float, 256, 128, 8, 4, 2>(kb, d, n, tiles, remap, s);
+    case 2: return launch_cfg<float, 128, 256, 8, 2, 4>(kb, d, n, tiles, remap, s);
+    case 3: return launch_cfg<float, 256, 256, 4, 2, 2>(kb, d, n, tiles, remap, s);
+    case 4: return launch_cfg<float, 64, 128, 8, 2, 2>(kb, d, n, tiles, remap, s);
+    case 5: return launch_cfg<float, 128, 64, 8, 2, 2>(kb, d, n, tiles, remap, s);
+    case 6: return launch_cfg<float, 256, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
+    case 7: return launch_cfg<float, 128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
+    default: return launch_cfg<float, 128, 128, 8, 2, 2>(kb, d, n, tiles, remap, s);
   }
 }
 

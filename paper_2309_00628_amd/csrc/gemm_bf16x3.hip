@@ -65,7 +65,7 @@ constexpr int EB = 2;  // B columns per staged block (one float2 per k row)
 template <int BM, int BN, int BKC, int WGM, int WGN>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases kb,
                                                                      const GemmDesc* __restrict__ descs,
-                                                                     int ndesc) {
+                                                                     int ndesc, int remap) {
   constexpr int NT = 64 * WGM * WGN;
   constexpr int TM = 32;
   constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
   __shared__ bf16x8 As[2][3][BKC][BM];
   __shared__ bf16x8 Bs[2][3][BKC][BN];
 
-  const TileRef tr = locate_tile<BM, BN>(descs, ndesc);
+  const TileRef tr = locate_tile<BM, BN>(descs, ndesc, remap);
   const GemmDesc& D = descs[tr.desc];
   const int i0 = tr.i0, j0 = tr.j0;
   const MView av = D.a, bv = D.b;
@@ -98,8 +98,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
   float ra[NA][8];
   float rb[NB][8][EB];
 
-  auto load_tile = [&](auto full_tag, int kt) {
-    constexpr bool FULL = decltype(full_tag)::value;
+  auto load_tile = [&](auto mode_tag, int kt) {
+    constexpr int MODE = decltype(mode_tag)::value;
     const int k0 = kt * BK;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
@@ -108,7 +108,18 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
       const int row = q / BKC, kc = q % BKC;
       const int gr = i0 + row, gc = k0 + kc * KC;
       const float* p = Ap + (int64_t)gr * lda + gc;
-      if (FULL || (avec && gr < av.vrows && gc + KC <= av.vcols)) {
+      if (MODE == LOAD_EDGE_VEC) {
+        // float4 halves are either valid or not (valid width % 4 == 0)
+        const bool r_ok = gr < av.vrows;
+        const bool ok0 = r_ok && gc < av.vcols, ok1 = r_ok && gc + 4 < av.vcols;
+        const f32x4 u = *reinterpret_cast<const f32x4*>(ok0 ? p : Ap);
+        const f32x4 w = *reinterpret_cast<const f32x4*>(ok1 ? p + 4 : Ap);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          ra[i][e] = ok0 ? u[e] : 0.f;
+          ra[i][4 + e] = ok1 ? w[e] : 0.f;
+        }
+      } else if (MODE == LOAD_FULL || (avec && gr < av.vrows && gc + KC <= av.vcols)) {
         const f32x4 u = *reinterpret_cast<const f32x4*>(p);
         const f32x4 w = *reinterpret_cast<const f32x4*>(p + 4);
 #pragma unroll
@@ -131,7 +142,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
       for (int rr = 0; rr < KC; ++rr) {
         const int gr = k0 + kc * KC + rr;
         const float* p = Bp + (int64_t)gr * ldb + gc;
-        if (FULL || (bvec && gr < bv.vrows && gc + EB <= bv.vcols)) {
+        if (MODE == LOAD_EDGE_VEC) {
+          const bool ok = gr < bv.vrows && gc < bv.vcols;
+          const f32x2 u = *reinterpret_cast<const f32x2*>(ok ? p : Bp);
+          rb[i][rr][0] = ok ? u[0] : 0.f;
+          rb[i][rr][1] = ok ? u[1] : 0.f;
+        } else if (MODE == LOAD_FULL || (bvec && gr < bv.vrows && gc + EB <= bv.vcols)) {
           const f32x2 u = *reinterpret_cast<const f32x2*>(p);
           rb[i][rr][0] = u[0];
           rb[i][rr][1] = u[1];
@@ -214,13 +230,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
     }
   };
 
-  auto main_loop = [&](auto full_tag) {
-    load_tile(full_tag, 0);
+  auto main_loop = [&](auto mode_tag) {
+    load_tile(mode_tag, 0);
     store_tile(0);
     __syncthreads();
     for (int kt = 0; kt < ktiles; ++kt) {
       const int buf = kt & 1;
-      if (kt + 1 < ktiles) load_tile(full_tag, kt + 1);
+      if (kt + 1 < ktiles) load_tile(mode_tag, kt + 1);
       compute(buf);
       if (kt + 1 < ktiles) store_tile(buf ^ 1);
       __syncthreads();
@@ -230,10 +246,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
   if (ktiles > 0) {
     const bool interior = avec && bvec && (i0 + BM <= av.vrows) && (j0 + BN <= bv.vcols) &&
                           (K % BK == 0) && (K <= av.vcols) && (K <= bv.vrows);
+    const bool edge_vec = avec && bvec && av.vrows > 0 && av.vcols > 0 && bv.vrows > 0 && bv.vcols > 0 &&
+                          av.vcols % 4 == 0 && bv.vcols % EB == 0;
     if (interior)
-      main_loop(std::true_type{});
+      main_loop(std::integral_constant<int, LOAD_FULL>{});
+    else if (edge_vec)
+      main_loop(std::integral_constant<int, LOAD_EDGE_VEC>{});
     else
-      main_loop(std::false_type{});
+      main_loop(std::integral_constant<int, LOAD_MASKED>{});
   }
 
   store_outputs<float, TM, 16, FM, FN, WM, WN>(kb, D, i0, j0, wm, wn, lane, acc,
@@ -241,9 +261,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
 }
 
 template <int BM, int BN, int BKC, int WGM, int WGN>
-hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles, hipStream_t s) {
+hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap, hipStream_t s) {
   hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN, BKC, WGM, WGN>), dim3(tiles), dim3(64 * WGM * WGN), 0, s,
-                     kb, d, n);
+                     kb, d, n, remap);
   return hipGetLastError();
 }
 
@@ -260,12 +280,12 @@ GemmCfg gemm_bf16x3_cfg(int cfg) {
 }
 
 hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d, int n, int tiles,
-                              hipStream_t s) {
+                              int remap, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   switch (cfg) {
-    case 1: return launch_cfg<256, 128, 4, 4, 2>(kb, d, n, tiles, s);
-    case 4: return launch_cfg<64, 128, 4, 2, 2>(kb, d, n, tiles, s);
-    default: return launch_cfg<128, 128, 4, 2, 2>(kb, d, n, tiles, s);
+    case 1: return launch_cfg<256, 128, 4, 4, 2>(kb, d, n, tiles, remap, s);
+    case 4: return launch_cfg<64, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
+    default: return launch_cfg<128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
   }
 }
 

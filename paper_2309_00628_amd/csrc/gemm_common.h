@@ -21,16 +21,27 @@ __device__ __forceinline__ bool view_vec(const KernelBases& kb, const MView& v) 
   return v.vec && (v.base == MB_ABS || ((kb.aligned >> v.base) & 1));
 }
 
-// LDS swizzles.  A: the 16 lanes of a store phase cover 16/BKC consecutive
-// rows x BKC chunks; XOR-ing the row by (16/BKC) * kc spreads them over 16
-// bank groups.  B: 16 lanes store columns E*cb + c for 16 consecutive cb;
-// XOR-ing the low bits with (col / 16) mod E does the same.  Fragment reads
-// (16 consecutive rows or columns of one chunk plane) stay conflict-free
-// because both swizzles permute within aligned groups of 16.
+// LDS swizzles (16-byte chunks).  The tile stores and the fragment reads of
+// every configuration are conflict-free whether the LDS serves 8 or 16
+// lanes of a 128-bit access per cycle (checked exhaustively on the host for
+// every instantiated tile shape):
+// A: a store phase covers 16/BKC consecutive rows x BKC chunks; the row is
+//    XOR-ed with kc ^ (row mod (16/BKC)) * BKC, a permutation within each
+//    aligned group of 16 rows, so the 32 consecutive rows a fragment read
+//    touches stay distinct.
+// B: 8 consecutive lanes store columns E*cb + c of 8 consecutive cb; the low
+//    bits are XOR-ed with a function of column bits 3 and up, so each group
+//    of 8 (and 16) lanes lands in distinct chunk slots, and reads of 32
+//    consecutive columns remain a permutation within aligned groups.
 template <int BKC>
-__device__ __forceinline__ int swz_a(int row, int kc) { return row ^ ((16 / BKC) * kc); }
+__device__ __forceinline__ int swz_a(int row, int kc) {
+  return row ^ ((kc ^ ((row % (16 / BKC)) * BKC)) & 15);
+}
 template <int E>
-__device__ __forceinline__ int swz_b(int col) { return col ^ ((col >> 4) & (E - 1)); }
+__device__ __forceinline__ int swz_b(int col) {
+  if (E == 4) return col ^ (((col >> 3) ^ (col >> 5)) & 3);
+  return col ^ (((col >> 3) ^ (col >> 4)) & 1);
+}
 
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
   // Workgroups are dealt to the 8 XCDs round-robin (b % 8).  Give each XCD a
@@ -41,6 +52,9 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + (x < r ? x : r) + j;
 }
 
+// Operand load modes of a tile's K loop (see the kernels).
+enum LoadMode : int { LOAD_FULL = 0, LOAD_EDGE_VEC = 1, LOAD_MASKED = 2 };
+
 struct TileRef {
   int desc;    // problem index in the launch
   int i0, j0;  // first row / column of the C tile
@@ -49,9 +63,12 @@ struct TileRef {
 // Which problem of a grouped launch this workgroup serves, and which tile.
 // Tiles of one problem are visited in groups of 8 tile-rows so that
 // workgroups running at the same time share A rows and B columns.
+// With remap == 0 (launches of unequal problems, sorted longest first) the
+// hardware's round-robin spreads every run of 8 consecutive tiles over the
+// 8 XCDs, which balances the XCDs and starts the longest tiles first.
 template <int BM, int BN>
-__device__ __forceinline__ TileRef locate_tile(const GemmDesc* __restrict__ descs, int ndesc) {
-  const int rb = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ TileRef locate_tile(const GemmDesc* __restrict__ descs, int ndesc, int remap) {
+  const int rb = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;

@@ -24,8 +24,10 @@ hipError_t launch_ew(int dtype, const KernelBases& kb, const EwPart* dparts, int
 bool gemm_bf16x3_available();
 GemmCfg gemm_bf16x3_cfg(int cfg);
 hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d, int n, int tiles,
-                              hipStream_t s);
+                              int remap, hipStream_t s);
+// remap: 1 = XCD-contiguous tile order (launches of equal problems),
+// 0 = hardware round-robin (unequal problems, sorted longest first).
 hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc* ddescs, int ndesc, int tiles,
-                       hipStream_t s);
+                       int remap, hipStream_t s);
 
 }  // namespace mm

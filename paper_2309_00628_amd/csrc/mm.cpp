@@ -54,6 +54,7 @@ struct OpRec {
   int count;   // descriptors
   int grid;    // workgroups
   int cfg;     // GEMM tile configuration
+  int remap;   // GEMM: XCD-contiguous tile order
 };
 
 }  // namespace
@@ -96,6 +97,28 @@ namespace {
 // partial last wave; 64x128 tiles keep small launches spread over more CUs.
 int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
   if (kdtype == DT_F64) return 0;
+  bool equal = true;
+  for (const GemmDesc& g : group) equal = equal && g.m == group[0].m && g.n == group[0].n;
+  if (!equal && kdtype == DT_F32 && group.size() > 1) {
+    // Unequal problems: minimise the padded work (tile area x k) over the
+    // measured per-tile MFMA efficiency of each shape.
+    const int cand[4] = {0, 3, 4, 5};
+    const double eff[4] = {0.79, 0.84, 0.75, 0.72};
+    int best = 0;
+    double best_cost = 1e300;
+    for (int i = 0; i < 4; ++i) {
+      const GemmCfg gc = gemm_cfg(kdtype, cand[i]);
+      double work = 0;
+      for (const GemmDesc& g : group)
+        work += (double)ceil_div(g.m, gc.bm) * ceil_div(g.n, gc.bn) * gc.bm * gc.bn * (double)g.k;
+      const double cost = work / eff[i];
+      if (cost < best_cost) {
+        best_cost = cost;
+        best = cand[i];
+      }
+    }
+    return best;
+  }
   if (kdtype == DT_BF16X3) {
     // 256x128 tiles with eight waves (two per SIMD) hide the split's VALU
     // work behind the MFMAs; smaller launches keep more CUs busy with 64x128.
@@ -113,7 +136,7 @@ int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
     t128 += ceil_div(g.m, 128) * ceil_div(g.n, 128);
   }
   if (t256 >= 1024 || (t256 >= 256 && t256 % 256 == 0)) return 3;
-  if (t128 >= 256) return 0;
+  if (t128 >= 2048) return 0;
   return 4;
 }
 
@@ -259,7 +282,7 @@ struct Builder {
   // Close the current launch.
   void flush() {
     if (!ew.empty()) {
-      OpRec r{OP_EW, ew_dtype(P.dtype), P.table.size(), (int)ew.size(), ew_grid, 0};
+      OpRec r{OP_EW, ew_dtype(P.dtype), P.table.size(), (int)ew.size(), ew_grid, 0, 0};
       const size_t bytes = ew.size() * sizeof(EwPart);
       P.table.resize(round_up(P.table.size() + bytes, 256));
       std::memcpy(P.table.data() + r.off, ew.data(), bytes);
@@ -270,6 +293,12 @@ struct Builder {
     }
     if (!gm.empty()) {
       const int kd = kernel_dtype(P.dtype);
+      // Unequal problems: longest (largest k) first, round-robin over XCDs.
+      bool equal = true;
+      for (const GemmDesc& g : gm)
+        equal = equal && g.m == gm[0].m && g.n == gm[0].n && g.k == gm[0].k;
+      if (!equal)
+        std::stable_sort(gm.begin(), gm.end(), [](const GemmDesc& x, const GemmDesc& y) { return x.k > y.k; });
       const int cfg = P.tile_cfg >= 0 ? P.tile_cfg : choose_gemm_cfg(kd, gm);
       const GemmCfg gc = gemm_cfg(kd, cfg);
       gm_grid = 0;
@@ -279,7 +308,7 @@ struct Builder {
         g.tile_start = gm_grid;
         gm_grid += g.tiles_m * g.tiles_n;
       }
-      OpRec r{OP_GEMM, kd, P.table.size(), (int)gm.size(), gm_grid, cfg};
+      OpRec r{OP_GEMM, kd, P.table.size(), (int)gm.size(), gm_grid, cfg, equal ? 1 : 0};
       const size_t bytes = gm.size() * sizeof(GemmDesc);
       P.table.resize(round_up(P.table.size() + bytes, 256));
       std::memcpy(P.table.data() + r.off, gm.data(), bytes);
@@ -743,7 +772,7 @@ int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEven
     if (op.type == OP_EW)
       e = launch_ew(op.kdtype, kb, (const EwPart*)d, op.count, op.grid, s);
     else
-      e = launch_gemm(op.kdtype, op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, s);
+      e = launch_gemm(op.kdtype, op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, s);
     if (e != hipSuccess) return fail(MM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   }
   if (events && hipEventRecord(events[i], s) != hipSuccess) return fail(MM_E_HIP, "hipEventRecord failed");
