@@ -148,6 +148,10 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
 /* Flags for mm_plan_create. */
 #define MM_PLAN_GRAPH 1u /* capture the launch sequence in a hipGraph per distinct
                             (A, B, C, workspace) address tuple and replay it */
+#define MM_PLAN_FUSE 2u /* form the last level's S/T sums in the leaf GEMM's tile loader instead
+                          of a separate pre-addition pass (float32, grouped schedule; results
+                          are bitwise the same).  Off by default: on MI355X it doubles the
+                          operand traffic into the CUs and measures slower. */
 /* Force the MFMA GEMM tile configuration c (0 .. 7) for every leaf launch
  * instead of the planner's choice.  float32: 0 128x128 (BK 32), 1 256x128,
  * 2 128x256, 3 256x256 (BK 16), 4 64x128, 5 128x64, 6 256x128 (BK 16),
@@ -179,7 +183,8 @@ int mm_plan_op_kind(mm_plan_t plan, int i);
 
 /* Plan facts: info[0] workspace bytes, [1] levels L, [2..4] padded m, n, k,
  * [5] kernel launches per execution, [6] leaf products, [7] schedule used,
- * [8] leaf edge (rows of a leaf block).  Returns the number of entries written. */
+ * [8] leaf edge (rows of a leaf block), [9] 1 if the last level's operand
+ * sums are formed in the leaf loader.  Returns the number of entries written. */
 int mm_plan_info(mm_plan_t plan, int64_t* info, int ninfo);
 
 /* Human-readable listing of the launch sequence (one line per block
@@ -209,14 +214,14 @@ int mm_batched(int count, const int64_t* mnk, void* const* A, void* const* B, vo
 
 /* ---- diagnostics ------------------------------------------------------ */
 
-/* Host-only: build the plan mm_plan_create would build, without touching a
- * device, and return its listing as mm_plan_describe does (and its facts as
+/* Host-only: build the plan mm_plan_create would build (same flags),
+ * without touching a device, and return its listing as mm_plan_describe does (and its facts as
  * mm_plan_info does, when info is not NULL).  Returns 0 when the arguments
  * are rejected (see mm_last_error).  Lets the launch sequence be inspected
  * and checked on a machine with no GPU. */
 size_t mm_describe(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb,
-                   int64_t ldc, int cutoff, int levels, int dtype, char* buf, size_t len, int64_t* info,
-                   int ninfo);
+                   int64_t ldc, int cutoff, int levels, int dtype, unsigned flags, char* buf, size_t len,
+                   int64_t* info, int ninfo);
 
 /* Host-only counterpart for mm_batched_plan_create.  The addresses are only
  * recorded (never dereferenced), so any values may be passed. */

@@ -21,6 +21,7 @@ MM_F64, MM_F32, MM_BF16X3_REFINED = 0, 1, 2
 MM_ALGO_NAIVE, MM_ALGO_STRASSEN, MM_ALGO_WINOGRAD = 0, 1, 2
 MM_SCHED_TWO_TEMP, MM_SCHED_IN_PLACE, MM_SCHED_GROUPED, MM_SCHED_DFS3, MM_SCHED_AUTO = 0, 1, 2, 3, 4
 MM_PLAN_GRAPH = 1
+MM_PLAN_FUSE = 2
 
 
 def plan_tile(c):
@@ -75,7 +76,7 @@ _SIGS = {
     "mm_batched": (c_int, [c_int, c_i64p, c_vpp, c_vpp, c_vpp, c_int, c_intp, c_intp, c_vp, c_sz,
                            c_vp]),
     "mm_describe": (c_sz, [c_int, c_int, c_i64, c_i64, c_i64, c_i64, c_i64, c_i64, c_int, c_int,
-                           c_int, ctypes.c_char_p, c_sz, c_i64p, c_int]),
+                           c_int, ctypes.c_uint, ctypes.c_char_p, c_sz, c_i64p, c_int]),
     "mm_batched_describe": (c_sz, [c_int, c_i64p, c_vpp, c_vpp, c_vpp, c_int, c_intp, c_intp,
                                    ctypes.c_char_p, c_sz, c_i64p, c_int]),
     "mm_last_error": (ctypes.c_char_p, []),
@@ -113,20 +114,21 @@ def check(status):
     return status
 
 
-def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None, ldc=None):
+def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None, ldc=None,
+             fuse=False):
     """Host-only plan listing and facts (no device needed)."""
     lib = load()
     lda = max(k, 1) if lda is None else lda
     ldb = max(n, 1) if ldb is None else ldb
     ldc = max(n, 1) if ldc is None else ldc
-    info = (ctypes.c_int64 * 9)()
+    info = (ctypes.c_int64 * 10)()
     args = (ALGOS.get(algo, algo), SCHEDS.get(sched, sched), m, n, k, lda, ldb, ldc, cutoff, levels,
-            DTYPES.get(dtype, dtype))
-    need = lib.mm_describe(*args, None, 0, info, 9)
+            DTYPES.get(dtype, dtype), MM_PLAN_FUSE if fuse else 0)
+    need = lib.mm_describe(*args, None, 0, info, 10)
     if need == 0:
         raise MMError(1, last_error())
     buf = ctypes.create_string_buffer(need + 1)
-    lib.mm_describe(*args, buf, need + 1, info, 9)
+    lib.mm_describe(*args, buf, need + 1, info, 10)
     return buf.value.decode(), _info_dict(info)
 
 
@@ -140,18 +142,18 @@ def batched_describe(mnk, addrs, dtype="f32", cutoff=None, levels=None):
     C = (c_vp * cnt)(*[c for _, _, c in addrs])
     cp = (c_int * cnt)(*cutoff) if cutoff is not None else None
     lp = (c_int * cnt)(*levels) if levels is not None else None
-    info = (ctypes.c_int64 * 9)()
+    info = (ctypes.c_int64 * 10)()
     need = lib.mm_batched_describe(cnt, flat, A, B, C, DTYPES.get(dtype, dtype), cp, lp, None, 0,
-                                   info, 9)
+                                   info, 10)
     if need == 0:
         raise MMError(1, last_error())
     buf = ctypes.create_string_buffer(need + 1)
     lib.mm_batched_describe(cnt, flat, A, B, C, DTYPES.get(dtype, dtype), cp, lp, buf, need + 1,
-                            info, 9)
+                            info, 10)
     return buf.value.decode(), _info_dict(info)
 
 
-INFO_KEYS = ("ws_bytes", "levels", "M", "N", "K", "launches", "leaves", "sched", "leaf_rows")
+INFO_KEYS = ("ws_bytes", "levels", "M", "N", "K", "launches", "leaves", "sched", "leaf_rows", "fused")
 
 
 def _info_dict(info):

@@ -48,7 +48,7 @@ class Plan:
     """A built launch sequence for one product shape (mm_plan_create)."""
 
     def __init__(self, algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None,
-                 ldc=None, graph=False, device=None, tile=None):
+                 ldc=None, graph=False, device=None, tile=None, fuse=False):
         lib = L.load()
         self.algo, self.sched, self.dtype = algo, sched, dtype
         self.m, self.n, self.k = m, n, k
@@ -61,10 +61,10 @@ class Plan:
         with torch.cuda.device(self.device):
             L.check(lib.mm_plan_create(L.ALGOS[algo], L.SCHEDS[sched], m, n, k, self.lda, self.ldb,
                                        self.ldc, cutoff, levels, L.DTYPES[dtype],
-                                       (L.MM_PLAN_GRAPH if graph else 0) | L.plan_tile(tile),
-                                       ctypes.byref(self._ptr)))
-        info = (ctypes.c_int64 * 9)()
-        lib.mm_plan_info(self._ptr, info, 9)
+                                       (L.MM_PLAN_GRAPH if graph else 0) | L.plan_tile(tile) |
+                                       (L.MM_PLAN_FUSE if fuse else 0), ctypes.byref(self._ptr)))
+        info = (ctypes.c_int64 * 10)()
+        lib.mm_plan_info(self._ptr, info, 10)
         self.info = L._info_dict(info)
         self.ws_bytes = self.info["ws_bytes"]
 
@@ -111,18 +111,19 @@ def workspace(nbytes, device, stream):
     return cur
 
 
-def get_plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile=None):
-    key = (str(device), algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, tile)
+def get_plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile=None,
+             fuse=False):
+    key = (str(device), algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, tile, fuse)
     with _plans_lock:
         p = _plans.get(key)
         if p is None:
-            p = Plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile)
+            p = Plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile, fuse)
             _plans[key] = p
     return p
 
 
 def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None, out=None,
-       graph=False, stream=None, clobber_inputs=False, tile=None):
+       graph=False, stream=None, clobber_inputs=False, tile=None, fuse=False):
     """C = A @ B on the GPU by ``algo`` in {"naive", "strassen", "winograd"}.
 
     ``cutoff`` / ``levels`` control the recursion as in mm.h; when both are
@@ -168,7 +169,7 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
         cutoff = 1
     elif levels is None:
         levels = -1
-    p = get_plan(algo, sched, m, n, k, cutoff, levels, dt, lda, ldb, ldc, graph, A.device, tile)
+    p = get_plan(algo, sched, m, n, k, cutoff, levels, dt, lda, ldb, ldc, graph, A.device, tile, fuse)
     with torch.cuda.device(A.device):
         p(A, B, C, stream=stream)
     return C
@@ -208,8 +209,8 @@ class BatchedPlan:
             L.check(lib.mm_batched_plan_create(cnt, flat, Ap, Bp, Cp, L.DTYPES[dt], cp, lp,
                                                (L.MM_PLAN_GRAPH if graph else 0) | L.plan_tile(tile),
                                                ctypes.byref(self._ptr)))
-        info = (ctypes.c_int64 * 9)()
-        lib.mm_plan_info(self._ptr, info, 9)
+        info = (ctypes.c_int64 * 10)()
+        lib.mm_plan_info(self._ptr, info, 10)
         self.info = L._info_dict(info)
         self.ws_bytes = self.info["ws_bytes"]
         self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)

@@ -67,13 +67,22 @@ struct GemmOut {
   int32_t sign;  // +1 or -1
 };
 
+// Operand kinds of a leaf product.  OK_PLAIN: the view is the operand.
+// OK_S1..OK_S4 / OK_T1..OK_T4: the view is the parent block and the operand
+// is the Winograd sum S_i of its A quadrants / T_i of its B quadrants
+// (Section 2.3), formed while the tile is staged (fused loader).
+enum OperandKind : int32_t {
+  OK_PLAIN = 0, OK_S1 = 1, OK_S2 = 2, OK_S3 = 3, OK_S4 = 4,
+  OK_T1 = 5, OK_T2 = 6, OK_T3 = 7, OK_T4 = 8
+};
+
 struct GemmDesc {
   MView a, b;
-  int32_t m, n, k;
+  int32_t m, n, k;     // operand extents: A operand m x k, B operand k x n
   int32_t tiles_m, tiles_n;
   int32_t tile_start;  // first tile of this problem in the launch
   int32_t nout;
-  int32_t pad_;
+  int32_t kinds;       // OperandKind of A (bits 0-7) and of B (bits 8-15)
   GemmOut out[2];
 };
 

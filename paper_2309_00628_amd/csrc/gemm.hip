@@ -128,6 +128,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
   // ---- global -> register staging ----------------------------------------
   chunk_t ra[NA];
   chunk_t rbk[NB][E];  // E rows (k) of E columns
+  // LOAD_EDGE_VEC validity of each staged chunk, applied when the stage is
+  // written to LDS (not right after the load, which would wait for it)
+  uint32_t amask = 0, bmask = 0;
 
   // LOAD_FULL: the whole stage is inside both operands' valid extents and
   // every access is a 16-byte vector load (no masks, no branches, so the
@@ -149,10 +152,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
         ra[i] = *reinterpret_cast<const chunk_t*>(p);
       } else if (MODE == LOAD_EDGE_VEC) {
         // whole chunks are either valid or not: load from a valid address
-        // and select zero, so the loop has no data-dependent branches
+        // and zero the invalid ones when storing, so the loop has no
+        // data-dependent branches
         const bool ok = gr < av.vrows && gc < av.vcols;
-        const chunk_t v = *reinterpret_cast<const chunk_t*>(ok ? p : Ap);
-        ra[i] = ok ? v : chunk_t{};
+        ra[i] = *reinterpret_cast<const chunk_t*>(ok ? p : Ap);
+        amask = ok ? (amask | (1u << i)) : (amask & ~(1u << i));
       } else if (avec && gr < av.vrows && gc + E <= av.vcols) {
         ra[i] = *reinterpret_cast<const chunk_t*>(p);
       } else {
@@ -175,8 +179,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
           rbk[i][rr] = *reinterpret_cast<const chunk_t*>(p);
         } else if (MODE == LOAD_EDGE_VEC) {
           const bool ok = gr < bv.vrows && gc < bv.vcols;
-          const chunk_t v = *reinterpret_cast<const chunk_t*>(ok ? p : Bp);
-          rbk[i][rr] = ok ? v : chunk_t{};
+          rbk[i][rr] = *reinterpret_cast<const chunk_t*>(ok ? p : Bp);
+          const uint32_t bit = 1u << (i * E + rr);
+          bmask = ok ? (bmask | bit) : (bmask & ~bit);
         } else if (bvec && gr < bv.vrows && gc + E <= bv.vcols) {
           rbk[i][rr] = *reinterpret_cast<const chunk_t*>(p);
         } else {
@@ -188,13 +193,15 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
     }
   };
 
-  auto store_tile = [&](int buf) {
+  auto store_tile = [&](auto mode_tag, int buf) {
+    constexpr int MODE = decltype(mode_tag)::value;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int q = tid + NT * i;
       if (NCH_A % NT != 0 && q >= NCH_A) break;
       const int row = q / BKC, kc = q % BKC;
-      As[buf][kc][swz_a<BKC>(row, kc)] = ra[i];
+      As[buf][kc][swz_a<BKC>(row, kc)] =
+          (MODE != LOAD_EDGE_VEC || ((amask >> i) & 1)) ? ra[i] : chunk_t{};
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -205,7 +212,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
       for (int c = 0; c < E; ++c) {
         chunk_t t;
 #pragma unroll
-        for (int rr = 0; rr < E; ++rr) t[rr] = rbk[i][rr][c];
+        for (int rr = 0; rr < E; ++rr)
+          t[rr] = (MODE != LOAD_EDGE_VEC || ((bmask >> (i * E + rr)) & 1)) ? rbk[i][rr][c] : T(0);
         Bs[buf][kc][swz_b<E>(cb * E + c)] = t;
       }
     }
@@ -221,33 +229,52 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
 
   const int g = lane / TM, t = lane % TM;
 
-  auto compute = [&](int buf) {
-#pragma unroll
-    for (int kb2 = 0; kb2 < BKC / M::KG; ++kb2) {
+  // MFMAs of k-blocks [kb_lo, kb_hi) of one LDS stage (a k-block is 8 k
+  // values).  The fragments of k-block j+1 are read into a second register
+  // set while the MFMAs of k-block j run.
+  auto compute = [&](int buf, auto lo_tag, auto hi_tag) {
+    constexpr int KLO = decltype(lo_tag)::value, KHI = decltype(hi_tag)::value;
+    chunk_t fa[2][FM], fb[2][FN];
+    auto read_frags = [&](int kb2, chunk_t (&xa)[FM], chunk_t (&xb)[FN]) {
       const int plane = kb2 * M::KG + g;
-      chunk_t fa[FM], fb[FN];
 #pragma unroll
-      for (int a = 0; a < FM; ++a) fa[a] = As[buf][plane][swz_a<BKC>(wm * WM + a * TM + t, plane)];
+      for (int a = 0; a < FM; ++a) xa[a] = As[buf][plane][swz_a<BKC>(wm * WM + a * TM + t, plane)];
 #pragma unroll
-      for (int b = 0; b < FN; ++b) fb[b] = Bs[buf][plane][swz_b<E>(wn * WN + b * TM + t)];
+      for (int b = 0; b < FN; ++b) xb[b] = Bs[buf][plane][swz_b<E>(wn * WN + b * TM + t)];
+    };
+    read_frags(KLO, fa[0], fb[0]);
+#pragma unroll
+    for (int kb2 = KLO; kb2 < KHI; ++kb2) {
+      const int cur = (kb2 - KLO) & 1;
+      if (kb2 + 1 < KHI) read_frags(kb2 + 1, fa[cur ^ 1], fb[cur ^ 1]);
 #pragma unroll
       for (int s = 0; s < E; ++s)
 #pragma unroll
         for (int a = 0; a < FM; ++a)
 #pragma unroll
-          for (int b = 0; b < FN; ++b) acc[a][b] = M::mfma(fa[a][s], fb[b][s], acc[a][b]);
+          for (int b = 0; b < FN; ++b) acc[a][b] = M::mfma(fa[cur][a][s], fb[cur][b][s], acc[a][b]);
     }
   };
+  constexpr int KB = BKC / M::KG;
+  constexpr int KMID = KB / 2;
 
+  // Pipeline: the global loads of stage t+1 are issued first; the stage is
+  // written to the other LDS buffer halfway through the MFMAs of stage t, so
+  // the wait for those loads and the LDS writes overlap the second half of
+  // the MFMAs; one barrier ends the stage.  Writing the other buffer is safe:
+  // every wave finished reading it before the barrier that ended stage t-1,
+  // and it is read again only after the barrier that ends stage t.
   auto main_loop = [&](auto mode_tag) {
     load_tile(mode_tag, 0);
-    store_tile(0);
+    store_tile(mode_tag, 0);
     __syncthreads();
     for (int kt = 0; kt < ktiles; ++kt) {
       const int buf = kt & 1;
-      if (kt + 1 < ktiles) load_tile(mode_tag, kt + 1);
-      compute(buf);
-      if (kt + 1 < ktiles) store_tile(buf ^ 1);
+      const bool more = kt + 1 < ktiles;
+      if (more) load_tile(mode_tag, kt + 1);
+      compute(buf, std::integral_constant<int, 0>{}, std::integral_constant<int, KMID>{});
+      if (more) store_tile(mode_tag, buf ^ 1);
+      compute(buf, std::integral_constant<int, KMID>{}, std::integral_constant<int, KB>{});
       __syncthreads();
     }
   };

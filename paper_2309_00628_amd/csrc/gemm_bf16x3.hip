@@ -97,6 +97,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
 
   float ra[NA][8];
   float rb[NB][8][EB];
+  // LOAD_EDGE_VEC validity, applied when the stage is split into LDS
+  uint32_t amask = 0, bmask = 0;
 
   auto load_tile = [&](auto mode_tag, int kt) {
     constexpr int MODE = decltype(mode_tag)::value;
@@ -116,9 +118,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
         const f32x4 w = *reinterpret_cast<const f32x4*>(ok1 ? p + 4 : Ap);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          ra[i][e] = ok0 ? u[e] : 0.f;
-          ra[i][4 + e] = ok1 ? w[e] : 0.f;
+          ra[i][e] = u[e];
+          ra[i][4 + e] = w[e];
         }
+        const uint32_t b0 = 1u << (2 * i), b1 = 1u << (2 * i + 1);
+        amask = ok0 ? (amask | b0) : (amask & ~b0);
+        amask = ok1 ? (amask | b1) : (amask & ~b1);
       } else if (MODE == LOAD_FULL || (avec && gr < av.vrows && gc + KC <= av.vcols)) {
         const f32x4 u = *reinterpret_cast<const f32x4*>(p);
         const f32x4 w = *reinterpret_cast<const f32x4*>(p + 4);
@@ -145,8 +150,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
         if (MODE == LOAD_EDGE_VEC) {
           const bool ok = gr < bv.vrows && gc < bv.vcols;
           const f32x2 u = *reinterpret_cast<const f32x2*>(ok ? p : Bp);
-          rb[i][rr][0] = ok ? u[0] : 0.f;
-          rb[i][rr][1] = ok ? u[1] : 0.f;
+          rb[i][rr][0] = u[0];
+          rb[i][rr][1] = u[1];
+          const uint32_t bit = 1u << (i * KC + rr);
+          bmask = ok ? (bmask | bit) : (bmask & ~bit);
         } else if (MODE == LOAD_FULL || (bvec && gr < bv.vrows && gc + EB <= bv.vcols)) {
           const f32x2 u = *reinterpret_cast<const f32x2*>(p);
           rb[i][rr][0] = u[0];
@@ -159,12 +166,18 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
     }
   };
 
-  auto store_tile = [&](int buf) {
+  auto store_tile = [&](auto mode_tag, int buf) {
+    constexpr int MODE = decltype(mode_tag)::value;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int q = tid + NT * i;
       if (NCH_A % NT != 0 && q >= NCH_A) break;
       const int row = q / BKC, kc = q % BKC;
+      if (MODE == LOAD_EDGE_VEC) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (!((amask >> (2 * i + e / 4)) & 1)) ra[i][e] = 0.f;
+      }
       bf16x8 h, l, r;
       split8(ra[i], h, l, r);
       const int sr = swz_a<BKC>(row, kc);
@@ -181,7 +194,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
       for (int c = 0; c < EB; ++c) {
         float col[8];
 #pragma unroll
-        for (int rr = 0; rr < KC; ++rr) col[rr] = rb[i][rr][c];
+        for (int rr = 0; rr < KC; ++rr)
+          col[rr] = (MODE != LOAD_EDGE_VEC || ((bmask >> (i * KC + rr)) & 1)) ? rb[i][rr][c] : 0.f;
         bf16x8 h, l, r;
         split8(col, h, l, r);
         const int sc = swz_b<EB>(cb * EB + c);
@@ -202,9 +216,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
 
   const int g = lane / TM, t = lane % TM;
 
-  auto compute = [&](int buf) {
+  auto compute = [&](int buf, int ks_lo, int ks_hi) {
 #pragma unroll
-    for (int ks = 0; ks < BKC / 2; ++ks) {
+    for (int ks = ks_lo; ks < ks_hi; ++ks) {
       const int plane = 2 * ks + g;
       bf16x8 fa[3][FM], fb[3][FN];
 #pragma unroll
@@ -230,15 +244,20 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
     }
   };
 
+  // As in the float32 kernel: the next stage is split into the other LDS
+  // buffer halfway through this stage's MFMAs (safe with two buffers: it was
+  // last read before the previous barrier and is read after the next one).
   auto main_loop = [&](auto mode_tag) {
     load_tile(mode_tag, 0);
-    store_tile(0);
+    store_tile(mode_tag, 0);
     __syncthreads();
     for (int kt = 0; kt < ktiles; ++kt) {
       const int buf = kt & 1;
-      if (kt + 1 < ktiles) load_tile(mode_tag, kt + 1);
-      compute(buf);
-      if (kt + 1 < ktiles) store_tile(buf ^ 1);
+      const bool more = kt + 1 < ktiles;
+      if (more) load_tile(mode_tag, kt + 1);
+      compute(buf, 0, BKC / 4);
+      if (more) store_tile(mode_tag, buf ^ 1);
+      compute(buf, BKC / 4, BKC / 2);
       __syncthreads();
     }
   };

@@ -25,6 +25,10 @@ bool gemm_bf16x3_available();
 GemmCfg gemm_bf16x3_cfg(int cfg);
 hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d, int n, int tiles,
                               int remap, hipStream_t s);
+// Float32 leaf products whose operands may be Winograd sums of parent
+// quadrants (GemmDesc::kinds); aligned, fully valid operands only.
+hipError_t launch_gemm_fused(int cfg, const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap,
+                             hipStream_t s);
 // remap: 1 = XCD-contiguous tile order (launches of equal problems),
 // 0 = hardware round-robin (unequal problems, sorted longest first).
 hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc* ddescs, int ndesc, int tiles,

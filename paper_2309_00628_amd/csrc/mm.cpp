@@ -55,6 +55,7 @@ struct OpRec {
   int grid;    // workgroups
   int cfg;     // GEMM tile configuration
   int remap;   // GEMM: XCD-contiguous tile order
+  int fused;   // GEMM: some operands are Winograd sums formed in the loader
 };
 
 }  // namespace
@@ -70,6 +71,10 @@ struct Plan {
   bool batched = false;
   unsigned flags = 0;
   int tile_cfg = -1;  // forced GEMM tile configuration, -1: planner's choice
+  bool fuse = false;  // fold the last level's S/T sums into the leaf loader
+  bool fused = false;          // the plan has leaf products with fused operands
+  bool fused_reads_ab = false;  // ... reading A or B directly (needs 16-byte aligned A, B)
+  std::unique_ptr<Plan> unfused;  // same product without fusion, for unaligned A or B
   std::vector<OpRec> ops;
   std::vector<uint8_t> table;
   std::string text;
@@ -151,6 +156,7 @@ struct Builder {
   std::vector<EwPart> ew;
   int ew_grid = 0;
   std::vector<GemmDesc> gm;
+  std::vector<char> gm_fusable;  // descriptor satisfies the fused loader's preconditions
   int gm_grid = 0;
   std::ostringstream txt;
 
@@ -245,15 +251,19 @@ struct Builder {
   static Out store(const MView& c, int sign = 1) { return Out{c, GM_STORE, sign, MView{}}; }
   static Out add(const MView& c, const MView& d, int sign) { return Out{c, GM_ADD, sign, d}; }
 
-  void gemm(const MView& a, const MView& b, std::initializer_list<Out> outs) {
+  // akind / bkind != OK_PLAIN: a / b is the parent block and the operand is
+  // the Winograd sum of its quadrants (formed in the loader).
+  void gemm(const MView& a, const MView& b, std::initializer_list<Out> outs, int akind = OK_PLAIN,
+            int bkind = OK_PLAIN, bool fusable = false) {
     if (!ew.empty()) flush();
     GemmDesc g;
     std::memset(&g, 0, sizeof g);
     g.a = a;
     g.b = b;
-    g.m = a.rows;
-    g.k = a.cols;
-    g.n = b.cols;
+    g.m = akind == OK_PLAIN ? a.rows : a.rows / 2;
+    g.k = akind == OK_PLAIN ? a.cols : a.cols / 2;
+    g.n = bkind == OK_PLAIN ? b.cols : b.cols / 2;
+    g.kinds = akind | (bkind << 8);
     g.nout = (int32_t)outs.size();
     int i = 0;
     for (const auto& o : outs) {
@@ -270,19 +280,15 @@ struct Builder {
       g.out[i].sign = 1;
     }
     P.leaves += 1;
-    txt << "GEMM " << g.m << " " << g.n << " " << g.k << " | " << vs(a) << " " << vs(b) << " |";
-    for (int j = 0; j < g.nout; ++j)
-      txt << " " << g.out[j].mode << ":" << g.out[j].sign << ":" << vs(g.out[j].c) << ":"
-          << vs(g.out[j].d);
-    txt << "\n";
     if (g.m == 0 || g.n == 0) return;
     gm.push_back(g);
+    gm_fusable.push_back(fusable ? 1 : 0);
   }
 
   // Close the current launch.
   void flush() {
     if (!ew.empty()) {
-      OpRec r{OP_EW, ew_dtype(P.dtype), P.table.size(), (int)ew.size(), ew_grid, 0, 0};
+      OpRec r{OP_EW, ew_dtype(P.dtype), P.table.size(), (int)ew.size(), ew_grid, 0, 0, 0};
       const size_t bytes = ew.size() * sizeof(EwPart);
       P.table.resize(round_up(P.table.size() + bytes, 256));
       std::memcpy(P.table.data() + r.off, ew.data(), bytes);
@@ -292,31 +298,61 @@ struct Builder {
       ew_grid = 0;
     }
     if (!gm.empty()) {
-      const int kd = kernel_dtype(P.dtype);
-      // Unequal problems: longest (largest k) first, round-robin over XCDs.
-      bool equal = true;
-      for (const GemmDesc& g : gm)
-        equal = equal && g.m == gm[0].m && g.n == gm[0].n && g.k == gm[0].k;
-      if (!equal)
-        std::stable_sort(gm.begin(), gm.end(), [](const GemmDesc& x, const GemmDesc& y) { return x.k > y.k; });
-      const int cfg = P.tile_cfg >= 0 ? P.tile_cfg : choose_gemm_cfg(kd, gm);
-      const GemmCfg gc = gemm_cfg(kd, cfg);
-      gm_grid = 0;
-      for (GemmDesc& g : gm) {
-        g.tiles_m = (int32_t)ceil_div(g.m, gc.bm);
-        g.tiles_n = (int32_t)ceil_div(g.n, gc.bn);
-        g.tile_start = gm_grid;
-        gm_grid += g.tiles_m * g.tiles_n;
+      // Products with operand sums (and the plain products of the same
+      // blocks) run in the fused kernel; everything else in the regular one.
+      bool any_fused = false;
+      for (const GemmDesc& g : gm) any_fused = any_fused || g.kinds != 0;
+      if (any_fused) {
+        std::vector<GemmDesc> f, r;
+        for (size_t i = 0; i < gm.size(); ++i) (gm_fusable[i] ? f : r).push_back(gm[i]);
+        gm.clear();
+        gm_fusable.clear();
+        emit_gemm(f, true);
+        emit_gemm(r, false);
+      } else {
+        emit_gemm(gm, false);
+        gm.clear();
+        gm_fusable.clear();
       }
-      OpRec r{OP_GEMM, kd, P.table.size(), (int)gm.size(), gm_grid, cfg, equal ? 1 : 0};
-      const size_t bytes = gm.size() * sizeof(GemmDesc);
-      P.table.resize(round_up(P.table.size() + bytes, 256));
-      std::memcpy(P.table.data() + r.off, gm.data(), bytes);
-      P.ops.push_back(r);
-      txt << "LAUNCH GEMM " << gm.size() << " " << gm_grid << " " << cfg << "\n";
-      gm.clear();
       gm_grid = 0;
     }
+  }
+
+  void emit_gemm(std::vector<GemmDesc>& group, bool fused) {
+    if (group.empty()) return;
+    const int kd = kernel_dtype(P.dtype);
+    // Unequal problems: longest (largest k) first, round-robin over XCDs.
+    bool equal = true;
+    for (const GemmDesc& g : group)
+      equal = equal && g.m == group[0].m && g.n == group[0].n && g.k == group[0].k;
+    if (!equal)
+      std::stable_sort(group.begin(), group.end(), [](const GemmDesc& x, const GemmDesc& y) { return x.k > y.k; });
+    int cfg = P.tile_cfg >= 0 ? P.tile_cfg : choose_gemm_cfg(kd, group);
+    // the fused kernel has 256x256, 128x128 and 64x128 tiles; its 128x128
+    // tile runs one wave per SIMD, so 64x128 is the default below 256x256
+    if (fused && cfg != 3 && (cfg != 0 || P.tile_cfg < 0)) cfg = 4;
+    const GemmCfg gc = gemm_cfg(kd, cfg);
+    int grid = 0;
+    for (GemmDesc& g : group) {
+      g.tiles_m = (int32_t)ceil_div(g.m, gc.bm);
+      g.tiles_n = (int32_t)ceil_div(g.n, gc.bn);
+      g.tile_start = grid;
+      grid += g.tiles_m * g.tiles_n;
+    }
+    for (const GemmDesc& g : group) {
+      txt << "GEMM " << g.m << " " << g.n << " " << g.k << " " << (g.kinds & 0xff) << " " << (g.kinds >> 8)
+          << " | " << vs(g.a) << " " << vs(g.b) << " |";
+      for (int j = 0; j < g.nout; ++j)
+        txt << " " << g.out[j].mode << ":" << g.out[j].sign << ":" << vs(g.out[j].c) << ":" << vs(g.out[j].d);
+      txt << "\n";
+    }
+    OpRec r{OP_GEMM, kd, P.table.size(), (int)group.size(), grid, cfg, equal ? 1 : 0, fused ? 1 : 0};
+    const size_t bytes = group.size() * sizeof(GemmDesc);
+    P.table.resize(round_up(P.table.size() + bytes, 256));
+    std::memcpy(P.table.data() + r.off, group.data(), bytes);
+    P.ops.push_back(r);
+    txt << "LAUNCH GEMM " << group.size() << " " << grid << " " << cfg << (fused ? " fused" : "") << "\n";
+    if (fused) P.fused = true;
   }
 };
 
@@ -541,7 +577,22 @@ void sched_strassen(Builder& b, const MView& A, const MView& B, const MView& C, 
 // bitwise the same as the depth-first schedules with the same leaf kernel.
 struct Sub {
   MView A, B, C;
+  int akind = OK_PLAIN, bkind = OK_PLAIN;
+  bool fusable = false;  // meets the fused loader's preconditions (aligned, fully valid)
 };
+
+// The last level's S/T sums can be formed in the leaf loader when both
+// operand blocks are float32, entirely valid (no virtual padding) and every
+// quadrant starts on a 16-byte boundary.
+bool can_fuse(const Builder& b, const Sub& s) {
+  if (!b.P.fuse || b.P.dtype != MM_F32) return false;
+  const MView& A = s.A;
+  const MView& B = s.B;
+  if (A.vrows != A.rows || A.vcols != A.cols || B.vrows != B.rows || B.vcols != B.cols) return false;
+  if (!A.vec || !B.vec) return false;
+  if ((A.cols / 2) % b.E || (B.cols / 2) % b.E || A.rows < 2 || A.cols < 2 || B.cols < 2) return false;
+  return true;
+}
 
 void sched_grouped(Builder& b, std::vector<Sub> subs) {
   const int L = b.P.L;
@@ -553,6 +604,23 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
     std::vector<std::array<MView, 11>> uargs;
     for (const Sub& s : subs) {
       const int64_t hm = s.A.rows / 2, hk = s.A.cols / 2, hn = s.B.cols / 2;
+      if (l == L - 1 && can_fuse(b, s)) {
+        // leaf operands read straight from the quadrants (fused loader)
+        MView Pt[7];
+        for (auto& v : Pt) v = b.temp(hm, hn);
+        next.push_back({b.quad(s.A, 0, 0), b.quad(s.B, 0, 0), Pt[0], OK_PLAIN, OK_PLAIN, true});
+        next.push_back({b.quad(s.A, 0, 1), b.quad(s.B, 1, 0), Pt[1], OK_PLAIN, OK_PLAIN, true});
+        next.push_back({s.A, b.quad(s.B, 1, 1), Pt[2], OK_S4, OK_PLAIN, true});
+        next.push_back({b.quad(s.A, 1, 1), s.B, Pt[3], OK_PLAIN, OK_T4, true});
+        next.push_back({s.A, s.B, Pt[4], OK_S1, OK_T1, true});
+        next.push_back({s.A, s.B, Pt[5], OK_S2, OK_T2, true});
+        next.push_back({s.A, s.B, Pt[6], OK_S3, OK_T3, true});
+        if (s.A.base == MB_A || s.A.base == MB_B || s.B.base == MB_A || s.B.base == MB_B)
+          b.P.fused_reads_ab = true;
+        uargs.push_back({Pt[0], Pt[1], Pt[2], Pt[3], Pt[4], Pt[5], Pt[6], b.quad(s.C, 0, 0),
+                         b.quad(s.C, 0, 1), b.quad(s.C, 1, 0), b.quad(s.C, 1, 1)});
+        continue;
+      }
       const MView A11 = b.quad(s.A, 0, 0), A12 = b.quad(s.A, 0, 1), A21 = b.quad(s.A, 1, 0),
                   A22 = b.quad(s.A, 1, 1);
       const MView B11 = b.quad(s.B, 0, 0), B12 = b.quad(s.B, 0, 1), B21 = b.quad(s.B, 1, 0),
@@ -590,7 +658,7 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
     }
     subs.swap(next);
   }
-  for (const Sub& s : subs) b.gemm(s.A, s.B, {Builder::store(s.C)});
+  for (const Sub& s : subs) b.gemm(s.A, s.B, {Builder::store(s.C)}, s.akind, s.bkind, s.fusable);
   b.flush();
   for (int l = L - 1; l >= 0; --l) {
     for (const EwPart& p : u_levels[l])
@@ -742,6 +810,10 @@ int upload(Plan& P) {
   int rc = check_device(&dev);
   if (rc != MM_OK) return rc;
   P.device = dev;
+  if (P.unfused) {
+    rc = upload(*P.unfused);
+    if (rc != MM_OK) return rc;
+  }
   if (P.table.empty()) return MM_OK;
   if (hipMalloc(&P.dtable, P.table.size()) != hipSuccess) {
     P.dtable = nullptr;
@@ -772,14 +844,20 @@ int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEven
     if (op.type == OP_EW)
       e = launch_ew(op.kdtype, kb, (const EwPart*)d, op.count, op.grid, s);
     else
-      e = launch_gemm(op.kdtype, op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, s);
+      e = op.fused ? launch_gemm_fused(op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, s)
+                   : launch_gemm(op.kdtype, op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, s);
     if (e != hipSuccess) return fail(MM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   }
   if (events && hipEventRecord(events[i], s) != hipSuccess) return fail(MM_E_HIP, "hipEventRecord failed");
   return MM_OK;
 }
 
+bool misaligned_ab(const void* A, const void* B) {
+  return (((uintptr_t)A) & 15) || (((uintptr_t)B) & 15);
+}
+
 int execute(Plan& P, void* A, void* B, void* C, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (P.fused_reads_ab && P.unfused && misaligned_ab(A, B)) return execute(*P.unfused, A, B, C, ws, ws_bytes, s);
   if (ws_bytes < P.ws_bytes || (P.ws_bytes > 0 && ws == nullptr))
     return fail(MM_E_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, plan needs " +
                                     std::to_string(P.ws_bytes));
@@ -879,9 +957,19 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   P->levels = levels;
   P->flags = flags;
   P->tile_cfg = (int)((flags >> 8) & 0xff) - 1;
+  P->fuse = (flags & MM_PLAN_FUSE) != 0;
   if (P->tile_cfg >= kNumGemmCfg) return fail(MM_E_INVALID, "unknown tile configuration");
   rc = build_plan(*P);
   if (rc != MM_OK) return rc;
+  if (P->fused_reads_ab) {
+    // A fused loader reads A and B with 16-byte vector loads; keep the
+    // unfused plan for calls whose A or B is not 16-byte aligned.
+    std::unique_ptr<Plan> U;
+    rc = make_plan(algo, sched, m, n, k, lda, ldb, ldc, cutoff, levels, dtype, flags & ~MM_PLAN_FUSE, &U);
+    if (rc != MM_OK) return rc;
+    P->ws_bytes = std::max(P->ws_bytes, U->ws_bytes);
+    P->unfused = std::move(U);
+  }
   *out = std::move(P);
   return MM_OK;
 }
@@ -1178,6 +1266,8 @@ int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, s
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != P.device)
     return fail(MM_E_INVALID, "plan was built for another device");
+  if (P.fused_reads_ab && misaligned_ab(A, B))
+    return fail(MM_E_UNSUPPORTED, "timed execution of a fused plan needs 16-byte aligned A and B");
   return enqueue(P, A, B, C, ws, stream, events);
 }
 
@@ -1189,9 +1279,9 @@ int mm_plan_op_kind(mm_plan_t plan, int i) {
 int mm_plan_info(mm_plan_t plan, int64_t* info, int ninfo) {
   if (!plan || !plan->p || !info) return 0;
   const Plan& P = *plan->p;
-  const int64_t v[9] = {(int64_t)P.ws_bytes, P.L, P.M, P.N, P.K, (int64_t)P.ops.size(), P.leaves, P.sched,
-                        P.leaf_rows};
-  const int cnt = std::min(ninfo, 9);
+  const int64_t v[10] = {(int64_t)P.ws_bytes, P.L, P.M, P.N, P.K, (int64_t)P.ops.size(), P.leaves, P.sched,
+                         P.leaf_rows, P.fused ? 1 : 0};
+  const int cnt = std::min(ninfo, 10);
   for (int i = 0; i < cnt; ++i) info[i] = v[i];
   return cnt;
 }
@@ -1213,10 +1303,10 @@ int mm_plan_destroy(mm_plan_t plan) {
 }
 
 size_t mm_describe(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb,
-                   int64_t ldc, int cutoff, int levels, int dtype, char* buf, size_t len, int64_t* info,
-                   int ninfo) {
+                   int64_t ldc, int cutoff, int levels, int dtype, unsigned flags, char* buf, size_t len,
+                   int64_t* info, int ninfo) {
   std::unique_ptr<Plan> P;
-  if (make_plan(algo, sched, m, n, k, lda, ldb, ldc, cutoff, levels, dtype, 0, &P) != MM_OK) return 0;
+  if (make_plan(algo, sched, m, n, k, lda, ldb, ldc, cutoff, levels, dtype, flags, &P) != MM_OK) return 0;
   mm_plan_s tmp{std::move(P)};
   if (info) mm_plan_info(&tmp, info, ninfo);
   const size_t r = mm_plan_describe(&tmp, buf, len);

@@ -50,6 +50,9 @@ def parse(text):
             _, kind, cnt, _grid = line.split()[:4]
             assert len(cur) == int(cnt), (line, len(cur))
             assert all(it[0] == kind for it in cur)
+            if line.split()[-1] == "fused":
+                for _, it in cur:
+                    check_fused_preconditions(it)
             launches.append((kind, cur))
             cur = []
             continue
@@ -61,7 +64,7 @@ def parse(text):
             outs = [_view(t) for t in rest[1].split()] if rest[1] else []
             cur.append(("EW", dict(kind=kind, rows=rows, cols=cols, mode=(m0, m1), ins=ins, outs=outs)))
         else:
-            m, n, k = map(int, h[1:])
+            m, n, k, ak, bk = map(int, h[1:])
             a, b = [_view(t) for t in rest[0].split()]
             outs = []
             for tok in rest[1].split():
@@ -70,9 +73,21 @@ def parse(text):
                 c = View([int(x) for x in f[2:9]])
                 d = None if f[9] == "-" else View([int(x) for x in f[9:16]])
                 outs.append((mode, sign, c, d))
-            cur.append(("GEMM", dict(m=m, n=n, k=k, a=a, b=b, outs=outs)))
+            cur.append(("GEMM", dict(m=m, n=n, k=k, a=a, b=b, outs=outs, ak=ak, bk=bk)))
     assert not cur, "listing ends inside a launch"
     return launches
+
+
+def check_fused_preconditions(it, vec=4):
+    """The fused loader reads every operand (or parent block) with 16-byte
+    vector loads and no masks: offsets and leading dimensions must be
+    multiples of the vector width and the blocks entirely valid."""
+    for v in (it["a"], it["b"]):
+        assert v.off % vec == 0 and v.ld % vec == 0, "fused operand not 16-byte aligned"
+        assert v.vrows == v.rows and v.vcols == v.cols, "fused operand partially valid"
+    for kind, v in ((it["ak"], it["a"]), (it["bk"], it["b"])):
+        if kind:
+            assert (v.cols // 2) % vec == 0 and v.rows % 2 == 0 and v.cols % 2 == 0
 
 
 class Memory:
@@ -204,6 +219,22 @@ def check_hazards(launch):
                 assert not (writes[i] & reads[j]), f"{kind}: one operation writes what another reads"
 
 
+def operand(M, kind):
+    """Operand of a leaf product: the block itself, or the Winograd sum of
+    its quadrants named by kind (1..4: S1..S4, 5..8: T1..T4)."""
+    if kind == 0:
+        return M
+    r, c = M.shape[0] // 2, M.shape[1] // 2
+    q11, q12, q21, q22 = M[:r, :c], M[:r, c:], M[r:, :c], M[r:, c:]
+    if kind <= 4:
+        s1 = q21 + q22
+        s2 = s1 - q11
+        return {1: s1, 2: s2, 3: q11 - q21, 4: q12 - s2}[kind]
+    t1 = q12 - q11
+    t2 = q22 - t1
+    return {5: t1, 6: t2, 7: q22 - q12, 8: t2 - q21}[kind]
+
+
 def run(text, bufs, hazards=True):
     mem = Memory(bufs)
     for launch in parse(text):
@@ -221,8 +252,8 @@ def run(text, bufs, hazards=True):
                     y = _recipe(it["kind"], x, it["mode"])
                 results.append(list(zip(it["outs"], y)))
             else:
-                a = mem.read(it["a"])
-                b = mem.read(it["b"])
+                a = operand(mem.read(it["a"]), it["ak"])
+                b = operand(mem.read(it["b"]), it["bk"])
                 acc = a @ b
                 outs = []
                 for mode, sign, c, d in it["outs"]:

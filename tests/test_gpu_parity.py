@@ -272,3 +272,39 @@ def test_graph_replay_matches_eager(api):
             s.synchronize()
             assert torch.equal(C, eager), rep
             del junk
+
+
+@pytest.mark.parametrize("m,n,k,levels", [(1024, 1024, 1024, 1), (1024, 1024, 1024, 2), (3000, 3000, 3000, 1),
+                                          (1024, 768, 512, 2), (2048, 2048, 2048, 1), (3000, 3000, 3000, 3)])
+def test_fused_loader_bitwise_equal_to_separate_pass(api, naive, m, n, k, levels):
+    # the S/T sums formed in the leaf loader must give the same bits as the
+    # separate pre-addition launch
+    A, B = inputs.pair("uniform", m, n, k, 30, np.float32)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    Cf = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, fuse=True)
+    Cu = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, fuse=False)
+    torch.cuda.synchronize()
+    p = api.get_plan("winograd", "grouped", m, n, k, 1, levels, "f32", k, n, n, False, At.device, None, True)  # fused
+    assert p.info["fused"] == 1
+    assert torch.equal(Cf, Cu)
+    rows = np.arange(0, m, max(1, m // 16))
+    assert rel_fro(Cf[torch.from_numpy(rows).cuda()].cpu().numpy(), naive.gemm_rows(A, B, rows)) < 1e-5
+
+
+def test_fused_plan_with_unaligned_operands_falls_back(api, naive):
+    # A and B start 4 bytes past a 16-byte boundary: the fused loader's vector
+    # loads would be misaligned, so the plan runs its unfused twin
+    m = n = k = 512
+    A, B = inputs.pair("uniform", m, n, k, 31, np.float32)
+    Ab = torch.zeros(m * k + 1, device="cuda")
+    Bb = torch.zeros(k * n + 1, device="cuda")
+    Ab[1:] = torch.from_numpy(A.ravel())
+    Bb[1:] = torch.from_numpy(B.ravel())
+    At, Bt = Ab[1:].view(m, k), Bb[1:].view(k, n)
+    assert At.data_ptr() % 16 != 0
+    C = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=1, fuse=True)
+    Ca = api.mm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), algo="winograd", sched="grouped",
+                cutoff=1, levels=1, fuse=False)
+    torch.cuda.synchronize()
+    assert torch.equal(C, Ca)
+    assert rel_fro(C.cpu().numpy(), naive.gemm(A, B)) < 1e-5

@@ -114,7 +114,57 @@ def test_grouped_launch_count_and_leaves(lib):
         _, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_)
         assert info["levels"] == L_
         assert info["launches"] == 2 * L_ + 1
-        assert info["leaves"] == 7 ** L_
+        assert info["leaves"] == 7 ** L_ and info["fused"] == 0
+        # with MM_PLAN_FUSE the last level's S/T pass is formed in the leaf loader
+        _, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_, fuse=True)
+        assert info["launches"] == 2 * L_ and info["fused"] == 1
+
+
+@pytest.mark.parametrize("m,n,k,cutoff,levels", [(16, 16, 16, 1, 1), (32, 64, 16, 1, 2), (64, 64, 64, 4, -1),
+                                                 (96, 40, 56, 1, 1), (200, 136, 72, 16, -1)])
+def test_fused_leaves_exact_and_equal_to_unfused(lib, m, n, k, cutoff, levels):
+    A = inputs.integers((m, k), 21, dtype=np.int64)
+    B = inputs.integers((k, n), 22, dtype=np.int64)
+    outs = []
+    for fuse in (True, False):
+        text, info = L.describe("winograd", "grouped", m, n, k, cutoff=cutoff, levels=levels, dtype="f32",
+                                fuse=fuse)
+        ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+        C = np.full(m * n, -(10**9), dtype=np.int64)
+        plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
+        outs.append((C.reshape(m, n), info))
+    assert np.array_equal(outs[0][0], A @ B)
+    assert np.array_equal(outs[1][0], A @ B)
+    if outs[0][1]["fused"]:
+        assert outs[0][1]["ws_bytes"] <= outs[1][1]["ws_bytes"]
+
+
+def test_fusion_needs_aligned_unpadded_operands(lib):
+    # 3000 = 8 * 375: one level splits into 1500 (a multiple of 4 floats) -> fused
+    text, info = L.describe("winograd", "grouped", 3000, 3000, 3000, cutoff=1, levels=1, fuse=True)
+    assert info["fused"] == 1
+    # float64 leaves are not fused
+    _, info = L.describe("winograd", "grouped", 512, 512, 512, cutoff=64, dtype="f64", fuse=True)
+    assert info["fused"] == 0
+    # with virtual padding only the blocks that lie wholly inside the matrix
+    # are fused; the listing marks every fused operand with a nonzero kind
+    text, info = L.describe("winograd", "grouped", 3000, 3000, 3000, cutoff=1, levels=3, fuse=True)
+    kinds = [tuple(map(int, l.split()[4:6])) for l in text.splitlines() if l.startswith("GEMM")]
+    assert any(k != (0, 0) for k in kinds)
+    assert sum(k == (0, 0) for k in kinds) > 2 * 49     # padded blocks stay unfused
+
+
+@pytest.mark.parametrize("m,n,k", [(40, 24, 56), (1000, 777, 555)])
+def test_partially_fused_padded_plan_is_exact(lib, m, n, k):
+    # unaligned leading dimensions and virtual padding: only the blocks that
+    # meet the fused loader's preconditions may go to the fused launch
+    A = inputs.integers((m, k), 23, dtype=np.int64)
+    B = inputs.integers((k, n), 24, dtype=np.int64)
+    text, info = L.describe("winograd", "grouped", m, n, k, cutoff=1, levels=2, dtype="f32", fuse=True)
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    C = np.full(m * n, -(10**9), dtype=np.int64)
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
+    assert np.array_equal(C.reshape(m, n), A @ B)
 
 
 def test_depth_first_leaf_count(lib):
