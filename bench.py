@@ -58,14 +58,16 @@ def _events(torch, n, stream):
 
 
 def time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup):
-    """Run warm-up steps, then exactly ``steps`` timed steps with per-launch
-    events.  Returns (wall ms per step, per-step ms list, per-launch ms lists)."""
+    """Run warm-up steps, then exactly ``steps`` timed steps with events
+    before and after every launch, recorded on the stream the launch runs on.
+    Returns (wall ms per step, per-step ms list, per-launch ms lists, kinds)."""
     import ctypes
     lib = L.load()
     s = torch.cuda.current_stream()
     nops = plan.info["launches"]
-    evsets = [_events(torch, nops + 1, s) for _ in range(steps)]
-    ptrs = [(ctypes.c_void_p * (nops + 1))(*[e.cuda_event for e in evs]) for evs in evsets]
+    nev = 2 * nops
+    evsets = [_events(torch, nev, s) for _ in range(steps)]
+    ptrs = [(ctypes.c_void_p * nev)(*[e.cuda_event for e in evs]) for evs in evsets]
     wsp, wsb = (ws.data_ptr(), ws.numel()) if ws is not None else (None, 0)
     for _ in range(warmup):
         L.check(lib.mm_plan_execute(plan._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), wsp, wsb,
@@ -74,13 +76,51 @@ def time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup):
     t0 = time.perf_counter()
     for i in range(steps):
         L.check(lib.mm_plan_execute_timed(plan._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), wsp,
-                                          wsb, s.cuda_stream, ptrs[i], nops + 1))
+                                          wsb, s.cuda_stream, ptrs[i], nev))
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3 / steps
     step_ms = [evs[0].elapsed_time(evs[-1]) for evs in evsets]
-    per_op = [[evs[j].elapsed_time(evs[j + 1]) for evs in evsets] for j in range(nops)]
+    per_op = [[evs[2 * j].elapsed_time(evs[2 * j + 1]) for evs in evsets] for j in range(nops)]
     kinds = [lib.mm_plan_op_kind(plan._ptr, j) for j in range(nops)]
     return wall_ms, step_ms, per_op, kinds
+
+
+def plan_launches(plan, esz):
+    """Per launch of a plan (in launch order): its kind ("EW", "GEMM",
+    "FORK", "JOIN"), stream (0 caller's, 1 auxiliary), algorithmic flops
+    (GEMM: 2 m n k per leaf product) and algorithmic HBM bytes (EW: every
+    valid input element read once, every valid output element written once),
+    read off the plan listing."""
+    out, flops, nbytes = [], 0.0, 0.0
+    for line in plan.describe().splitlines():
+        w = line.split()
+        if not w:
+            continue
+        if line in ("FORK", "JOIN"):
+            out.append(dict(kind=line, stream=0, flops=0.0, bytes=0.0))
+        elif w[0] == "LAUNCH":
+            out.append(dict(kind=w[1], stream=1 if w[-1] == "aux" else 0, flops=flops, bytes=nbytes))
+            flops, nbytes = 0.0, 0.0
+        elif w[0] == "GEMM":
+            m, n, k = map(int, w[1:4])
+            flops += 2.0 * m * n * k
+        elif w[0] == "EW":
+            _, ins, outs = [x.strip() for x in line.split("|")]
+            for tok in (ins + " " + outs).split():
+                if tok != "-":
+                    f = tok.split(":")
+                    nbytes += int(f[5]) * int(f[6]) * esz
+    return out
+
+
+def tuned_leaf(tuner, n, levels):
+    """The autotuner's leaf tile and overlap choice for an n x n x n product
+    at this level count (None / False when the cache holds another level
+    count for the size class)."""
+    ch = tuner.choose(n, n, n, "f32")
+    if ch["source"] == "tuned" and ch["levels"] == levels:
+        return ch["tile"], bool(ch.get("overlap", False))
+    return None, False
 
 
 def pct(xs, q):
@@ -88,8 +128,9 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtype="f32", tile=None):
-    plan = api.Plan(algo, sched, n, n, n, cutoff=1, levels=levels, dtype=dtype, tile=tile)
+def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtype="f32", tile=None,
+                overlap=False):
+    plan = api.Plan(algo, sched, n, n, n, cutoff=1, levels=levels, dtype=dtype, tile=tile, overlap=overlap)
     ws = torch.empty(max(plan.ws_bytes, 256), dtype=torch.uint8, device=A.device)
     C = torch.empty((n, n), dtype=A.dtype, device=A.device)
     wall, step_ms, per_op, kinds = time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup)
@@ -98,13 +139,15 @@ def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtyp
 
 
 def gemm_roofline(res, n):
-    """Roofline of the leaf GEMM launch (the dominant kernel)."""
-    info = res["plan"].info
-    Lv = info["levels"]
-    leaf_flops = 2.0 * (info["M"] >> Lv) * (info["N"] >> Lv) * (info["K"] >> Lv)
-    flops = leaf_flops * 7 ** Lv
-    durs = [sum(d) / len(d) for d, k in zip(res["per_op"], res["kinds"]) if k == 1]
-    avg_ms = durs[0] if durs else float("nan")
+    """Roofline of the dominant kernel: the leaf-product GEMM launch with the
+    most flops (on the caller's stream, not sharing the GPU with the
+    overlapped S/T pass)."""
+    launches = plan_launches(res["plan"], 4)
+    best = None
+    for lau, d, k in zip(launches, res["per_op"], res["kinds"]):
+        if k == 1 and (best is None or lau["flops"] > best[0]):
+            best = (lau["flops"], sum(d) / len(d))
+    flops, avg_ms = best if best else (0.0, float("nan"))
     achieved = flops / (avg_ms * 1e-3) / 1e12
     return dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=None,
@@ -113,24 +156,16 @@ def gemm_roofline(res, n):
 
 
 def ew_bandwidth(res, n):
-    """Achieved HBM rate of the element-wise launches (algorithmic bytes)."""
-    info = res["plan"].info
-    Lv = info["levels"]
+    """Achieved HBM rate of the element-wise launches (algorithmic bytes);
+    launches on the auxiliary stream share the GPU with leaf products."""
+    launches = plan_launches(res["plan"], 4)
     out = []
-    ew = [sum(d) / len(d) for d, k in zip(res["per_op"], res["kinds"]) if k == 0]
-    # S/T launch of level l: reads A and B blocks (4+4 quarters), writes 8
-    # quarters; U launch: reads 7 quarters, writes 4 (float32, per block).
-    for l in range(Lv):
-        q = (n >> (l + 1)) ** 2 * 4.0 * 7 ** l
-        out.append(("ST", l, 16 * q))
-    for l in reversed(range(Lv)):
-        q = (n >> (l + 1)) ** 2 * 4.0 * 7 ** l
-        out.append(("U", l, 11 * q))
-    res_list = []
-    for (kind, l, bytes_), ms in zip(out, ew):
-        res_list.append(dict(kind=kind, level=l, bytes=bytes_, ms=round(ms, 4),
-                             gbs=round(bytes_ / (ms * 1e-3) / 1e9, 1)))
-    return res_list
+    for lau, d, k in zip(launches, res["per_op"], res["kinds"]):
+        if k % 4 == 0:
+            ms = sum(d) / len(d)
+            out.append(dict(stream="aux" if k >= 4 else "main", bytes=lau["bytes"], ms=round(ms, 4),
+                            gbs=round(lau["bytes"] / (ms * 1e-3) / 1e9, 1)))
+    return out
 
 
 def cpu_baseline(A_np, B_np, seconds):
@@ -302,9 +337,9 @@ def main():
     else:
         levels = args.levels
 
-    tile = ch["tile"] if (ch["source"] == "tuned" and ch["levels"] == levels) else None
+    tile, overlap = tuned_leaf(tuner, n, levels)
     win = run_product(torch, api, L, "winograd", args.sched, n, levels, A, B, args.steps, args.warmup,
-                      tile=tile)
+                      tile=tile, overlap=overlap)
     print(f"# winograd L={levels}: {win['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
     if args.profile_only:
         print(json.dumps({"profile_only": True, "n": n, "levels": levels,
@@ -345,7 +380,8 @@ def main():
         "data": "synthetic (uniform[-1,1], seeded)",
         "config": {"workload": f"square fp32 matmul n={n}, Strassen-Winograd {args.sched} "
                                f"L={levels} vs plain MFMA GEMM",
-                   "n": n, "levels": levels, "schedule": args.sched},
+                   "n": n, "levels": levels, "schedule": args.sched, "leaf_tile_cfg": tile,
+                   "overlap": overlap},
         "p50_ms": round(win["p50"], 4),
         "p99_ms": round(win["p99"], 4),
         "plain_gemm": {"tflops": round(plain["tflops"], 3), "p50_ms": round(plain["p50"], 4),
@@ -372,7 +408,9 @@ def main():
             p2 = run_product(torch, api, L, "naive", "auto", n2, 0, A2, B2, 5, 2)
             e = {"plain_tflops": round(p2["tflops"], 3)}
             for lv in lvls:
-                w2 = run_product(torch, api, L, "winograd", args.sched, n2, lv, A2, B2, 5, 2)
+                t2, o2 = tuned_leaf(tuner, n2, lv)
+                w2 = run_product(torch, api, L, "winograd", args.sched, n2, lv, A2, B2, 5, 2, tile=t2,
+                                 overlap=o2)
                 e[f"winograd_L{lv}_tflops"] = round(w2["tflops"], 3)
                 e[f"winograd_L{lv}_p99_ms"] = round(w2["p99"], 4)
             extra[str(n2)] = e

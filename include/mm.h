@@ -152,6 +152,13 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                           of a separate pre-addition pass (float32, grouped schedule; results
                           are bitwise the same).  Off by default: on MI355X it doubles the
                           operand traffic into the CUs and measures slower. */
+#define MM_PLAN_OVERLAP 4u /* grouped schedule: run the S/T pre-addition passes on an
+                             auxiliary stream of the plan, concurrently with the leaf
+                             products that read only blocks of A and B (P1 = A11 B11,
+                             P2 = A12 B21 and their counterparts below); the leaves are then
+                             split over two launches.  Results are bitwise the same as
+                             without the flag; whether it is faster depends on the shape
+                             and tile (the autotuner tries both). */
 /* Force the MFMA GEMM tile configuration c (0 .. 7) for every leaf launch
  * instead of the planner's choice.  float32: 0 128x128 (BK 32), 1 256x128,
  * 2 128x256, 3 256x256 (BK 16), 4 64x128, 5 128x64, 6 256x128 (BK 16),
@@ -161,7 +168,9 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
 
 /* Build (once) the launch sequence and device descriptor table of one
  * product shape on the current device.  The plan owns a small device table
- * (freed by mm_plan_destroy) and, with MM_PLAN_GRAPH, its graphs. */
+ * (freed by mm_plan_destroy), with MM_PLAN_GRAPH its graphs, and, when its
+ * schedule overlaps launches, one auxiliary stream (default priority) and
+ * two events per caller stream it has run on. */
 int mm_plan_create(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb,
                    int64_t ldc, int cutoff, int levels, int dtype, unsigned flags, mm_plan_t* plan);
 
@@ -169,16 +178,19 @@ int mm_plan_create(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t
 int mm_plan_execute(mm_plan_t plan, void* A, void* B, void* C, void* ws, size_t ws_bytes,
                     hipStream_t stream);
 
-/* mm_plan_execute with timing: events[i] (created by the caller with
- * hipEventCreate, i = 0 .. launches) is recorded on `stream` before launch i,
- * and events[launches] after the last one, so the caller can read each
- * launch's duration with hipEventElapsedTime after synchronising.  Graph
+/* mm_plan_execute with timing: events[2i] and events[2i+1] (created by the
+ * caller with hipEventCreate; nevents >= 2 * launches) are recorded before
+ * and after launch i on the stream that launch runs on, so the caller can
+ * read each launch's duration with hipEventElapsedTime after synchronising.
+ * The whole product spans events[0] to events[2 * launches - 1].  Graph
  * capture is not used on this path. */
 int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, size_t ws_bytes,
                           hipStream_t stream, hipEvent_t* events, int nevents);
 
 /* Kind of launch i of a plan: 0 element-wise block operations, 1 MFMA GEMM
- * group (leaf products); -1 if i is out of range. */
+ * group (leaf products), 2 fork to / 3 join of the plan's auxiliary stream;
+ * plus 4 when the launch runs on the auxiliary stream; -1 if i is out of
+ * range. */
 int mm_plan_op_kind(mm_plan_t plan, int i);
 
 /* Plan facts: info[0] workspace bytes, [1] levels L, [2..4] padded m, n, k,

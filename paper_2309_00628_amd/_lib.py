@@ -22,6 +22,7 @@ MM_ALGO_NAIVE, MM_ALGO_STRASSEN, MM_ALGO_WINOGRAD = 0, 1, 2
 MM_SCHED_TWO_TEMP, MM_SCHED_IN_PLACE, MM_SCHED_GROUPED, MM_SCHED_DFS3, MM_SCHED_AUTO = 0, 1, 2, 3, 4
 MM_PLAN_GRAPH = 1
 MM_PLAN_FUSE = 2
+MM_PLAN_OVERLAP = 4
 
 
 def plan_tile(c):
@@ -115,7 +116,7 @@ def check(status):
 
 
 def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None, ldc=None,
-             fuse=False):
+             fuse=False, overlap=False):
     """Host-only plan listing and facts (no device needed)."""
     lib = load()
     lda = max(k, 1) if lda is None else lda
@@ -123,7 +124,7 @@ def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, l
     ldc = max(n, 1) if ldc is None else ldc
     info = (ctypes.c_int64 * 10)()
     args = (ALGOS.get(algo, algo), SCHEDS.get(sched, sched), m, n, k, lda, ldb, ldc, cutoff, levels,
-            DTYPES.get(dtype, dtype), MM_PLAN_FUSE if fuse else 0)
+            DTYPES.get(dtype, dtype), (MM_PLAN_FUSE if fuse else 0) | (MM_PLAN_OVERLAP if overlap else 0))
     need = lib.mm_describe(*args, None, 0, info, 10)
     if need == 0:
         raise MMError(1, last_error())

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <list>
 #include <mutex>
 #include <sstream>
 #include <string>
@@ -45,7 +46,9 @@ size_t elem_size(int dtype) { return dtype == MM_F64 ? 8 : 4; }
 int kernel_dtype(int dtype) { return dtype == MM_F64 ? DT_F64 : (dtype == MM_F32 ? DT_F32 : DT_BF16X3); }
 int ew_dtype(int dtype) { return dtype == MM_F64 ? DT_F64 : DT_F32; }
 
-enum OpType { OP_EW = 0, OP_GEMM = 1 };
+// OP_FORK: the auxiliary stream waits for the work enqueued so far on the
+// main stream; OP_JOIN: the main stream waits for the auxiliary stream.
+enum OpType { OP_EW = 0, OP_GEMM = 1, OP_FORK = 2, OP_JOIN = 3 };
 
 struct OpRec {
   int type;
@@ -56,6 +59,7 @@ struct OpRec {
   int cfg;     // GEMM tile configuration
   int remap;   // GEMM: XCD-contiguous tile order
   int fused;   // GEMM: some operands are Winograd sums formed in the loader
+  int stream;  // 0: the caller's stream, 1: the plan's auxiliary stream
 };
 
 }  // namespace
@@ -72,6 +76,14 @@ struct Plan {
   unsigned flags = 0;
   int tile_cfg = -1;  // forced GEMM tile configuration, -1: planner's choice
   bool fuse = false;  // fold the last level's S/T sums into the leaf loader
+  bool overlap = false;  // run the S/T passes beside the products that do not need them
+  bool has_aux = false;  // some launches go to the auxiliary stream
+  struct Aux {
+    hipStream_t main, aux;
+    hipEvent_t fork, join;
+  };
+  std::list<Aux> aux;  // one auxiliary stream and event pair per caller stream
+  std::mutex aux_mu;   // guards aux (enqueue may run while mu is held)
   bool fused = false;          // the plan has leaf products with fused operands
   bool fused_reads_ab = false;  // ... reading A or B directly (needs 16-byte aligned A, B)
   std::unique_ptr<Plan> unfused;  // same product without fusion, for unaligned A or B
@@ -89,6 +101,12 @@ struct Plan {
   std::mutex mu;
   ~Plan() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto& a : aux) {
+      (void)hipStreamSynchronize(a.aux);
+      (void)hipEventDestroy(a.fork);
+      (void)hipEventDestroy(a.join);
+      (void)hipStreamDestroy(a.aux);
+    }
     if (dtable) (void)hipFree(dtable);
   }
 };
@@ -155,6 +173,7 @@ struct Builder {
   int64_t ws_top = 0, ws_peak = 0;
   std::vector<EwPart> ew;
   int ew_grid = 0;
+  int cur_stream = 0;  // stream the next launches go to (0 main, 1 auxiliary)
   std::vector<GemmDesc> gm;
   std::vector<char> gm_fusable;  // descriptor satisfies the fused loader's preconditions
   int gm_grid = 0;
@@ -286,14 +305,46 @@ struct Builder {
   }
 
   // Close the current launch.
+  // Start / end a section in which launches on the auxiliary stream run
+  // concurrently with launches on the main stream.
+  void fork() {
+    flush();
+    P.ops.push_back(OpRec{OP_FORK, 0, 0, 0, 0, 0, 0, 0, 0});
+    txt << "FORK\n";
+  }
+  // Some launch since the last fork runs on the auxiliary stream.
+  bool window_has_aux() const {
+    for (size_t f = P.ops.size(); f > 0 && P.ops[f - 1].type != OP_FORK; --f)
+      if (P.ops[f - 1].stream) return true;
+    return false;
+  }
+  void join() {
+    flush();
+    if (!window_has_aux()) {
+      size_t f = P.ops.size();
+      while (P.ops[f - 1].type != OP_FORK) --f;
+      // nothing runs on the auxiliary stream: drop the fork
+      P.ops.erase(P.ops.begin() + (f - 1));
+      std::string t = txt.str();
+      const size_t at = t.rfind("FORK\n");
+      t.erase(at, 5);
+      txt.str(t);
+      txt.seekp(0, std::ios_base::end);
+      return;
+    }
+    P.ops.push_back(OpRec{OP_JOIN, 0, 0, 0, 0, 0, 0, 0, 0});
+    P.has_aux = true;
+    txt << "JOIN\n";
+  }
+
   void flush() {
     if (!ew.empty()) {
-      OpRec r{OP_EW, ew_dtype(P.dtype), P.table.size(), (int)ew.size(), ew_grid, 0, 0, 0};
+      OpRec r{OP_EW, ew_dtype(P.dtype), P.table.size(), (int)ew.size(), ew_grid, 0, 0, 0, cur_stream};
       const size_t bytes = ew.size() * sizeof(EwPart);
       P.table.resize(round_up(P.table.size() + bytes, 256));
       std::memcpy(P.table.data() + r.off, ew.data(), bytes);
       P.ops.push_back(r);
-      txt << "LAUNCH EW " << ew.size() << " " << ew_grid << "\n";
+      txt << "LAUNCH EW " << ew.size() << " " << ew_grid << (cur_stream ? " aux" : "") << "\n";
       ew.clear();
       ew_grid = 0;
     }
@@ -346,12 +397,13 @@ struct Builder {
         txt << " " << g.out[j].mode << ":" << g.out[j].sign << ":" << vs(g.out[j].c) << ":" << vs(g.out[j].d);
       txt << "\n";
     }
-    OpRec r{OP_GEMM, kd, P.table.size(), (int)group.size(), grid, cfg, equal ? 1 : 0, fused ? 1 : 0};
+    OpRec r{OP_GEMM, kd, P.table.size(), (int)group.size(), grid, cfg, equal ? 1 : 0, fused ? 1 : 0, cur_stream};
     const size_t bytes = group.size() * sizeof(GemmDesc);
     P.table.resize(round_up(P.table.size() + bytes, 256));
     std::memcpy(P.table.data() + r.off, group.data(), bytes);
     P.ops.push_back(r);
-    txt << "LAUNCH GEMM " << group.size() << " " << grid << " " << cfg << (fused ? " fused" : "") << "\n";
+    txt << "LAUNCH GEMM " << group.size() << " " << grid << " " << cfg << (fused ? " fused" : "")
+        << (cur_stream ? " aux" : "") << "\n";
     if (fused) P.fused = true;
   }
 };
@@ -597,7 +649,14 @@ bool can_fuse(const Builder& b, const Sub& s) {
 void sched_grouped(Builder& b, std::vector<Sub> subs) {
   const int L = b.P.L;
   std::vector<std::vector<EwPart>> u_levels;  // recorded, emitted in reverse
-  std::vector<std::string> u_text;
+  // The S/T passes run on the auxiliary stream while the leaf products whose
+  // operands are plain blocks of A and B (P1 = A11 B11, P2 = A12 B21 at the
+  // top level, and their counterparts below) run on the main stream.
+  const bool overlap_req = b.P.overlap && L >= 1;
+  if (overlap_req) {
+    b.fork();
+    b.cur_stream = 1;
+  }
   for (int l = 0; l < L; ++l) {
     std::vector<Sub> next;
     next.reserve(subs.size() * 7);
@@ -658,7 +717,23 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
     }
     subs.swap(next);
   }
-  for (const Sub& s : subs) b.gemm(s.A, s.B, {Builder::store(s.C)}, s.akind, s.bkind, s.fusable);
+  b.flush();
+  b.cur_stream = 0;
+  auto plain = [](const Sub& s) {
+    return s.A.base != MB_WS && s.B.base != MB_WS && s.akind == OK_PLAIN && s.bkind == OK_PLAIN;
+  };
+  bool overlap = overlap_req;
+  if (overlap && !b.window_has_aux()) {
+    b.join();  // every S/T sum is formed in the leaf loader: nothing to overlap
+    overlap = false;
+  }
+  if (overlap) {
+    for (const Sub& s : subs)
+      if (plain(s)) b.gemm(s.A, s.B, {Builder::store(s.C)}, s.akind, s.bkind, s.fusable);
+    b.join();
+  }
+  for (const Sub& s : subs)
+    if (!overlap || !plain(s)) b.gemm(s.A, s.B, {Builder::store(s.C)}, s.akind, s.bkind, s.fusable);
   b.flush();
   for (int l = L - 1; l >= 0; --l) {
     for (const EwPart& p : u_levels[l])
@@ -825,6 +900,31 @@ int upload(Plan& P) {
   return MM_OK;
 }
 
+// The auxiliary stream and fork/join events of a plan for caller stream s
+// (created on first use with that stream, default priority).
+int aux_for(Plan& P, hipStream_t s, Plan::Aux** out) {
+  std::lock_guard<std::mutex> lk(P.aux_mu);
+  for (auto& a : P.aux)
+    if (a.main == s) {
+      *out = &a;
+      return MM_OK;
+    }
+  Plan::Aux a{s, nullptr, nullptr, nullptr};
+  if (hipStreamCreateWithFlags(&a.aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess) {
+    if (a.join) (void)hipEventDestroy(a.join);
+    if (a.fork) (void)hipEventDestroy(a.fork);
+    if (a.aux) (void)hipStreamDestroy(a.aux);
+    return fail(MM_E_HIP, "could not create the plan's auxiliary stream");
+  }
+  P.aux.push_back(a);
+  *out = &P.aux.back();
+  return MM_OK;
+}
+
+// events (timed execution): events[2i] / events[2i+1] are recorded before /
+// after launch i on the stream that launch runs on.
 int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEvent_t* events = nullptr) {
   KernelBases kb;
   kb.p[MB_A] = A;
@@ -835,20 +935,35 @@ int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEven
   kb.aligned = 0;
   for (int i = 0; i < 4; ++i)
     if (((uintptr_t)kb.p[i] & 15) == 0) kb.aligned |= 1 << i;
+  Plan::Aux* ax = nullptr;
+  if (P.has_aux) {
+    int rc = aux_for(P, s, &ax);
+    if (rc != MM_OK) return rc;
+  }
   int i = 0;
   for (const OpRec& op : P.ops) {
-    const void* d = (const char*)P.dtable + op.off;
-    hipError_t e;
-    if (events && hipEventRecord(events[i], s) != hipSuccess) return fail(MM_E_HIP, "hipEventRecord failed");
-    ++i;
-    if (op.type == OP_EW)
-      e = launch_ew(op.kdtype, kb, (const EwPart*)d, op.count, op.grid, s);
-    else
-      e = op.fused ? launch_gemm_fused(op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, s)
-                   : launch_gemm(op.kdtype, op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, s);
+    const hipStream_t st = (op.stream && ax) ? ax->aux : s;
+    if (events && hipEventRecord(events[2 * i], st) != hipSuccess) return fail(MM_E_HIP, "hipEventRecord failed");
+    hipError_t e = hipSuccess;
+    if (op.type == OP_FORK) {
+      if (hipEventRecord(ax->fork, s) != hipSuccess || hipStreamWaitEvent(ax->aux, ax->fork, 0) != hipSuccess)
+        return fail(MM_E_HIP, "fork to the auxiliary stream failed");
+    } else if (op.type == OP_JOIN) {
+      if (hipEventRecord(ax->join, ax->aux) != hipSuccess || hipStreamWaitEvent(s, ax->join, 0) != hipSuccess)
+        return fail(MM_E_HIP, "join of the auxiliary stream failed");
+    } else {
+      const void* d = (const char*)P.dtable + op.off;
+      if (op.type == OP_EW)
+        e = launch_ew(op.kdtype, kb, (const EwPart*)d, op.count, op.grid, st);
+      else
+        e = op.fused ? launch_gemm_fused(op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, st)
+                     : launch_gemm(op.kdtype, op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, st);
+    }
     if (e != hipSuccess) return fail(MM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    if (events && hipEventRecord(events[2 * i + 1], st) != hipSuccess)
+      return fail(MM_E_HIP, "hipEventRecord failed");
+    ++i;
   }
-  if (events && hipEventRecord(events[i], s) != hipSuccess) return fail(MM_E_HIP, "hipEventRecord failed");
   return MM_OK;
 }
 
@@ -958,6 +1073,7 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   P->flags = flags;
   P->tile_cfg = (int)((flags >> 8) & 0xff) - 1;
   P->fuse = (flags & MM_PLAN_FUSE) != 0;
+  P->overlap = (flags & MM_PLAN_OVERLAP) != 0;
   if (P->tile_cfg >= kNumGemmCfg) return fail(MM_E_INVALID, "unknown tile configuration");
   rc = build_plan(*P);
   if (rc != MM_OK) return rc;
@@ -1255,8 +1371,8 @@ int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, s
                           hipStream_t stream, hipEvent_t* events, int nevents) {
   if (!plan || !plan->p) return fail(MM_E_INVALID, "NULL plan");
   Plan& P = *plan->p;
-  if (!events || nevents < (int)P.ops.size() + 1)
-    return fail(MM_E_INVALID, "need one event per launch plus one");
+  if (!events || nevents < 2 * (int)P.ops.size())
+    return fail(MM_E_INVALID, "need two events per launch");
   if (!P.batched) {
     int rc = check_args(P.m, P.n, P.k, A, P.lda, B, P.ldb, C, P.ldc, P.dtype);
     if (rc != MM_OK) return rc;
@@ -1273,7 +1389,7 @@ int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, s
 
 int mm_plan_op_kind(mm_plan_t plan, int i) {
   if (!plan || !plan->p || i < 0 || i >= (int)plan->p->ops.size()) return -1;
-  return plan->p->ops[i].type;
+  return plan->p->ops[i].type + 4 * plan->p->ops[i].stream;
 }
 
 int mm_plan_info(mm_plan_t plan, int64_t* info, int ninfo) {

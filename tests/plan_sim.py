@@ -1,14 +1,16 @@
 """Test-side simulator of libmm launch sequences (not the oracle).
 
 ``mm_describe`` lists a plan as text, one line per block operation and one
-``LAUNCH`` line closing each kernel launch.  This module parses that listing
-and executes it on numpy buffers, doing per block what the kernels do per
-element: reads outside a view's valid extent give zero, writes there are
+``LAUNCH`` line closing each kernel launch (tagged ``aux`` when it runs on
+the plan's auxiliary stream, between ``FORK`` and ``JOIN`` lines).  This
+module parses that listing and executes it on numpy buffers, doing per
+block what the kernels do per element: reads outside a view's valid extent give zero, writes there are
 dropped, element-wise recipes combine their inputs, GEMM descriptors form
 a @ b and apply their epilogues.  It also checks that no two operations of
 one launch touch memory in a conflicting way (the kernels of one launch run
-concurrently), so a planner bug shows up as a hazard even when the numbers
-happen to come out right.
+concurrently), and that launches on the two streams of a fork window never
+touch memory the other stream writes, so a planner bug shows up as a hazard
+even when the numbers happen to come out right.
 
 Run on integer matrices, the simulated product must equal the oracle's
 exactly.
@@ -41,19 +43,26 @@ def _view(tok):
 
 
 def parse(text):
-    """List of launches; each launch is ("EW"|"GEMM", [items])."""
+    """List of launches; each launch is ("EW"|"GEMM", [items], stream) with
+    stream 0 (the caller's) or 1 (the plan's auxiliary stream), or a
+    ("FORK"|"JOIN", [], 0) marker."""
     launches, cur = [], []
     for line in text.splitlines():
         if not line.strip():
             continue
+        if line in ("FORK", "JOIN"):
+            assert not cur, "fork/join inside a launch"
+            launches.append((line, [], 0))
+            continue
         if line.startswith("LAUNCH"):
-            _, kind, cnt, _grid = line.split()[:4]
+            words = line.split()
+            _, kind, cnt, _grid = words[:4]
             assert len(cur) == int(cnt), (line, len(cur))
             assert all(it[0] == kind for it in cur)
-            if line.split()[-1] == "fused":
+            if "fused" in words[4:]:
                 for _, it in cur:
                     check_fused_preconditions(it)
-            launches.append((kind, cur))
+            launches.append((kind, cur, 1 if words[-1] == "aux" else 0))
             cur = []
             continue
         head, *rest = [s.strip() for s in line.split("|")]
@@ -75,7 +84,54 @@ def parse(text):
                 outs.append((mode, sign, c, d))
             cur.append(("GEMM", dict(m=m, n=n, k=k, a=a, b=b, outs=outs, ak=ak, bk=bk)))
     assert not cur, "listing ends inside a launch"
+    check_streams(launches)
     return launches
+
+
+def check_streams(launches):
+    """Auxiliary-stream launches appear only between FORK and JOIN, windows do
+    not nest, and no launch on one stream inside a window touches memory that
+    a launch on the other stream writes (the two streams run concurrently)."""
+    inside = False
+    window = []
+    for kind, items, stream in launches:
+        if kind == "FORK":
+            assert not inside, "nested fork"
+            inside, window = True, []
+        elif kind == "JOIN":
+            assert inside, "join without fork"
+            assert any(st == 1 for _, _, st in window), "empty auxiliary window"
+            fp = {0: (set(), set()), 1: (set(), set())}
+            for k2, it2, st in window:
+                r, w = _launch_footprint(k2, it2)
+                fp[st][0].update(r)
+                fp[st][1].update(w)
+            (r0, w0), (r1, w1) = fp[0], fp[1]
+            assert not (w0 & w1), "both streams write the same memory"
+            assert not (w0 & r1) and not (w1 & r0), "one stream writes what the other reads"
+            inside = False
+        else:
+            assert inside or stream == 0, "auxiliary launch outside a fork window"
+            if inside:
+                window.append((kind, items, stream))
+    assert not inside, "listing ends inside a fork window"
+
+
+def _launch_footprint(kind, items):
+    reads, writes = set(), set()
+    for _, it in items:
+        if kind == "EW":
+            for v in it["ins"]:
+                reads |= _footprint(v)
+            for v in it["outs"]:
+                writes |= _footprint(v)
+        else:
+            reads |= _footprint(it["a"]) | _footprint(it["b"])
+            for mode, sign, c, d in it["outs"]:
+                writes |= _footprint(c)
+                if d is not None and mode == GM_ADD:
+                    reads |= _footprint(d)
+    return reads, writes
 
 
 def check_fused_preconditions(it, vec=4):
@@ -171,7 +227,7 @@ def check_hazards(launch):
     """No operation of a launch writes what another one reads or writes, and
     a GEMM never writes its own operands (element-wise parts may read and
     write the same element in place)."""
-    kind, items = launch
+    kind, items = launch[0], launch[1]
     reads, writes = [], []
     for _, it in items:
         if kind == "EW":
@@ -238,9 +294,11 @@ def operand(M, kind):
 def run(text, bufs, hazards=True):
     mem = Memory(bufs)
     for launch in parse(text):
+        kind, items = launch[0], launch[1]
+        if kind in ("FORK", "JOIN"):
+            continue
         if hazards:
             check_hazards(launch)
-        kind, items = launch
         results = []
         for _, it in items:
             if kind == "EW":

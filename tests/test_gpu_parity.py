@@ -308,3 +308,68 @@ def test_fused_plan_with_unaligned_operands_falls_back(api, naive):
     torch.cuda.synchronize()
     assert torch.equal(C, Ca)
     assert rel_fro(C.cpu().numpy(), naive.gemm(A, B)) < 1e-5
+
+
+@pytest.mark.parametrize("m,n,k,levels", [(1024, 1024, 1024, 1), (2048, 2048, 2048, 2), (3000, 3000, 3000, 1),
+                                          (1000, 777, 555, 2), (640, 384, 1152, 3)])
+def test_overlapped_schedule_bitwise_equal_to_serial(api, naive, m, n, k, levels):
+    # the S/T passes on the plan's auxiliary stream beside P1/P2 must give
+    # the same bits as the serial launch order, on the default stream and on
+    # a side stream, eagerly and from a replayed graph
+    A, B = inputs.pair("uniform", m, n, k, 32, np.float32)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    print(f"overlap {m}x{n}x{k} L={levels}", flush=True)
+    serial = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels)
+    over = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, overlap=True)
+    torch.cuda.synchronize()
+    p = api.get_plan("winograd", "grouped", m, n, k, 1, levels, "f32", k, n, n, False, At.device, overlap=True)
+    assert "FORK" in p.describe()
+    assert torch.equal(over, serial)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        C = torch.empty((m, n), device="cuda")
+        for rep in range(3):
+            C.fill_(float("nan"))
+            api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, out=C, graph=rep > 0,
+                   stream=s, overlap=True)
+            s.synchronize()
+            junk = At[:64] @ Bt  # unrelated eager work between replays
+            s.synchronize()
+            assert torch.equal(C, serial), rep
+            del junk
+    rows = np.arange(0, m, max(1, m // 16))
+    assert rel_fro(over[torch.from_numpy(rows).cuda()].cpu().numpy(), naive.gemm_rows(A, B, rows)) < 1e-5
+
+
+def test_timed_execution_events_per_launch(api):
+    # mm_plan_execute_timed records two events per launch on the stream the
+    # launch runs on; the result equals an untimed run
+    from paper_2309_00628_amd import _lib as L
+    lib = L.load()
+    m = n = k = 1024
+    A, B = inputs.pair("uniform", m, n, k, 33, np.float32)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    p = api.Plan("winograd", "grouped", m, n, k, cutoff=1, levels=2, overlap=True)
+    ws = torch.empty(p.ws_bytes, dtype=torch.uint8, device="cuda")
+    ref = torch.empty((m, n), device="cuda")
+    p(At, Bt, ref, ws)
+    nops = p.info["launches"]
+    kinds = [lib.mm_plan_op_kind(p._ptr, j) for j in range(nops)]
+    assert kinds[0] == 2 and 3 in kinds and any(x >= 4 for x in kinds)
+    assert lib.mm_plan_op_kind(p._ptr, nops) == -1
+    s = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nops)]
+    for e in evs:
+        e.record(s)
+    torch.cuda.synchronize()
+    arr = (ctypes.c_void_p * (2 * nops))(*[e.cuda_event for e in evs])
+    C = torch.full((m, n), float("nan"), device="cuda")
+    assert lib.mm_plan_execute_timed(p._ptr, At.data_ptr(), Bt.data_ptr(), C.data_ptr(), ws.data_ptr(),
+                                     ws.numel(), s.cuda_stream, arr, 2 * nops - 1) == 1  # MM_E_INVALID
+    L.check(lib.mm_plan_execute_timed(p._ptr, At.data_ptr(), Bt.data_ptr(), C.data_ptr(), ws.data_ptr(),
+                                      ws.numel(), s.cuda_stream, arr, 2 * nops))
+    torch.cuda.synchronize()
+    assert torch.equal(C, ref)
+    durs = [evs[2 * j].elapsed_time(evs[2 * j + 1]) for j in range(nops)]
+    assert all(d >= 0 for d in durs)
+    assert evs[0].elapsed_time(evs[-1]) >= max(durs) * 0.99

@@ -115,9 +115,46 @@ def test_grouped_launch_count_and_leaves(lib):
         assert info["levels"] == L_
         assert info["launches"] == 2 * L_ + 1
         assert info["leaves"] == 7 ** L_ and info["fused"] == 0
+        # with MM_PLAN_OVERLAP: fork, L S/T passes (auxiliary stream), the
+        # products of blocks of A and B, join, the other products, L U passes
+        _, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_, overlap=True)
+        assert info["launches"] == 2 * L_ + 4
         # with MM_PLAN_FUSE the last level's S/T pass is formed in the leaf loader
         _, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_, fuse=True)
         assert info["launches"] == 2 * L_ and info["fused"] == 1
+
+
+def test_grouped_overlap_window(lib):
+    # one level: the S and T passes run on the auxiliary stream beside
+    # P1 = A11 B11 and P2 = A12 B21, which read only blocks of A and B
+    text, info = L.describe("winograd", "grouped", 512, 512, 512, cutoff=1, levels=1, overlap=True)
+    lines = [l for l in text.splitlines() if l in ("FORK", "JOIN") or l.startswith("LAUNCH")]
+    assert lines[0] == "FORK" and lines[1].endswith(" aux") and lines[1].startswith("LAUNCH EW")
+    assert lines[2].startswith("LAUNCH GEMM 2 ") and lines[3] == "JOIN"
+    assert lines[4].startswith("LAUNCH GEMM 5 ") and lines[5].startswith("LAUNCH EW")
+    # with the fused loader at one level there is nothing left to overlap
+    text, info = L.describe("winograd", "grouped", 512, 512, 512, cutoff=1, levels=1, fuse=True,
+                            overlap=True)
+    assert "FORK" not in text and " aux" not in text and info["launches"] == 2
+    for lv in (1, 2, 3):
+        text, info = L.describe("winograd", "grouped", 1024, 1024, 1024, cutoff=1, levels=lv, overlap=True)
+        plain = [l for l in text.split("JOIN")[0].splitlines() if l.startswith("GEMM")]
+        assert len(plain) == 2 ** lv        # products of plain blocks of A and B
+
+
+@pytest.mark.parametrize("m,n,k,levels,fuse", [(64, 64, 64, 1, False), (96, 40, 56, 2, False),
+                                               (200, 136, 72, 3, False), (1000, 777, 555, 2, True),
+                                               (130, 70, 90, 2, False)])
+def test_overlapped_plan_is_exact(lib, m, n, k, levels, fuse):
+    A = inputs.integers((m, k), 25, dtype=np.int64)
+    B = inputs.integers((k, n), 26, dtype=np.int64)
+    text, info = L.describe("winograd", "grouped", m, n, k, cutoff=1, levels=levels, dtype="f32", fuse=fuse,
+                            overlap=True)
+    assert "FORK" in text
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    C = np.full(m * n, -(10**9), dtype=np.int64)
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
+    assert np.array_equal(C.reshape(m, n), A @ B)
 
 
 @pytest.mark.parametrize("m,n,k,cutoff,levels", [(16, 16, 16, 1, 1), (32, 64, 16, 1, 2), (64, 64, 64, 4, -1),
