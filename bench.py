@@ -87,10 +87,11 @@ def time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup):
 
 def plan_launches(plan, esz):
     """Per launch of a plan (in launch order): its kind ("EW", "GEMM",
-    "FORK", "JOIN"), stream (0 caller's, 1 auxiliary), algorithmic flops
-    (GEMM: 2 m n k per leaf product) and algorithmic HBM bytes (EW: every
-    valid input element read once, every valid output element written once),
-    read off the plan listing."""
+    "WINO", "FORK", "JOIN"), stream (0 caller's, 1 auxiliary), algorithmic
+    flops (GEMM: 2 m n k per leaf product; WINO: seven such products per
+    subproblem) and algorithmic HBM bytes (EW: every valid input element read
+    once, every valid output element written once), read off the plan
+    listing."""
     out, flops, nbytes = [], 0.0, 0.0
     for line in plan.describe().splitlines():
         w = line.split()
@@ -104,6 +105,9 @@ def plan_launches(plan, esz):
         elif w[0] == "GEMM":
             m, n, k = map(int, w[1:4])
             flops += 2.0 * m * n * k
+        elif w[0] == "WINO":
+            m, n, k = map(int, w[1:4])
+            flops += 7 * 2.0 * m * n * k
         elif w[0] == "EW":
             _, ins, outs = [x.strip() for x in line.split("|")]
             for tok in (ins + " " + outs).split():
@@ -139,19 +143,21 @@ def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtyp
 
 
 def gemm_roofline(res, n):
-    """Roofline of the dominant kernel: the leaf-product GEMM launch with the
-    most flops (on the caller's stream, not sharing the GPU with the
-    overlapped S/T pass)."""
+    """Roofline of the dominant kernel: the leaf-product launch (plain GEMM
+    group or fused last Winograd level) with the most flops, on the caller's
+    stream (not sharing the GPU with an overlapped S/T pass)."""
     launches = plan_launches(res["plan"], 4)
-    best = None
+    best, kind = None, 1
     for lau, d, k in zip(launches, res["per_op"], res["kinds"]):
-        if k == 1 and (best is None or lau["flops"] > best[0]):
+        if k in (1, 4) and (best is None or lau["flops"] > best[0]):
+            kind = k
             best = (lau["flops"], sum(d) / len(d))
     flops, avg_ms = best if best else (0.0, float("nan"))
     achieved = flops / (avg_ms * 1e-3) / 1e12
     return dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=None,
-                kernel="gemm_kernel<float> (grouped leaf products)",
+                kernel=("gemm_wino_kernel (last level: products + U in registers)" if kind == 4
+                        else "gemm_kernel<float> (grouped leaf products)"),
                 flops_per_launch=flops, avg_launch_ms=round(avg_ms, 4))
 
 
@@ -161,9 +167,9 @@ def ew_bandwidth(res, n):
     launches = plan_launches(res["plan"], 4)
     out = []
     for lau, d, k in zip(launches, res["per_op"], res["kinds"]):
-        if k % 4 == 0:
+        if k % 8 == 0:
             ms = sum(d) / len(d)
-            out.append(dict(stream="aux" if k >= 4 else "main", bytes=lau["bytes"], ms=round(ms, 4),
+            out.append(dict(stream="aux" if k >= 8 else "main", bytes=lau["bytes"], ms=round(ms, 4),
                             gbs=round(lau["bytes"] / (ms * 1e-3) / 1e9, 1)))
     return out
 

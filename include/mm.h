@@ -159,11 +159,20 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                              split over two launches.  Results are bitwise the same as
                              without the flag; whether it is faster depends on the shape
                              and tile (the autotuner tries both). */
+#define MM_PLAN_LEAF_U 8u /* Strassen-Winograd, grouped schedule, float32: run the last level
+                            as one kernel in which each workgroup forms the seven products
+                            (Section 2.3) of one output tile and their U combinations in
+                            registers, so no product is stored and the last level's U pass
+                            disappears.  Sums are rounded in the same order as the separate
+                            U pass: results are bitwise the same.  Ignored for other dtypes
+                            and schedules; excludes MM_PLAN_FUSE. */
 /* Force the MFMA GEMM tile configuration c (0 .. 7) for every leaf launch
  * instead of the planner's choice.  float32: 0 128x128 (BK 32), 1 256x128,
  * 2 128x256, 3 256x256 (BK 16), 4 64x128, 5 128x64, 6 256x128 (BK 16),
  * 7 128x128 (BK 16); float64: 0 128x128,
- * 5 128x64 (others fall back to 0). */
+ * 5 128x64 (others fall back to 0).  With MM_PLAN_LEAF_U in effect c picks
+ * the fused leaf-level kernel's tile instead: 0 128x128 (4 waves), 1 128x128
+ * (8 waves), 2 64x128 (4 waves). */
 #define MM_PLAN_TILE(c) ((unsigned)((c) + 1) << 8)
 
 /* Build (once) the launch sequence and device descriptor table of one
@@ -188,15 +197,16 @@ int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, s
                           hipStream_t stream, hipEvent_t* events, int nevents);
 
 /* Kind of launch i of a plan: 0 element-wise block operations, 1 MFMA GEMM
- * group (leaf products), 2 fork to / 3 join of the plan's auxiliary stream;
- * plus 4 when the launch runs on the auxiliary stream; -1 if i is out of
- * range. */
+ * group (leaf products), 2 fork to / 3 join of the plan's auxiliary stream,
+ * 4 fused last Winograd level (MM_PLAN_LEAF_U); plus 8 when the launch runs
+ * on the auxiliary stream; -1 if i is out of range. */
 int mm_plan_op_kind(mm_plan_t plan, int i);
 
 /* Plan facts: info[0] workspace bytes, [1] levels L, [2..4] padded m, n, k,
  * [5] kernel launches per execution, [6] leaf products, [7] schedule used,
  * [8] leaf edge (rows of a leaf block), [9] 1 if the last level's operand
- * sums are formed in the leaf loader.  Returns the number of entries written. */
+ * sums are formed in the leaf loader, [10] 1 if the last level runs as the
+ * fused products-and-U kernel.  Returns the number of entries written. */
 int mm_plan_info(mm_plan_t plan, int64_t* info, int ninfo);
 
 /* Human-readable listing of the launch sequence (one line per block

@@ -23,6 +23,7 @@ MM_SCHED_TWO_TEMP, MM_SCHED_IN_PLACE, MM_SCHED_GROUPED, MM_SCHED_DFS3, MM_SCHED_
 MM_PLAN_GRAPH = 1
 MM_PLAN_FUSE = 2
 MM_PLAN_OVERLAP = 4
+MM_PLAN_LEAF_U = 8
 
 
 def plan_tile(c):
@@ -116,20 +117,21 @@ def check(status):
 
 
 def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None, ldc=None,
-             fuse=False, overlap=False):
+             fuse=False, overlap=False, leaf_u=False):
     """Host-only plan listing and facts (no device needed)."""
     lib = load()
     lda = max(k, 1) if lda is None else lda
     ldb = max(n, 1) if ldb is None else ldb
     ldc = max(n, 1) if ldc is None else ldc
-    info = (ctypes.c_int64 * 10)()
+    info = (ctypes.c_int64 * NINFO)()
     args = (ALGOS.get(algo, algo), SCHEDS.get(sched, sched), m, n, k, lda, ldb, ldc, cutoff, levels,
-            DTYPES.get(dtype, dtype), (MM_PLAN_FUSE if fuse else 0) | (MM_PLAN_OVERLAP if overlap else 0))
-    need = lib.mm_describe(*args, None, 0, info, 10)
+            DTYPES.get(dtype, dtype), (MM_PLAN_FUSE if fuse else 0) | (MM_PLAN_OVERLAP if overlap else 0) |
+            (MM_PLAN_LEAF_U if leaf_u else 0))
+    need = lib.mm_describe(*args, None, 0, info, NINFO)
     if need == 0:
         raise MMError(1, last_error())
     buf = ctypes.create_string_buffer(need + 1)
-    lib.mm_describe(*args, buf, need + 1, info, 10)
+    lib.mm_describe(*args, buf, need + 1, info, NINFO)
     return buf.value.decode(), _info_dict(info)
 
 
@@ -143,18 +145,20 @@ def batched_describe(mnk, addrs, dtype="f32", cutoff=None, levels=None):
     C = (c_vp * cnt)(*[c for _, _, c in addrs])
     cp = (c_int * cnt)(*cutoff) if cutoff is not None else None
     lp = (c_int * cnt)(*levels) if levels is not None else None
-    info = (ctypes.c_int64 * 10)()
+    info = (ctypes.c_int64 * NINFO)()
     need = lib.mm_batched_describe(cnt, flat, A, B, C, DTYPES.get(dtype, dtype), cp, lp, None, 0,
-                                   info, 10)
+                                   info, NINFO)
     if need == 0:
         raise MMError(1, last_error())
     buf = ctypes.create_string_buffer(need + 1)
     lib.mm_batched_describe(cnt, flat, A, B, C, DTYPES.get(dtype, dtype), cp, lp, buf, need + 1,
-                            info, 10)
+                            info, NINFO)
     return buf.value.decode(), _info_dict(info)
 
 
-INFO_KEYS = ("ws_bytes", "levels", "M", "N", "K", "launches", "leaves", "sched", "leaf_rows", "fused")
+INFO_KEYS = ("ws_bytes", "levels", "M", "N", "K", "launches", "leaves", "sched", "leaf_rows", "fused",
+             "leaf_u")
+NINFO = len(INFO_KEYS)
 
 
 def _info_dict(info):

@@ -48,7 +48,7 @@ class Plan:
     """A built launch sequence for one product shape (mm_plan_create)."""
 
     def __init__(self, algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None,
-                 ldc=None, graph=False, device=None, tile=None, fuse=False, overlap=False):
+                 ldc=None, graph=False, device=None, tile=None, fuse=False, overlap=False, leaf_u=False):
         lib = L.load()
         self.algo, self.sched, self.dtype = algo, sched, dtype
         self.m, self.n, self.k = m, n, k
@@ -63,9 +63,10 @@ class Plan:
                                        self.ldc, cutoff, levels, L.DTYPES[dtype],
                                        (L.MM_PLAN_GRAPH if graph else 0) | L.plan_tile(tile) |
                                        (L.MM_PLAN_FUSE if fuse else 0) |
-                                       (L.MM_PLAN_OVERLAP if overlap else 0), ctypes.byref(self._ptr)))
-        info = (ctypes.c_int64 * 10)()
-        lib.mm_plan_info(self._ptr, info, 10)
+                                       (L.MM_PLAN_OVERLAP if overlap else 0) |
+                                       (L.MM_PLAN_LEAF_U if leaf_u else 0), ctypes.byref(self._ptr)))
+        info = (ctypes.c_int64 * L.NINFO)()
+        lib.mm_plan_info(self._ptr, info, L.NINFO)
         self.info = L._info_dict(info)
         self.ws_bytes = self.info["ws_bytes"]
 
@@ -113,20 +114,20 @@ def workspace(nbytes, device, stream):
 
 
 def get_plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile=None,
-             fuse=False, overlap=False):
+             fuse=False, overlap=False, leaf_u=False):
     key = (str(device), algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, tile, fuse,
-           overlap)
+           overlap, leaf_u)
     with _plans_lock:
         p = _plans.get(key)
         if p is None:
             p = Plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile, fuse,
-                     overlap)
+                     overlap, leaf_u)
             _plans[key] = p
     return p
 
 
 def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None, out=None,
-       graph=False, stream=None, clobber_inputs=False, tile=None, fuse=False, overlap=None):
+       graph=False, stream=None, clobber_inputs=False, tile=None, fuse=False, overlap=None, leaf_u=None):
     """C = A @ B on the GPU by ``algo`` in {"naive", "strassen", "winograd"}.
 
     ``cutoff`` / ``levels`` control the recursion as in mm.h; when both are
@@ -136,8 +137,8 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
     ``sched``: "auto", "grouped", "two_temp", "in_place" (Winograd) or
     "dfs3" (Strassen).  ``dtype``: None (from the tensors), "f64", "f32" or
     "bf16x3" (float32 tensors, split-bfloat16 leaf products).  ``fuse`` /
-    ``overlap``: MM_PLAN_FUSE / MM_PLAN_OVERLAP (None: the autotuner's choice
-    when it picks the recursion, else off).  The in-place
+    ``overlap`` / ``leaf_u``: MM_PLAN_FUSE / MM_PLAN_OVERLAP / MM_PLAN_LEAF_U
+    (None: the autotuner's choice when it picks the recursion, else off).  The in-place
     schedule overwrites its operands, so unless ``clobber_inputs`` is set the
     wrapper hands it copies.
     """
@@ -172,12 +173,14 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
                 tile = ch["tile"]
             if overlap is None:
                 overlap = bool(ch.get("overlap", False))
+            if leaf_u is None:
+                leaf_u = bool(ch.get("leaf_u", False))
     elif cutoff is None:
         cutoff = 1
     elif levels is None:
         levels = -1
     p = get_plan(algo, sched, m, n, k, cutoff, levels, dt, lda, ldb, ldc, graph, A.device, tile, fuse,
-                 bool(overlap))
+                 bool(overlap), bool(leaf_u))
     with torch.cuda.device(A.device):
         p(A, B, C, stream=stream)
     return C
@@ -217,8 +220,8 @@ class BatchedPlan:
             L.check(lib.mm_batched_plan_create(cnt, flat, Ap, Bp, Cp, L.DTYPES[dt], cp, lp,
                                                (L.MM_PLAN_GRAPH if graph else 0) | L.plan_tile(tile),
                                                ctypes.byref(self._ptr)))
-        info = (ctypes.c_int64 * 10)()
-        lib.mm_plan_info(self._ptr, info, 10)
+        info = (ctypes.c_int64 * L.NINFO)()
+        lib.mm_plan_info(self._ptr, info, L.NINFO)
         self.info = L._info_dict(info)
         self.ws_bytes = self.info["ws_bytes"]
         self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)

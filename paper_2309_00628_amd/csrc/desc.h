@@ -86,6 +86,20 @@ struct GemmDesc {
   GemmOut out[2];
 };
 
+// One subproblem at the last level of a Winograd recursion, done by one
+// launch that forms the seven leaf products and the U combinations of
+// Section 2.3 tile by tile in registers (no product is stored):
+//   P1 = A11 B11, P2 = A12 B21, P3 = S4 B22, P4 = A22 T4,
+//   P5 = S1 T1,   P6 = S2 T2,   P7 = S3 T3,
+//   C11 = P1 + P2, C12 = U5, C21 = U6, C22 = U7.
+struct WinoLeafDesc {
+  MView a[7], b[7];    // operands of P1 .. P7
+  MView c[4];          // C11 C12 C21 C22
+  int32_t m, n, k;     // product extents: operand A m x k, B k x n
+  int32_t tiles_m, tiles_n;
+  int32_t tile_start;  // first tile of this subproblem in the launch
+};
+
 struct KernelBases {
   void* p[kNumBases];
   int32_t aligned;  // bit b set: base b is 16-byte aligned

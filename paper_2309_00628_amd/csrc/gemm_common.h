@@ -66,15 +66,15 @@ struct TileRef {
 // With remap == 0 (launches of unequal problems, sorted longest first) the
 // hardware's round-robin spreads every run of 8 consecutive tiles over the
 // 8 XCDs, which balances the XCDs and starts the longest tiles first.
-template <int BM, int BN>
-__device__ __forceinline__ TileRef locate_tile(const GemmDesc* __restrict__ descs, int ndesc, int remap) {
+template <int BM, int BN, typename Desc>
+__device__ __forceinline__ TileRef locate_tile(const Desc* __restrict__ descs, int ndesc, int remap) {
   const int rb = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (descs[mid].tile_start <= rb) lo = mid; else hi = mid - 1;
   }
-  const GemmDesc& D = descs[lo];
+  const Desc& D = descs[lo];
   const int lt = rb - D.tile_start;
   const int tiles_m = D.tiles_m, tiles_n = D.tiles_n;
   constexpr int GROUP = 8;

@@ -1,0 +1,297 @@
+// The K loop of one output tile of a leaf product on the MFMA units, shared
+// by the GEMM kernels that accumulate products tile by tile: the plain /
+// grouped leaf-product kernel and the kernel that forms a Winograd level's
+// seven products and their U combinations in registers.
+//
+// Workgroup: a BM x BN tile of C split among WGM x WGN wave64s.  The K loop
+// stages BM x BK and BK x BN tiles of A and B in LDS, double-buffered: the
+// global loads of stage t+1 are in flight while the MFMAs consume stage t,
+// one barrier per stage.
+//
+// LDS layout ("k-chunked"): a 16-byte chunk holds E consecutive k values
+// (E = 4 floats / 2 doubles) of one row of A or one column of B, so every MFMA
+// operand fetch is one ds_read_b128 that feeds E MFMAs.  Row (A) and column
+// (B) indices are XOR-swizzled so that both the stores of the global tile and
+// the fragment reads touch 16 distinct 16-byte bank groups per 16 lanes.
+//
+// Edges: operand reads outside a view's valid extent are zero (this is also
+// how quadrants of a zero-padded matrix are read without a copy).  Interior
+// tiles take an unmasked vector path.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "desc.h"
+#include "gemm_common.h"
+
+namespace mm {
+namespace gemm_detail {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct MT;
+
+// v_mfma_f32_32x32x2_f32: lanes 0-31 supply k = 0 and lanes 32-63 k = 1 of a
+// 32 x 2 by 2 x 32 product; lane l holds A[l % 32][l / 32] and B[l / 32][l % 32].
+// Result register r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+template <>
+struct MT<float> {
+  static constexpr int TM = 32;  // MFMA tile edge
+  static constexpr int KG = 2;   // lane groups along k
+  static constexpr int E = 4;    // elements per 16-byte chunk
+  static constexpr int NACC = 16;
+  typedef f32x16 acc_t;
+  typedef f32x4 chunk_t;
+  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) {
+    return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+  }
+};
+
+// v_mfma_f64_16x16x4_f64: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16];
+// result register r of lane l is C[4 r + l / 16][l % 16] (rows interleaved
+// across the four lane groups, unlike the float32 16x16 form).
+template <>
+struct MT<double> {
+  static constexpr int TM = 16;
+  static constexpr int KG = 4;
+  static constexpr int E = 2;
+  static constexpr int NACC = 4;
+  typedef f64x4 acc_t;
+  typedef f64x2 chunk_t;
+  static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+
+constexpr int BKC_MAX = 8;
+
+// One operand of a tile product: element (r, c) at p[r * ld + c], zero
+// outside [0, vrows) x [0, vcols); vec: p and ld allow 16-byte loads.
+template <typename T>
+struct Operand {
+  const T* __restrict__ p;
+  int64_t ld;
+  int vrows, vcols;
+  bool vec;
+};
+
+template <typename T>
+__device__ __forceinline__ Operand<T> operand(const KernelBases& kb, const MView& v) {
+  return Operand<T>{resolve<T>(kb, v), v.ld, v.vrows, v.vcols, view_vec(kb, v)};
+}
+
+// BM x BN tile per workgroup, WGM x WGN waves (each (BM/WGM) x (BN/WGN)),
+// BKC 16-byte chunks of k per LDS stage.
+template <typename T, int BM, int BN, int BKC, int WGM, int WGN>
+struct TileLoop {
+  typedef MT<T> M;
+  typedef typename M::chunk_t chunk_t;
+  typedef typename M::acc_t acc_t;
+  static constexpr int NT = 64 * WGM * WGN;
+  static constexpr int E = M::E;
+  static constexpr int TM = M::TM;
+  static constexpr int WM = BM / WGM, WN = BN / WGN;
+  static constexpr int FM = WM / TM, FN = WN / TM;
+  static constexpr int BK = BKC * E;
+  static constexpr int NBLK_B = BKC * (BN / E);      // E x E blocks of B per stage
+  static constexpr int NB = (NBLK_B + NT - 1) / NT;  // ... per thread
+  static constexpr int NCH_A = BM * BKC;             // chunks of A per stage
+  static constexpr int NA = (NCH_A + NT - 1) / NT;
+  static constexpr int KB = BKC / M::KG;             // k-blocks per stage
+  static constexpr int KMID = KB / 2;
+  static_assert(FM >= 1 && FN >= 1 && WM % TM == 0 && WN % TM == 0, "wave tile");
+  static_assert(BKC % M::KG == 0 && BKC <= BKC_MAX && 16 % BKC == 0, "k chunks");
+
+  struct Smem {
+    chunk_t As[2][BKC][BM];
+    chunk_t Bs[2][BKC][BN];
+  };
+
+  typedef acc_t Acc[FM][FN];
+
+  static __device__ __forceinline__ void zero(Acc& acc) {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < M::NACC; ++r) acc[a][b][r] = T(0);
+  }
+
+  // Global -> register staging of stage kt.
+  // LOAD_FULL: the whole stage is inside both operands' valid extents and
+  // every access is a 16-byte vector load (no masks, no branches, so the
+  // loads of the next stage stay in flight while the MFMAs of this one run).
+  // LOAD_EDGE_VEC: edge tile of aligned operands whose valid widths are
+  // multiples of the chunk: whole chunks are in or out, selected without
+  // branches (the validity is applied when the stage is written to LDS, not
+  // right after the load, which would wait for it).  Otherwise per-element
+  // masked loads.
+  template <int MODE>
+  static __device__ __forceinline__ void load_tile(const Operand<T>& A, const Operand<T>& B, int i0, int j0,
+                                                   int kt, chunk_t (&ra)[NA], chunk_t (&rbk)[NB][E],
+                                                   uint32_t& amask, uint32_t& bmask) {
+    const int tid = threadIdx.x;
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + NT * i;
+      if (NCH_A % NT != 0 && q >= NCH_A) break;
+      const int row = q / BKC, kc = q % BKC;
+      const int gr = i0 + row, gc = k0 + kc * E;
+      const T* p = A.p + (int64_t)gr * A.ld + gc;
+      if (MODE == LOAD_FULL) {
+        ra[i] = *reinterpret_cast<const chunk_t*>(p);
+      } else if (MODE == LOAD_EDGE_VEC) {
+        const bool ok = gr < A.vrows && gc < A.vcols;
+        ra[i] = *reinterpret_cast<const chunk_t*>(ok ? p : A.p);
+        amask = ok ? (amask | (1u << i)) : (amask & ~(1u << i));
+      } else if (A.vec && gr < A.vrows && gc + E <= A.vcols) {
+        ra[i] = *reinterpret_cast<const chunk_t*>(p);
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          ra[i][e] = (gr < A.vrows && gc + e < A.vcols) ? p[e] : T(0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + NT * i;
+      if (NBLK_B % NT != 0 && q >= NBLK_B) break;
+      const int kc = q / (BN / E), cb = q % (BN / E);
+      const int gc = j0 + cb * E;
+#pragma unroll
+      for (int rr = 0; rr < E; ++rr) {
+        const int gr = k0 + kc * E + rr;
+        const T* p = B.p + (int64_t)gr * B.ld + gc;
+        if (MODE == LOAD_FULL) {
+          rbk[i][rr] = *reinterpret_cast<const chunk_t*>(p);
+        } else if (MODE == LOAD_EDGE_VEC) {
+          const bool ok = gr < B.vrows && gc < B.vcols;
+          rbk[i][rr] = *reinterpret_cast<const chunk_t*>(ok ? p : B.p);
+          const uint32_t bit = 1u << (i * E + rr);
+          bmask = ok ? (bmask | bit) : (bmask & ~bit);
+        } else if (B.vec && gr < B.vrows && gc + E <= B.vcols) {
+          rbk[i][rr] = *reinterpret_cast<const chunk_t*>(p);
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+            rbk[i][rr][e] = (gr < B.vrows && gc + e < B.vcols) ? p[e] : T(0);
+        }
+      }
+    }
+  }
+
+  template <int MODE>
+  static __device__ __forceinline__ void store_tile(Smem& sm, int buf, const chunk_t (&ra)[NA],
+                                                    const chunk_t (&rbk)[NB][E], uint32_t amask,
+                                                    uint32_t bmask) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + NT * i;
+      if (NCH_A % NT != 0 && q >= NCH_A) break;
+      const int row = q / BKC, kc = q % BKC;
+      sm.As[buf][kc][swz_a<BKC>(row, kc)] =
+          (MODE != LOAD_EDGE_VEC || ((amask >> i) & 1)) ? ra[i] : chunk_t{};
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + NT * i;
+      if (NBLK_B % NT != 0 && q >= NBLK_B) break;
+      const int kc = q / (BN / E), cb = q % (BN / E);
+#pragma unroll
+      for (int c = 0; c < E; ++c) {
+        chunk_t t;
+#pragma unroll
+        for (int rr = 0; rr < E; ++rr)
+          t[rr] = (MODE != LOAD_EDGE_VEC || ((bmask >> (i * E + rr)) & 1)) ? rbk[i][rr][c] : T(0);
+        sm.Bs[buf][kc][swz_b<E>(cb * E + c)] = t;
+      }
+    }
+  }
+
+  // MFMAs of k-blocks [KLO, KHI) of one LDS stage (a k-block is KG * E k
+  // values).  The fragments of k-block j+1 are read into a second register
+  // set while the MFMAs of k-block j run.
+  template <int KLO, int KHI>
+  static __device__ __forceinline__ void compute(const Smem& sm, int buf, Acc& acc) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int g = lane / TM, t = lane % TM;
+    chunk_t fa[2][FM], fb[2][FN];
+    auto read_frags = [&](int kb2, chunk_t (&xa)[FM], chunk_t (&xb)[FN]) {
+      const int plane = kb2 * M::KG + g;
+#pragma unroll
+      for (int a = 0; a < FM; ++a) xa[a] = sm.As[buf][plane][swz_a<BKC>(wm * WM + a * TM + t, plane)];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) xb[b] = sm.Bs[buf][plane][swz_b<E>(wn * WN + b * TM + t)];
+    };
+    read_frags(KLO, fa[0], fb[0]);
+#pragma unroll
+    for (int kb2 = KLO; kb2 < KHI; ++kb2) {
+      const int cur = (kb2 - KLO) & 1;
+      if (kb2 + 1 < KHI) read_frags(kb2 + 1, fa[cur ^ 1], fb[cur ^ 1]);
+#pragma unroll
+      for (int s = 0; s < E; ++s)
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) acc[a][b] = M::mfma(fa[cur][a][s], fb[cur][b][s], acc[a][b]);
+    }
+  }
+
+  // Pipeline: the global loads of stage t+1 are issued first; the stage is
+  // written to the other LDS buffer halfway through the MFMAs of stage t, so
+  // the wait for those loads and the LDS writes overlap the second half of
+  // the MFMAs; one barrier ends the stage.  Writing the other buffer is safe:
+  // every wave finished reading it before the barrier that ended stage t-1,
+  // and it is read again only after the barrier that ends stage t.  The loop
+  // ends with a barrier, so the next product may reuse the LDS at once.
+  template <int MODE>
+  static __device__ __forceinline__ void main_loop(Smem& sm, const Operand<T>& A, const Operand<T>& B, int i0,
+                                                   int j0, int ktiles, Acc& acc) {
+    chunk_t ra[NA];
+    chunk_t rbk[NB][E];  // E rows (k) of E columns
+    uint32_t amask = 0, bmask = 0;
+    load_tile<MODE>(A, B, i0, j0, 0, ra, rbk, amask, bmask);
+    store_tile<MODE>(sm, 0, ra, rbk, amask, bmask);
+    __syncthreads();
+    for (int kt = 0; kt < ktiles; ++kt) {
+      const int buf = kt & 1;
+      const bool more = kt + 1 < ktiles;
+      if (more) load_tile<MODE>(A, B, i0, j0, kt + 1, ra, rbk, amask, bmask);
+      compute<0, KMID>(sm, buf, acc);
+      if (more) store_tile<MODE>(sm, buf ^ 1, ra, rbk, amask, bmask);
+      compute<KMID, KB>(sm, buf, acc);
+      __syncthreads();
+    }
+  }
+
+  // acc += A[i0 : i0 + BM, 0 : K] B[0 : K, j0 : j0 + BN].
+  static __device__ __forceinline__ void product(Smem& sm, const Operand<T>& A, const Operand<T>& B, int i0,
+                                                 int j0, int K, Acc& acc) {
+    const int ktiles = (K + BK - 1) / BK;
+    if (ktiles <= 0) return;
+    const bool interior = A.vec && B.vec && (i0 + BM <= A.vrows) && (j0 + BN <= B.vcols) && (K % BK == 0) &&
+                          (K <= A.vcols) && (K <= B.vrows);
+    const bool edge_vec = A.vec && B.vec && A.vrows > 0 && A.vcols > 0 && B.vrows > 0 && B.vcols > 0 &&
+                          A.vcols % E == 0 && B.vcols % E == 0;
+    if (interior)
+      main_loop<LOAD_FULL>(sm, A, B, i0, j0, ktiles, acc);
+    else if (edge_vec)
+      main_loop<LOAD_EDGE_VEC>(sm, A, B, i0, j0, ktiles, acc);
+    else
+      main_loop<LOAD_MASKED>(sm, A, B, i0, j0, ktiles, acc);
+  }
+};
+
+}  // namespace gemm_detail
+}  // namespace mm

@@ -1,0 +1,119 @@
+// The last level of a Strassen-Winograd recursion in one launch: each
+// workgroup computes one BM x BN tile of the four output quadrants of one
+// subproblem by running the seven leaf products of Section 2.3 on that tile
+// one after another (float32 MFMA, the K loop of gemm_tile.h) and forming
+// the U combinations in registers:
+//   U1 = P1 + P2 -> C11,  U2 = P1 + P6,  U3 = U2 + P7,  U4 = U2 + P5,
+//   U5 = U4 + P3 -> C12,  U6 = U3 - P4 -> C21,  U7 = U3 + P5 -> C22.
+// No product is written to memory, so the seven product stores and the
+// separate U pass (seven reads and four writes of a quadrant) disappear.
+// The products are ordered so that at most three tile accumulators are
+// live; every sum is rounded in the order of the separate U pass, so the
+// result has the same bits as the three-step path (products, then U).
+#include <hip/hip_runtime.h>
+
+#include "desc.h"
+#include "gemm_common.h"
+#include "gemm_tile.h"
+#include "kernels.h"
+
+namespace mm {
+
+namespace {
+
+using namespace gemm_detail;
+
+template <int BM, int BN, int BKC, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_wino_kernel(KernelBases kb,
+                                                                   const WinoLeafDesc* __restrict__ descs,
+                                                                   int ndesc, int remap) {
+  typedef TileLoop<float, BM, BN, BKC, WGM, WGN> TL;
+  typedef MT<float> M;
+  typedef typename TL::Acc Acc;
+  constexpr int FM = TL::FM, FN = TL::FN, TM = TL::TM;
+  __shared__ typename TL::Smem sm;
+
+  const TileRef tr = locate_tile<BM, BN>(descs, ndesc, remap);
+  const WinoLeafDesc& D = descs[tr.desc];
+  const int i0 = tr.i0, j0 = tr.j0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+
+  auto prod = [&](int p, Acc& acc) {
+    TL::zero(acc);
+    TL::product(sm, operand<float>(kb, D.a[p]), operand<float>(kb, D.b[p]), i0, j0, D.k, acc);
+  };
+  // v(a, b) gives the 16 values of MFMA tile (a, b) this lane stores.
+  auto store = [&](const MView& cv, auto v) {
+    float* __restrict__ Cp = resolve<float>(kb, cv);
+    const int t = lane % TM;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const typename M::acc_t x = v(a, b);
+        const int col = j0 + wn * TL::WN + b * TM + t;
+        const int rbase = i0 + wm * TL::WM + a * TM;
+        float* cpt = Cp + (int64_t)rbase * cv.ld + col;
+#pragma unroll
+        for (int r = 0; r < M::NACC; ++r) {
+          const int rr = M::row(lane, r);
+          if (rbase + rr < cv.vrows && col < cv.vcols) cpt[(int64_t)rr * cv.ld] = x[r];
+        }
+      }
+  };
+  auto add_to = [](Acc& x, const Acc& y) {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) x[a][b] = x[a][b] + y[a][b];
+  };
+
+  Acc X, Y, Z;
+  prod(0, X);                                                    // P1
+  prod(1, Y);                                                    // P2
+  store(D.c[0], [&](int a, int b) { return X[a][b] + Y[a][b]; });  // C11 = U1
+  prod(5, Y);                                                    // P6
+  add_to(X, Y);                                                  // X = U2
+  prod(6, Y);                                                    // P7
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) Y[a][b] = X[a][b] + Y[a][b];    // Y = U3
+  prod(4, Z);                                                    // P5
+  store(D.c[3], [&](int a, int b) { return Y[a][b] + Z[a][b]; });  // C22 = U7
+  add_to(X, Z);                                                  // X = U4
+  prod(2, Z);                                                    // P3
+  add_to(X, Z);                                                  // X = U5
+  store(D.c[1], [&](int a, int b) { return X[a][b]; });          // C12
+  prod(3, Z);                                                    // P4
+  store(D.c[2], [&](int a, int b) { return Y[a][b] - Z[a][b]; });  // C21 = U6
+}
+
+template <int BM, int BN, int BKC, int WGM, int WGN>
+hipError_t launch_cfg(const KernelBases& kb, const WinoLeafDesc* d, int n, int tiles, int remap, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_wino_kernel<BM, BN, BKC, WGM, WGN>), dim3(tiles), dim3(64 * WGM * WGN), 0, s, kb, d,
+                     n, remap);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+GemmCfg gemm_wino_cfg(int cfg) {
+  switch (cfg) {
+    case 2: return {64, 128};
+    default: return {128, 128};
+  }
+}
+
+hipError_t launch_gemm_wino(int cfg, const KernelBases& kb, const WinoLeafDesc* d, int n, int tiles, int remap,
+                            hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  switch (cfg) {
+    case 1: return launch_cfg<128, 128, 8, 4, 2>(kb, d, n, tiles, remap, s);
+    case 2: return launch_cfg<64, 128, 8, 2, 2>(kb, d, n, tiles, remap, s);
+    default: return launch_cfg<128, 128, 8, 2, 2>(kb, d, n, tiles, remap, s);
+  }
+}
+
+}  // namespace mm

@@ -29,6 +29,12 @@ hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d,
 // quadrants (GemmDesc::kinds); aligned, fully valid operands only.
 hipError_t launch_gemm_fused(int cfg, const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap,
                              hipStream_t s);
+// Last-level Winograd subproblems: seven float32 products and their U
+// combinations per output tile (WinoLeafDesc); cfg as gemm_wino_cfg.
+constexpr int kNumWinoCfg = 3;
+GemmCfg gemm_wino_cfg(int cfg);
+hipError_t launch_gemm_wino(int cfg, const KernelBases& kb, const WinoLeafDesc* d, int n, int tiles, int remap,
+                            hipStream_t s);
 // remap: 1 = XCD-contiguous tile order (launches of equal problems),
 // 0 = hardware round-robin (unequal problems, sorted longest first).
 hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc* ddescs, int ndesc, int tiles,

@@ -48,7 +48,9 @@ int ew_dtype(int dtype) { return dtype == MM_F64 ? DT_F64 : DT_F32; }
 
 // OP_FORK: the auxiliary stream waits for the work enqueued so far on the
 // main stream; OP_JOIN: the main stream waits for the auxiliary stream.
-enum OpType { OP_EW = 0, OP_GEMM = 1, OP_FORK = 2, OP_JOIN = 3 };
+// OP_WINO: last-level Winograd subproblems, products and U combinations in
+// one kernel (WinoLeafDesc).
+enum OpType { OP_EW = 0, OP_GEMM = 1, OP_FORK = 2, OP_JOIN = 3, OP_WINO = 4 };
 
 struct OpRec {
   int type;
@@ -77,6 +79,8 @@ struct Plan {
   int tile_cfg = -1;  // forced GEMM tile configuration, -1: planner's choice
   bool fuse = false;  // fold the last level's S/T sums into the leaf loader
   bool overlap = false;  // run the S/T passes beside the products that do not need them
+  bool leaf_u = false;   // last level: products and U combinations in one kernel (float32)
+  bool wino = false;     // the plan has such a launch
   bool has_aux = false;  // some launches go to the auxiliary stream
   struct Aux {
     hipStream_t main, aux;
@@ -176,6 +180,7 @@ struct Builder {
   int cur_stream = 0;  // stream the next launches go to (0 main, 1 auxiliary)
   std::vector<GemmDesc> gm;
   std::vector<char> gm_fusable;  // descriptor satisfies the fused loader's preconditions
+  std::vector<WinoLeafDesc> wl;  // last-level subproblems of the current launch
   int gm_grid = 0;
   std::ostringstream txt;
 
@@ -337,7 +342,27 @@ struct Builder {
     txt << "JOIN\n";
   }
 
+  // One last-level Winograd subproblem C = A B with its S/T sums already
+  // formed: operands of P1 .. P7 and the output quadrants.
+  void wino(const MView (&a)[7], const MView (&bop)[7], const MView (&c)[4], int64_t m, int64_t n, int64_t k) {
+    if (!ew.empty() || !gm.empty()) flush();
+    WinoLeafDesc d;
+    std::memset(&d, 0, sizeof d);
+    for (int i = 0; i < 7; ++i) {
+      d.a[i] = a[i];
+      d.b[i] = bop[i];
+    }
+    for (int i = 0; i < 4; ++i) d.c[i] = c[i];
+    d.m = (int32_t)m;
+    d.n = (int32_t)n;
+    d.k = (int32_t)k;
+    P.leaves += 7;
+    if (m == 0 || n == 0) return;
+    wl.push_back(d);
+  }
+
   void flush() {
+    if (!wl.empty()) emit_wino();
     if (!ew.empty()) {
       OpRec r{OP_EW, ew_dtype(P.dtype), P.table.size(), (int)ew.size(), ew_grid, 0, 0, 0, cur_stream};
       const size_t bytes = ew.size() * sizeof(EwPart);
@@ -367,6 +392,36 @@ struct Builder {
       }
       gm_grid = 0;
     }
+  }
+
+  void emit_wino() {
+    int cfg = P.tile_cfg;
+    if (cfg < 0) {
+      int64_t t128 = 0;
+      for (const WinoLeafDesc& d : wl) t128 += ceil_div(d.m, 128) * ceil_div(d.n, 128);
+      cfg = t128 >= 256 ? 1 : 2;
+    }
+    const GemmCfg gc = gemm_wino_cfg(cfg);
+    int grid = 0;
+    for (WinoLeafDesc& d : wl) {
+      d.tiles_m = (int32_t)ceil_div(d.m, gc.bm);
+      d.tiles_n = (int32_t)ceil_div(d.n, gc.bn);
+      d.tile_start = grid;
+      grid += d.tiles_m * d.tiles_n;
+      txt << "WINO " << d.m << " " << d.n << " " << d.k << " |";
+      for (int i = 0; i < 7; ++i) txt << " " << vs(d.a[i]) << " " << vs(d.b[i]);
+      txt << " |";
+      for (int i = 0; i < 4; ++i) txt << " " << vs(d.c[i]);
+      txt << "\n";
+    }
+    OpRec r{OP_WINO, kernel_dtype(P.dtype), P.table.size(), (int)wl.size(), grid, cfg, 1, 0, cur_stream};
+    const size_t bytes = wl.size() * sizeof(WinoLeafDesc);
+    P.table.resize(round_up(P.table.size() + bytes, 256));
+    std::memcpy(P.table.data() + r.off, wl.data(), bytes);
+    P.ops.push_back(r);
+    txt << "LAUNCH WINO " << wl.size() << " " << grid << " " << cfg << (cur_stream ? " aux" : "") << "\n";
+    wl.clear();
+    P.wino = true;
   }
 
   void emit_gemm(std::vector<GemmDesc>& group, bool fused) {
@@ -649,10 +704,16 @@ bool can_fuse(const Builder& b, const Sub& s) {
 void sched_grouped(Builder& b, std::vector<Sub> subs) {
   const int L = b.P.L;
   std::vector<std::vector<EwPart>> u_levels;  // recorded, emitted in reverse
+  struct WinoSub {
+    MView a[7], b[7], c[4];
+    int64_t m, n, k;
+  };
+  std::vector<WinoSub> wl_pending;  // last-level subproblems (leaf_u)
   // The S/T passes run on the auxiliary stream while the leaf products whose
   // operands are plain blocks of A and B (P1 = A11 B11, P2 = A12 B21 at the
   // top level, and their counterparts below) run on the main stream.
-  const bool overlap_req = b.P.overlap && L >= 1;
+  const bool leaf_u = b.P.leaf_u && L >= 1;
+  const bool overlap_req = b.P.overlap && L >= 1 && !leaf_u;
   if (overlap_req) {
     b.fork();
     b.cur_stream = 1;
@@ -663,6 +724,23 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
     std::vector<std::array<MView, 11>> uargs;
     for (const Sub& s : subs) {
       const int64_t hm = s.A.rows / 2, hk = s.A.cols / 2, hn = s.B.cols / 2;
+      if (l == L - 1 && leaf_u) {
+        // products and U combinations of the last level in one kernel
+        const MView A11 = b.quad(s.A, 0, 0), A12 = b.quad(s.A, 0, 1), A21 = b.quad(s.A, 1, 0),
+                    A22 = b.quad(s.A, 1, 1);
+        const MView B11 = b.quad(s.B, 0, 0), B12 = b.quad(s.B, 0, 1), B21 = b.quad(s.B, 1, 0),
+                    B22 = b.quad(s.B, 1, 1);
+        MView S[4], T[4];
+        for (auto& v : S) v = b.temp(hm, hk);
+        for (auto& v : T) v = b.temp(hk, hn);
+        b.ew_part(EW_WINO_S, hm, hk, {A11, A12, A21, A22}, {S[0], S[1], S[2], S[3]});
+        b.ew_part(EW_WINO_T, hk, hn, {B11, B12, B21, B22}, {T[0], T[1], T[2], T[3]});
+        wl_pending.push_back({{A11, A12, S[3], A22, S[0], S[1], S[2]},
+                              {B11, B21, B22, T[3], T[0], T[1], T[2]},
+                              {b.quad(s.C, 0, 0), b.quad(s.C, 0, 1), b.quad(s.C, 1, 0), b.quad(s.C, 1, 1)},
+                              hm, hn, hk});
+        continue;
+      }
       if (l == L - 1 && can_fuse(b, s)) {
         // leaf operands read straight from the quadrants (fused loader)
         MView Pt[7];
@@ -719,6 +797,8 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
   }
   b.flush();
   b.cur_stream = 0;
+  for (const WinoSub& w : wl_pending) b.wino(w.a, w.b, w.c, w.m, w.n, w.k);
+  b.flush();
   auto plain = [](const Sub& s) {
     return s.A.base != MB_WS && s.B.base != MB_WS && s.akind == OK_PLAIN && s.bkind == OK_PLAIN;
   };
@@ -955,6 +1035,8 @@ int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEven
       const void* d = (const char*)P.dtable + op.off;
       if (op.type == OP_EW)
         e = launch_ew(op.kdtype, kb, (const EwPart*)d, op.count, op.grid, st);
+      else if (op.type == OP_WINO)
+        e = launch_gemm_wino(op.cfg, kb, (const WinoLeafDesc*)d, op.count, op.grid, op.remap, st);
       else
         e = op.fused ? launch_gemm_fused(op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, st)
                      : launch_gemm(op.kdtype, op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, st);
@@ -1074,7 +1156,13 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   P->tile_cfg = (int)((flags >> 8) & 0xff) - 1;
   P->fuse = (flags & MM_PLAN_FUSE) != 0;
   P->overlap = (flags & MM_PLAN_OVERLAP) != 0;
-  if (P->tile_cfg >= kNumGemmCfg) return fail(MM_E_INVALID, "unknown tile configuration");
+  // the fused Winograd leaf level computes in float32 and replaces the
+  // grouped schedule's last level; other dtypes and schedules ignore it
+  P->leaf_u = (flags & MM_PLAN_LEAF_U) != 0 && dtype == MM_F32 && sched == MM_SCHED_GROUPED &&
+              algo == MM_ALGO_WINOGRAD;
+  if (P->leaf_u && P->fuse) return fail(MM_E_INVALID, "MM_PLAN_FUSE and MM_PLAN_LEAF_U exclude each other");
+  if (P->tile_cfg >= (P->leaf_u ? kNumWinoCfg : kNumGemmCfg))
+    return fail(MM_E_INVALID, "unknown tile configuration");
   rc = build_plan(*P);
   if (rc != MM_OK) return rc;
   if (P->fused_reads_ab) {
@@ -1389,15 +1477,15 @@ int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, s
 
 int mm_plan_op_kind(mm_plan_t plan, int i) {
   if (!plan || !plan->p || i < 0 || i >= (int)plan->p->ops.size()) return -1;
-  return plan->p->ops[i].type + 4 * plan->p->ops[i].stream;
+  return plan->p->ops[i].type + 8 * plan->p->ops[i].stream;
 }
 
 int mm_plan_info(mm_plan_t plan, int64_t* info, int ninfo) {
   if (!plan || !plan->p || !info) return 0;
   const Plan& P = *plan->p;
-  const int64_t v[10] = {(int64_t)P.ws_bytes, P.L, P.M, P.N, P.K, (int64_t)P.ops.size(), P.leaves, P.sched,
-                         P.leaf_rows, P.fused ? 1 : 0};
-  const int cnt = std::min(ninfo, 10);
+  const int64_t v[11] = {(int64_t)P.ws_bytes, P.L, P.M, P.N, P.K, (int64_t)P.ops.size(), P.leaves, P.sched,
+                         P.leaf_rows, P.fused ? 1 : 0, P.wino ? 1 : 0};
+  const int cnt = std::min(ninfo, 11);
   for (int i = 0; i < cnt; ++i) info[i] = v[i];
   return cnt;
 }

@@ -6,7 +6,8 @@ the plan's auxiliary stream, between ``FORK`` and ``JOIN`` lines).  This
 module parses that listing and executes it on numpy buffers, doing per
 block what the kernels do per element: reads outside a view's valid extent give zero, writes there are
 dropped, element-wise recipes combine their inputs, GEMM descriptors form
-a @ b and apply their epilogues.  It also checks that no two operations of
+a @ b and apply their epilogues, and WINO descriptors (a last Winograd level
+in one kernel) form the seven products and write the four U combinations.  It also checks that no two operations of
 one launch touch memory in a conflicting way (the kernels of one launch run
 concurrently), and that launches on the two streams of a fork window never
 touch memory the other stream writes, so a planner bug shows up as a hazard
@@ -67,7 +68,13 @@ def parse(text):
             continue
         head, *rest = [s.strip() for s in line.split("|")]
         h = head.split()
-        if h[0] == "EW":
+        if h[0] == "WINO":
+            m, n, k = map(int, h[1:])
+            ops = [_view(t) for t in rest[0].split()]
+            cs = [_view(t) for t in rest[1].split()]
+            assert len(ops) == 14 and len(cs) == 4
+            cur.append(("WINO", dict(m=m, n=n, k=k, a=ops[0::2], b=ops[1::2], c=cs)))
+        elif h[0] == "EW":
             kind, rows, cols, m0, m1 = map(int, h[1:])
             ins = [_view(t) for t in rest[0].split()] if rest[0] else []
             outs = [_view(t) for t in rest[1].split()] if rest[1] else []
@@ -124,6 +131,11 @@ def _launch_footprint(kind, items):
             for v in it["ins"]:
                 reads |= _footprint(v)
             for v in it["outs"]:
+                writes |= _footprint(v)
+        elif kind == "WINO":
+            for v in it["a"] + it["b"]:
+                reads |= _footprint(v)
+            for v in it["c"]:
                 writes |= _footprint(v)
         else:
             reads |= _footprint(it["a"]) | _footprint(it["b"])
@@ -252,6 +264,11 @@ def check_hazards(launch):
                         for x in common.tolist():
                             pi, po = pos_in[x], pos_out[x]
                             assert (pi // ci, pi % ci) == (po // co, po % co), "EW cross-element alias"
+        elif kind == "WINO":
+            r, w = _launch_footprint(kind, [(kind, it)])
+            fcs = [_footprint(v) for v in it["c"]]
+            assert sum(len(f) for f in fcs) == len(w), "WINO output quadrants overlap"
+            assert not (w & r), "WINO writes its own operands"
         else:
             r = _footprint(it["a"]) | _footprint(it["b"])
             w = set()
@@ -309,6 +326,13 @@ def run(text, bufs, hazards=True):
                 else:
                     y = _recipe(it["kind"], x, it["mode"])
                 results.append(list(zip(it["outs"], y)))
+            elif kind == "WINO":
+                p = [mem.read(a) @ mem.read(b) for a, b in zip(it["a"], it["b"])]
+                u2 = p[0] + p[5]
+                u3 = u2 + p[6]
+                u4 = u2 + p[4]
+                vals = [p[0] + p[1], u4 + p[2], u3 - p[3], u3 + p[4]]
+                results.append(list(zip(it["c"], vals)))
             else:
                 a = operand(mem.read(it["a"]), it["ak"])
                 b = operand(mem.read(it["b"]), it["bk"])

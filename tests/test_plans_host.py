@@ -268,3 +268,36 @@ def test_batched_plan_exact(lib):
     for (m, n, k), (A, B, a, b, c) in zip(shapes, mats):
         got = flat[1024 + c:1024 + c + m * n].reshape(m, n)
         assert np.array_equal(got, A @ B), (m, n, k)
+
+
+def test_leaf_u_plan_shape(lib):
+    # MM_PLAN_LEAF_U: L S/T passes, one launch for the last level's products
+    # and U combinations, L - 1 U passes; no product temporaries at the last
+    # level
+    for lv in (1, 2, 3):
+        _, ref = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=lv)
+        text, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=lv, leaf_u=True)
+        assert info["leaf_u"] == 1 and info["launches"] == 2 * lv and info["leaves"] == 7 ** lv
+        assert info["ws_bytes"] < ref["ws_bytes"]
+        assert sum(l.startswith("WINO") for l in text.splitlines()) == 7 ** (lv - 1)
+        assert "GEMM" not in text
+    # other dtypes / schedules ignore the flag; it excludes the fused loader
+    _, info = L.describe("winograd", "grouped", 512, 512, 512, cutoff=64, dtype="f64", leaf_u=True)
+    assert info["leaf_u"] == 0
+    _, info = L.describe("winograd", "two_temp", 512, 512, 512, cutoff=64, leaf_u=True)
+    assert info["leaf_u"] == 0
+    with pytest.raises(L.MMError):
+        L.describe("winograd", "grouped", 512, 512, 512, cutoff=1, levels=1, leaf_u=True, fuse=True)
+
+
+@pytest.mark.parametrize("m,n,k,levels", [(16, 16, 16, 1), (64, 64, 64, 2), (96, 40, 56, 2), (200, 136, 72, 3),
+                                          (1000, 777, 555, 2), (130, 70, 90, 1), (8, 300, 64, 1)])
+def test_leaf_u_plan_is_exact(lib, m, n, k, levels):
+    A = inputs.integers((m, k), 27, dtype=np.int64)
+    B = inputs.integers((k, n), 28, dtype=np.int64)
+    text, info = L.describe("winograd", "grouped", m, n, k, cutoff=1, levels=levels, dtype="f32", leaf_u=True)
+    assert info["leaf_u"] == 1
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    C = np.full(m * n, -(10**9), dtype=np.int64)
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
+    assert np.array_equal(C.reshape(m, n), A @ B)
