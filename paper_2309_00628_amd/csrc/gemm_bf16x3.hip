@@ -4,16 +4,22 @@
 // Every float32 operand element x is split once, when its tile is staged in
 // LDS, into three bfloat16 parts (round to nearest even at each step):
 //   hi  = bf16(x)
-//   lo  = bf16(x - hi)                      (x - hi is exact in float32)
-//   res = bf16(x - hi - lo), the residual formed in float64
-// so that x = hi + lo + res up to about 2^-25 |x|.  A product of two parts is
-// exact in float32 (8 x 8 significant bits), so v_mfma_f32_32x32x16_bf16
-// accumulates them in float32 without extra rounding.  Per 16-wide k step
-// each C tile receives the three leading products hi*hi + hi*lo + lo*hi and
-// the one-step correction lo*lo + res*hi + hi*res, smallest first; the
-// neglected terms (lo*res, res*lo, res*res) are below 2^-24 relative.  The
-// result therefore carries float32-level error while every multiply runs at
-// the bfloat16 MFMA rate.
+//   lo  = bf16(x - hi)
+//   res = bf16(x - hi - lo)
+// Each difference is exact in float32: x - hi is a multiple of x's float32
+// unit in the last place and at most half a bfloat16 unit of x, so it needs
+// at most 16 significant bits, and (x - hi) - lo needs at most 8.  The
+// residual is thus formed exactly in float32 registers: forming it in
+// float64, as a refinement residual is usually formed, gives the same bits at
+// twice the vector cost.  For |x| >= 2^-110 the residual is itself a
+// bfloat16 number and x = hi + lo + res exactly; below that it falls into
+// bfloat16's subnormal range and is rounded.  A product of two parts is exact in float32 (8 x 8
+// significant bits), so v_mfma_f32_32x32x16_bf16 accumulates them in float32
+// without extra rounding.  Per 16-wide k step each C tile receives the three
+// leading products hi*hi + hi*lo + lo*hi and the one-step correction
+// lo*lo + res*hi + hi*res, smallest first; the neglected terms (lo*res,
+// res*lo, res*res) are below 2^-24 relative.  The result therefore carries
+// float32-level error while every multiply runs at the bfloat16 MFMA rate.
 //
 // Structure as in the float32 kernel: grouped problems, XCD-aware tile order,
 // LDS double buffering (three planes per operand: hi, lo, res), masked edge
@@ -44,18 +50,19 @@ __device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
 }
 __device__ __forceinline__ int row32(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-// Split 8 floats into their bfloat16 hi, lo and residual parts.
+// Split 8 floats into their bfloat16 hi, lo and residual parts (both
+// differences are exact, see above).
 __device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo, bf16x8& rs) {
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const __bf16 h = (__bf16)x[e];
     const float hf = (float)h;
-    const __bf16 l = (__bf16)(x[e] - hf);
-    const float lf = (float)l;
-    const double r = ((double)x[e] - (double)hf) - (double)lf;
+    const float d1 = x[e] - hf;
+    const __bf16 l = (__bf16)d1;
+    const float d2 = d1 - (float)l;
     hi[e] = h;
     lo[e] = l;
-    rs[e] = (__bf16)(float)r;
+    rs[e] = (__bf16)d2;
   }
 }
 
