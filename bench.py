@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the n=3000 / n=8192 side runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batch")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop runs")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the n=8192 split-bfloat16 precision runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the timed Winograd steps (for rocprofv3 runs)")
@@ -118,13 +120,13 @@ def plan_launches(plan, esz):
 
 
 def tuned_leaf(tuner, n, levels):
-    """The autotuner's leaf tile and overlap choice for an n x n x n product
-    at this level count (None / False when the cache holds another level
-    count for the size class)."""
+    """The autotuner's (tile, overlap, leaf_u) choice for an n x n x n
+    float32 product at this level count (planner defaults when the cache
+    holds another level count for the size class)."""
     ch = tuner.choose(n, n, n, "f32")
     if ch["source"] == "tuned" and ch["levels"] == levels:
-        return ch["tile"], bool(ch.get("overlap", False))
-    return None, False
+        return ch["tile"], bool(ch.get("overlap", False)), bool(ch.get("leaf_u", False))
+    return None, False, False
 
 
 def pct(xs, q):
@@ -133,8 +135,9 @@ def pct(xs, q):
 
 
 def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtype="f32", tile=None,
-                overlap=False):
-    plan = api.Plan(algo, sched, n, n, n, cutoff=1, levels=levels, dtype=dtype, tile=tile, overlap=overlap)
+                overlap=False, leaf_u=False):
+    plan = api.Plan(algo, sched, n, n, n, cutoff=1, levels=levels, dtype=dtype, tile=tile, overlap=overlap,
+                    leaf_u=leaf_u)
     ws = torch.empty(max(plan.ws_bytes, 256), dtype=torch.uint8, device=A.device)
     C = torch.empty((n, n), dtype=A.dtype, device=A.device)
     wall, step_ms, per_op, kinds = time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup)
@@ -206,6 +209,37 @@ def rel_err(C, rows, ref):
     import torch
     got = C[torch.from_numpy(rows).to(C.device)].double().cpu().numpy()
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def bench_precision(torch, api, L, inputs, tuner, n=8192, steps=5, warmup=2, rows=48):
+    """n = 8192, A and B Gaussian with rows scaled by 10^u, u ~ U[-3, 3]:
+    split-bfloat16 refined leaves under two Winograd levels (and plain), the
+    float32 Winograd and plain products beside them, each with its relative
+    Frobenius error against the float64 oracle on a sample of rows."""
+    import numpy as np
+    from oracle import naive
+    A_np = inputs.gauss_rowscaled((n, n), 20)
+    B_np = inputs.gauss_rowscaled((n, n), 21)
+    A, B = torch.from_numpy(A_np).cuda(), torch.from_numpy(B_np).cuda()
+    sample = np.linspace(0, n - 1, rows).astype(np.int64)
+    ref = naive.gemm_rows(A_np, B_np, sample)
+    out = {"workload": f"square n={n}, Gaussian rows scaled by 10^U[-3,3]",
+           "oracle_rows": rows}
+    for name, algo, lv, dt in (("bf16x3_winograd_L2", "winograd", 2, "bf16x3"),
+                               ("bf16x3_plain", "naive", 0, "bf16x3"),
+                               ("f32_winograd_L2", "winograd", 2, "f32"),
+                               ("f32_plain", "naive", 0, "f32")):
+        ch = tuner.choose(n, n, n, dt)
+        tile = ch["tile"] if ch["source"] == "tuned" and ch["levels"] == lv else None
+        r = run_product(torch, api, L, algo, "grouped" if lv else "auto", n, lv, A, B, steps, warmup,
+                        dtype=dt, tile=tile)
+        out[name] = {"tflops": round(r["tflops"], 3), "p50_ms": round(r["p50"], 4),
+                     "rel_err": rel_err(r["C"], sample, ref), "tile": tile}
+        print(f"# precision {name}: {out[name]}", file=sys.stderr, flush=True)
+        del r
+    out["speedup_bf16x3_winograd_vs_f32_plain"] = round(out["bf16x3_winograd_L2"]["tflops"] /
+                                                        out["f32_plain"]["tflops"], 4)
+    return out
 
 
 def bench_batched(torch, api, inputs, tuner, count=512, steps=10, warmup=3, seed=7):
@@ -343,9 +377,9 @@ def main():
     else:
         levels = args.levels
 
-    tile, overlap = tuned_leaf(tuner, n, levels)
+    tile, overlap, leaf_u = tuned_leaf(tuner, n, levels)
     win = run_product(torch, api, L, "winograd", args.sched, n, levels, A, B, args.steps, args.warmup,
-                      tile=tile, overlap=overlap)
+                      tile=tile, overlap=overlap, leaf_u=leaf_u)
     print(f"# winograd L={levels}: {win['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
     if args.profile_only:
         print(json.dumps({"profile_only": True, "n": n, "levels": levels,
@@ -387,7 +421,7 @@ def main():
         "config": {"workload": f"square fp32 matmul n={n}, Strassen-Winograd {args.sched} "
                                f"L={levels} vs plain MFMA GEMM",
                    "n": n, "levels": levels, "schedule": args.sched, "leaf_tile_cfg": tile,
-                   "overlap": overlap},
+                   "overlap": overlap, "leaf_u": leaf_u},
         "p50_ms": round(win["p50"], 4),
         "p99_ms": round(win["p99"], 4),
         "plain_gemm": {"tflops": round(plain["tflops"], 3), "p50_ms": round(plain["p50"], 4),
@@ -414,9 +448,9 @@ def main():
             p2 = run_product(torch, api, L, "naive", "auto", n2, 0, A2, B2, 5, 2)
             e = {"plain_tflops": round(p2["tflops"], 3)}
             for lv in lvls:
-                t2, o2 = tuned_leaf(tuner, n2, lv)
+                t2, o2, u2 = tuned_leaf(tuner, n2, lv)
                 w2 = run_product(torch, api, L, "winograd", args.sched, n2, lv, A2, B2, 5, 2, tile=t2,
-                                 overlap=o2)
+                                 overlap=o2, leaf_u=u2)
                 e[f"winograd_L{lv}_tflops"] = round(w2["tflops"], 3)
                 e[f"winograd_L{lv}_p99_ms"] = round(w2["p99"], 4)
             extra[str(n2)] = e
@@ -424,6 +458,8 @@ def main():
             del A2, B2
         out["extra"] = extra
 
+    if not args.no_precision:
+        out["precision"] = bench_precision(torch, api, L, inputs, tuner)
     if not args.no_batched:
         out["batched"] = bench_batched(torch, api, inputs, tuner)
         print(f"# batched: {out['batched']}", file=sys.stderr, flush=True)

@@ -6,7 +6,8 @@ MFMA rate against HBM bandwidth instead, so it is measured: for a size class
 the tuner times each candidate (levels L = 0..Lmax of Strassen-Winograd with
 the grouped schedule, L = 0 being the plain MFMA GEMM, crossed with a few
 leaf tile shapes and, for L > 0, with and without the S/T passes overlapped
-on a second stream) on the GPU with HIP events and keeps the fastest.
+on a second stream, and (float32) the fused last-level kernel with its own
+tiles) on the GPU with HIP events and keeps the fastest.
 
 Choices are cached per (GPU architecture, dtype, size class) in a JSON file
 (``tuning/<arch>.json`` next to this module) so that a process, a batch or a
@@ -77,7 +78,7 @@ def rule_of_thumb(m, n, k, dtype):
     L = 0
     while L < 2 and min(m, n, k) >> (L + 1) >= leaf:
         L += 1
-    return {"levels": L, "tile": None, "cutoff": 1, "overlap": False, "source": "rule"}
+    return {"levels": L, "tile": None, "cutoff": 1, "overlap": False, "leaf_u": False, "source": "rule"}
 
 
 def choose(m, n, k, dtype="f32"):
@@ -113,6 +114,18 @@ def _time_plan(plan, A, B, C, reps, warmup):
 
 
 TILES = {"f32": (None, 0, 3, 4), "bf16x3": (None, 0, 1, 4), "f64": (None,)}
+LEAF_U_TILES = (None, 0, 1, 2)  # tiles of the fused last-level kernel (float32)
+
+
+def candidates(dtype, L_, tiles=None):
+    """(tile, overlap, leaf_u) triples tried at L_ levels."""
+    out = []
+    for tile in (tiles or TILES.get(dtype, (None,))):
+        for ov in ((False, True) if L_ else (False,)):
+            out.append((tile, ov, False))
+    if L_ and dtype == "f32" and tiles is None:
+        out += [(tile, False, True) for tile in LEAF_U_TILES]
+    return out
 
 
 def tune(m, n, k, dtype="f32", max_levels=3, reps=7, warmup=2, tiles=None, save=True, verbose=False):
@@ -131,25 +144,24 @@ def tune(m, n, k, dtype="f32", max_levels=3, reps=7, warmup=2, tiles=None, save=
     for L_ in range(0, max_levels + 1):
         if L_ > 0 and min(m, n, k) >> L_ < 64:
             break
-        for tile in (tiles or TILES.get(dtype, (None,))):
-            for ov in ((False, True) if L_ else (False,)):
-                try:
-                    algo = "naive" if L_ == 0 else "winograd"
-                    p = api.Plan(algo, "grouped" if L_ else "auto", m, n, k, cutoff=1, levels=L_,
-                                 dtype=dtype, tile=tile, overlap=ov)
-                    t = _time_plan(p, A, B, C, reps, warmup)
-                except Exception as e:  # an unsupported candidate is skipped
-                    if verbose:
-                        print(f"  skip L={L_} tile={tile} overlap={ov}: {e}")
-                    continue
-                results.append((t, L_, tile, ov))
+        for tile, ov, lu in candidates(dtype, L_, tiles):
+            try:
+                algo = "naive" if L_ == 0 else "winograd"
+                p = api.Plan(algo, "grouped" if L_ else "auto", m, n, k, cutoff=1, levels=L_,
+                             dtype=dtype, tile=tile, overlap=ov, leaf_u=lu)
+                t = _time_plan(p, A, B, C, reps, warmup)
+            except Exception as e:  # an unsupported candidate is skipped
                 if verbose:
-                    print(f"  {dtype} {m}x{n}x{k} L={L_} tile={tile} overlap={int(ov)}: {t:.3f} ms "
-                          f"{2.0 * m * n * k / t / 1e9:.1f} TFLOP/s", flush=True)
-    t, L_, tile, ov = min(results, key=lambda r: r[0])
+                    print(f"  skip L={L_} tile={tile} overlap={ov} leaf_u={lu}: {e}")
+                continue
+            results.append((t, L_, tile, ov, lu))
+            if verbose:
+                print(f"  {dtype} {m}x{n}x{k} L={L_} tile={tile} overlap={int(ov)} leaf_u={int(lu)}: "
+                      f"{t:.3f} ms {2.0 * m * n * k / t / 1e9:.1f} TFLOP/s", flush=True)
+    t, L_, tile, ov, lu = min(results, key=lambda r: r[0])
     leaf = min(m, n, k) >> L_
     # the cutoff that stops the recursion after L_ halvings: the leaf order
-    entry = {"levels": L_, "tile": tile, "overlap": ov, "cutoff": leaf if L_ else min(m, n, k),
+    entry = {"levels": L_, "tile": tile, "overlap": ov, "leaf_u": lu, "cutoff": leaf if L_ else min(m, n, k),
              "ms": round(t, 4), "tflops": round(2.0 * m * n * k / t / 1e9, 2),
              "shape": [m, n, k]}
     arch = _arch()
@@ -174,7 +186,7 @@ def main(argv=None):
         for n in [int(x) for x in args.n.split(",")]:
             e = tune(n, n, n, dt, max_levels=args.max_levels, reps=args.reps, verbose=True)
             print(f"{dt} n={n}: levels={e['levels']} tile={e['tile']} overlap={e['overlap']} "
-                  f"{e['tflops']} TFLOP/s", flush=True)
+                  f"leaf_u={e['leaf_u']} {e['tflops']} TFLOP/s", flush=True)
     if args.copy_to:
         shutil.copy(cache_path(), args.copy_to)
 
