@@ -166,6 +166,13 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                             disappears.  Sums are rounded in the same order as the separate
                             U pass: results are bitwise the same.  Ignored for other dtypes
                             and schedules; excludes MM_PLAN_FUSE. */
+#define MM_PLAN_SPLIT_PASS 16u /* MM_BF16X3_REFINED, grouped schedule or plain product: split
+                                 each float32 operand into its bfloat16 parts once, in a split
+                                 pass (which also forms the last level's S/T sums), and run
+                                 the leaves on the stored parts, instead of splitting every
+                                 staged tile inside the leaf kernel (the default).  Both give
+                                 the same bits; the stored parts move 1.5x the bytes of the
+                                 float32 operands, and on MI355X the default measures faster. */
 /* Force the MFMA GEMM tile configuration c (0 .. 7) for every leaf launch
  * instead of the planner's choice.  float32: 0 128x128 (BK 32), 1 256x128,
  * 2 128x256, 3 256x256 (BK 16), 4 64x128, 5 128x64, 6 256x128 (BK 16),
@@ -198,8 +205,9 @@ int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, s
 
 /* Kind of launch i of a plan: 0 element-wise block operations, 1 MFMA GEMM
  * group (leaf products), 2 fork to / 3 join of the plan's auxiliary stream,
- * 4 fused last Winograd level (MM_PLAN_LEAF_U); plus 8 when the launch runs
- * on the auxiliary stream; -1 if i is out of range. */
+ * 4 fused last Winograd level (MM_PLAN_LEAF_U), 5 split pass of the
+ * split-bfloat16 leaves; plus 8 when the launch runs on the auxiliary
+ * stream; -1 if i is out of range. */
 int mm_plan_op_kind(mm_plan_t plan, int i);
 
 /* Plan facts: info[0] workspace bytes, [1] levels L, [2..4] padded m, n, k,

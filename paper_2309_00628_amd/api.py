@@ -48,7 +48,8 @@ class Plan:
     """A built launch sequence for one product shape (mm_plan_create)."""
 
     def __init__(self, algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None,
-                 ldc=None, graph=False, device=None, tile=None, fuse=False, overlap=False, leaf_u=False):
+                 ldc=None, graph=False, device=None, tile=None, fuse=False, overlap=False, leaf_u=False,
+                 split_pass=False):
         lib = L.load()
         self.algo, self.sched, self.dtype = algo, sched, dtype
         self.m, self.n, self.k = m, n, k
@@ -64,7 +65,9 @@ class Plan:
                                        (L.MM_PLAN_GRAPH if graph else 0) | L.plan_tile(tile) |
                                        (L.MM_PLAN_FUSE if fuse else 0) |
                                        (L.MM_PLAN_OVERLAP if overlap else 0) |
-                                       (L.MM_PLAN_LEAF_U if leaf_u else 0), ctypes.byref(self._ptr)))
+                                       (L.MM_PLAN_LEAF_U if leaf_u else 0) |
+                                       (L.MM_PLAN_SPLIT_PASS if split_pass else 0),
+                                       ctypes.byref(self._ptr)))
         info = (ctypes.c_int64 * L.NINFO)()
         lib.mm_plan_info(self._ptr, info, L.NINFO)
         self.info = L._info_dict(info)
@@ -114,20 +117,21 @@ def workspace(nbytes, device, stream):
 
 
 def get_plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile=None,
-             fuse=False, overlap=False, leaf_u=False):
+             fuse=False, overlap=False, leaf_u=False, split_pass=False):
     key = (str(device), algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, tile, fuse,
-           overlap, leaf_u)
+           overlap, leaf_u, split_pass)
     with _plans_lock:
         p = _plans.get(key)
         if p is None:
             p = Plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile, fuse,
-                     overlap, leaf_u)
+                     overlap, leaf_u, split_pass)
             _plans[key] = p
     return p
 
 
 def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None, out=None,
-       graph=False, stream=None, clobber_inputs=False, tile=None, fuse=False, overlap=None, leaf_u=None):
+       graph=False, stream=None, clobber_inputs=False, tile=None, fuse=False, overlap=None, leaf_u=None,
+       split_pass=False):
     """C = A @ B on the GPU by ``algo`` in {"naive", "strassen", "winograd"}.
 
     ``cutoff`` / ``levels`` control the recursion as in mm.h; when both are
@@ -138,7 +142,8 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
     "dfs3" (Strassen).  ``dtype``: None (from the tensors), "f64", "f32" or
     "bf16x3" (float32 tensors, split-bfloat16 leaf products).  ``fuse`` /
     ``overlap`` / ``leaf_u``: MM_PLAN_FUSE / MM_PLAN_OVERLAP / MM_PLAN_LEAF_U
-    (None: the autotuner's choice when it picks the recursion, else off).  The in-place
+    (None: the autotuner's choice when it picks the recursion, else off);
+    ``split_pass``: MM_PLAN_SPLIT_PASS.  The in-place
     schedule overwrites its operands, so unless ``clobber_inputs`` is set the
     wrapper hands it copies.
     """
@@ -180,7 +185,7 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
     elif levels is None:
         levels = -1
     p = get_plan(algo, sched, m, n, k, cutoff, levels, dt, lda, ldb, ldc, graph, A.device, tile, fuse,
-                 bool(overlap), bool(leaf_u))
+                 bool(overlap), bool(leaf_u), bool(split_pass))
     with torch.cuda.device(A.device):
         p(A, B, C, stream=stream)
     return C

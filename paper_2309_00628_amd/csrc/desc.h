@@ -42,10 +42,25 @@ enum EwKind : int32_t {
                    //                          o = C11(U1) C12(U4) C21(U6) C22(U7)
   EW_DIST = 10,    // o_j = mode_j(d_j, z): i = Z D0 D1 ; mode 1: z, 2: d + z, 3: d - z
   EW_ZERO = 11,    // o0 = 0
+  // Split recipes (split kernel): float32 inputs, outputs in the split
+  // bfloat16 layout below; mode[0] = 1 stores each output transposed.
+  EW_SPLIT = 12,       // o0 = split(i0)
+  EW_WINO_S_SPL = 13,  // i = A11 A12 A21 A22 ; o = S1 S2 S3 S4 A11 A12 A22
+  EW_WINO_T_SPL = 14,  // i = B11 B12 B21 B22 ; o = T1 T2 T3 T4 B11 B21 B22 (transposed)
 };
 
 constexpr int kEwMaxIn = 7;
-constexpr int kEwMaxOut = 4;
+constexpr int kEwMaxOut = 7;
+
+// Split bfloat16 layout ("SPL") of a float32 matrix X with R rows and Kc
+// columns, as read by the split-operand leaf kernel: every element is
+// x = hi + lo + res (three bfloat16 numbers), and each row holds chunks of 8
+// consecutive columns, chunk q of row r being 48 bytes at bfloat16 index
+// off + r * ld + 24 q: hi[8] lo[8] res[8].  An MView of an SPL matrix counts
+// off and ld in bfloat16 elements (ld = 24 * ceil(Kc / 8) or more), rows = R
+// and cols = Kc; columns past Kc inside the last chunk hold zeros.  The B
+// operand of a product is stored transposed (R = its columns), so both
+// operands of the leaf kernel are read as runs of 8 consecutive k.
 
 struct EwPart {
   int32_t kind;

@@ -18,6 +18,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kItems = 2;  // chunks per thread
+constexpr int kOut = 4;    // outputs of the element-wise recipes of this kernel
+static_assert(kOut <= kEwMaxOut, "outputs");
 
 template <typename T>
 struct VecT;
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(kThreads) void ew_kernel(KernelBases kb, const EwPa
     const int r = (int)(q / cpr);
     const int c0 = (int)(q - (int64_t)r * cpr) * V;
     T x[kEwMaxIn][V];
-    T y[kEwMaxOut][V];
+    T y[kOut][V];
 #pragma unroll
     for (int i = 0; i < kEwMaxIn; ++i)
       if (i < nin) load_chunk<T, V>(kb, P.in[i], r, c0, vec, x[i]);
@@ -178,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void ew_kernel(KernelBases kb, const EwPa
       }
     }
 #pragma unroll
-    for (int o = 0; o < kEwMaxOut; ++o)
+    for (int o = 0; o < kOut; ++o)
       if (o < nout) store_chunk<T, V>(kb, P.out[o], r, c0, vec, y[o]);
   }
 }

@@ -58,6 +58,7 @@ hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles
 
 GemmCfg gemm_cfg(int dtype, int cfg) {
   if (dtype == DT_BF16X3) return gemm_bf16x3_cfg(cfg);
+  if (dtype == DT_BF16X3_SPL) return gemm_bf16s_cfg(cfg);
   if (dtype == DT_F64) {
     switch (cfg) {
       case 5: return {128, 64};
@@ -80,6 +81,7 @@ hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc
                        int remap, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   if (dtype == DT_BF16X3) return launch_gemm_bf16x3(cfg, kb, d, n, tiles, remap, s);
+  if (dtype == DT_BF16X3_SPL) return launch_gemm_bf16s(cfg, kb, d, n, tiles, remap, s);
   if (dtype == DT_F64) {
     switch (cfg) {
       case 5: return launch_cfg<double, 128, 64, 8, 2, 2>(kb, d, n, tiles, remap, s);

@@ -286,6 +286,194 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
                                                [](int l, int r) { return row32(l, r); });
 }
 
+// The same products from operands already split by the split pass (SPL
+// layout, desc.h): a is the m x k A operand, b the n x k transpose of the B
+// operand, each a run of 48-byte chunks (hi, lo, res of 8 consecutive k).
+// Staging a tile is three 16-byte loads per chunk and three LDS stores, with
+// no conversion work; the LDS layout, the MFMA sequence and the order of the
+// six products are those of the kernel above, so both give the same bits.
+template <int BM, int BN, int BKC, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16s_kernel(KernelBases kb,
+                                                                    const GemmDesc* __restrict__ descs,
+                                                                    int ndesc, int remap) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int TM = 32;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / TM, FN = WN / TM;
+  constexpr int BK = BKC * KC;
+  constexpr int NCH_A = BM * BKC, NA = (NCH_A + NT - 1) / NT;
+  constexpr int NCH_B = BN * BKC, NB = (NCH_B + NT - 1) / NT;
+  static_assert(BKC % 2 == 0 && 16 % BKC == 0 && FM >= 1 && FN >= 1, "tile shape");
+
+  __shared__ bf16x8 As[2][3][BKC][BM];
+  __shared__ bf16x8 Bs[2][3][BKC][BN];
+
+  const TileRef tr = locate_tile<BM, BN>(descs, ndesc, remap);
+  const GemmDesc& D = descs[tr.desc];
+  const int i0 = tr.i0, j0 = tr.j0;
+  const MView av = D.a, bv = D.b;
+  auto spl = [&](const MView& v) {
+    char* b = v.base == MB_ABS ? nullptr : reinterpret_cast<char*>(kb.p[v.base]);
+    return reinterpret_cast<const __bf16*>(b) + v.off;
+  };
+  const __bf16* __restrict__ Ap = spl(av);
+  const __bf16* __restrict__ Bp = spl(bv);
+  const int64_t lda = av.ld, ldb = bv.ld;
+  const int K = D.k;
+  const int ktiles = (K + BK - 1) / BK;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+
+  bf16x8 ra[NA][3], rb[NB][3];
+
+  // FULL: the stage lies inside both operands; otherwise rows past the valid
+  // extent and chunks past the k extent read as zero.
+  auto load_tile = [&](auto full_tag, int kt) {
+    constexpr bool FULL = decltype(full_tag)::value;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + NT * i;
+      if (NCH_A % NT != 0 && q >= NCH_A) break;
+      const int row = q / BKC, kc = q % BKC;
+      const int gr = i0 + row, gq = kt * BKC + kc;
+      const bf16x8* p = reinterpret_cast<const bf16x8*>(Ap + (int64_t)gr * lda + 24 * (int64_t)gq);
+      const bool ok = FULL || (gr < av.vrows && 8 * gq < av.vcols);
+#pragma unroll
+      for (int pl = 0; pl < 3; ++pl) ra[i][pl] = ok ? p[pl] : bf16x8{};
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + NT * i;
+      if (NCH_B % NT != 0 && q >= NCH_B) break;
+      const int col = q / BKC, kc = q % BKC;
+      const int gc = j0 + col, gq = kt * BKC + kc;
+      const bf16x8* p = reinterpret_cast<const bf16x8*>(Bp + (int64_t)gc * ldb + 24 * (int64_t)gq);
+      const bool ok = FULL || (gc < bv.vrows && 8 * gq < bv.vcols);
+#pragma unroll
+      for (int pl = 0; pl < 3; ++pl) rb[i][pl] = ok ? p[pl] : bf16x8{};
+    }
+  };
+
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + NT * i;
+      if (NCH_A % NT != 0 && q >= NCH_A) break;
+      const int row = q / BKC, kc = q % BKC;
+      const int sr = swz_a<BKC>(row, kc);
+#pragma unroll
+      for (int pl = 0; pl < 3; ++pl) As[buf][pl][kc][sr] = ra[i][pl];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + NT * i;
+      if (NCH_B % NT != 0 && q >= NCH_B) break;
+      const int col = q / BKC, kc = q % BKC;
+      const int sc = swz_a<BKC>(col, kc);
+#pragma unroll
+      for (int pl = 0; pl < 3; ++pl) Bs[buf][pl][kc][sc] = rb[i][pl];
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  const int g = lane / TM, t = lane % TM;
+
+  // MFMAs of k-step ks (16 k values) for tile rows [a_lo, a_hi) with the B
+  // fragments fb of that step.  The six products of a tile are issued in
+  // the refinement order (smallest first); tiles of one product type are
+  // interleaved so consecutive MFMAs are independent.
+  auto read_fb = [&](int buf, int ks, bf16x8 (&fb)[3][FN]) {
+    const int plane = 2 * ks + g;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) fb[p][b] = Bs[buf][p][plane][swz_a<BKC>(wn * WN + b * TM + t, plane)];
+  };
+  auto compute = [&](int buf, int ks, int a_lo, int a_hi, const bf16x8 (&fb)[3][FN]) {
+    const int plane = 2 * ks + g;
+#pragma unroll
+    for (int a = a_lo; a < a_hi; ++a) {
+      bf16x8 fa[3];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) fa[p] = As[buf][p][plane][swz_a<BKC>(wm * WM + a * TM + t, plane)];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[1], fb[1][b], acc[a][b]);  // lo  * lo
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[2], fb[0][b], acc[a][b]);  // res * hi
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[0], fb[2][b], acc[a][b]);  // hi  * res
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[1], fb[0][b], acc[a][b]);  // lo  * hi
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[0], fb[1][b], acc[a][b]);  // hi  * lo
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[0], fb[0][b], acc[a][b]);  // hi  * hi
+    }
+  };
+
+  // The next stage is written to the other LDS buffer in the middle of this
+  // stage's MFMAs: after the first k-step when a stage has two, else after
+  // the first half of the tile rows.
+  auto main_loop = [&](auto full_tag) {
+    load_tile(full_tag, 0);
+    store_tile(0);
+    __syncthreads();
+    for (int kt = 0; kt < ktiles; ++kt) {
+      const int buf = kt & 1;
+      const bool more = kt + 1 < ktiles;
+      if (more) load_tile(full_tag, kt + 1);
+      bf16x8 fb[3][FN];
+      if constexpr (BKC == 2) {
+        read_fb(buf, 0, fb);
+        compute(buf, 0, 0, FM / 2, fb);
+        if (more) store_tile(buf ^ 1);
+        compute(buf, 0, FM / 2, FM, fb);
+      } else {
+#pragma unroll
+        for (int ks = 0; ks < BKC / 4; ++ks) {
+          read_fb(buf, ks, fb);
+          compute(buf, ks, 0, FM, fb);
+        }
+        if (more) store_tile(buf ^ 1);
+#pragma unroll
+        for (int ks = BKC / 4; ks < BKC / 2; ++ks) {
+          read_fb(buf, ks, fb);
+          compute(buf, ks, 0, FM, fb);
+        }
+      }
+      __syncthreads();
+    }
+  };
+
+  if (ktiles > 0) {
+    const bool interior = (i0 + BM <= av.vrows) && (j0 + BN <= bv.vrows) && (K % BK == 0) &&
+                          (K <= av.vcols) && (K <= bv.vcols);
+    if (interior)
+      main_loop(std::integral_constant<bool, true>{});
+    else
+      main_loop(std::integral_constant<bool, false>{});
+  }
+
+  store_outputs<float, TM, 16, FM, FN, WM, WN>(kb, D, i0, j0, wm, wn, lane, acc,
+                                               [](int l, int r) { return row32(l, r); });
+}
+
+template <int BM, int BN, int BKC, int WGM, int WGN>
+hipError_t launch_spl(const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_bf16s_kernel<BM, BN, BKC, WGM, WGN>), dim3(tiles), dim3(64 * WGM * WGN), 0, s, kb,
+                     d, n, remap);
+  return hipGetLastError();
+}
+
 template <int BM, int BN, int BKC, int WGM, int WGN>
 hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap, hipStream_t s) {
   hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN, BKC, WGM, WGN>), dim3(tiles), dim3(64 * WGM * WGN), 0, s,
@@ -296,6 +484,16 @@ hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles
 }  // namespace
 
 bool gemm_bf16x3_available() { return true; }
+
+GemmCfg gemm_bf16s_cfg(int cfg) {
+  switch (cfg) {
+    case 1: return {256, 128};
+    case 3: return {256, 256};
+    case 4: return {64, 128};
+    case 5: return {256, 128};
+    default: return {128, 128};
+  }
+}
 
 GemmCfg gemm_bf16x3_cfg(int cfg) {
   switch (cfg) {
@@ -312,6 +510,18 @@ hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d,
     case 1: return launch_cfg<256, 128, 4, 4, 2>(kb, d, n, tiles, remap, s);
     case 4: return launch_cfg<64, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
     default: return launch_cfg<128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
+  }
+}
+
+hipError_t launch_gemm_bf16s(int cfg, const KernelBases& kb, const GemmDesc* d, int n, int tiles,
+                             int remap, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  switch (cfg) {
+    case 1: return launch_spl<256, 128, 4, 4, 2>(kb, d, n, tiles, remap, s);
+    case 3: return launch_spl<256, 256, 2, 2, 2>(kb, d, n, tiles, remap, s);
+    case 4: return launch_spl<64, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
+    case 5: return launch_spl<256, 128, 2, 2, 2>(kb, d, n, tiles, remap, s);
+    default: return launch_spl<128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
   }
 }
 

@@ -50,7 +50,8 @@ int ew_dtype(int dtype) { return dtype == MM_F64 ? DT_F64 : DT_F32; }
 // main stream; OP_JOIN: the main stream waits for the auxiliary stream.
 // OP_WINO: last-level Winograd subproblems, products and U combinations in
 // one kernel (WinoLeafDesc).
-enum OpType { OP_EW = 0, OP_GEMM = 1, OP_FORK = 2, OP_JOIN = 3, OP_WINO = 4 };
+// OP_SPLIT: split passes of the split-bfloat16 leaves (split kernel).
+enum OpType { OP_EW = 0, OP_GEMM = 1, OP_FORK = 2, OP_JOIN = 3, OP_WINO = 4, OP_SPLIT = 5 };
 
 struct OpRec {
   int type;
@@ -81,6 +82,7 @@ struct Plan {
   bool overlap = false;  // run the S/T passes beside the products that do not need them
   bool leaf_u = false;   // last level: products and U combinations in one kernel (float32)
   bool wino = false;     // the plan has such a launch
+  bool spl = false;      // split-bfloat16 leaves read operands split by a split pass
   bool has_aux = false;  // some launches go to the auxiliary stream
   struct Aux {
     hipStream_t main, aux;
@@ -146,7 +148,7 @@ int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
     }
     return best;
   }
-  if (kdtype == DT_BF16X3) {
+  if (kdtype == DT_BF16X3 || kdtype == DT_BF16X3_SPL) {
     // 256x128 tiles with eight waves (two per SIMD) hide the split's VALU
     // work behind the MFMAs; smaller launches keep more CUs busy with 64x128.
     int64_t t256 = 0, t128 = 0;
@@ -181,6 +183,9 @@ struct Builder {
   std::vector<GemmDesc> gm;
   std::vector<char> gm_fusable;  // descriptor satisfies the fused loader's preconditions
   std::vector<WinoLeafDesc> wl;  // last-level subproblems of the current launch
+  std::vector<EwPart> sp;        // split parts of the current launch
+  int sp_grid = 0;
+  bool gm_spl = false;           // the pending GEMM descriptors read SPL operands
   int gm_grid = 0;
   std::ostringstream txt;
 
@@ -226,6 +231,22 @@ struct Builder {
     return view(MB_WS, off, ld, rows, cols, rows, cols);
   }
 
+  // An R x Kc matrix in the split bfloat16 layout (desc.h) in the workspace.
+  MView spl_temp(int64_t R, int64_t Kc) {
+    const int64_t nq = std::max<int64_t>((Kc + 7) / 8, 1);
+    const int64_t off = ws_top;           // 4-byte units
+    ws_top += round_up(R * 12 * nq, 64);  // 48 bytes per chunk
+    ws_peak = std::max(ws_peak, ws_top);
+    MView v;
+    v.base = MB_WS;
+    v.off = 2 * off;  // bfloat16 units
+    v.ld = 24 * nq;
+    v.rows = v.vrows = (int32_t)R;
+    v.cols = v.vcols = (int32_t)Kc;
+    v.vec = 1;
+    return v;
+  }
+
   static std::string vs(const MView& v) {
     std::ostringstream o;
     if (v.base == MB_NONE) return "-";
@@ -237,7 +258,7 @@ struct Builder {
   // ---- element-wise parts ------------------------------------------------
   void ew_part(int kind, int64_t rows, int64_t cols, std::initializer_list<MView> ins,
                std::initializer_list<MView> outs, int mode0 = 0, int mode1 = 0) {
-    if (!gm.empty()) flush();
+    if (!gm.empty() || !wl.empty()) flush();
     EwPart p;
     std::memset(&p, 0, sizeof p);
     p.kind = kind;
@@ -265,7 +286,7 @@ struct Builder {
     txt << "\n";
   }
 
-  // ---- leaf products -------------------------------------------------------
+  // GEMM epilogue outputs
   struct Out {
     MView c;
     int mode;
@@ -275,11 +296,78 @@ struct Builder {
   static Out store(const MView& c, int sign = 1) { return Out{c, GM_STORE, sign, MView{}}; }
   static Out add(const MView& c, const MView& d, int sign) { return Out{c, GM_ADD, sign, d}; }
 
+  // ---- split passes -------------------------------------------------------
+  // rows x cols: the float32 input block; transposed: outputs hold its
+  // transpose.
+  void split_part(int kind, int64_t rows, int64_t cols, bool transposed, std::initializer_list<MView> ins,
+                  std::initializer_list<MView> outs) {
+    if (!ew.empty() || !gm.empty() || !wl.empty()) flush();
+    EwPart p;
+    std::memset(&p, 0, sizeof p);
+    p.kind = kind;
+    p.rows = (int32_t)rows;
+    p.cols = (int32_t)cols;
+    p.nin = (int32_t)ins.size();
+    p.nout = (int32_t)outs.size();
+    p.mode[0] = transposed ? 1 : 0;
+    int i = 0;
+    for (const auto& v : ins) p.in[i++] = v;
+    for (; i < kEwMaxIn; ++i) p.in[i] = none();
+    i = 0;
+    for (const auto& v : outs) p.out[i++] = v;
+    for (; i < kEwMaxOut; ++i) p.out[i] = none();
+    const int blocks = split_blocks((int)rows, (int)cols, transposed ? 1 : 0);
+    if (blocks == 0) return;
+    p.blk_start = sp_grid;
+    sp_grid += blocks;
+    sp.push_back(p);
+    txt << "SPLIT " << kind << " " << rows << " " << cols << " " << p.mode[0] << " |";
+    for (const auto& v : ins) txt << " " << vs(v);
+    txt << " |";
+    for (const auto& v : outs) txt << " " << vs(v);
+    txt << "\n";
+  }
+
+  // C = a b^T-stored: a is an m x k SPL matrix, bt the n x k SPL transpose of
+  // the B operand.
+  void gemm_spl(const MView& a, const MView& bt, std::initializer_list<Out> outs) {
+    if (!ew.empty() || !sp.empty() || (!gm.empty() && !gm_spl)) flush();
+    gm_spl = true;
+    GemmDesc g;
+    std::memset(&g, 0, sizeof g);
+    g.a = a;
+    g.b = bt;
+    g.m = a.rows;
+    g.k = a.cols;
+    g.n = bt.rows;
+    g.nout = (int32_t)outs.size();
+    int i = 0;
+    for (const auto& o : outs) {
+      g.out[i].c = o.c;
+      g.out[i].mode = o.mode;
+      g.out[i].sign = o.sign;
+      g.out[i].d = o.mode == GM_ADD ? o.d : none();
+      ++i;
+    }
+    for (; i < 2; ++i) {
+      g.out[i].c = none();
+      g.out[i].d = none();
+      g.out[i].mode = GM_NONE;
+      g.out[i].sign = 1;
+    }
+    P.leaves += 1;
+    if (g.m == 0 || g.n == 0) return;
+    gm.push_back(g);
+    gm_fusable.push_back(0);
+  }
+
+  // ---- leaf products -------------------------------------------------------
+
   // akind / bkind != OK_PLAIN: a / b is the parent block and the operand is
   // the Winograd sum of its quadrants (formed in the loader).
   void gemm(const MView& a, const MView& b, std::initializer_list<Out> outs, int akind = OK_PLAIN,
             int bkind = OK_PLAIN, bool fusable = false) {
-    if (!ew.empty()) flush();
+    if (!ew.empty() || !sp.empty() || gm_spl) flush();
     GemmDesc g;
     std::memset(&g, 0, sizeof g);
     g.a = a;
@@ -363,6 +451,16 @@ struct Builder {
 
   void flush() {
     if (!wl.empty()) emit_wino();
+    if (!sp.empty()) {
+      OpRec r{OP_SPLIT, DT_BF16X3_SPL, P.table.size(), (int)sp.size(), sp_grid, 0, 0, 0, cur_stream};
+      const size_t bytes = sp.size() * sizeof(EwPart);
+      P.table.resize(round_up(P.table.size() + bytes, 256));
+      std::memcpy(P.table.data() + r.off, sp.data(), bytes);
+      P.ops.push_back(r);
+      txt << "LAUNCH SPLIT " << sp.size() << " " << sp_grid << (cur_stream ? " aux" : "") << "\n";
+      sp.clear();
+      sp_grid = 0;
+    }
     if (!ew.empty()) {
       OpRec r{OP_EW, ew_dtype(P.dtype), P.table.size(), (int)ew.size(), ew_grid, 0, 0, 0, cur_stream};
       const size_t bytes = ew.size() * sizeof(EwPart);
@@ -391,6 +489,7 @@ struct Builder {
         gm_fusable.clear();
       }
       gm_grid = 0;
+      gm_spl = false;
     }
   }
 
@@ -426,7 +525,7 @@ struct Builder {
 
   void emit_gemm(std::vector<GemmDesc>& group, bool fused) {
     if (group.empty()) return;
-    const int kd = kernel_dtype(P.dtype);
+    const int kd = gm_spl ? DT_BF16X3_SPL : kernel_dtype(P.dtype);
     // Unequal problems: longest (largest k) first, round-robin over XCDs.
     bool equal = true;
     for (const GemmDesc& g : group)
@@ -458,7 +557,7 @@ struct Builder {
     std::memcpy(P.table.data() + r.off, group.data(), bytes);
     P.ops.push_back(r);
     txt << "LAUNCH GEMM " << group.size() << " " << grid << " " << cfg << (fused ? " fused" : "")
-        << (cur_stream ? " aux" : "") << "\n";
+        << (gm_spl ? " spl" : "") << (cur_stream ? " aux" : "") << "\n";
     if (fused) P.fused = true;
   }
 };
@@ -686,6 +785,7 @@ struct Sub {
   MView A, B, C;
   int akind = OK_PLAIN, bkind = OK_PLAIN;
   bool fusable = false;  // meets the fused loader's preconditions (aligned, fully valid)
+  bool spl = false;      // A is an SPL matrix, B the SPL transpose of the B operand
 };
 
 // The last level's S/T sums can be formed in the leaf loader when both
@@ -713,7 +813,7 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
   // operands are plain blocks of A and B (P1 = A11 B11, P2 = A12 B21 at the
   // top level, and their counterparts below) run on the main stream.
   const bool leaf_u = b.P.leaf_u && L >= 1;
-  const bool overlap_req = b.P.overlap && L >= 1 && !leaf_u;
+  const bool overlap_req = b.P.overlap && L >= 1 && !leaf_u && !b.P.spl;
   if (overlap_req) {
     b.fork();
     b.cur_stream = 1;
@@ -739,6 +839,37 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
                               {B11, B21, B22, T[3], T[0], T[1], T[2]},
                               {b.quad(s.C, 0, 0), b.quad(s.C, 0, 1), b.quad(s.C, 1, 0), b.quad(s.C, 1, 1)},
                               hm, hn, hk});
+        continue;
+      }
+      if (l == L - 1 && b.P.spl) {
+        // split-bfloat16 leaves: the split pass forms S1..S4 / T1..T4 and
+        // splits the quadrants read as plain leaf operands
+        const MView A11 = b.quad(s.A, 0, 0), A12 = b.quad(s.A, 0, 1), A21 = b.quad(s.A, 1, 0),
+                    A22 = b.quad(s.A, 1, 1);
+        const MView B11 = b.quad(s.B, 0, 0), B12 = b.quad(s.B, 0, 1), B21 = b.quad(s.B, 1, 0),
+                    B22 = b.quad(s.B, 1, 1);
+        MView S[4], T[4], Pt[7];
+        for (auto& v : S) v = b.spl_temp(hm, hk);
+        const MView a11 = b.spl_temp(hm, hk), a12 = b.spl_temp(hm, hk), a22 = b.spl_temp(hm, hk);
+        for (auto& v : T) v = b.spl_temp(hn, hk);
+        const MView b11 = b.spl_temp(hn, hk), b21 = b.spl_temp(hn, hk), b22 = b.spl_temp(hn, hk);
+        for (auto& v : Pt) v = b.temp(hm, hn);
+        b.split_part(EW_WINO_S_SPL, hm, hk, false, {A11, A12, A21, A22}, {S[0], S[1], S[2], S[3], a11, a12, a22});
+        b.split_part(EW_WINO_T_SPL, hk, hn, true, {B11, B12, B21, B22}, {T[0], T[1], T[2], T[3], b11, b21, b22});
+        auto leaf = [](const MView& x, const MView& y, const MView& c) {
+          Sub r{x, y, c};
+          r.spl = true;
+          return r;
+        };
+        next.push_back(leaf(a11, b11, Pt[0]));
+        next.push_back(leaf(a12, b21, Pt[1]));
+        next.push_back(leaf(S[3], b22, Pt[2]));
+        next.push_back(leaf(a22, T[3], Pt[3]));
+        next.push_back(leaf(S[0], T[0], Pt[4]));
+        next.push_back(leaf(S[1], T[1], Pt[5]));
+        next.push_back(leaf(S[2], T[2], Pt[6]));
+        uargs.push_back({Pt[0], Pt[1], Pt[2], Pt[3], Pt[4], Pt[5], Pt[6], b.quad(s.C, 0, 0),
+                         b.quad(s.C, 0, 1), b.quad(s.C, 1, 0), b.quad(s.C, 1, 1)});
         continue;
       }
       if (l == L - 1 && can_fuse(b, s)) {
@@ -812,8 +943,13 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
       if (plain(s)) b.gemm(s.A, s.B, {Builder::store(s.C)}, s.akind, s.bkind, s.fusable);
     b.join();
   }
-  for (const Sub& s : subs)
-    if (!overlap || !plain(s)) b.gemm(s.A, s.B, {Builder::store(s.C)}, s.akind, s.bkind, s.fusable);
+  for (const Sub& s : subs) {
+    if (overlap && plain(s)) continue;
+    if (s.spl)
+      b.gemm_spl(s.A, s.B, {Builder::store(s.C)});
+    else
+      b.gemm(s.A, s.B, {Builder::store(s.C)}, s.akind, s.bkind, s.fusable);
+  }
   b.flush();
   for (int l = L - 1; l >= 0; --l) {
     for (const EwPart& p : u_levels[l])
@@ -892,10 +1028,17 @@ int build_plan(Plan& P) {
     const MView A = b.view(MB_A, 0, P.lda, m, k, m, k);
     const MView B = b.view(MB_B, 0, P.ldb, k, n, k, n);
     const MView C = b.view(MB_C, 0, P.ldc, m, n, m, n);
-    if (k == 0)
+    if (k == 0) {
       b.ew_part(EW_ZERO, m, n, {}, {C});
-    else
+    } else if (P.spl) {
+      const MView As = b.spl_temp(m, k), Bt = b.spl_temp(n, k);
+      b.split_part(EW_SPLIT, m, k, false, {A}, {As});
+      b.split_part(EW_SPLIT, k, n, true, {B}, {Bt});
+      b.flush();
+      b.gemm_spl(As, Bt, {Builder::store(C)});
+    } else {
       b.gemm(A, B, {Builder::store(C)});
+    }
     b.flush();
   } else if (P.sched == MM_SCHED_GROUPED) {
     const MView A = b.view(MB_A, 0, P.lda, P.M, P.K, m, k);
@@ -1037,6 +1180,8 @@ int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEven
         e = launch_ew(op.kdtype, kb, (const EwPart*)d, op.count, op.grid, st);
       else if (op.type == OP_WINO)
         e = launch_gemm_wino(op.cfg, kb, (const WinoLeafDesc*)d, op.count, op.grid, op.remap, st);
+      else if (op.type == OP_SPLIT)
+        e = launch_split(kb, (const EwPart*)d, op.count, op.grid, st);
       else
         e = op.fused ? launch_gemm_fused(op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, st)
                      : launch_gemm(op.kdtype, op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, st);
@@ -1058,6 +1203,8 @@ int execute(Plan& P, void* A, void* B, void* C, void* ws, size_t ws_bytes, hipSt
   if (ws_bytes < P.ws_bytes || (P.ws_bytes > 0 && ws == nullptr))
     return fail(MM_E_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, plan needs " +
                                     std::to_string(P.ws_bytes));
+  if (P.spl && P.ws_bytes > 0 && ((uintptr_t)ws & 15))
+    return fail(MM_E_INVALID, "split-bfloat16 plans need a 16-byte aligned workspace");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != P.device)
     return fail(MM_E_INVALID, "plan was built for another device");
@@ -1161,6 +1308,11 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   P->leaf_u = (flags & MM_PLAN_LEAF_U) != 0 && dtype == MM_F32 && sched == MM_SCHED_GROUPED &&
               algo == MM_ALGO_WINOGRAD;
   if (P->leaf_u && P->fuse) return fail(MM_E_INVALID, "MM_PLAN_FUSE and MM_PLAN_LEAF_U exclude each other");
+  // on request, split-bfloat16 leaves of the grouped schedule and of the
+  // plain product read operands split once by a split pass
+  const int rs = resolve_sched(algo, sched);
+  P->spl = dtype == MM_BF16X3_REFINED && (flags & MM_PLAN_SPLIT_PASS) != 0 &&
+           (rs == MM_SCHED_GROUPED || algo == MM_ALGO_NAIVE);
   if (P->tile_cfg >= (P->leaf_u ? kNumWinoCfg : kNumGemmCfg))
     return fail(MM_E_INVALID, "unknown tile configuration");
   rc = build_plan(*P);
@@ -1467,6 +1619,8 @@ int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, s
   }
   if (ws_bytes < P.ws_bytes || (P.ws_bytes > 0 && ws == nullptr))
     return fail(MM_E_WORKSPACE, "workspace smaller than the plan needs");
+  if (P.spl && P.ws_bytes > 0 && ((uintptr_t)ws & 15))
+    return fail(MM_E_INVALID, "split-bfloat16 plans need a 16-byte aligned workspace");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != P.device)
     return fail(MM_E_INVALID, "plan was built for another device");

@@ -20,6 +20,7 @@ import numpy as np
 
 EW_COPY, EW_ADD, EW_SUB, EW_WINO_S, EW_WINO_T, EW_WINO_U, EW_TT_U = range(7)
 EW_IP_A, EW_IP_B, EW_IP_U, EW_DIST, EW_ZERO = 7, 8, 9, 10, 11
+EW_SPLIT, EW_WINO_S_SPL, EW_WINO_T_SPL = 12, 13, 14
 GM_STORE, GM_ADD = 1, 2
 MB_A, MB_B, MB_C, MB_WS, MB_ABS = 0, 1, 2, 3, 4
 
@@ -35,6 +36,23 @@ class View:
         c = self.vcols if valid_only else self.cols
         return (self.off + np.arange(r, dtype=np.int64)[:, None] * self.ld
                 + np.arange(c, dtype=np.int64)[None, :])
+
+
+def spl_index(v, valid_only=True):
+    """bfloat16 indices of the hi / lo / res slots of an SPL matrix view
+    (rows x cols, chunks of 8 columns, 24 slots per chunk)."""
+    r = v.vrows if valid_only else v.rows
+    c = v.vcols if valid_only else v.cols
+    k = np.arange(c, dtype=np.int64)
+    base = (v.off + np.arange(r, dtype=np.int64)[:, None] * v.ld + (k // 8 * 24 + k % 8)[None, :])
+    return base, base + 8, base + 16
+
+
+def _spl_footprint(v):
+    if v is None or not (v.vrows and v.vcols):
+        return set()
+    idx = np.concatenate([x.ravel() for x in spl_index(v)]) // 2  # 4-byte units
+    return set(zip([v.base] * idx.size, idx.tolist()))
 
 
 def _view(tok):
@@ -63,12 +81,20 @@ def parse(text):
             if "fused" in words[4:]:
                 for _, it in cur:
                     check_fused_preconditions(it)
+            if "spl" in words[4:]:
+                for _, it in cur:
+                    it["spl"] = True
             launches.append((kind, cur, 1 if words[-1] == "aux" else 0))
             cur = []
             continue
         head, *rest = [s.strip() for s in line.split("|")]
         h = head.split()
-        if h[0] == "WINO":
+        if h[0] == "SPLIT":
+            kind, rows, cols, mode = map(int, h[1:])
+            ins = [_view(t) for t in rest[0].split()]
+            outs = [_view(t) for t in rest[1].split()]
+            cur.append(("SPLIT", dict(kind=kind, rows=rows, cols=cols, mode=mode, ins=ins, outs=outs)))
+        elif h[0] == "WINO":
             m, n, k = map(int, h[1:])
             ops = [_view(t) for t in rest[0].split()]
             cs = [_view(t) for t in rest[1].split()]
@@ -137,8 +163,14 @@ def _launch_footprint(kind, items):
                 reads |= _footprint(v)
             for v in it["c"]:
                 writes |= _footprint(v)
+        elif kind == "SPLIT":
+            for v in it["ins"]:
+                reads |= _footprint(v)
+            for v in it["outs"]:
+                writes |= _spl_footprint(v)
         else:
-            reads |= _footprint(it["a"]) | _footprint(it["b"])
+            fp = _spl_footprint if it.get("spl") else _footprint
+            reads |= fp(it["a"]) | fp(it["b"])
             for mode, sign, c, d in it["outs"]:
                 writes |= _footprint(c)
                 if d is not None and mode == GM_ADD:
@@ -161,6 +193,24 @@ def check_fused_preconditions(it, vec=4):
 class Memory:
     def __init__(self, bufs):
         self.bufs = bufs  # base -> flat numpy array
+        self.spl = {}     # base -> bfloat16 slots of SPL matrices (values kept exactly)
+
+    def spl_read(self, v):
+        out = np.zeros((v.rows, v.cols), dtype=self.dtype)
+        if v.vrows and v.vcols:
+            mem = self.spl[v.base]
+            hi, lo, rs = spl_index(v)
+            out[:v.vrows, :v.vcols] = mem[hi] + mem[lo] + mem[rs]
+        return out
+
+    def spl_write(self, v, val):
+        # the simulator keeps each value whole in the hi slot
+        mem = self.spl.setdefault(v.base, np.zeros(2 * len(self.bufs[v.base]), dtype=self.dtype))
+        if v.vrows and v.vcols:
+            hi, lo, rs = spl_index(v)
+            mem[hi] = val[:v.vrows, :v.vcols]
+            mem[lo] = 0
+            mem[rs] = 0
 
     def read(self, v, shape=None):
         rows, cols = (v.rows, v.cols) if shape is None else shape
@@ -264,13 +314,18 @@ def check_hazards(launch):
                         for x in common.tolist():
                             pi, po = pos_in[x], pos_out[x]
                             assert (pi // ci, pi % ci) == (po // co, po % co), "EW cross-element alias"
+        elif kind == "SPLIT":
+            r, w = _launch_footprint(kind, [(kind, it)])
+            assert sum(len(_spl_footprint(v)) for v in it["outs"]) == len(w), "SPLIT outputs overlap"
+            assert not (w & r), "SPLIT writes its own inputs"
         elif kind == "WINO":
             r, w = _launch_footprint(kind, [(kind, it)])
             fcs = [_footprint(v) for v in it["c"]]
             assert sum(len(f) for f in fcs) == len(w), "WINO output quadrants overlap"
             assert not (w & r), "WINO writes its own operands"
         else:
-            r = _footprint(it["a"]) | _footprint(it["b"])
+            fp = _spl_footprint if it.get("spl") else _footprint
+            r = fp(it["a"]) | fp(it["b"])
             w = set()
             for mode, sign, c, d in it["outs"]:
                 fc = _footprint(c)
@@ -326,6 +381,23 @@ def run(text, bufs, hazards=True):
                 else:
                     y = _recipe(it["kind"], x, it["mode"])
                 results.append(list(zip(it["outs"], y)))
+            elif kind == "SPLIT":
+                x = [mem.read(v, (it["rows"], it["cols"])) for v in it["ins"]]
+                if it["kind"] == EW_SPLIT:
+                    y = [x[0]]
+                elif it["kind"] == EW_WINO_S_SPL:
+                    a11, a12, a21, a22 = x
+                    s1 = a21 + a22
+                    s2 = s1 - a11
+                    y = [s1, s2, a11 - a21, a12 - s2, a11, a12, a22]
+                else:
+                    b11, b12, b21, b22 = x
+                    t1 = b12 - b11
+                    t2 = b22 - t1
+                    y = [t1, t2, b22 - b12, t2 - b21, b11, b21, b22]
+                if it["mode"]:
+                    y = [t.T for t in y]
+                results.append([("spl", v, t) for v, t in zip(it["outs"], y)])
             elif kind == "WINO":
                 p = [mem.read(a) @ mem.read(b) for a, b in zip(it["a"], it["b"])]
                 u2 = p[0] + p[5]
@@ -334,8 +406,12 @@ def run(text, bufs, hazards=True):
                 vals = [p[0] + p[1], u4 + p[2], u3 - p[3], u3 + p[4]]
                 results.append(list(zip(it["c"], vals)))
             else:
-                a = operand(mem.read(it["a"]), it["ak"])
-                b = operand(mem.read(it["b"]), it["bk"])
+                if it.get("spl"):
+                    a = mem.spl_read(it["a"])
+                    b = mem.spl_read(it["b"]).T
+                else:
+                    a = operand(mem.read(it["a"]), it["ak"])
+                    b = operand(mem.read(it["b"]), it["bk"])
                 acc = a @ b
                 outs = []
                 for mode, sign, c, d in it["outs"]:
@@ -343,6 +419,9 @@ def run(text, bufs, hazards=True):
                     outs.append((c, val))
                 results.append(outs)
         for outs in results:
-            for v, val in outs:
-                mem.write(v, val)
+            for o in outs:
+                if o[0] == "spl":
+                    mem.spl_write(o[1], o[2])
+                else:
+                    mem.write(*o)
     return mem

@@ -83,3 +83,26 @@ def test_precision_workload_8192_sampled(api, naive):
     err = rel_fro(C[torch.from_numpy(rows).cuda()].cpu().numpy(), ref)
     print(f"bf16x3 winograd n=8192 L=2 sampled rows: {err:.3e}", flush=True)
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("algo,m,n,k,levels", [("naive", 1, 1, 1, 0), ("naive", 17, 33, 65, 0),
+                                               ("naive", 333, 517, 259, 0), ("naive", 1024, 768, 520, 0),
+                                               ("winograd", 512, 512, 512, 1), ("winograd", 1000, 777, 555, 2),
+                                               ("winograd", 2048, 2048, 2048, 2), ("winograd", 384, 640, 256, 3)])
+def test_split_pass_bitwise_equal_to_split_pass(api, naive, algo, m, n, k, levels):
+    # operands split once by the split pass (MM_PLAN_SPLIT_PASS) must give
+    # the same bits as the leaf kernel splitting every staged tile, for every
+    # tile configuration of the split-operand kernel
+    A, B = inputs.pair("gauss_rowscaled", m, n, k, 5, np.float32)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    sched = "grouped" if levels else "auto"
+    print(f"split pass {algo} {m}x{n}x{k} L={levels}", flush=True)
+    ref = api.mm(At, Bt, algo=algo, sched=sched, cutoff=1, levels=levels, dtype="bf16x3")
+    for tile in (None, 0, 1, 3, 4, 5):
+        C = torch.full((m, n), float("nan"), device="cuda")
+        api.mm(At, Bt, algo=algo, sched=sched, cutoff=1, levels=levels, dtype="bf16x3", tile=tile, out=C,
+               split_pass=True)
+        torch.cuda.synchronize()
+        assert torch.equal(C, ref), tile
+    rows = np.arange(0, m, max(1, m // 16))
+    assert rel_fro(ref[torch.from_numpy(rows).cuda()].cpu().numpy(), naive.gemm_rows(A, B, rows)) < 1e-5

@@ -301,3 +301,26 @@ def test_leaf_u_plan_is_exact(lib, m, n, k, levels):
     C = np.full(m * n, -(10**9), dtype=np.int64)
     plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
     assert np.array_equal(C.reshape(m, n), A @ B)
+
+
+@pytest.mark.parametrize("algo,m,n,k,levels", [("naive", 100, 60, 36, 0), ("naive", 33, 17, 9, 0),
+                                               ("winograd", 64, 64, 64, 1), ("winograd", 96, 40, 56, 2),
+                                               ("winograd", 130, 70, 90, 1), ("winograd", 72, 48, 40, 3)])
+def test_split_bf16_plans_are_exact(lib, algo, m, n, k, levels):
+    # refined split-bfloat16 leaves read operands split by a split pass (the
+    # last level's S/T sums formed there too); the listing, simulated on
+    # integers, gives the exact product and has no hazards
+    A = inputs.integers((m, k), 29, dtype=np.int64)
+    B = inputs.integers((k, n), 30, dtype=np.int64)
+    text, info = L.describe(algo, "grouped" if levels else "auto", m, n, k, cutoff=1, levels=levels,
+                            dtype="bf16x3", split_pass=True)
+    assert "LAUNCH SPLIT" in text and " spl" in text
+    assert sum(l.startswith("GEMM") for l in text.splitlines()) == 7 ** levels
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    C = np.full(m * n, -(10**9), dtype=np.int64)
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
+    assert np.array_equal(C.reshape(m, n), A @ B)
+    # by default the leaf kernel splits its tiles itself
+    text, _ = L.describe(algo, "grouped" if levels else "auto", m, n, k, cutoff=1, levels=levels,
+                         dtype="bf16x3")
+    assert "SPLIT" not in text and " spl" not in text
