@@ -69,7 +69,7 @@ __device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& 
 constexpr int KC = 8;  // k values per 16-byte chunk (bfloat16)
 constexpr int EB = 2;  // B columns per staged block (one float2 per k row)
 
-template <int BM, int BN, int BKC, int WGM, int WGN>
+template <int BM, int BN, int BKC, int WGM, int WGN, bool LATE>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases kb,
                                                                      const GemmDesc* __restrict__ descs,
                                                                      int ndesc, int remap) {
@@ -223,37 +223,43 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
 
   const int g = lane / TM, t = lane % TM;
 
+  // MFMAs of k-steps [ks_lo, ks_hi) (16 k values each).  The six products
+  // of a tile are issued in the refinement order (smallest first); tiles of
+  // one product type are interleaved so consecutive MFMAs are independent.
   auto compute = [&](int buf, int ks_lo, int ks_hi) {
 #pragma unroll
     for (int ks = ks_lo; ks < ks_hi; ++ks) {
       const int plane = 2 * ks + g;
-      bf16x8 fa[3][FM], fb[3][FN];
+      bf16x8 fb[3][FN];
 #pragma unroll
-      for (int p = 0; p < 3; ++p) {
-#pragma unroll
-        for (int a = 0; a < FM; ++a) fa[p][a] = As[buf][p][plane][swz_a<BKC>(wm * WM + a * TM + t, plane)];
+      for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int b = 0; b < FN; ++b) fb[p][b] = Bs[buf][p][plane][swz_b<EB>(wn * WN + b * TM + t)];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        bf16x8 fa[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) fa[p] = As[buf][p][plane][swz_a<BKC>(wm * WM + a * TM + t, plane)];
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[1], fb[1][b], acc[a][b]);  // lo  * lo
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[2], fb[0][b], acc[a][b]);  // res * hi
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[0], fb[2][b], acc[a][b]);  // hi  * res
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[1], fb[0][b], acc[a][b]);  // lo  * hi
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[0], fb[1][b], acc[a][b]);  // hi  * lo
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[0], fb[0][b], acc[a][b]);  // hi  * hi
       }
-#pragma unroll
-      for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b) {
-          f32x16 c = acc[a][b];
-          c = mfma_bf16(fa[1][a], fb[1][b], c);  // lo  * lo
-          c = mfma_bf16(fa[2][a], fb[0][b], c);  // res * hi
-          c = mfma_bf16(fa[0][a], fb[2][b], c);  // hi  * res
-          c = mfma_bf16(fa[1][a], fb[0][b], c);  // lo  * hi
-          c = mfma_bf16(fa[0][a], fb[1][b], c);  // hi  * lo
-          c = mfma_bf16(fa[0][a], fb[0][b], c);  // hi  * hi
-          acc[a][b] = c;
-        }
     }
   };
 
-  // As in the float32 kernel: the next stage is split into the other LDS
-  // buffer halfway through this stage's MFMAs (safe with two buffers: it was
-  // last read before the previous barrier and is read after the next one).
+  // The next stage is split into the other LDS buffer halfway through this
+  // stage's MFMAs, or (LATE) after all of them, which gives its global loads
+  // a whole stage to arrive (safe with two buffers: it was last read before
+  // the previous barrier and is read after the next one).
   auto main_loop = [&](auto mode_tag) {
     load_tile(mode_tag, 0);
     store_tile(mode_tag, 0);
@@ -262,9 +268,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
       const int buf = kt & 1;
       const bool more = kt + 1 < ktiles;
       if (more) load_tile(mode_tag, kt + 1);
-      compute(buf, 0, BKC / 4);
-      if (more) store_tile(mode_tag, buf ^ 1);
-      compute(buf, BKC / 4, BKC / 2);
+      if constexpr (LATE) {
+        compute(buf, 0, BKC / 2);
+        if (more) store_tile(mode_tag, buf ^ 1);
+      } else {
+        compute(buf, 0, BKC / 4);
+        if (more) store_tile(mode_tag, buf ^ 1);
+        compute(buf, BKC / 4, BKC / 2);
+      }
       __syncthreads();
     }
   };
@@ -474,9 +485,9 @@ hipError_t launch_spl(const KernelBases& kb, const GemmDesc* d, int n, int tiles
   return hipGetLastError();
 }
 
-template <int BM, int BN, int BKC, int WGM, int WGN>
+template <int BM, int BN, int BKC, int WGM, int WGN, bool LATE = false>
 hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN, BKC, WGM, WGN>), dim3(tiles), dim3(64 * WGM * WGN), 0, s,
+  hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN, BKC, WGM, WGN, LATE>), dim3(tiles), dim3(64 * WGM * WGN), 0, s,
                      kb, d, n, remap);
   return hipGetLastError();
 }
@@ -507,7 +518,10 @@ hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d,
                               int remap, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   switch (cfg) {
-    case 1: return launch_cfg<256, 128, 4, 4, 2>(kb, d, n, tiles, remap, s);
+    // 256x128 (eight waves, two per SIMD) writes the next stage after all of
+    // this stage's MFMAs (measured 2-3% faster at n = 8192); the four-wave
+    // tiles write it halfway
+    case 1: return launch_cfg<256, 128, 4, 4, 2, true>(kb, d, n, tiles, remap, s);
     case 4: return launch_cfg<64, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
     default: return launch_cfg<128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
   }
