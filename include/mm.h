@@ -173,6 +173,14 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                                  staged tile inside the leaf kernel (the default).  Both give
                                  the same bits; the stored parts move 1.5x the bytes of the
                                  float32 operands, and on MI355X the default measures faster. */
+#define MM_PLAN_ACCUMULATE 32u /* the plan computes C <- A B + beta C, beta given per call by
+                                 mm_plan_execute_beta (mm_plan_execute uses beta = 1).  With
+                                 beta == 0 the old C is not read (it may hold anything).  The
+                                 plain product and the grouped schedule apply beta in their
+                                 last step (the GEMM epilogue or the top level's U pass, as
+                                 fma(beta, Cold, x)); the depth-first schedules form A B in a
+                                 workspace block of m x n (they use C as scratch) and add it
+                                 in one more element-wise pass.  Not for batched plans. */
 /* Force the MFMA GEMM tile configuration c (0 .. 7) for every leaf launch
  * instead of the planner's choice.  float32: 0 128x128 (BK 32), 1 256x128,
  * 2 128x256, 3 256x256 (BK 16), 4 64x128, 5 128x64, 6 256x128 (BK 16),
@@ -193,6 +201,13 @@ int mm_plan_create(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t
 /* Enqueue the plan on `stream` for these operands.  No allocation. */
 int mm_plan_execute(mm_plan_t plan, void* A, void* B, void* C, void* ws, size_t ws_bytes,
                     hipStream_t stream);
+
+/* C <- A B + beta C for a plan created with MM_PLAN_ACCUMULATE (the
+ * accumulating form C <- A B + beta C; beta finite).  Otherwise as
+ * mm_plan_execute; MM_E_INVALID for other plans or a non-finite beta.  With
+ * MM_PLAN_GRAPH a graph is captured per (A, B, C, ws, beta). */
+int mm_plan_execute_beta(mm_plan_t plan, void* A, void* B, void* C, void* ws, size_t ws_bytes, double beta,
+                         hipStream_t stream);
 
 /* mm_plan_execute with timing: events[2i] and events[2i+1] (created by the
  * caller with hipEventCreate; nevents >= 2 * launches) are recorded before

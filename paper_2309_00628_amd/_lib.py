@@ -25,6 +25,7 @@ MM_PLAN_FUSE = 2
 MM_PLAN_OVERLAP = 4
 MM_PLAN_LEAF_U = 8
 MM_PLAN_SPLIT_PASS = 16
+MM_PLAN_ACCUMULATE = 32
 
 
 def plan_tile(c):
@@ -70,6 +71,7 @@ _SIGS = {
                                c_int, ctypes.c_uint, ctypes.POINTER(c_vp)]),
     "mm_plan_execute": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "mm_plan_info": (c_int, [c_vp, c_i64p, c_int]),
+    "mm_plan_execute_beta": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, ctypes.c_double, c_vp]),
     "mm_plan_execute_timed": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp, c_vpp, c_int]),
     "mm_plan_op_kind": (c_int, [c_vp, c_int]),
     "mm_plan_describe": (c_sz, [c_vp, ctypes.c_char_p, c_sz]),
@@ -118,7 +120,7 @@ def check(status):
 
 
 def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None, ldc=None,
-             fuse=False, overlap=False, leaf_u=False, split_pass=False):
+             fuse=False, overlap=False, leaf_u=False, split_pass=False, accumulate=False):
     """Host-only plan listing and facts (no device needed)."""
     lib = load()
     lda = max(k, 1) if lda is None else lda
@@ -127,7 +129,8 @@ def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, l
     info = (ctypes.c_int64 * NINFO)()
     args = (ALGOS.get(algo, algo), SCHEDS.get(sched, sched), m, n, k, lda, ldb, ldc, cutoff, levels,
             DTYPES.get(dtype, dtype), (MM_PLAN_FUSE if fuse else 0) | (MM_PLAN_OVERLAP if overlap else 0) |
-            (MM_PLAN_LEAF_U if leaf_u else 0) | (MM_PLAN_SPLIT_PASS if split_pass else 0))
+            (MM_PLAN_LEAF_U if leaf_u else 0) | (MM_PLAN_SPLIT_PASS if split_pass else 0) |
+            (MM_PLAN_ACCUMULATE if accumulate else 0))
     need = lib.mm_describe(*args, None, 0, info, NINFO)
     if need == 0:
         raise MMError(1, last_error())

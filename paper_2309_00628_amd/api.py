@@ -49,7 +49,7 @@ class Plan:
 
     def __init__(self, algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None,
                  ldc=None, graph=False, device=None, tile=None, fuse=False, overlap=False, leaf_u=False,
-                 split_pass=False):
+                 split_pass=False, accumulate=False):
         lib = L.load()
         self.algo, self.sched, self.dtype = algo, sched, dtype
         self.m, self.n, self.k = m, n, k
@@ -66,8 +66,10 @@ class Plan:
                                        (L.MM_PLAN_FUSE if fuse else 0) |
                                        (L.MM_PLAN_OVERLAP if overlap else 0) |
                                        (L.MM_PLAN_LEAF_U if leaf_u else 0) |
-                                       (L.MM_PLAN_SPLIT_PASS if split_pass else 0),
+                                       (L.MM_PLAN_SPLIT_PASS if split_pass else 0) |
+                                       (L.MM_PLAN_ACCUMULATE if accumulate else 0),
                                        ctypes.byref(self._ptr)))
+        self.accumulate = accumulate
         info = (ctypes.c_int64 * L.NINFO)()
         lib.mm_plan_info(self._ptr, info, L.NINFO)
         self.info = L._info_dict(info)
@@ -80,14 +82,22 @@ class Plan:
         lib.mm_plan_describe(self._ptr, buf, need + 1)
         return buf.value.decode()
 
-    def __call__(self, A, B, C, ws=None, stream=None):
+    def __call__(self, A, B, C, ws=None, stream=None, beta=None):
+        """C = A @ B, or C = A @ B + beta * C for an accumulating plan
+        (beta None means 1)."""
         s = _stream(stream, self.device)
         if self.ws_bytes and ws is None:
             ws = workspace(self.ws_bytes, self.device, s)
         wptr = ws.data_ptr() if ws is not None else None
         wbytes = ws.numel() * ws.element_size() if ws is not None else 0
-        L.check(L.load().mm_plan_execute(self._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), wptr,
-                                         wbytes, s.cuda_stream))
+        if self.accumulate:
+            L.check(L.load().mm_plan_execute_beta(self._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), wptr,
+                                                  wbytes, 1.0 if beta is None else float(beta), s.cuda_stream))
+        else:
+            if beta is not None:
+                raise ValueError("beta needs a plan created with accumulate=True")
+            L.check(L.load().mm_plan_execute(self._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), wptr,
+                                             wbytes, s.cuda_stream))
         return C
 
     def __del__(self):
@@ -117,21 +127,21 @@ def workspace(nbytes, device, stream):
 
 
 def get_plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile=None,
-             fuse=False, overlap=False, leaf_u=False, split_pass=False):
+             fuse=False, overlap=False, leaf_u=False, split_pass=False, accumulate=False):
     key = (str(device), algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, tile, fuse,
-           overlap, leaf_u, split_pass)
+           overlap, leaf_u, split_pass, accumulate)
     with _plans_lock:
         p = _plans.get(key)
         if p is None:
             p = Plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile, fuse,
-                     overlap, leaf_u, split_pass)
+                     overlap, leaf_u, split_pass, accumulate)
             _plans[key] = p
     return p
 
 
 def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None, out=None,
        graph=False, stream=None, clobber_inputs=False, tile=None, fuse=False, overlap=None, leaf_u=None,
-       split_pass=False):
+       split_pass=False, beta=None):
     """C = A @ B on the GPU by ``algo`` in {"naive", "strassen", "winograd"}.
 
     ``cutoff`` / ``levels`` control the recursion as in mm.h; when both are
@@ -143,7 +153,8 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
     "bf16x3" (float32 tensors, split-bfloat16 leaf products).  ``fuse`` /
     ``overlap`` / ``leaf_u``: MM_PLAN_FUSE / MM_PLAN_OVERLAP / MM_PLAN_LEAF_U
     (None: the autotuner's choice when it picks the recursion, else off);
-    ``split_pass``: MM_PLAN_SPLIT_PASS.  The in-place
+    ``split_pass``: MM_PLAN_SPLIT_PASS.  ``beta`` (needs ``out``): the
+    accumulating form out = A @ B + beta * out (MM_PLAN_ACCUMULATE).  The in-place
     schedule overwrites its operands, so unless ``clobber_inputs`` is set the
     wrapper hands it copies.
     """
@@ -161,6 +172,8 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
         A = A.contiguous().clone()
         B = B.contiguous().clone()
     lda, ldb = _ld(A, "A"), _ld(B, "B")
+    if beta is not None and out is None:
+        raise ValueError("beta needs out (the C that is accumulated into)")
     C = out if out is not None else torch.empty((m, n), dtype=A.dtype, device=A.device)
     if C.shape != (m, n) or C.dtype != A.dtype or C.device != A.device:
         raise ValueError("out has the wrong shape, dtype or device")
@@ -185,9 +198,9 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
     elif levels is None:
         levels = -1
     p = get_plan(algo, sched, m, n, k, cutoff, levels, dt, lda, ldb, ldc, graph, A.device, tile, fuse,
-                 bool(overlap), bool(leaf_u), bool(split_pass))
+                 bool(overlap), bool(leaf_u), bool(split_pass), beta is not None)
     with torch.cuda.device(A.device):
-        p(A, B, C, stream=stream)
+        p(A, B, C, stream=stream, beta=beta)
     return C
 
 

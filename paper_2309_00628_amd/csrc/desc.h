@@ -47,9 +47,14 @@ enum EwKind : int32_t {
   EW_SPLIT = 12,       // o0 = split(i0)
   EW_WINO_S_SPL = 13,  // i = A11 A12 A21 A22 ; o = S1 S2 S3 S4 A11 A12 A22
   EW_WINO_T_SPL = 14,  // i = B11 B12 B21 B22 ; o = T1 T2 T3 T4 B11 B21 B22 (transposed)
+  // Accumulating form C <- A B + beta C (beta from KernelBases, applied as
+  // one fused multiply-add beta * Cold + x; with beta == 0 the old C is not
+  // read):
+  EW_WINO_U_ACC = 15,  // i = P1..P7 C11 C12 C21 C22 ; o = C11..C22 = beta Cij + (U1 U5 U6 U7)
+  EW_AXPBY = 16,       // i = X C ; o0 = beta C + X
 };
 
-constexpr int kEwMaxIn = 7;
+constexpr int kEwMaxIn = 11;
 constexpr int kEwMaxOut = 7;
 
 // Split bfloat16 layout ("SPL") of a float32 matrix X with R rows and Kc
@@ -72,8 +77,10 @@ struct EwPart {
   MView out[kEwMaxOut];
 };
 
-// GEMM epilogue: out = sign * acc (store) or out = d + sign * acc (add).
-enum GemmMode : int32_t { GM_NONE = 0, GM_STORE = 1, GM_ADD = 2 };
+// GEMM epilogue: out = sign * acc (store), out = d + sign * acc (add), or
+// out = fma(beta, d, sign * acc) (axpby; beta from KernelBases, d not read
+// when beta == 0).
+enum GemmMode : int32_t { GM_NONE = 0, GM_STORE = 1, GM_ADD = 2, GM_AXPBY = 3 };
 
 struct GemmOut {
   MView c;
@@ -113,11 +120,13 @@ struct WinoLeafDesc {
   int32_t m, n, k;     // product extents: operand A m x k, B k x n
   int32_t tiles_m, tiles_n;
   int32_t tile_start;  // first tile of this subproblem in the launch
+  int32_t acc;         // 1: C = beta C + U (top level of an accumulating product)
 };
 
 struct KernelBases {
   void* p[kNumBases];
   int32_t aligned;  // bit b set: base b is 16-byte aligned
+  double beta;      // C <- A B + beta C (accumulating plans; 1 otherwise)
 };
 
 }  // namespace mm

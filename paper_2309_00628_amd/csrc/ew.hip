@@ -87,7 +87,12 @@ __global__ __launch_bounds__(kThreads) void ew_kernel(KernelBases kb, const EwPa
     if (parts[mid].blk_start <= b) lo = mid; else hi = mid - 1;
   }
   const EwPart& P = parts[lo];
-  const int kind = P.kind, nin = P.nin, nout = P.nout;
+  const int kind = P.kind, nout = P.nout;
+  // with beta == 0 the old C (the trailing inputs of the accumulating
+  // recipes) is not read
+  const bool drop_c = kb.beta == 0.0 && (kind == EW_WINO_U_ACC || kind == EW_AXPBY);
+  const int nin = drop_c ? (kind == EW_AXPBY ? 1 : 7) : P.nin;
+  const T beta = drop_c ? T(0) : T(kb.beta);
   bool vec = true;
   for (int i = 0; i < nin; ++i)
     vec = vec && (P.in[i].base == MB_NONE ||
@@ -106,8 +111,13 @@ __global__ __launch_bounds__(kThreads) void ew_kernel(KernelBases kb, const EwPa
     T x[kEwMaxIn][V];
     T y[kOut][V];
 #pragma unroll
-    for (int i = 0; i < kEwMaxIn; ++i)
-      if (i < nin) load_chunk<T, V>(kb, P.in[i], r, c0, vec, x[i]);
+    for (int i = 0; i < kEwMaxIn; ++i) {
+      if (i < nin)
+        load_chunk<T, V>(kb, P.in[i], r, c0, vec, x[i]);
+      else
+#pragma unroll
+        for (int e = 0; e < V; ++e) x[i][e] = T(0);
+    }
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       switch (kind) {
@@ -169,6 +179,21 @@ __global__ __launch_bounds__(kThreads) void ew_kernel(KernelBases kb, const EwPa
           y[0][e] = u1; y[1][e] = u4; y[2][e] = u6; y[3][e] = u7;
           break;
         }
+        case EW_WINO_U_ACC: {  // x = P1..P7 C11 C12 C21 C22
+          const T u1 = x[0][e] + x[1][e];
+          const T u2 = x[0][e] + x[5][e];
+          const T u3 = u2 + x[6][e];
+          const T u4 = u2 + x[4][e];
+          const T u5 = u4 + x[2][e];
+          const T u6 = u3 - x[3][e];
+          const T u7 = u3 + x[4][e];
+          y[0][e] = fma(beta, x[7][e], u1);
+          y[1][e] = fma(beta, x[8][e], u5);
+          y[2][e] = fma(beta, x[9][e], u6);
+          y[3][e] = fma(beta, x[10][e], u7);
+          break;
+        }
+        case EW_AXPBY: y[0][e] = fma(beta, x[1][e], x[0][e]); break;  // x = X C
         case EW_DIST: {  // x = Z D0 D1
           for (int o = 0; o < 2; ++o) {
             const int md = P.mode[o];

@@ -87,8 +87,8 @@ __device__ __forceinline__ TileRef locate_tile(const Desc* __restrict__ descs, i
   return TileRef{lo, tm * BM, tn * BN};
 }
 
-// Epilogue: every output of the descriptor gets C = s * acc or
-// C = D + s * acc at the positions this lane owns.  ROW(lane, r) gives the
+// Epilogue: every output of the descriptor gets C = s * acc,
+// C = D + s * acc or C = beta * D + s * acc at the positions this lane owns.  ROW(lane, r) gives the
 // row (within an MFMA tile of edge TM) of accumulator register r.
 template <typename T, int TM, int NACC, int FM, int FN, int WM, int WN, typename Acc, typename RowFn>
 __device__ __forceinline__ void store_outputs(const KernelBases& kb, const GemmDesc& D, int i0, int j0,
@@ -102,7 +102,10 @@ __device__ __forceinline__ void store_outputs(const KernelBases& kb, const GemmD
     const int mode = D.out[o].mode;
     const T sg = T(D.out[o].sign);
     T* __restrict__ Cp = resolve<T>(kb, cv);
-    const bool add = mode == GM_ADD;
+    const T beta = T(kb.beta);
+    // d is read for GM_ADD, and for GM_AXPBY unless beta == 0
+    const bool add = mode == GM_ADD || (mode == GM_AXPBY && kb.beta != 0.0);
+    const T dscale = mode == GM_AXPBY ? beta : T(1);
     const T* Dp = add ? resolve<T>(kb, dv) : nullptr;
     const int64_t ldc = cv.ld, ldd = add ? dv.ld : 0;
     const int crows = cv.vrows, ccols = cv.vcols;
@@ -119,7 +122,8 @@ __device__ __forceinline__ void store_outputs(const KernelBases& kb, const GemmD
           const int rr = rowfn(lane, r);
           if (rbase + rr < crows && col < ccols) {
             const T v = sg * acc[a][b][r];
-            cpt[(int64_t)rr * ldc] = add ? dpt[(int64_t)rr * ldd] + v : v;
+            // one rounding: the same as the element-wise accumulating recipes
+            cpt[(int64_t)rr * ldc] = add ? fma(dscale, dpt[(int64_t)rr * ldd], v) : v;
           }
         }
       }

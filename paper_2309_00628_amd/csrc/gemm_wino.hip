@@ -43,7 +43,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_wino_kernel(KernelBases k
     TL::zero(acc);
     TL::product(sm, operand<float>(kb, D.a[p]), operand<float>(kb, D.b[p]), i0, j0, D.k, acc);
   };
-  // v(a, b) gives the 16 values of MFMA tile (a, b) this lane stores.
+  // v(a, b) gives the 16 values of MFMA tile (a, b) this lane stores; an
+  // accumulating top level stores fma(beta, Cold, v) instead.
+  const bool accum = D.acc && kb.beta != 0.0;
+  const float beta = (float)kb.beta;
   auto store = [&](const MView& cv, auto v) {
     float* __restrict__ Cp = resolve<float>(kb, cv);
     const int t = lane % TM;
@@ -58,7 +61,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_wino_kernel(KernelBases k
 #pragma unroll
         for (int r = 0; r < M::NACC; ++r) {
           const int rr = M::row(lane, r);
-          if (rbase + rr < cv.vrows && col < cv.vcols) cpt[(int64_t)rr * cv.ld] = x[r];
+          if (rbase + rr < cv.vrows && col < cv.vcols) {
+            float* q = cpt + (int64_t)rr * cv.ld;
+            *q = accum ? fma(beta, *q, x[r]) : x[r];
+          }
         }
       }
   };

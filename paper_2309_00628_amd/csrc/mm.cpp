@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <array>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -83,6 +84,7 @@ struct Plan {
   bool leaf_u = false;   // last level: products and U combinations in one kernel (float32)
   bool wino = false;     // the plan has such a launch
   bool spl = false;      // split-bfloat16 leaves read operands split by a split pass
+  bool accumulate = false;  // C <- A B + beta C (beta given per execution)
   bool has_aux = false;  // some launches go to the auxiliary stream
   struct Aux {
     hipStream_t main, aux;
@@ -100,6 +102,7 @@ struct Plan {
   int device = -1;
   struct Graph {
     void *a, *b, *c, *ws;
+    double beta;
     hipStream_t stream;
     hipGraphExec_t exec;
   };
@@ -295,6 +298,8 @@ struct Builder {
   };
   static Out store(const MView& c, int sign = 1) { return Out{c, GM_STORE, sign, MView{}}; }
   static Out add(const MView& c, const MView& d, int sign) { return Out{c, GM_ADD, sign, d}; }
+  // c = beta c + acc (accumulating plans)
+  static Out axpby(const MView& c) { return Out{c, GM_AXPBY, 1, c}; }
 
   // ---- split passes -------------------------------------------------------
   // rows x cols: the float32 input block; transposed: outputs hold its
@@ -346,7 +351,7 @@ struct Builder {
       g.out[i].c = o.c;
       g.out[i].mode = o.mode;
       g.out[i].sign = o.sign;
-      g.out[i].d = o.mode == GM_ADD ? o.d : none();
+      g.out[i].d = (o.mode == GM_ADD || o.mode == GM_AXPBY) ? o.d : none();
       ++i;
     }
     for (; i < 2; ++i) {
@@ -382,7 +387,7 @@ struct Builder {
       g.out[i].c = o.c;
       g.out[i].mode = o.mode;
       g.out[i].sign = o.sign;
-      g.out[i].d = o.mode == GM_ADD ? o.d : none();
+      g.out[i].d = (o.mode == GM_ADD || o.mode == GM_AXPBY) ? o.d : none();
       ++i;
     }
     for (; i < 2; ++i) {
@@ -432,7 +437,8 @@ struct Builder {
 
   // One last-level Winograd subproblem C = A B with its S/T sums already
   // formed: operands of P1 .. P7 and the output quadrants.
-  void wino(const MView (&a)[7], const MView (&bop)[7], const MView (&c)[4], int64_t m, int64_t n, int64_t k) {
+  void wino(const MView (&a)[7], const MView (&bop)[7], const MView (&c)[4], int64_t m, int64_t n, int64_t k,
+            bool acc = false) {
     if (!ew.empty() || !gm.empty()) flush();
     WinoLeafDesc d;
     std::memset(&d, 0, sizeof d);
@@ -444,6 +450,7 @@ struct Builder {
     d.m = (int32_t)m;
     d.n = (int32_t)n;
     d.k = (int32_t)k;
+    d.acc = acc ? 1 : 0;
     P.leaves += 7;
     if (m == 0 || n == 0) return;
     wl.push_back(d);
@@ -507,7 +514,7 @@ struct Builder {
       d.tiles_n = (int32_t)ceil_div(d.n, gc.bn);
       d.tile_start = grid;
       grid += d.tiles_m * d.tiles_n;
-      txt << "WINO " << d.m << " " << d.n << " " << d.k << " |";
+      txt << "WINO " << d.m << " " << d.n << " " << d.k << " " << d.acc << " |";
       for (int i = 0; i < 7; ++i) txt << " " << vs(d.a[i]) << " " << vs(d.b[i]);
       txt << " |";
       for (int i = 0; i < 4; ++i) txt << " " << vs(d.c[i]);
@@ -807,6 +814,7 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
   struct WinoSub {
     MView a[7], b[7], c[4];
     int64_t m, n, k;
+    bool acc;
   };
   std::vector<WinoSub> wl_pending;  // last-level subproblems (leaf_u)
   // The S/T passes run on the auxiliary stream while the leaf products whose
@@ -838,7 +846,7 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
         wl_pending.push_back({{A11, A12, S[3], A22, S[0], S[1], S[2]},
                               {B11, B21, B22, T[3], T[0], T[1], T[2]},
                               {b.quad(s.C, 0, 0), b.quad(s.C, 0, 1), b.quad(s.C, 1, 0), b.quad(s.C, 1, 1)},
-                              hm, hn, hk});
+                              hm, hn, hk, l == 0 && b.P.accumulate});
         continue;
       }
       if (l == L - 1 && b.P.spl) {
@@ -928,7 +936,7 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
   }
   b.flush();
   b.cur_stream = 0;
-  for (const WinoSub& w : wl_pending) b.wino(w.a, w.b, w.c, w.m, w.n, w.k);
+  for (const WinoSub& w : wl_pending) b.wino(w.a, w.b, w.c, w.m, w.n, w.k, w.acc);
   b.flush();
   auto plain = [](const Sub& s) {
     return s.A.base != MB_WS && s.B.base != MB_WS && s.akind == OK_PLAIN && s.bkind == OK_PLAIN;
@@ -952,9 +960,16 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
   }
   b.flush();
   for (int l = L - 1; l >= 0; --l) {
-    for (const EwPart& p : u_levels[l])
-      b.ew_part(EW_WINO_U, p.rows, p.cols, {p.in[0], p.in[1], p.in[2], p.in[3], p.in[4], p.in[5], p.in[6]},
-                {p.out[0], p.out[1], p.out[2], p.out[3]});
+    for (const EwPart& p : u_levels[l]) {
+      if (l == 0 && b.P.accumulate)  // C = beta C + U at the top level
+        b.ew_part(EW_WINO_U_ACC, p.rows, p.cols,
+                  {p.in[0], p.in[1], p.in[2], p.in[3], p.in[4], p.in[5], p.in[6], p.out[0], p.out[1], p.out[2],
+                   p.out[3]},
+                  {p.out[0], p.out[1], p.out[2], p.out[3]});
+      else
+        b.ew_part(EW_WINO_U, p.rows, p.cols, {p.in[0], p.in[1], p.in[2], p.in[3], p.in[4], p.in[5], p.in[6]},
+                  {p.out[0], p.out[1], p.out[2], p.out[3]});
+    }
     b.flush();
   }
 }
@@ -1028,16 +1043,20 @@ int build_plan(Plan& P) {
     const MView A = b.view(MB_A, 0, P.lda, m, k, m, k);
     const MView B = b.view(MB_B, 0, P.ldb, k, n, k, n);
     const MView C = b.view(MB_C, 0, P.ldc, m, n, m, n);
+    const Builder::Out out = P.accumulate ? Builder::axpby(C) : Builder::store(C);
     if (k == 0) {
-      b.ew_part(EW_ZERO, m, n, {}, {C});
+      if (P.accumulate)  // C = beta C + 0
+        b.ew_part(EW_AXPBY, m, n, {b.view(MB_C, 0, P.ldc, m, n, 0, 0), C}, {C});
+      else
+        b.ew_part(EW_ZERO, m, n, {}, {C});
     } else if (P.spl) {
       const MView As = b.spl_temp(m, k), Bt = b.spl_temp(n, k);
       b.split_part(EW_SPLIT, m, k, false, {A}, {As});
       b.split_part(EW_SPLIT, k, n, true, {B}, {Bt});
       b.flush();
-      b.gemm_spl(As, Bt, {Builder::store(C)});
+      b.gemm_spl(As, Bt, {out});
     } else {
-      b.gemm(A, B, {Builder::store(C)});
+      b.gemm(A, B, {out});
     }
     b.flush();
   } else if (P.sched == MM_SCHED_GROUPED) {
@@ -1052,6 +1071,9 @@ int build_plan(Plan& P) {
     MView B = b.view(MB_B, 0, P.ldb, k, n, k, n);
     MView C = b.view(MB_C, 0, P.ldc, m, n, m, n);
     MView Cw = C;
+    // an accumulating depth-first plan forms the product in a temporary
+    // (the schedules use C as scratch) and adds it to beta C at the end
+    if (P.accumulate && !pad) Cw = b.temp(m, n);
     if (pad) {
       const MView Ap = b.temp(P.M, P.K), Bp = b.temp(P.K, P.N), Cp = b.temp(P.M, P.N);
       b.ew_part(EW_COPY, P.M, P.K, {b.view(MB_A, 0, P.lda, P.M, P.K, m, k)}, {Ap});
@@ -1067,7 +1089,10 @@ int build_plan(Plan& P) {
       sched_in_place(b, A, B, Cw, 0);
     else
       sched_strassen(b, A, B, Cw, 0);
-    if (pad) {
+    if (P.accumulate) {
+      b.ew_part(EW_AXPBY, m, n, {b.corner(Cw, m, n), C}, {C});
+      b.flush();
+    } else if (pad) {
       b.ew_part(EW_COPY, m, n, {b.corner(Cw, m, n)}, {C});
       b.flush();
     }
@@ -1148,8 +1173,10 @@ int aux_for(Plan& P, hipStream_t s, Plan::Aux** out) {
 
 // events (timed execution): events[2i] / events[2i+1] are recorded before /
 // after launch i on the stream that launch runs on.
-int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEvent_t* events = nullptr) {
+int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEvent_t* events = nullptr,
+            double beta = 1.0) {
   KernelBases kb;
+  kb.beta = beta;
   kb.p[MB_A] = A;
   kb.p[MB_B] = B;
   kb.p[MB_C] = C;
@@ -1198,8 +1225,9 @@ bool misaligned_ab(const void* A, const void* B) {
   return (((uintptr_t)A) & 15) || (((uintptr_t)B) & 15);
 }
 
-int execute(Plan& P, void* A, void* B, void* C, void* ws, size_t ws_bytes, hipStream_t s) {
-  if (P.fused_reads_ab && P.unfused && misaligned_ab(A, B)) return execute(*P.unfused, A, B, C, ws, ws_bytes, s);
+int execute(Plan& P, void* A, void* B, void* C, void* ws, size_t ws_bytes, hipStream_t s, double beta = 1.0) {
+  if (P.fused_reads_ab && P.unfused && misaligned_ab(A, B))
+    return execute(*P.unfused, A, B, C, ws, ws_bytes, s, beta);
   if (ws_bytes < P.ws_bytes || (P.ws_bytes > 0 && ws == nullptr))
     return fail(MM_E_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, plan needs " +
                                     std::to_string(P.ws_bytes));
@@ -1209,17 +1237,17 @@ int execute(Plan& P, void* A, void* B, void* C, void* ws, size_t ws_bytes, hipSt
   if (hipGetDevice(&dev) != hipSuccess || dev != P.device)
     return fail(MM_E_INVALID, "plan was built for another device");
   if (P.ops.empty()) return MM_OK;
-  if (!(P.flags & MM_PLAN_GRAPH) || s == nullptr) return enqueue(P, A, B, C, ws, s);
+  if (!(P.flags & MM_PLAN_GRAPH) || s == nullptr) return enqueue(P, A, B, C, ws, s, nullptr, beta);
   std::lock_guard<std::mutex> lk(P.mu);
   for (auto& g : P.graphs)
-    if (g.a == A && g.b == B && g.c == C && g.ws == ws) {
+    if (g.a == A && g.b == B && g.c == C && g.ws == ws && g.beta == beta) {
       if (hipGraphLaunch(g.exec, s) != hipSuccess) return fail(MM_E_HIP, "hipGraphLaunch failed");
       return MM_OK;
     }
   hipGraph_t graph = nullptr;
   if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return fail(MM_E_HIP, "hipStreamBeginCapture failed");
-  int rc = enqueue(P, A, B, C, ws, s);
+  int rc = enqueue(P, A, B, C, ws, s, nullptr, beta);
   hipError_t e = hipStreamEndCapture(s, &graph);
   if (rc != MM_OK) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -1236,7 +1264,7 @@ int execute(Plan& P, void* A, void* B, void* C, void* ws, size_t ws_bytes, hipSt
     (void)hipGraphExecDestroy(P.graphs.front().exec);
     P.graphs.erase(P.graphs.begin());
   }
-  P.graphs.push_back({A, B, C, ws, s, exec});
+  P.graphs.push_back({A, B, C, ws, beta, s, exec});
   if (hipGraphLaunch(exec, s) != hipSuccess) return fail(MM_E_HIP, "hipGraphLaunch failed");
   return MM_OK;
 }
@@ -1303,6 +1331,7 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   P->tile_cfg = (int)((flags >> 8) & 0xff) - 1;
   P->fuse = (flags & MM_PLAN_FUSE) != 0;
   P->overlap = (flags & MM_PLAN_OVERLAP) != 0;
+  P->accumulate = (flags & MM_PLAN_ACCUMULATE) != 0;
   // the fused Winograd leaf level computes in float32 and replaces the
   // grouped schedule's last level; other dtypes and schedules ignore it
   P->leaf_u = (flags & MM_PLAN_LEAF_U) != 0 && dtype == MM_F32 && sched == MM_SCHED_GROUPED &&
@@ -1607,6 +1636,17 @@ int mm_plan_execute(mm_plan_t plan, void* A, void* B, void* C, void* ws, size_t 
   return execute(P, A, B, C, ws, ws_bytes, stream);
 }
 
+int mm_plan_execute_beta(mm_plan_t plan, void* A, void* B, void* C, void* ws, size_t ws_bytes, double beta,
+                         hipStream_t stream) {
+  if (!plan || !plan->p) return fail(MM_E_INVALID, "NULL plan");
+  Plan& P = *plan->p;
+  if (!P.accumulate) return fail(MM_E_INVALID, "plan was not created with MM_PLAN_ACCUMULATE");
+  if (!std::isfinite(beta)) return fail(MM_E_INVALID, "beta must be finite");
+  int rc = check_args(P.m, P.n, P.k, A, P.lda, B, P.ldb, C, P.ldc, P.dtype);
+  if (rc != MM_OK) return rc;
+  return execute(P, A, B, C, ws, ws_bytes, stream, beta);
+}
+
 int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, size_t ws_bytes,
                           hipStream_t stream, hipEvent_t* events, int nevents) {
   if (!plan || !plan->p) return fail(MM_E_INVALID, "NULL plan");
@@ -1695,6 +1735,7 @@ int mm_batched_plan_create(int count, const int64_t* mnk, void* const* A, void* 
   if (count < 0 || (count > 0 && (!mnk || !A || !B || !C))) return fail(MM_E_INVALID, "bad batch arrays");
   int rc = check_enums(MM_ALGO_WINOGRAD, MM_SCHED_GROUPED, dtype);
   if (rc != MM_OK) return rc;
+  if (flags & MM_PLAN_ACCUMULATE) return fail(MM_E_UNSUPPORTED, "batched plans do not accumulate");
   std::unique_ptr<Plan> P(new Plan);
   P->algo = MM_ALGO_WINOGRAD;
   P->sched = MM_SCHED_GROUPED;

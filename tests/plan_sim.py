@@ -20,8 +20,8 @@ import numpy as np
 
 EW_COPY, EW_ADD, EW_SUB, EW_WINO_S, EW_WINO_T, EW_WINO_U, EW_TT_U = range(7)
 EW_IP_A, EW_IP_B, EW_IP_U, EW_DIST, EW_ZERO = 7, 8, 9, 10, 11
-EW_SPLIT, EW_WINO_S_SPL, EW_WINO_T_SPL = 12, 13, 14
-GM_STORE, GM_ADD = 1, 2
+EW_SPLIT, EW_WINO_S_SPL, EW_WINO_T_SPL, EW_WINO_U_ACC, EW_AXPBY = 12, 13, 14, 15, 16
+GM_STORE, GM_ADD, GM_AXPBY = 1, 2, 3
 MB_A, MB_B, MB_C, MB_WS, MB_ABS = 0, 1, 2, 3, 4
 
 
@@ -95,11 +95,11 @@ def parse(text):
             outs = [_view(t) for t in rest[1].split()]
             cur.append(("SPLIT", dict(kind=kind, rows=rows, cols=cols, mode=mode, ins=ins, outs=outs)))
         elif h[0] == "WINO":
-            m, n, k = map(int, h[1:])
+            m, n, k, acc = map(int, h[1:])
             ops = [_view(t) for t in rest[0].split()]
             cs = [_view(t) for t in rest[1].split()]
             assert len(ops) == 14 and len(cs) == 4
-            cur.append(("WINO", dict(m=m, n=n, k=k, a=ops[0::2], b=ops[1::2], c=cs)))
+            cur.append(("WINO", dict(m=m, n=n, k=k, acc=acc, a=ops[0::2], b=ops[1::2], c=cs)))
         elif h[0] == "EW":
             kind, rows, cols, m0, m1 = map(int, h[1:])
             ins = [_view(t) for t in rest[0].split()] if rest[0] else []
@@ -173,7 +173,7 @@ def _launch_footprint(kind, items):
             reads |= fp(it["a"]) | fp(it["b"])
             for mode, sign, c, d in it["outs"]:
                 writes |= _footprint(c)
-                if d is not None and mode == GM_ADD:
+                if d is not None and mode in (GM_ADD, GM_AXPBY):
                     reads |= _footprint(d)
     return reads, writes
 
@@ -332,7 +332,7 @@ def check_hazards(launch):
                 assert not (fc & r), "GEMM writes its own operand"
                 assert not (fc & w), "GEMM outputs overlap"
                 w |= fc
-                if d is not None and mode == GM_ADD:
+                if d is not None and mode in (GM_ADD, GM_AXPBY):
                     fd = _footprint(d)
                     if fd & fc:
                         assert d.off == c.off and d.ld == c.ld and d.base == c.base, \
@@ -363,7 +363,7 @@ def operand(M, kind):
     return {5: t1, 6: t2, 7: q22 - q12, 8: t2 - q21}[kind]
 
 
-def run(text, bufs, hazards=True):
+def run(text, bufs, hazards=True, beta=1):
     mem = Memory(bufs)
     for launch in parse(text):
         kind, items = launch[0], launch[1]
@@ -378,6 +378,11 @@ def run(text, bufs, hazards=True):
                      for v in it["ins"]]
                 if it["kind"] == EW_ZERO:
                     y = [np.zeros((it["rows"], it["cols"]), dtype=mem.dtype)]
+                elif it["kind"] == EW_WINO_U_ACC:
+                    u = _recipe(EW_WINO_U, x[:7], it["mode"])
+                    y = [beta * c + v for c, v in zip(x[7:], u)]
+                elif it["kind"] == EW_AXPBY:
+                    y = [beta * x[1] + x[0]]
                 else:
                     y = _recipe(it["kind"], x, it["mode"])
                 results.append(list(zip(it["outs"], y)))
@@ -404,6 +409,8 @@ def run(text, bufs, hazards=True):
                 u3 = u2 + p[6]
                 u4 = u2 + p[4]
                 vals = [p[0] + p[1], u4 + p[2], u3 - p[3], u3 + p[4]]
+                if it["acc"]:
+                    vals = [beta * mem.read(c) + v for c, v in zip(it["c"], vals)]
                 results.append(list(zip(it["c"], vals)))
             else:
                 if it.get("spl"):
@@ -415,7 +422,12 @@ def run(text, bufs, hazards=True):
                 acc = a @ b
                 outs = []
                 for mode, sign, c, d in it["outs"]:
-                    val = sign * acc if mode == GM_STORE else mem.read(d) + sign * acc
+                    if mode == GM_STORE:
+                        val = sign * acc
+                    elif mode == GM_AXPBY:
+                        val = beta * mem.read(d) + sign * acc
+                    else:
+                        val = mem.read(d) + sign * acc
                     outs.append((c, val))
                 results.append(outs)
         for outs in results:

@@ -413,3 +413,64 @@ def test_leaf_u_integer_exact_and_strided(api, naive):
     got = Cbuf[:, :n].cpu().numpy()
     assert np.array_equal(got, naive.gemm(Ai.astype(np.float64), Bi.astype(np.float64)))
     assert torch.isnan(Cbuf[:, n:]).all()
+
+
+ACC_GPU = [("naive", "auto", 300, 200, 100, 0, "f32", {}), ("naive", "auto", 257, 129, 65, 0, "f64", {}),
+           ("winograd", "grouped", 1024, 768, 512, 2, "f32", {}),
+           ("winograd", "grouped", 1000, 777, 555, 1, "f32", {"leaf_u": True}),
+           ("winograd", "grouped", 512, 512, 512, 2, "f64", {}),
+           ("winograd", "two_temp", 512, 256, 384, 2, "f32", {}),
+           ("winograd", "in_place", 512, 256, 256, 1, "f32", {}),
+           ("strassen", "dfs3", 384, 320, 256, 2, "f64", {}),
+           ("winograd", "grouped", 1024, 1024, 1024, 2, "bf16x3", {}),
+           ("naive", "auto", 640, 384, 200, 0, "bf16x3", {"split_pass": True})]
+
+
+@pytest.mark.parametrize("algo,sched,m,n,k,levels,dt,opts", ACC_GPU)
+def test_accumulating_form(api, naive, algo, sched, m, n, k, levels, dt, opts):
+    # C <- A B + beta C against the oracle's A B plus beta C0 (float64); with
+    # beta = 0 a C full of NaN must not leak into the result
+    npdt = np.float64 if dt == "f64" else np.float32
+    A, B = inputs.pair("uniform", m, n, k, 36, npdt)
+    C0 = inputs.uniform((m, n), 37, dtype=npdt)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    AB = naive.gemm(A, B)
+    tol = 1e-12 if dt == "f64" else 1e-5
+    print(f"accumulate {algo} {sched} {m}x{n}x{k} L={levels} {dt} {opts}", flush=True)
+    for beta in (1.5, -1.0, 0.0):
+        C = torch.from_numpy(C0.copy()).cuda() if beta else torch.full((m, n), float("nan"), dtype=At.dtype,
+                                                                        device="cuda")
+        api.mm(At, Bt, algo=algo, sched=sched, cutoff=1, levels=levels, dtype=dt, out=C, beta=beta, **opts)
+        torch.cuda.synchronize()
+        want = AB + beta * C0.astype(np.float64)
+        assert rel_fro(C.cpu().numpy(), want) < tol, beta
+
+
+def test_accumulating_leaf_u_and_graph_bitwise(api):
+    # the fused last level applies beta exactly as the separate U pass does,
+    # and a graph captured per beta replays the eager result
+    m = n = k = 1024
+    A, B = inputs.pair("uniform", m, n, k, 38, np.float32)
+    C0 = torch.from_numpy(inputs.uniform((m, n), 39, dtype=np.float32)).cuda()
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    outs = []
+    for leaf_u in (False, True):
+        C = C0.clone()
+        api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=1, out=C, beta=0.75, leaf_u=leaf_u)
+        outs.append(C)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+    p = api.Plan("winograd", "grouped", m, n, k, cutoff=1, levels=2, graph=True, accumulate=True)
+    ws = torch.empty(p.ws_bytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()  # graphs are captured on non-default streams
+    for beta in (0.5, 2.0, 0.5):
+        eager = C0.clone()
+        api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=2, out=eager, beta=beta)
+        C = C0.clone()
+        torch.cuda.synchronize()
+        p(At, Bt, C, ws, stream=s, beta=beta)
+        s.synchronize()
+        assert torch.equal(C, eager), beta
+    with pytest.raises(ValueError):
+        api.Plan("naive", "auto", 8, 8, 8)(At[:8, :8].contiguous(), Bt[:8, :8].contiguous(),
+                                           torch.empty(8, 8, device="cuda"), beta=2.0)

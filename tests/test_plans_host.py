@@ -324,3 +324,30 @@ def test_split_bf16_plans_are_exact(lib, algo, m, n, k, levels):
     text, _ = L.describe(algo, "grouped" if levels else "auto", m, n, k, cutoff=1, levels=levels,
                          dtype="bf16x3")
     assert "SPLIT" not in text and " spl" not in text
+
+
+ACC_CASES = [("naive", "auto", 40, 24, 56, -1, {}), ("naive", "auto", 17, 9, 0, -1, {}),
+             ("winograd", "grouped", 64, 64, 64, 1, {}), ("winograd", "grouped", 96, 40, 56, 2, {}),
+             ("winograd", "grouped", 130, 70, 90, 2, {"leaf_u": True}),
+             ("winograd", "grouped", 64, 48, 32, 1, {"leaf_u": True}),
+             ("winograd", "grouped", 96, 64, 64, 2, {"overlap": True}),
+             ("winograd", "grouped", 64, 64, 64, 1, {"fuse": True}),
+             ("winograd", "two_temp", 64, 32, 48, 2, {}), ("winograd", "in_place", 64, 32, 32, 2, {}),
+             ("winograd", "two_temp", 50, 30, 40, 2, {}), ("strassen", "dfs3", 48, 40, 24, 2, {})]
+
+
+@pytest.mark.parametrize("algo,sched,m,n,k,levels,opts", ACC_CASES)
+@pytest.mark.parametrize("beta", [2, 0, -1])
+def test_accumulating_plans_are_exact(lib, algo, sched, m, n, k, levels, opts, beta):
+    # MM_PLAN_ACCUMULATE: C <- A B + beta C, exact on integers for every
+    # schedule; with beta = 0 the old C is never read
+    A = inputs.integers((m, k), 31, dtype=np.int64)
+    B = inputs.integers((k, n), 32, dtype=np.int64)
+    C0 = inputs.integers((m, n), 33, dtype=np.int64)
+    text, info = L.describe(algo, sched, m, n, k, cutoff=1, levels=levels, dtype="f32", accumulate=True,
+                            **opts)
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    C = C0.ravel().copy() if beta else np.full(m * n, 10**12, dtype=np.int64)
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws}, beta=beta)
+    want = A @ B + (beta * C0 if beta else 0)
+    assert np.array_equal(C.reshape(m, n), want)
