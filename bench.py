@@ -33,8 +33,9 @@ PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    # enough untimed steps for the GPU clocks to settle under MFMA load
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--levels", type=int, default=None, help="recursion levels (default: tuned)")
     ap.add_argument("--sched", default="grouped")

@@ -20,6 +20,7 @@ import json
 import math
 import os
 import threading
+import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE_DIR = os.path.join(HERE, "tuning")
@@ -128,7 +129,7 @@ def candidates(dtype, L_, tiles=None):
     return out
 
 
-def tune(m, n, k, dtype="f32", max_levels=3, reps=7, warmup=2, tiles=None, save=True, verbose=False):
+def tune(m, n, k, dtype="f32", max_levels=3, reps=5, warmup=2, tiles=None, save=True, verbose=False, rounds=3):
     """Measure the candidates for this size class and cache the fastest."""
     import numpy as np
     import torch
@@ -140,24 +141,40 @@ def tune(m, n, k, dtype="f32", max_levels=3, reps=7, warmup=2, tiles=None, save=
     A = torch.from_numpy(A_np).cuda()
     B = torch.from_numpy(B_np).cuda()
     C = torch.empty((m, n), dtype=tdt, device="cuda")
-    results = []
+    # every candidate is timed in several interleaved rounds (after the GPU
+    # has run for a while), so clock drift does not favour whichever
+    # candidate happens to run first; the median of the rounds decides
+    cands = []
     for L_ in range(0, max_levels + 1):
         if L_ > 0 and min(m, n, k) >> L_ < 64:
             break
         for tile, ov, lu in candidates(dtype, L_, tiles):
+            algo = "naive" if L_ == 0 else "winograd"
             try:
-                algo = "naive" if L_ == 0 else "winograd"
                 p = api.Plan(algo, "grouped" if L_ else "auto", m, n, k, cutoff=1, levels=L_,
                              dtype=dtype, tile=tile, overlap=ov, leaf_u=lu)
-                t = _time_plan(p, A, B, C, reps, warmup)
             except Exception as e:  # an unsupported candidate is skipped
                 if verbose:
                     print(f"  skip L={L_} tile={tile} overlap={ov} leaf_u={lu}: {e}")
                 continue
-            results.append((t, L_, tile, ov, lu))
-            if verbose:
-                print(f"  {dtype} {m}x{n}x{k} L={L_} tile={tile} overlap={int(ov)} leaf_u={int(lu)}: "
-                      f"{t:.3f} ms {2.0 * m * n * k / t / 1e9:.1f} TFLOP/s", flush=True)
+            cands.append(((L_, tile, ov, lu), p))
+    if not cands:
+        raise RuntimeError("no tuning candidate")
+    warm_until = time.perf_counter() + 0.1
+    while time.perf_counter() < warm_until:
+        _time_plan(cands[0][1], A, B, C, 1, 1)
+    times = {key: [] for key, _ in cands}
+    for _ in range(rounds):
+        for key, p in cands:
+            times[key].append(_time_plan(p, A, B, C, reps, warmup))
+    results = []
+    for key, ts in times.items():
+        t = sorted(ts)[len(ts) // 2]
+        results.append((t,) + key)
+        if verbose:
+            L_, tile, ov, lu = key
+            print(f"  {dtype} {m}x{n}x{k} L={L_} tile={tile} overlap={int(ov)} leaf_u={int(lu)}: "
+                  f"{t:.3f} ms {2.0 * m * n * k / t / 1e9:.1f} TFLOP/s", flush=True)
     t, L_, tile, ov, lu = min(results, key=lambda r: r[0])
     leaf = min(m, n, k) >> L_
     # the cutoff that stops the recursion after L_ halvings: the leaf order
