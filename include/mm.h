@@ -182,9 +182,10 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                                  workspace block of m x n (they use C as scratch) and add it
                                  in one more element-wise pass.  Not for batched plans. */
 /* Force the MFMA GEMM tile configuration c (0 .. 7) for every leaf launch
- * instead of the planner's choice.  float32: 0 128x128 (BK 32), 1 256x128,
- * 2 128x256, 3 256x256 (BK 16), 4 64x128, 5 128x64, 6 256x128 (BK 16),
- * 7 128x128 (BK 16); float64: 0 128x128,
+ * instead of the planner's choice.  float32: 0 128x128 (BK 32, 8 waves),
+ * 1 256x128 (8 waves), 2 128x256 (8 waves), 3 256x256 (BK 32, 8 waves),
+ * 4 64x128, 5 128x64, 6 256x128 (BK 16, 4 waves), 7 128x128 (BK 16,
+ * 4 waves); float64: 0 128x128,
  * 5 128x64 (others fall back to 0).  With MM_PLAN_LEAF_U in effect c picks
  * the fused leaf-level kernel's tile instead: 0 128x128 (4 waves), 1 128x128
  * (8 waves), 2 64x128 (4 waves). */

@@ -91,12 +91,15 @@ hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc
   switch (cfg) {
     case 1: return launch_cfg<float, 256, 128, 8, 4, 2>(kb, d, n, tiles, remap, s);
     case 2: return launch_cfg<float, 128, 256, 8, 2, 4>(kb, d, n, tiles, remap, s);
-    case 3: return launch_cfg<float, 256, 256, 4, 2, 2>(kb, d, n, tiles, remap, s);
+    // 256x256 with eight waves (two per SIMD, each 64x128): while one wave
+    // of a SIMD waits for memory the other keeps the matrix core busy
+    case 3: return launch_cfg<float, 256, 256, 8, 4, 2>(kb, d, n, tiles, remap, s);
     case 4: return launch_cfg<float, 64, 128, 8, 2, 2>(kb, d, n, tiles, remap, s);
     case 5: return launch_cfg<float, 128, 64, 8, 2, 2>(kb, d, n, tiles, remap, s);
     case 6: return launch_cfg<float, 256, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
     case 7: return launch_cfg<float, 128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
-    default: return launch_cfg<float, 128, 128, 8, 2, 2>(kb, d, n, tiles, remap, s);
+
+    default: return launch_cfg<float, 128, 128, 8, 4, 2>(kb, d, n, tiles, remap, s);
   }
 }
 

@@ -135,7 +135,7 @@ int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
     // Unequal problems: minimise the padded work (tile area x k) over the
     // measured per-tile MFMA efficiency of each shape.
     const int cand[4] = {0, 3, 4, 5};
-    const double eff[4] = {0.79, 0.84, 0.75, 0.72};
+    const double eff[4] = {0.81, 0.87, 0.75, 0.72};
     int best = 0;
     double best_cost = 1e300;
     for (int i = 0; i < 4; ++i) {
@@ -167,8 +167,9 @@ int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
     t256 += ceil_div(g.m, 256) * ceil_div(g.n, 256);
     t128 += ceil_div(g.m, 128) * ceil_div(g.n, 128);
   }
+  // whole rounds of 256 workgroups (one per CU) suit the eight-wave tiles
   if (t256 >= 1024 || (t256 >= 256 && t256 % 256 == 0)) return 3;
-  if (t128 >= 2048) return 0;
+  if (t128 >= 2048 || (t128 >= 256 && t128 % 256 == 0)) return 0;
   return 4;
 }
 
