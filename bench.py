@@ -125,8 +125,9 @@ def tuned_leaf(tuner, n, levels):
     float32 product at this level count (planner defaults when the cache
     holds another level count for the size class)."""
     ch = tuner.choose(n, n, n, "f32")
-    if ch["source"] == "tuned" and ch["levels"] == levels:
-        return ch["tile"], bool(ch.get("overlap", False)), bool(ch.get("leaf_u", False))
+    for c in (ch, ch.get("best_recursive") or {}):
+        if ch["source"] == "tuned" and c.get("levels") == levels:
+            return c["tile"], bool(c.get("overlap", False)), bool(c.get("leaf_u", False))
     return None, False, False
 
 
@@ -365,8 +366,11 @@ def main():
     # level choice: the tuner's cached choice for this size class; without one
     # time L = 1..3 briefly and keep the fastest
     ch = tuner.choose(n, n, n, "f32")
+    rec = ch.get("best_recursive") if ch["source"] == "tuned" else None
     if args.levels is None and ch["source"] == "tuned" and ch["levels"] > 0:
         levels = ch["levels"]
+    elif args.levels is None and rec:
+        levels = rec["levels"]  # the plain product won the size class; time the best recursion
     elif args.levels is None:
         best = None
         for lv in (1, 2, 3):

@@ -181,6 +181,14 @@ def tune(m, n, k, dtype="f32", max_levels=3, reps=5, warmup=2, tiles=None, save=
     entry = {"levels": L_, "tile": tile, "overlap": ov, "leaf_u": lu, "cutoff": leaf if L_ else min(m, n, k),
              "ms": round(t, 4), "tflops": round(2.0 * m * n * k / t / 1e9, 2),
              "shape": [m, n, k]}
+    # the fastest recursive candidate too (for callers that ask for a
+    # recursion, and to report how close the recursion comes to the plain
+    # product when it does not win)
+    rec = [r for r in results if r[1] > 0]
+    if rec:
+        t2, L2, tile2, ov2, lu2 = min(rec, key=lambda r: r[0])
+        entry["best_recursive"] = {"levels": L2, "tile": tile2, "overlap": ov2, "leaf_u": lu2,
+                                   "ms": round(t2, 4), "tflops": round(2.0 * m * n * k / t2 / 1e9, 2)}
     arch = _arch()
     load_cache(arch)[class_key(dtype, m, n, k)] = entry
     if save:
