@@ -131,6 +131,16 @@ def tuned_leaf(tuner, n, levels):
     return None, False, False
 
 
+def tuned_plain_tile(tuner, n, dtype="f32"):
+    """The autotuner's fastest tile for the plain n x n x n product."""
+    ch = tuner.choose(n, n, n, dtype)
+    if ch["source"] != "tuned":
+        return None
+    if ch.get("best_plain"):
+        return ch["best_plain"]["tile"]
+    return ch["tile"] if ch["levels"] == 0 else None
+
+
 def pct(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs), q))
@@ -213,7 +223,7 @@ def rel_err(C, rows, ref):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
-def bench_precision(torch, api, L, inputs, tuner, n=8192, steps=5, warmup=2, rows=48):
+def bench_precision(torch, api, L, inputs, tuner, n=8192, steps=10, warmup=10, rows=48):
     """n = 8192, A and B Gaussian with rows scaled by 10^u, u ~ U[-3, 3]:
     split-bfloat16 refined leaves under two Winograd levels (and plain), the
     float32 Winograd and plain products beside them, each with its relative
@@ -232,7 +242,11 @@ def bench_precision(torch, api, L, inputs, tuner, n=8192, steps=5, warmup=2, row
                                ("f32_winograd_L2", "winograd", 2, "f32"),
                                ("f32_plain", "naive", 0, "f32")):
         ch = tuner.choose(n, n, n, dt)
-        tile = ch["tile"] if ch["source"] == "tuned" and ch["levels"] == lv else None
+        tile = None
+        for c in (ch, ch.get("best_recursive") or {}, ch.get("best_plain") or {}):
+            if ch["source"] == "tuned" and c.get("levels") == lv:
+                tile = c["tile"]
+                break
         r = run_product(torch, api, L, algo, "grouped" if lv else "auto", n, lv, A, B, steps, warmup,
                         dtype=dt, tile=tile)
         out[name] = {"tflops": round(r["tflops"], 3), "p50_ms": round(r["p50"], 4),
@@ -391,10 +405,7 @@ def main():
                           "tflops": round(win["tflops"], 3),
                           "roofline": gemm_roofline(win, n)}), flush=True)
         return
-    pch = tuner.load_cache().get(tuner.class_key("f32", n, n, n), {})
-    plain_tile = None
-    if pch.get("levels") == 0:
-        plain_tile = pch.get("tile")
+    plain_tile = tuned_plain_tile(tuner, n)
     plain = run_product(torch, api, L, "naive", "auto", n, 0, A, B, args.steps, args.warmup,
                         tile=plain_tile)
     print(f"# plain mfma gemm: {plain['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
@@ -450,11 +461,12 @@ def main():
         for n2, lvls in ((3000, (1, 2)), (8192, (1, 2))):
             A2_np, B2_np = inputs.pair("uniform", n2, n2, n2, 1, np.float32)
             A2, B2 = torch.from_numpy(A2_np).cuda(), torch.from_numpy(B2_np).cuda()
-            p2 = run_product(torch, api, L, "naive", "auto", n2, 0, A2, B2, 5, 2)
+            p2 = run_product(torch, api, L, "naive", "auto", n2, 0, A2, B2, 20, 10,
+                             tile=tuned_plain_tile(tuner, n2))
             e = {"plain_tflops": round(p2["tflops"], 3)}
             for lv in lvls:
                 t2, o2, u2 = tuned_leaf(tuner, n2, lv)
-                w2 = run_product(torch, api, L, "winograd", args.sched, n2, lv, A2, B2, 5, 2, tile=t2,
+                w2 = run_product(torch, api, L, "winograd", args.sched, n2, lv, A2, B2, 20, 10, tile=t2,
                                  overlap=o2, leaf_u=u2)
                 e[f"winograd_L{lv}_tflops"] = round(w2["tflops"], 3)
                 e[f"winograd_L{lv}_p99_ms"] = round(w2["p99"], 4)

@@ -184,6 +184,11 @@ def tune(m, n, k, dtype="f32", max_levels=3, reps=5, warmup=2, tiles=None, save=
     # the fastest recursive candidate too (for callers that ask for a
     # recursion, and to report how close the recursion comes to the plain
     # product when it does not win)
+    plain = [r for r in results if r[1] == 0]
+    if plain:
+        t0, _, tile0, _, _ = min(plain, key=lambda r: r[0])
+        entry["best_plain"] = {"levels": 0, "tile": tile0, "ms": round(t0, 4),
+                               "tflops": round(2.0 * m * n * k / t0 / 1e9, 2)}
     rec = [r for r in results if r[1] > 0]
     if rec:
         t2, L2, tile2, ov2, lu2 = min(rec, key=lambda r: r[0])
