@@ -103,7 +103,8 @@ def plan_launches(plan, esz):
         if line in ("FORK", "JOIN"):
             out.append(dict(kind=line, stream=0, flops=0.0, bytes=0.0))
         elif w[0] == "LAUNCH":
-            out.append(dict(kind=w[1], stream=1 if w[-1] == "aux" else 0, flops=flops, bytes=nbytes))
+            out.append(dict(kind=w[1], stream=1 if w[-1] == "aux" else 0, flops=flops, bytes=nbytes,
+                            grid=int(w[3]) if len(w) > 3 else 0))
             flops, nbytes = 0.0, 0.0
         elif w[0] == "GEMM":
             m, n, k = map(int, w[1:4])
@@ -157,23 +158,57 @@ def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtyp
                 per_op=per_op, kinds=kinds, tflops=2.0 * n ** 3 / (wall * 1e-3) / 1e12)
 
 
+def source_digest():
+    """SHA-256 over the library sources (csrc/ and include/), to tell
+    whether stored counter results were taken with the kernels built now."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for d in ("paper_2309_00628_amd/csrc", "include"):
+        for name in sorted(os.listdir(os.path.join(root, d))):
+            if name.endswith((".hip", ".h", ".cpp")):
+                h.update(name.encode())
+                with open(os.path.join(root, d, name), "rb") as f:
+                    h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, grid):
+    """HBM bytes per launch of (kernel, grid) from the rocprofv3 counter
+    summary in profiles/hbm_traffic.json, or None when there is none or it
+    was taken with other kernel sources."""
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic.json")
+    try:
+        with open(p) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if data.get("source_sha256") != source_digest():
+        return None
+    for e in data.get("launches", []):
+        if kernel in e["kernel"] and e["grid"] == grid:
+            return e["bytes_per_launch"]
+    return None
+
+
 def gemm_roofline(res, n):
     """Roofline of the dominant kernel: the leaf-product launch (plain GEMM
     group or fused last Winograd level) with the most flops, on the caller's
     stream (not sharing the GPU with an overlapped S/T pass)."""
     launches = plan_launches(res["plan"], 4)
-    best, kind = None, 1
+    best, kind, grid = None, 1, None
     for lau, d, k in zip(launches, res["per_op"], res["kinds"]):
         if k in (1, 4) and (best is None or lau["flops"] > best[0]):
-            kind = k
+            kind, grid = k, lau["grid"]
             best = (lau["flops"], sum(d) / len(d))
     flops, avg_ms = best if best else (0.0, float("nan"))
     achieved = flops / (avg_ms * 1e-3) / 1e12
+    kname = "gemm_wino_kernel" if kind == 4 else "gemm_kernel<float"
     return dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=None,
+                frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=measured_traffic(kname, grid),
                 kernel=("gemm_wino_kernel (last level: products + U in registers)" if kind == 4
                         else "gemm_kernel<float> (grouped leaf products)"),
-                flops_per_launch=flops, avg_launch_ms=round(avg_ms, 4))
+                flops_per_launch=flops, avg_launch_ms=round(avg_ms, 4), grid=grid)
 
 
 def ew_bandwidth(res, n):
