@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the timed Winograd steps (for rocprofv3 runs)")
+    ap.add_argument("--profile-set", choices=("gemm", "bf16x3"), default=None,
+                    help="for rocprofv3 runs at --n: 'gemm' = the plain float32 product, the fastest "
+                         "Winograd plan and torch.matmul (hipBLASLt); 'bf16x3' = the refined "
+                         "split-bfloat16 Winograd L=2 and plain products on row-scaled Gaussians")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB float32 buffer 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -258,6 +262,43 @@ def rel_err(C, rows, ref):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
+def profile_set(torch, api, L, inputs, tuner, args):
+    """Short runs of a fixed set of products for rocprofv3 (--profile-set)."""
+    import numpy as np
+    n = args.n
+    out = {"profile_set": args.profile_set, "n": n}
+    if args.profile_set == "gemm":
+        A, B = [torch.from_numpy(x).cuda() for x in inputs.pair("uniform", n, n, n, 0, np.float32)]
+        p = run_product(torch, api, L, "naive", "auto", n, 0, A, B, args.steps, args.warmup,
+                        tile=tuned_plain_tile(tuner, n))
+        out["plain_tflops"] = round(p["tflops"], 2)
+        ch = tuner.choose(n, n, n, "f32")
+        rec = ch.get("best_recursive") if ch["source"] == "tuned" else None
+        lv = ch["levels"] if ch["levels"] > 0 else (rec["levels"] if rec else 1)
+        t, o, u = tuned_leaf(tuner, n, lv)
+        w = run_product(torch, api, L, "winograd", "grouped", n, lv, A, B, args.steps, args.warmup, tile=t,
+                        overlap=o, leaf_u=u)
+        out["winograd"] = {"levels": lv, "tflops": round(w["tflops"], 2)}
+        torch.backends.cuda.matmul.allow_tf32 = False
+        C = torch.empty((n, n), device="cuda")
+        for _ in range(args.warmup):
+            torch.matmul(A, B, out=C)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            torch.matmul(A, B, out=C)
+        torch.cuda.synchronize()
+        out["hipblaslt_tflops"] = round(2.0 * n ** 3 * args.steps / (time.perf_counter() - t0) / 1e12, 2)
+    else:
+        A = torch.from_numpy(inputs.gauss_rowscaled((n, n), 20)).cuda()
+        B = torch.from_numpy(inputs.gauss_rowscaled((n, n), 21)).cuda()
+        for name, algo, lv in (("winograd_L2", "winograd", 2), ("plain", "naive", 0)):
+            r = run_product(torch, api, L, algo, "grouped" if lv else "auto", n, lv, A, B, args.steps,
+                            args.warmup, dtype="bf16x3")
+            out[name] = round(r["tflops"], 2)
+    print(json.dumps(out), flush=True)
+
+
 def bench_precision(torch, api, L, inputs, tuner, n=8192, steps=10, warmup=10, rows=48):
     """n = 8192, A and B Gaussian with rows scaled by 10^u, u ~ U[-3, 3]:
     split-bfloat16 refined leaves under two Winograd levels (and plain), the
@@ -405,6 +446,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": src.numel() * 4}), flush=True)
+        return
+    if args.profile_set:
+        profile_set(torch, api, L, inputs, tuner, args)
         return
     n = args.n
     A_np, B_np = inputs.pair("uniform", n, n, n, 0, np.float32)
