@@ -502,6 +502,7 @@ GemmCfg gemm_bf16s_cfg(int cfg) {
     case 3: return {256, 256};
     case 4: return {64, 128};
     case 5: return {256, 128};
+    case 6: return {256, 256};
     default: return {128, 128};
   }
 }
@@ -509,6 +510,7 @@ GemmCfg gemm_bf16s_cfg(int cfg) {
 GemmCfg gemm_bf16x3_cfg(int cfg) {
   switch (cfg) {
     case 1: return {256, 128};
+    case 3: return {256, 256};
     case 4: return {64, 128};
     default: return {128, 128};
   }
@@ -522,6 +524,7 @@ hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d,
     // this stage's MFMAs (measured 2-3% faster at n = 8192); the four-wave
     // tiles write it halfway
     case 1: return launch_cfg<256, 128, 4, 4, 2, true>(kb, d, n, tiles, remap, s);
+    case 3: return launch_cfg<256, 256, 2, 4, 2, true>(kb, d, n, tiles, remap, s);
     case 4: return launch_cfg<64, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
     default: return launch_cfg<128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
   }
@@ -535,6 +538,7 @@ hipError_t launch_gemm_bf16s(int cfg, const KernelBases& kb, const GemmDesc* d, 
     case 3: return launch_spl<256, 256, 2, 2, 2>(kb, d, n, tiles, remap, s);
     case 4: return launch_spl<64, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
     case 5: return launch_spl<256, 128, 2, 2, 2>(kb, d, n, tiles, remap, s);
+    case 6: return launch_spl<256, 256, 2, 4, 2>(kb, d, n, tiles, remap, s);
     default: return launch_spl<128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
   }
 }

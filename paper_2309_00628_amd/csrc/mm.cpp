@@ -152,13 +152,16 @@ int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
     return best;
   }
   if (kdtype == DT_BF16X3 || kdtype == DT_BF16X3_SPL) {
-    // 256x128 tiles with eight waves (two per SIMD) hide the split's VALU
-    // work behind the MFMAs; smaller launches keep more CUs busy with 64x128.
-    int64_t t256 = 0, t128 = 0;
+    // eight-wave tiles (two waves per SIMD) hide the split's vector work
+    // behind the MFMAs, and the 256x256 tile splits each element for half as
+    // many tiles as 256x128; smaller launches keep more CUs busy with 64x128.
+    int64_t t2x2 = 0, t256 = 0, t128 = 0;
     for (const GemmDesc& g : group) {
+      t2x2 += ceil_div(g.m, 256) * ceil_div(g.n, 256);
       t256 += ceil_div(g.m, 256) * ceil_div(g.n, 128);
       t128 += ceil_div(g.m, 128) * ceil_div(g.n, 128);
     }
+    if (kdtype == DT_BF16X3 && t2x2 >= 512) return 3;
     if (t256 >= 256) return 1;
     return t128 >= 256 ? 0 : 4;
   }
