@@ -547,6 +547,44 @@ struct Builder {
     // the fused kernel has 256x256, 128x128 and 64x128 tiles; its 128x128
     // tile runs one wave per SIMD, so 64x128 is the default below 256x256
     if (fused && cfg != 3 && (cfg != 0 || P.tile_cfg < 0)) cfg = 4;
+    if (P.tile_cfg < 0 && equal && !fused && kd == DT_F32 && (cfg == 0 || cfg == 3)) {
+      const int p3 = split_for_rounds(group);
+      if (p3 > 0 && p3 < (int)group.size()) {
+        std::vector<GemmDesc> big(group.begin(), group.begin() + p3), small(group.begin() + p3, group.end());
+        emit_gemm_cfg(big, false, 3, true);
+        emit_gemm_cfg(small, false, 0, true);
+        return;
+      }
+    }
+    emit_gemm_cfg(group, fused, cfg, equal);
+  }
+
+  // Equal float32 problems on the eight-wave tiles (one workgroup per CU):
+  // how many of them to give 256x256 tiles, the rest 128x128, so that both
+  // launches fill whole rounds of 256 workgroups.  Time model per problem
+  // class: rounds x tile work / measured tile efficiency (0.87 for 256x256,
+  // 0.84 for 128x128).  Returns the count, or -1 when one tile shape for
+  // all is as good.
+  static int split_for_rounds(const std::vector<GemmDesc>& group) {
+    const int64_t P = (int64_t)group.size();
+    const int64_t m = group[0].m, n = group[0].n;
+    const int64_t T3 = ceil_div(m, 256) * ceil_div(n, 256), T0 = ceil_div(m, 128) * ceil_div(n, 128);
+    const double t3 = 256.0 * 256.0 / 0.87, t0 = 128.0 * 128.0 / 0.84;
+    auto cost = [&](int64_t p) {
+      return (double)ceil_div(p * T3, 256) * t3 + (double)ceil_div((P - p) * T0, 256) * t0;
+    };
+    int64_t best = -1;
+    double best_cost = 0.99 * std::min(cost(0), cost(P));
+    for (int64_t p = 1; p < P; ++p)
+      if (cost(p) < best_cost) {
+        best_cost = cost(p);
+        best = p;
+      }
+    return (int)best;
+  }
+
+  void emit_gemm_cfg(std::vector<GemmDesc>& group, bool fused, int cfg, bool equal) {
+    const int kd = gm_spl ? DT_BF16X3_SPL : kernel_dtype(P.dtype);
     const GemmCfg gc = gemm_cfg(kd, cfg);
     int grid = 0;
     for (GemmDesc& g : group) {
