@@ -110,18 +110,37 @@ def test_in_place_needs_no_workspace(lib):
 
 
 def test_grouped_launch_count_and_leaves(lib):
+    def count(text, what):
+        return sum(l.startswith("LAUNCH " + what) for l in text.splitlines())
     for L_ in (1, 2, 3):
-        _, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_)
+        text, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_)
         assert info["levels"] == L_
-        assert info["launches"] == 2 * L_ + 1
+        # L S/T passes, the leaf products (one launch, or two that each fill
+        # whole rounds of workgroups), L U passes
+        g = count(text, "GEMM")
+        assert count(text, "EW") == 2 * L_ and g in (1, 2)
+        assert info["launches"] == 2 * L_ + g
         assert info["leaves"] == 7 ** L_ and info["fused"] == 0
         # with MM_PLAN_OVERLAP: fork, L S/T passes (auxiliary stream), the
         # products of blocks of A and B, join, the other products, L U passes
-        _, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_, overlap=True)
-        assert info["launches"] == 2 * L_ + 4
+        text, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_, overlap=True)
+        g = count(text, "GEMM")
+        assert "FORK" in text and "JOIN" in text and g >= 2
+        assert info["launches"] == 2 * L_ + g + 2
         # with MM_PLAN_FUSE the last level's S/T pass is formed in the leaf loader
-        _, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_, fuse=True)
-        assert info["launches"] == 2 * L_ and info["fused"] == 1
+        text, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_, fuse=True)
+        assert count(text, "EW") == 2 * L_ - 1 and info["fused"] == 1
+
+
+def test_leaf_launches_fill_whole_rounds(lib):
+    # seven 2048^3 leaves: four on 256x256 tiles (256 workgroups, one round)
+    # and three on 128x128 tiles (768 workgroups, three rounds)
+    text, _ = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=1)
+    gl = [l.split() for l in text.splitlines() if l.startswith("LAUNCH GEMM")]
+    assert [(int(w[2]), int(w[3]), int(w[4])) for w in gl] == [(4, 256, 3), (3, 768, 0)]
+    # a forced tile keeps one launch
+    text, _ = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=1, tile=0)
+    assert sum(l.startswith("LAUNCH GEMM") for l in text.splitlines()) == 1
 
 
 def test_grouped_overlap_window(lib):
