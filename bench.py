@@ -488,6 +488,11 @@ def main():
     plain = run_product(torch, api, L, "naive", "auto", n, 0, A, B, args.steps, args.warmup,
                         tile=plain_tile)
     print(f"# plain mfma gemm: {plain['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    # Strassen (Section 2.2) breadth first at the same levels and leaf tile
+    # (a tile of the fused leaf-level kernel names another kernel: then the default)
+    strs = run_product(torch, api, L, "strassen", "grouped", n, levels, A, B, 20, 10,
+                       tile=None if leaf_u else tile)
+    print(f"# strassen L={levels}: {strs['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
 
     # vendor GEMM (hipBLASLt through torch.matmul) as context only
     torch.backends.cuda.matmul.allow_tf32 = False
@@ -522,6 +527,8 @@ def main():
         "plain_gemm": {"tflops": round(plain["tflops"], 3), "p50_ms": round(plain["p50"], 4),
                        "p99_ms": round(plain["p99"], 4)},
         "speedup_vs_plain": round(win["tflops"] / plain["tflops"], 4),
+        "strassen_grouped": {"levels": levels, "tflops": round(strs["tflops"], 3),
+                             "p50_ms": round(strs["p50"], 4), "p99_ms": round(strs["p99"], 4)},
         "vendor_hipblaslt_tflops": round(vendor_tflops, 3),
         "roofline": gemm_roofline(win, n),
         "plain_gemm_roofline": gemm_roofline(plain, n),
@@ -533,6 +540,7 @@ def main():
         out["cpu_baseline"] = cb
         out["rel_err"] = rel_err(win["C"], rows, ref)
         out["plain_rel_err"] = rel_err(plain["C"], rows, ref)
+        out["strassen_grouped"]["rel_err"] = rel_err(strs["C"], rows, ref)
         out["rel_err_note"] = "relative Frobenius error vs the float64 oracle on the sampled rows"
 
     if not args.no_extra:
@@ -549,6 +557,9 @@ def main():
                                  overlap=o2, leaf_u=u2)
                 e[f"winograd_L{lv}_tflops"] = round(w2["tflops"], 3)
                 e[f"winograd_L{lv}_p99_ms"] = round(w2["p99"], 4)
+                s2 = run_product(torch, api, L, "strassen", "grouped", n2, lv, A2, B2, 20, 10,
+                                 tile=None if u2 else t2)
+                e[f"strassen_L{lv}_tflops"] = round(s2["tflops"], 3)
             extra[str(n2)] = e
             print(f"# extra n={n2}: {e}", file=sys.stderr, flush=True)
             del A2, B2

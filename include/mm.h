@@ -77,12 +77,15 @@ typedef enum { MM_ALGO_NAIVE = 0, MM_ALGO_STRASSEN = 1, MM_ALGO_WINOGRAD = 2 } m
  *                     launch forms all S and T blocks, the 7^L leaf products
  *                     run as one grouped MFMA launch, and one fused launch per
  *                     level forms the U blocks.  More workspace, far fewer
- *                     launches, leaves fill the GPU.  Winograd only.
+ *                     launches, leaves fill the GPU.  Winograd and Strassen
+ *                     (for Strassen: five A sums and five B sums per block,
+ *                     and the C quadrants combined in the order of DFS3, so
+ *                     the two Strassen schedules give the same bits).
  *  MM_SCHED_DFS3      Strassen, depth-first with three temporaries (the paper
  *                     gives no reduced-memory schedule for Strassen): X and Y
  *                     hold the operand sums, Z the product of a non-leaf level;
  *                     leaf products add themselves into their C quadrants.
- *  MM_SCHED_AUTO      GROUPED for Winograd, DFS3 for Strassen.
+ *  MM_SCHED_AUTO      GROUPED.
  * For MM_ALGO_NAIVE the schedule is ignored. */
 typedef enum {
   MM_SCHED_TWO_TEMP = 0,
@@ -113,7 +116,7 @@ int mm_naive(int64_t m, int64_t n, int64_t k, const void* A, const void* B, void
              hipStream_t stream);
 
 /* Strassen (Section 2.2, Algorithm 2 with the cutoff of Section 3.4),
- * schedule MM_SCHED_DFS3.  Uses the workspace registered for `stream` with
+ * schedule MM_SCHED_AUTO.  Uses the workspace registered for `stream` with
  * mm_set_workspace, else a workspace the library allocates once per
  * (device, stream) and keeps (first call only; later calls allocate nothing
  * unless a larger size is needed). */
@@ -166,7 +169,7 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                             disappears.  Sums are rounded in the same order as the separate
                             U pass: results are bitwise the same.  Ignored for other dtypes
                             and schedules; excludes MM_PLAN_FUSE. */
-#define MM_PLAN_SPLIT_PASS 16u /* MM_BF16X3_REFINED, grouped schedule or plain product: split
+#define MM_PLAN_SPLIT_PASS 16u /* MM_BF16X3_REFINED, grouped Winograd or plain product: split
                                  each float32 operand into its bfloat16 parts once, in a split
                                  pass (which also forms the last level's S/T sums), and run
                                  the leaves on the stored parts, instead of splitting every

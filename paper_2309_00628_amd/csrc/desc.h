@@ -52,6 +52,12 @@ enum EwKind : int32_t {
   // read):
   EW_WINO_U_ACC = 15,  // i = P1..P7 C11 C12 C21 C22 ; o = C11..C22 = beta Cij + (U1 U5 U6 U7)
   EW_AXPBY = 16,       // i = X C ; o0 = beta C + X
+  // Strassen (Section 2.2), grouped schedule:
+  EW_STR_S = 17,      // i = A11 A12 A21 A22 ; o = A11+A22, A21+A22, A11+A12, A21-A11, A12-A22
+  EW_STR_T = 18,      // i = B11 B12 B21 B22 ; o = B11+B22, B12-B22, B21-B11, B11+B12, B21+B22
+  EW_STR_U = 19,      // i = P1..P7 ; o = C11 = ((P1+P4)-P5)+P7, C12 = P3+P5, C21 = P2+P4,
+                      //              C22 = ((P1+P3)-P2)+P6
+  EW_STR_U_ACC = 20,  // i = P1..P7 C11 C12 C21 C22 ; o = fma(beta, Cij, EW_STR_U's Cij)
 };
 
 constexpr int kEwMaxIn = 11;

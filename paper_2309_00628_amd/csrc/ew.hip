@@ -18,7 +18,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kItems = 2;  // chunks per thread
-constexpr int kOut = 4;    // outputs of the element-wise recipes of this kernel
+constexpr int kOut = 5;    // outputs of the element-wise recipes of this kernel
 static_assert(kOut <= kEwMaxOut, "outputs");
 
 template <typename T>
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void ew_kernel(KernelBases kb, const EwPa
   const int kind = P.kind, nout = P.nout;
   // with beta == 0 the old C (the trailing inputs of the accumulating
   // recipes) is not read
-  const bool drop_c = kb.beta == 0.0 && (kind == EW_WINO_U_ACC || kind == EW_AXPBY);
+  const bool drop_c = kb.beta == 0.0 && (kind == EW_WINO_U_ACC || kind == EW_STR_U_ACC || kind == EW_AXPBY);
   const int nin = drop_c ? (kind == EW_AXPBY ? 1 : 7) : P.nin;
   const T beta = drop_c ? T(0) : T(kb.beta);
   bool vec = true;
@@ -194,6 +194,38 @@ __global__ __launch_bounds__(kThreads) void ew_kernel(KernelBases kb, const EwPa
           break;
         }
         case EW_AXPBY: y[0][e] = fma(beta, x[1][e], x[0][e]); break;  // x = X C
+        case EW_STR_S: {  // x = A11 A12 A21 A22
+          y[0][e] = x[0][e] + x[3][e];
+          y[1][e] = x[2][e] + x[3][e];
+          y[2][e] = x[0][e] + x[1][e];
+          y[3][e] = x[2][e] - x[0][e];
+          y[4][e] = x[1][e] - x[3][e];
+          break;
+        }
+        case EW_STR_T: {  // x = B11 B12 B21 B22
+          y[0][e] = x[0][e] + x[3][e];
+          y[1][e] = x[1][e] - x[3][e];
+          y[2][e] = x[2][e] - x[0][e];
+          y[3][e] = x[0][e] + x[1][e];
+          y[4][e] = x[2][e] + x[3][e];
+          break;
+        }
+        case EW_STR_U:
+        case EW_STR_U_ACC: {  // x = P1..P7 (C11 C12 C21 C22)
+          const T c11 = ((x[0][e] + x[3][e]) - x[4][e]) + x[6][e];
+          const T c12 = x[2][e] + x[4][e];
+          const T c21 = x[1][e] + x[3][e];
+          const T c22 = ((x[0][e] + x[2][e]) - x[1][e]) + x[5][e];
+          if (kind == EW_STR_U) {
+            y[0][e] = c11; y[1][e] = c12; y[2][e] = c21; y[3][e] = c22;
+          } else {
+            y[0][e] = fma(beta, x[7][e], c11);
+            y[1][e] = fma(beta, x[8][e], c12);
+            y[2][e] = fma(beta, x[9][e], c21);
+            y[3][e] = fma(beta, x[10][e], c22);
+          }
+          break;
+        }
         case EW_DIST: {  // x = Z D0 D1
           for (int o = 0; o < 2; ++o) {
             const int md = P.mode[o];

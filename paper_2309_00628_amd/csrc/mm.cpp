@@ -850,8 +850,17 @@ bool can_fuse(const Builder& b, const Sub& s) {
   return true;
 }
 
+// With Strassen's algorithm (Section 2.2) the same level-by-level form
+// applies: one launch per level forms the five A sums and five B sums of
+// every block, the 7^L leaf products run as one grouped launch, and one launch
+// per level forms the four C quadrants from P1..P7.  The sums and the order in
+// which the products are combined are those of the depth-first Strassen
+// schedule, so the two give the same bits.  The options that are particular
+// to Winograd's operands (fused loader, leaf-side U, split pass, overlap of
+// plain-operand products) do not apply and are ignored.
 void sched_grouped(Builder& b, std::vector<Sub> subs) {
   const int L = b.P.L;
+  const bool strassen = b.P.algo == MM_ALGO_STRASSEN;
   std::vector<std::vector<EwPart>> u_levels;  // recorded, emitted in reverse
   struct WinoSub {
     MView a[7], b[7], c[4];
@@ -862,8 +871,8 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
   // The S/T passes run on the auxiliary stream while the leaf products whose
   // operands are plain blocks of A and B (P1 = A11 B11, P2 = A12 B21 at the
   // top level, and their counterparts below) run on the main stream.
-  const bool leaf_u = b.P.leaf_u && L >= 1;
-  const bool overlap_req = b.P.overlap && L >= 1 && !leaf_u && !b.P.spl;
+  const bool leaf_u = b.P.leaf_u && L >= 1 && !strassen;
+  const bool overlap_req = b.P.overlap && L >= 1 && !leaf_u && !b.P.spl && !strassen;
   if (overlap_req) {
     b.fork();
     b.cur_stream = 1;
@@ -874,6 +883,28 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
     std::vector<std::array<MView, 11>> uargs;
     for (const Sub& s : subs) {
       const int64_t hm = s.A.rows / 2, hk = s.A.cols / 2, hn = s.B.cols / 2;
+      if (strassen) {
+        const MView A11 = b.quad(s.A, 0, 0), A12 = b.quad(s.A, 0, 1), A21 = b.quad(s.A, 1, 0),
+                    A22 = b.quad(s.A, 1, 1);
+        const MView B11 = b.quad(s.B, 0, 0), B12 = b.quad(s.B, 0, 1), B21 = b.quad(s.B, 1, 0),
+                    B22 = b.quad(s.B, 1, 1);
+        MView X[5], Y[5], Pt[7];
+        for (auto& v : X) v = b.temp(hm, hk);
+        for (auto& v : Y) v = b.temp(hk, hn);
+        for (auto& v : Pt) v = b.temp(hm, hn);
+        b.ew_part(EW_STR_S, hm, hk, {A11, A12, A21, A22}, {X[0], X[1], X[2], X[3], X[4]});
+        b.ew_part(EW_STR_T, hk, hn, {B11, B12, B21, B22}, {Y[0], Y[1], Y[2], Y[3], Y[4]});
+        next.push_back({X[0], Y[0], Pt[0]});  // P1 = (A11 + A22)(B11 + B22)
+        next.push_back({X[1], B11, Pt[1]});   // P2 = (A21 + A22) B11
+        next.push_back({A11, Y[1], Pt[2]});   // P3 = A11 (B12 - B22)
+        next.push_back({A22, Y[2], Pt[3]});   // P4 = A22 (B21 - B11)
+        next.push_back({X[2], B22, Pt[4]});   // P5 = (A11 + A12) B22
+        next.push_back({X[3], Y[3], Pt[5]});  // P6 = (A21 - A11)(B11 + B12)
+        next.push_back({X[4], Y[4], Pt[6]});  // P7 = (A12 - A22)(B21 + B22)
+        uargs.push_back({Pt[0], Pt[1], Pt[2], Pt[3], Pt[4], Pt[5], Pt[6], b.quad(s.C, 0, 0),
+                         b.quad(s.C, 0, 1), b.quad(s.C, 1, 0), b.quad(s.C, 1, 1)});
+        continue;
+      }
       if (l == L - 1 && leaf_u) {
         // products and U combinations of the last level in one kernel
         const MView A11 = b.quad(s.A, 0, 0), A12 = b.quad(s.A, 0, 1), A21 = b.quad(s.A, 1, 0),
@@ -891,7 +922,7 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
                               hm, hn, hk, l == 0 && b.P.accumulate});
         continue;
       }
-      if (l == L - 1 && b.P.spl) {
+      if (l == L - 1 && b.P.spl) {  // (never with Strassen: handled above)
         // split-bfloat16 leaves: the split pass forms S1..S4 / T1..T4 and
         // splits the quadrants read as plain leaf operands
         const MView A11 = b.quad(s.A, 0, 0), A12 = b.quad(s.A, 0, 1), A21 = b.quad(s.A, 1, 0),
@@ -965,7 +996,7 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
     for (const auto& u : uargs) {
       EwPart p;
       std::memset(&p, 0, sizeof p);
-      p.kind = EW_WINO_U;
+      p.kind = strassen ? EW_STR_U : EW_WINO_U;
       p.rows = u[7].rows;
       p.cols = u[7].cols;
       p.nin = 7;
@@ -1004,12 +1035,12 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
   for (int l = L - 1; l >= 0; --l) {
     for (const EwPart& p : u_levels[l]) {
       if (l == 0 && b.P.accumulate)  // C = beta C + U at the top level
-        b.ew_part(EW_WINO_U_ACC, p.rows, p.cols,
+        b.ew_part(strassen ? EW_STR_U_ACC : EW_WINO_U_ACC, p.rows, p.cols,
                   {p.in[0], p.in[1], p.in[2], p.in[3], p.in[4], p.in[5], p.in[6], p.out[0], p.out[1], p.out[2],
                    p.out[3]},
                   {p.out[0], p.out[1], p.out[2], p.out[3]});
       else
-        b.ew_part(EW_WINO_U, p.rows, p.cols, {p.in[0], p.in[1], p.in[2], p.in[3], p.in[4], p.in[5], p.in[6]},
+        b.ew_part(p.kind, p.rows, p.cols, {p.in[0], p.in[1], p.in[2], p.in[3], p.in[4], p.in[5], p.in[6]},
                   {p.out[0], p.out[1], p.out[2], p.out[3]});
     }
     b.flush();
@@ -1043,7 +1074,7 @@ int check_enums(int algo, int sched, int dtype) {
 
 int resolve_sched(int algo, int sched) {
   if (algo == MM_ALGO_NAIVE) return MM_SCHED_AUTO;
-  if (sched == MM_SCHED_AUTO) return algo == MM_ALGO_STRASSEN ? MM_SCHED_DFS3 : MM_SCHED_GROUPED;
+  if (sched == MM_SCHED_AUTO) return MM_SCHED_GROUPED;
   return sched;
 }
 
@@ -1052,8 +1083,8 @@ int build_plan(Plan& P) {
   P.sched = resolve_sched(P.algo, P.sched);
   if (P.dtype == MM_BF16X3_REFINED && !bf16x3_available())
     return fail(MM_E_UNSUPPORTED, "split-bfloat16 leaves are not built into this library");
-  if (P.algo == MM_ALGO_STRASSEN && P.sched != MM_SCHED_DFS3)
-    return fail(MM_E_UNSUPPORTED, "Strassen supports the DFS3 schedule only");
+  if (P.algo == MM_ALGO_STRASSEN && P.sched != MM_SCHED_DFS3 && P.sched != MM_SCHED_GROUPED)
+    return fail(MM_E_UNSUPPORTED, "Strassen supports the DFS3 and grouped schedules only");
   if (P.algo == MM_ALGO_WINOGRAD && P.sched == MM_SCHED_DFS3)
     return fail(MM_E_UNSUPPORTED, "DFS3 is a Strassen schedule");
   const int64_t m = P.m, n = P.n, k = P.k;
@@ -1383,7 +1414,7 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   // plain product read operands split once by a split pass
   const int rs = resolve_sched(algo, sched);
   P->spl = dtype == MM_BF16X3_REFINED && (flags & MM_PLAN_SPLIT_PASS) != 0 &&
-           (rs == MM_SCHED_GROUPED || algo == MM_ALGO_NAIVE);
+           ((rs == MM_SCHED_GROUPED && algo == MM_ALGO_WINOGRAD) || algo == MM_ALGO_NAIVE);
   if (P->tile_cfg >= (P->leaf_u ? kNumWinoCfg : kNumGemmCfg))
     return fail(MM_E_INVALID, "unknown tile configuration");
   rc = build_plan(*P);

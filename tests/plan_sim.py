@@ -21,6 +21,7 @@ import numpy as np
 EW_COPY, EW_ADD, EW_SUB, EW_WINO_S, EW_WINO_T, EW_WINO_U, EW_TT_U = range(7)
 EW_IP_A, EW_IP_B, EW_IP_U, EW_DIST, EW_ZERO = 7, 8, 9, 10, 11
 EW_SPLIT, EW_WINO_S_SPL, EW_WINO_T_SPL, EW_WINO_U_ACC, EW_AXPBY = 12, 13, 14, 15, 16
+EW_STR_S, EW_STR_T, EW_STR_U, EW_STR_U_ACC = 17, 18, 19, 20
 GM_STORE, GM_ADD, GM_AXPBY = 1, 2, 3
 MB_A, MB_B, MB_C, MB_WS, MB_ABS = 0, 1, 2, 3, 4
 
@@ -251,6 +252,15 @@ def _recipe(kind, x, mode):
         u2 = p1 + p6
         u3 = u2 + p7
         return [p1 + p2, u2 + p5 + p3, u3 - p4, u3 + p5]
+    if kind == EW_STR_S:
+        a11, a12, a21, a22 = x
+        return [a11 + a22, a21 + a22, a11 + a12, a21 - a11, a12 - a22]
+    if kind == EW_STR_T:
+        b11, b12, b21, b22 = x
+        return [b11 + b22, b12 - b22, b21 - b11, b11 + b12, b21 + b22]
+    if kind == EW_STR_U:
+        p1, p2, p3, p4, p5, p6, p7 = x
+        return [((p1 + p4) - p5) + p7, p3 + p5, p2 + p4, ((p1 + p3) - p2) + p6]
     if kind == EW_TT_U:
         xp, c11, c12, c21, c22 = x
         u2 = xp + c12
@@ -378,8 +388,9 @@ def run(text, bufs, hazards=True, beta=1):
                      for v in it["ins"]]
                 if it["kind"] == EW_ZERO:
                     y = [np.zeros((it["rows"], it["cols"]), dtype=mem.dtype)]
-                elif it["kind"] == EW_WINO_U_ACC:
-                    u = _recipe(EW_WINO_U, x[:7], it["mode"])
+                elif it["kind"] in (EW_WINO_U_ACC, EW_STR_U_ACC):
+                    base = EW_WINO_U if it["kind"] == EW_WINO_U_ACC else EW_STR_U
+                    u = _recipe(base, x[:7], it["mode"])
                     y = [beta * c + v for c, v in zip(x[7:], u)]
                 elif it["kind"] == EW_AXPBY:
                     y = [beta * x[1] + x[0]]

@@ -69,7 +69,7 @@ def test_naive_gemm_exact_on_integers(api, naive, dtype):
     assert np.array_equal(gpu_mm(api, A, B, algo="naive").astype(np.float64), naive.gemm(A, B))
 
 
-VARIANTS = [("naive", "auto"), ("strassen", "dfs3"), ("winograd", "two_temp"),
+VARIANTS = [("naive", "auto"), ("strassen", "dfs3"), ("strassen", "grouped"), ("winograd", "two_temp"),
             ("winograd", "in_place"), ("winograd", "grouped")]
 
 
@@ -97,6 +97,8 @@ def test_fp64_512_cutoff_64(api, naive):
     # the three Winograd schedules do the same operations in the same order
     assert np.array_equal(res[("winograd", "two_temp")], res[("winograd", "in_place")])
     assert np.array_equal(res[("winograd", "two_temp")], res[("winograd", "grouped")])
+    # and so do the two Strassen schedules
+    assert np.array_equal(res[("strassen", "dfs3")], res[("strassen", "grouped")])
 
 
 def test_fp64_512_integer_exact(api, naive):
@@ -124,6 +126,8 @@ def test_fp32_schedules_bitwise(api):
             for s in ("two_temp", "in_place", "grouped")]
     assert np.array_equal(outs[0], outs[1])
     assert np.array_equal(outs[0], outs[2])
+    outs = [gpu_mm(api, A, B, algo="strassen", sched=s, cutoff=1, levels=2) for s in ("dfs3", "grouped")]
+    assert np.array_equal(outs[0], outs[1])
 
 
 @pytest.mark.parametrize("m,n,k,cutoff,levels", [(100, 60, 80, 8, -1), (1000, 777, 555, 1, 2),
@@ -131,7 +135,8 @@ def test_fp32_schedules_bitwise(api):
 def test_padding_shapes_fp32(api, naive, m, n, k, cutoff, levels):
     A, B = inputs.pair("uniform", m, n, k, 8, np.float32)
     ref = naive.gemm(A, B)
-    for algo, sched in [("winograd", "grouped"), ("winograd", "two_temp"), ("strassen", "dfs3")]:
+    for algo, sched in [("winograd", "grouped"), ("winograd", "two_temp"), ("strassen", "dfs3"),
+                        ("strassen", "grouped")]:
         got = gpu_mm(api, A, B, algo=algo, sched=sched, cutoff=cutoff, levels=levels)
         err = rel_fro(got, ref)
         assert err < 1e-5, (algo, sched, err)
@@ -168,7 +173,7 @@ def test_fp32_full_size_sampled_rows(api, naive, n):
     At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
     for algo, sched, lv in [("naive", "auto", 0), ("winograd", "grouped", 1), ("winograd", "grouped", 2),
                             ("winograd", "grouped", 3), ("winograd", "two_temp", 2),
-                            ("strassen", "dfs3", 1)]:
+                            ("strassen", "dfs3", 1), ("strassen", "grouped", 2)]:
         print(f"fp32 {n} {algo}/{sched} L={lv}", flush=True)
         C = api.mm(At, Bt, algo=algo, sched=sched, cutoff=1, levels=lv)
         torch.cuda.synchronize()

@@ -65,6 +65,11 @@ CASES = [
     ("strassen", "dfs3", 16, 8, 32, 2),
     ("strassen", "dfs3", 13, 7, 5, 1),
     ("strassen", "dfs3", 64, 64, 64, 4),
+    ("strassen", "grouped", 4, 4, 4, 1),
+    ("strassen", "grouped", 8, 8, 8, 1),
+    ("strassen", "grouped", 13, 7, 5, 1),       # virtual padding
+    ("strassen", "grouped", 100, 60, 80, 8),
+    ("strassen", "grouped", 200, 136, 72, 16),
 ]
 
 
@@ -130,6 +135,25 @@ def test_grouped_launch_count_and_leaves(lib):
         # with MM_PLAN_FUSE the last level's S/T pass is formed in the leaf loader
         text, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_, fuse=True)
         assert count(text, "EW") == 2 * L_ - 1 and info["fused"] == 1
+
+
+def test_grouped_strassen_launches(lib):
+    # Strassen breadth first: one pass per level forms the ten operand sums,
+    # the 7^L leaves run grouped, one pass per level forms the C quadrants;
+    # the options particular to Winograd's operands are ignored
+    def count(text, what):
+        return sum(l.startswith("LAUNCH " + what) for l in text.splitlines())
+    for L_ in (1, 2, 3):
+        for opts in ({}, {"overlap": True}, {"fuse": True}, {"leaf_u": True}):
+            text, info = L.describe("strassen", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_, **opts)
+            g = count(text, "GEMM")
+            assert count(text, "EW") == 2 * L_ and g in (1, 2) and "FORK" not in text
+            assert info["launches"] == 2 * L_ + g and info["leaves"] == 7 ** L_
+            assert info["fused"] == 0 and info["leaf_u"] == 0
+    # the schedule AUTO resolves to for Strassen
+    _, info = L.describe("strassen", "auto", 512, 512, 512, cutoff=64)
+    _, info_g = L.describe("strassen", "grouped", 512, 512, 512, cutoff=64)
+    assert info["sched"] == info_g["sched"]
 
 
 def test_leaf_launches_fill_whole_rounds(lib):
@@ -352,7 +376,8 @@ ACC_CASES = [("naive", "auto", 40, 24, 56, -1, {}), ("naive", "auto", 17, 9, 0, 
              ("winograd", "grouped", 96, 64, 64, 2, {"overlap": True}),
              ("winograd", "grouped", 64, 64, 64, 1, {"fuse": True}),
              ("winograd", "two_temp", 64, 32, 48, 2, {}), ("winograd", "in_place", 64, 32, 32, 2, {}),
-             ("winograd", "two_temp", 50, 30, 40, 2, {}), ("strassen", "dfs3", 48, 40, 24, 2, {})]
+             ("winograd", "two_temp", 50, 30, 40, 2, {}), ("strassen", "dfs3", 48, 40, 24, 2, {}),
+             ("strassen", "grouped", 48, 40, 24, 2, {}), ("strassen", "grouped", 70, 50, 90, 1, {})]
 
 
 @pytest.mark.parametrize("algo,sched,m,n,k,levels,opts", ACC_CASES)
