@@ -184,6 +184,14 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                                  fma(beta, Cold, x)); the depth-first schedules form A B in a
                                  workspace block of m x n (they use C as scratch) and add it
                                  in one more element-wise pass.  Not for batched plans. */
+#define MM_PLAN_PEEL 64u /* grouped schedule: instead of reading A, B and C as if zero-padded to
+                           multiples of 2^L g, run the recursion on the largest leading block
+                           whose sides are such multiples (pm x pk times pk x pn) and cover
+                           the rest with one launch of thin products (dynamic peeling, the
+                           alternative to padding that Section 3.1 mentions): C[:pm,:pn] +=
+                           A[:pm,pk:] B[pk:,:pn], C[:pm,pn:] = A[:pm,:] B[:,pn:], C[pm:,:] =
+                           A[pm:,:] B.  No effect when every side is already such a multiple
+                           or when a side of the leading block would be empty. */
 /* Force the MFMA GEMM tile configuration c (0 .. 7) for every leaf launch
  * instead of the planner's choice.  float32: 0 128x128 (BK 32, 8 waves),
  * 1 256x128 (8 waves), 2 128x256 (8 waves), 3 256x256 (BK 32, 8 waves),

@@ -85,6 +85,8 @@ struct Plan {
   bool wino = false;     // the plan has such a launch
   bool spl = false;      // split-bfloat16 leaves read operands split by a split pass
   bool accumulate = false;  // C <- A B + beta C (beta given per execution)
+  bool peel = false;        // grouped: peel ragged rows / columns / k instead of padding
+  int64_t pm = 0, pn = 0, pk = 0;  // peeled: the leading block the recursion runs on
   bool has_aux = false;  // some launches go to the auxiliary stream
   struct Aux {
     hipStream_t main, aux;
@@ -1101,6 +1103,19 @@ int build_plan(Plan& P) {
   P.M = round_up(m, step * g);
   P.N = round_up(n, step * g);
   P.K = round_up(k, step * g);
+  // Peeling: the recursion runs on the largest leading block whose sides are
+  // multiples of 2^L g and thin products cover the rest (when every side of
+  // that block is nonempty; otherwise the plan pads).
+  P.pm = m / (step * g) * (step * g);
+  P.pn = n / (step * g) * (step * g);
+  P.pk = k / (step * g) * (step * g);
+  const bool peel = P.peel && P.sched == MM_SCHED_GROUPED && P.L > 0 && P.pm > 0 && P.pn > 0 && P.pk > 0 &&
+                    (P.pm != m || P.pn != n || P.pk != k);
+  if (peel) {
+    P.M = P.pm;
+    P.N = P.pn;
+    P.K = P.pk;
+  }
   if (P.L == 0) {
     P.M = m;
     P.N = n;
@@ -1131,6 +1146,28 @@ int build_plan(Plan& P) {
     } else {
       b.gemm(A, B, {out});
     }
+    b.flush();
+  } else if (P.sched == MM_SCHED_GROUPED && peel) {
+    // C[:pm, :pn] = A[:pm, :pk] B[:pk, :pn] by the recursion, then one
+    // launch of thin products: C[:pm, :pn] += A[:pm, pk:] B[pk:, :pn],
+    // C[:pm, pn:] = A[:pm, :] B[:, pn:] and C[pm:, :] = A[pm:, :] B
+    // (beta C + ... for those two in accumulating plans; the recursion's
+    // top-level combination applies beta to the leading block).
+    const int64_t pm = P.pm, pn = P.pn, pk = P.pk;
+    sched_grouped(b, {Sub{b.view(MB_A, 0, P.lda, pm, pk, pm, pk), b.view(MB_B, 0, P.ldb, pk, pn, pk, pn),
+                          b.view(MB_C, 0, P.ldc, pm, pn, pm, pn)}});
+    auto out = [&](const MView& c) { return P.accumulate ? Builder::axpby(c) : Builder::store(c); };
+    if (pk < k) {
+      const MView Cl = b.view(MB_C, 0, P.ldc, pm, pn, pm, pn);
+      b.gemm(b.view(MB_A, pk, P.lda, pm, k - pk, pm, k - pk), b.view(MB_B, pk * P.ldb, P.ldb, k - pk, pn, k - pk, pn),
+             {Builder::add(Cl, Cl, +1)});
+    }
+    if (pn < n)
+      b.gemm(b.view(MB_A, 0, P.lda, pm, k, pm, k), b.view(MB_B, pn, P.ldb, k, n - pn, k, n - pn),
+             {out(b.view(MB_C, pn, P.ldc, pm, n - pn, pm, n - pn))});
+    if (pm < m)
+      b.gemm(b.view(MB_A, pm * P.lda, P.lda, m - pm, k, m - pm, k), b.view(MB_B, 0, P.ldb, k, n, k, n),
+             {out(b.view(MB_C, pm * P.ldc, P.ldc, m - pm, n, m - pm, n))});
     b.flush();
   } else if (P.sched == MM_SCHED_GROUPED) {
     const MView A = b.view(MB_A, 0, P.lda, P.M, P.K, m, k);
@@ -1405,6 +1442,7 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   P->fuse = (flags & MM_PLAN_FUSE) != 0;
   P->overlap = (flags & MM_PLAN_OVERLAP) != 0;
   P->accumulate = (flags & MM_PLAN_ACCUMULATE) != 0;
+  P->peel = (flags & MM_PLAN_PEEL) != 0;
   // the fused Winograd leaf level computes in float32 and replaces the
   // grouped schedule's last level; other dtypes and schedules ignore it
   P->leaf_u = (flags & MM_PLAN_LEAF_U) != 0 && dtype == MM_F32 && sched == MM_SCHED_GROUPED &&

@@ -428,7 +428,30 @@ ACC_GPU = [("naive", "auto", 300, 200, 100, 0, "f32", {}), ("naive", "auto", 257
            ("winograd", "in_place", 512, 256, 256, 1, "f32", {}),
            ("strassen", "dfs3", 384, 320, 256, 2, "f64", {}),
            ("winograd", "grouped", 1024, 1024, 1024, 2, "bf16x3", {}),
-           ("naive", "auto", 640, 384, 200, 0, "bf16x3", {"split_pass": True})]
+           ("naive", "auto", 640, 384, 200, 0, "bf16x3", {"split_pass": True}),
+           ("strassen", "grouped", 640, 384, 512, 2, "f32", {}),
+           ("winograd", "grouped", 1000, 777, 555, 2, "f32", {"peel": True}),
+           ("strassen", "grouped", 301, 290, 257, 2, "f64", {"peel": True})]
+
+
+PEEL_GPU = [("winograd", 1000, 777, 555, 2, "f32"), ("winograd", 1200, 1300, 1100, 3, "f32"),
+            ("winograd", 1023, 1025, 1027, 2, "f64"), ("strassen", 1000, 777, 555, 2, "f32"),
+            ("winograd", 1030, 1100, 1050, 2, "bf16x3")]
+
+
+@pytest.mark.parametrize("algo,m,n,k,levels,dt", PEEL_GPU)
+def test_peeled_plans(api, naive, algo, m, n, k, levels, dt):
+    # MM_PLAN_PEEL against the oracle, and exact on small integers
+    npdt = np.float64 if dt == "f64" else np.float32
+    print(f"peel {algo} {m}x{n}x{k} L={levels} {dt}", flush=True)
+    A, B = inputs.pair("uniform", m, n, k, 46, npdt)
+    got = gpu_mm(api, A, B, algo=algo, sched="grouped", cutoff=1, levels=levels, dtype=dt, peel=True)
+    tol = 1e-12 if dt == "f64" else 1e-5
+    assert rel_fro(got, naive.gemm(A, B)) < tol
+    A, B = inputs.pair("int", m, n, k, 47, npdt)
+    A, B = np.clip(A, -1, 1), np.clip(B, -1, 1)
+    got = gpu_mm(api, A, B, algo=algo, sched="grouped", cutoff=1, levels=levels, dtype=dt, peel=True)
+    assert np.array_equal(got.astype(np.float64), naive.gemm(A, B))
 
 
 @pytest.mark.parametrize("algo,sched,m,n,k,levels,dt,opts", ACC_GPU)

@@ -395,3 +395,57 @@ def test_accumulating_plans_are_exact(lib, algo, sched, m, n, k, levels, opts, b
     plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws}, beta=beta)
     want = A @ B + (beta * C0 if beta else 0)
     assert np.array_equal(C.reshape(m, n), want)
+
+
+PEEL_CASES = [("winograd", 13, 7, 5, 1, -1), ("winograd", 100, 60, 80, 8, -1), ("winograd", 200, 136, 72, 1, 2),
+              ("winograd", 161, 130, 199, 1, 2), ("winograd", 64, 64, 70, 1, 1), ("winograd", 70, 64, 64, 1, 1),
+              ("winograd", 64, 70, 64, 1, 1), ("strassen", 161, 130, 199, 1, 2), ("strassen", 29, 31, 37, 1, 2)]
+
+
+@pytest.mark.parametrize("algo,m,n,k,cutoff,levels", PEEL_CASES)
+def test_peeled_plans_are_exact(lib, algo, m, n, k, cutoff, levels):
+    # MM_PLAN_PEEL: the recursion on the leading block, thin products for the
+    # rest; exact on integers, no virtual padding
+    A = inputs.integers((m, k), 41, dtype=np.int64)
+    B = inputs.integers((k, n), 42, dtype=np.int64)
+    text, info = L.describe(algo, "grouped", m, n, k, cutoff=cutoff, levels=levels, dtype="f32", peel=True)
+    _, info0 = L.describe(algo, "grouped", m, n, k, cutoff=cutoff, levels=levels, dtype="f32")
+    dims, dims0 = (info["M"], info["N"], info["K"]), (info0["M"], info0["N"], info0["K"])
+    # peeled (no side beyond the matrix), or padded when a side of the leading
+    # block would be empty (13 x 7 x 5 has three levels: 5 < 2^3)
+    assert (dims[0] <= m and dims[1] <= n and dims[2] <= k) or dims == dims0
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    C = np.full(m * n, -(10**9), dtype=np.int64)
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
+    assert np.array_equal(C.reshape(m, n), A @ B)
+    assert info0["levels"] == info["levels"]
+
+
+@pytest.mark.parametrize("beta", [3, 0])
+def test_peeled_accumulating_plan(lib, beta):
+    m, n, k = 150, 98, 123
+    A = inputs.integers((m, k), 43, dtype=np.int64)
+    B = inputs.integers((k, n), 44, dtype=np.int64)
+    C0 = inputs.integers((m, n), 45, dtype=np.int64)
+    text, info = L.describe("winograd", "grouped", m, n, k, cutoff=1, levels=2, dtype="f32", peel=True,
+                            accumulate=True)
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    C = C0.ravel().copy() if beta else np.full(m * n, 10**12, dtype=np.int64)
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws}, beta=beta)
+    assert np.array_equal(C.reshape(m, n), A @ B + (beta * C0 if beta else 0))
+
+
+def test_peel_launch_structure(lib):
+    # 3000 = 93 * 32 + 24 with L = 3 and groups of 4 float32 (16 bytes): the
+    # recursion runs on 2976^3 and one more launch holds the three thin products
+    text, info = L.describe("winograd", "grouped", 3000, 3000, 3000, cutoff=1, levels=3, peel=True)
+    _, info0 = L.describe("winograd", "grouped", 3000, 3000, 3000, cutoff=1, levels=3)
+    assert (info["M"], info["N"], info["K"]) == (2976, 2976, 2976)
+    assert (info0["M"], info0["N"], info0["K"]) == (3008, 3008, 3008)
+    assert info["launches"] == info0["launches"] + 1
+    last = [l for l in text.splitlines() if l.startswith("LAUNCH")][-1].split()
+    assert last[1] == "GEMM" and int(last[2]) == 3
+    # nothing to peel: the same plan
+    t1, _ = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=2, peel=True)
+    t0, _ = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=2)
+    assert t1 == t0
