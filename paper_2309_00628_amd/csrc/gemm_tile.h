@@ -108,6 +108,7 @@ struct TileLoop {
   static constexpr int KMID = KB / 2;
   static_assert(FM >= 1 && FN >= 1 && WM % TM == 0 && WN % TM == 0, "wave tile");
   static_assert(BKC % M::KG == 0 && BKC <= BKC_MAX && 16 % BKC == 0, "k chunks");
+  static_assert(NA * E <= 64 && NB * E * E <= 64, "one validity bit per staged element");
 
   struct Smem {
     chunk_t As[2][BKC][BM];
@@ -132,12 +133,14 @@ struct TileLoop {
   // LOAD_EDGE_VEC: edge tile of aligned operands whose valid widths are
   // multiples of the chunk: whole chunks are in or out, selected without
   // branches (the validity is applied when the stage is written to LDS, not
-  // right after the load, which would wait for it).  Otherwise per-element
-  // masked loads.
+  // right after the load, which would wait for it).  LOAD_MASKED: one load
+  // per element, from the element itself when it is valid and from the
+  // operand's first element otherwise, with the validity applied at the LDS
+  // write in the same way (the operands are nonempty: see product).
   template <int MODE>
   static __device__ __forceinline__ void load_tile(const Operand<T>& A, const Operand<T>& B, int i0, int j0,
                                                    int kt, chunk_t (&ra)[NA], chunk_t (&rbk)[NB][E],
-                                                   uint32_t& amask, uint32_t& bmask) {
+                                                   uint64_t& amask, uint64_t& bmask) {
     const int tid = threadIdx.x;
     const int k0 = kt * BK;
 #pragma unroll
@@ -152,13 +155,16 @@ struct TileLoop {
       } else if (MODE == LOAD_EDGE_VEC) {
         const bool ok = gr < A.vrows && gc < A.vcols;
         ra[i] = *reinterpret_cast<const chunk_t*>(ok ? p : A.p);
-        amask = ok ? (amask | (1u << i)) : (amask & ~(1u << i));
-      } else if (A.vec && gr < A.vrows && gc + E <= A.vcols) {
-        ra[i] = *reinterpret_cast<const chunk_t*>(p);
+        const uint64_t bit = 1ull << i;
+        amask = ok ? (amask | bit) : (amask & ~bit);
       } else {
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-          ra[i][e] = (gr < A.vrows && gc + e < A.vcols) ? p[e] : T(0);
+        for (int e = 0; e < E; ++e) {
+          const bool ok = gr < A.vrows && gc + e < A.vcols;
+          ra[i][e] = *(ok ? p + e : A.p);
+          const uint64_t bit = 1ull << (i * E + e);
+          amask = ok ? (amask | bit) : (amask & ~bit);
+        }
       }
     }
 #pragma unroll
@@ -176,14 +182,16 @@ struct TileLoop {
         } else if (MODE == LOAD_EDGE_VEC) {
           const bool ok = gr < B.vrows && gc < B.vcols;
           rbk[i][rr] = *reinterpret_cast<const chunk_t*>(ok ? p : B.p);
-          const uint32_t bit = 1u << (i * E + rr);
+          const uint64_t bit = 1ull << (i * E + rr);
           bmask = ok ? (bmask | bit) : (bmask & ~bit);
-        } else if (B.vec && gr < B.vrows && gc + E <= B.vcols) {
-          rbk[i][rr] = *reinterpret_cast<const chunk_t*>(p);
         } else {
 #pragma unroll
-          for (int e = 0; e < E; ++e)
-            rbk[i][rr][e] = (gr < B.vrows && gc + e < B.vcols) ? p[e] : T(0);
+          for (int e = 0; e < E; ++e) {
+            const bool ok = gr < B.vrows && gc + e < B.vcols;
+            rbk[i][rr][e] = *(ok ? p + e : B.p);
+            const uint64_t bit = 1ull << ((i * E + rr) * E + e);
+            bmask = ok ? (bmask | bit) : (bmask & ~bit);
+          }
         }
       }
     }
@@ -191,16 +199,23 @@ struct TileLoop {
 
   template <int MODE>
   static __device__ __forceinline__ void store_tile(Smem& sm, int buf, const chunk_t (&ra)[NA],
-                                                    const chunk_t (&rbk)[NB][E], uint32_t amask,
-                                                    uint32_t bmask) {
+                                                    const chunk_t (&rbk)[NB][E], uint64_t amask,
+                                                    uint64_t bmask) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int q = tid + NT * i;
       if (NCH_A % NT != 0 && q >= NCH_A) break;
       const int row = q / BKC, kc = q % BKC;
-      sm.As[buf][kc][swz_a<BKC>(row, kc)] =
-          (MODE != LOAD_EDGE_VEC || ((amask >> i) & 1)) ? ra[i] : chunk_t{};
+      chunk_t v = ra[i];
+      if (MODE == LOAD_EDGE_VEC) {
+        if (!((amask >> i) & 1)) v = chunk_t{};
+      } else if (MODE == LOAD_MASKED) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (!((amask >> (i * E + e)) & 1)) v[e] = T(0);
+      }
+      sm.As[buf][kc][swz_a<BKC>(row, kc)] = v;
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -211,8 +226,12 @@ struct TileLoop {
       for (int c = 0; c < E; ++c) {
         chunk_t t;
 #pragma unroll
-        for (int rr = 0; rr < E; ++rr)
-          t[rr] = (MODE != LOAD_EDGE_VEC || ((bmask >> (i * E + rr)) & 1)) ? rbk[i][rr][c] : T(0);
+        for (int rr = 0; rr < E; ++rr) {
+          bool ok = true;
+          if (MODE == LOAD_EDGE_VEC) ok = (bmask >> (i * E + rr)) & 1;
+          if (MODE == LOAD_MASKED) ok = (bmask >> ((i * E + rr) * E + c)) & 1;
+          t[rr] = ok ? rbk[i][rr][c] : T(0);
+        }
         sm.Bs[buf][kc][swz_b<E>(cb * E + c)] = t;
       }
     }
@@ -260,7 +279,7 @@ struct TileLoop {
                                                    int j0, int ktiles, Acc& acc) {
     chunk_t ra[NA];
     chunk_t rbk[NB][E];  // E rows (k) of E columns
-    uint32_t amask = 0, bmask = 0;
+    uint64_t amask = 0, bmask = 0;
     load_tile<MODE>(A, B, i0, j0, 0, ra, rbk, amask, bmask);
     store_tile<MODE>(sm, 0, ra, rbk, amask, bmask);
     __syncthreads();
@@ -280,6 +299,9 @@ struct TileLoop {
                                                  int j0, int K, Acc& acc) {
     const int ktiles = (K + BK - 1) / BK;
     if (ktiles <= 0) return;
+    // an operand with no valid element is zero: nothing to add (and the
+    // loaders may then read its first element)
+    if (A.vrows <= 0 || A.vcols <= 0 || B.vrows <= 0 || B.vcols <= 0) return;
     const bool interior = A.vec && B.vec && (i0 + BM <= A.vrows) && (j0 + BN <= B.vcols) && (K % BK == 0) &&
                           (K <= A.vcols) && (K <= B.vrows);
     const bool edge_vec = A.vec && B.vec && A.vrows > 0 && A.vcols > 0 && B.vrows > 0 && B.vcols > 0 &&
