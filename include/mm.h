@@ -111,7 +111,11 @@ typedef struct mm_plan_s* mm_plan_t;
 
 /* ---- short forms (contiguous operands) --------------------------------- */
 
-/* The naive method (Section 2.1) as one MFMA GEMM.  Needs no workspace. */
+/* The naive method (Section 2.1) as one MFMA GEMM.  Needs no workspace,
+ * except when a leading dimension or width of A or B is not a multiple of
+ * 16 bytes and the product is large (m, n, k >= 64, mnk >= 2^27): then both
+ * are first copied into aligned blocks of a workspace obtained as for
+ * mm_strassen. */
 int mm_naive(int64_t m, int64_t n, int64_t k, const void* A, const void* B, void* C, int dtype,
              hipStream_t stream);
 

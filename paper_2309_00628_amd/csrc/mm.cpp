@@ -1137,6 +1137,18 @@ int build_plan(Plan& P) {
         b.ew_part(EW_AXPBY, m, n, {b.view(MB_C, 0, P.ldc, m, n, 0, 0), C}, {C});
       else
         b.ew_part(EW_ZERO, m, n, {}, {C});
+    } else if (P.dtype != MM_BF16X3_REFINED && (P.lda % b.E || P.ldb % b.E || k % b.E || n % b.E) &&
+               m >= 64 && n >= 64 && k >= 64 && (double)m * n * k >= 134217728.0) {
+      // Operands that cannot be read in 16-byte chunks (a leading dimension
+      // or width not a multiple of 16 bytes) would put every tile on the
+      // element-wise load path: copy them once into aligned blocks (k and n
+      // rounded up, the extra k rows / columns zero) and run the GEMM on those.
+      const int64_t k4 = round_up(k, b.E), n4 = round_up(n, b.E);
+      const MView Ap = b.temp(m, k4), Bp = b.temp(k4, n4);
+      b.ew_part(EW_COPY, m, k4, {b.view(MB_A, 0, P.lda, m, k4, m, k)}, {Ap});
+      b.ew_part(EW_COPY, k4, n4, {b.view(MB_B, 0, P.ldb, k4, n4, k, n)}, {Bp});
+      b.flush();
+      b.gemm(Ap, Bp, {out});
     } else if (P.spl) {
       const MView As = b.spl_temp(m, k), Bt = b.spl_temp(n, k);
       b.split_part(EW_SPLIT, m, k, false, {A}, {As});

@@ -64,6 +64,17 @@ def test_naive_gemm_shapes(api, naive, dtype, m, n, k):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("m,n,k", [(601, 603, 605), (1000, 1001, 640)])
+def test_naive_gemm_unaligned_copies(api, naive, dtype, m, n, k):
+    # rows that are not 16-byte multiples: the plan copies A and B into
+    # aligned blocks first
+    A, B = inputs.pair("uniform", m, n, k, 50, dtype)
+    got = gpu_mm(api, A, B, algo="naive")
+    tol = 1e-13 if dtype == np.float64 else 2e-6
+    assert rel_fro(got, naive.gemm(A, B)) < tol
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_naive_gemm_exact_on_integers(api, naive, dtype):
     A, B = inputs.pair("int", 300, 200, 250, 4, dtype)
     assert np.array_equal(gpu_mm(api, A, B, algo="naive").astype(np.float64), naive.gemm(A, B))

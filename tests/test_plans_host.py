@@ -449,3 +449,23 @@ def test_peel_launch_structure(lib):
     t1, _ = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=2, peel=True)
     t0, _ = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=2)
     assert t1 == t0
+
+
+def test_plain_product_copies_unaligned_operands(lib):
+    # a large plain product whose rows are not 16-byte multiples runs on
+    # aligned copies (one copy launch, then the GEMM); exact on integers
+    m, n, k = 513, 515, 517
+    A = inputs.integers((m, k), 48, dtype=np.int64)
+    B = inputs.integers((k, n), 49, dtype=np.int64)
+    text, info = L.describe("naive", "auto", m, n, k, dtype="f32")
+    kinds = [l.split()[1] for l in text.splitlines() if l.startswith("LAUNCH")]
+    assert kinds == ["EW", "GEMM"] and info["ws_bytes"] > 0
+    ws = np.full(info["ws_bytes"] // 4, 10**9, dtype=np.int64)
+    C = np.full(m * n, -(10**9), dtype=np.int64)
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
+    assert np.array_equal(C.reshape(m, n), A @ B)
+    # aligned, or small: one GEMM, no workspace
+    for shape in ((512, 512, 512), (100, 101, 99)):
+        text, info = L.describe("naive", "auto", *shape, dtype="f32")
+        assert [l.split()[1] for l in text.splitlines() if l.startswith("LAUNCH")] == ["GEMM"]
+        assert info["ws_bytes"] == 0
