@@ -172,7 +172,12 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                             registers, so no product is stored and the last level's U pass
                             disappears.  Sums are rounded in the same order as the separate
                             U pass: results are bitwise the same.  Ignored for other dtypes
-                            and schedules; excludes MM_PLAN_FUSE. */
+                            and schedules.  With MM_PLAN_FUSE as well, that kernel also forms
+                            S1..S4 and T1..T4 in its tile loader (when every last-level block
+                            is 16-byte aligned and has no padding): the last level then uses
+                            no temporaries at all (a one-level product touches only A, B
+                            and C; its workspace size still covers the unfused plan that runs
+                            when A or B is not 16-byte aligned). */
 #define MM_PLAN_SPLIT_PASS 16u /* MM_BF16X3_REFINED, grouped Winograd or plain product: split
                                  each float32 operand into its bfloat16 parts once, in a split
                                  pass (which also forms the last level's S/T sums), and run

@@ -52,6 +52,46 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + (x < r ? x : r) + j;
 }
 
+// Quadrants read by each operand kind (bit q: quadrant q, order 11 12 21 22).
+__host__ __device__ constexpr int kind_quads(int kind) {
+  switch (kind) {
+    case OK_S1: return 0b1100;  // A21 A22
+    case OK_S2: return 0b1101;  // A11 A21 A22
+    case OK_S3: return 0b0101;  // A11 A21
+    case OK_S4: return 0b1111;
+    case OK_T1: return 0b0011;  // B11 B12
+    case OK_T2: return 0b1011;  // B11 B12 B22
+    case OK_T3: return 0b1010;  // B12 B22
+    case OK_T4: return 0b1111;
+    default: return 0b0001;     // the view itself
+  }
+}
+__host__ __device__ constexpr int popc4(int m) { return (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1) + ((m >> 3) & 1); }
+// The j-th quadrant (in order 11 12 21 22) of a quadrant mask.
+__host__ __device__ constexpr int nth_quad(int mask, int j) {
+  for (int q = 0; q < 4; ++q)
+    if ((mask >> q) & 1) {
+      if (j == 0) return q;
+      --j;
+    }
+  return 0;
+}
+
+// The operand sum of kind KIND from the loaded quadrant values (indexed by
+// quadrant, only the needed ones are read), in the order of Section 2.3.
+template <int KIND, typename T>
+__device__ __forceinline__ T combine(const T (&q)[4]) {
+  if (KIND == OK_S1) return q[2] + q[3];
+  if (KIND == OK_S2) return (q[2] + q[3]) - q[0];
+  if (KIND == OK_S3) return q[0] - q[2];
+  if (KIND == OK_S4) return q[1] - ((q[2] + q[3]) - q[0]);
+  if (KIND == OK_T1) return q[1] - q[0];
+  if (KIND == OK_T2) return q[3] - (q[1] - q[0]);
+  if (KIND == OK_T3) return q[3] - q[1];
+  if (KIND == OK_T4) return (q[3] - (q[1] - q[0])) - q[2];
+  return q[0];
+}
+
 // Operand load modes of a tile's K loop (see the kernels).
 enum LoadMode : int { LOAD_FULL = 0, LOAD_EDGE_VEC = 1, LOAD_MASKED = 2 };
 

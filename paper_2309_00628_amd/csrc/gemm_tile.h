@@ -17,6 +17,11 @@
 // Edges: operand reads outside a view's valid extent are zero (this is also
 // how quadrants of a zero-padded matrix are read without a copy).  Interior
 // tiles take an unmasked vector path.
+//
+// Operand sums: an operand may be one of the Strassen-Winograd sums S1..S4 /
+// T1..T4 of Section 2.3 of a parent block's quadrants; the loader then
+// reads the quadrants it needs and forms the sum, in the order of Section
+// 2.3, when the stage is written to LDS (the same bits as a separate pass).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -73,18 +78,29 @@ struct MT<double> {
 constexpr int BKC_MAX = 8;
 
 // One operand of a tile product: element (r, c) at p[r * ld + c], zero
-// outside [0, vrows) x [0, vcols); vec: p and ld allow 16-byte loads.
+// outside [0, vrows) x [0, vcols); vec: p and ld allow 16-byte loads.  For an
+// operand sum p is the parent block's first element, (vrows, vcols) the
+// extent of one (entirely valid) quadrant and q[i] the offset of quadrant i
+// (order 11 12 21 22); a plain operand has q[0] = 0.
 template <typename T>
 struct Operand {
   const T* __restrict__ p;
   int64_t ld;
   int vrows, vcols;
   bool vec;
+  int64_t q[4];
 };
 
 template <typename T>
 __device__ __forceinline__ Operand<T> operand(const KernelBases& kb, const MView& v) {
-  return Operand<T>{resolve<T>(kb, v), v.ld, v.vrows, v.vcols, view_vec(kb, v)};
+  return Operand<T>{resolve<T>(kb, v), v.ld, v.vrows, v.vcols, view_vec(kb, v), {0, 0, 0, 0}};
+}
+
+// The sums of the quadrants of parent block v, each quadrant rows x cols.
+template <typename T>
+__device__ __forceinline__ Operand<T> operand_sum(const KernelBases& kb, const MView& v, int rows, int cols) {
+  const int64_t r = (int64_t)rows * v.ld;
+  return Operand<T>{resolve<T>(kb, v), v.ld, rows, cols, view_vec(kb, v), {0, cols, r, r + cols}};
 }
 
 // BM x BN tile per workgroup, WGM x WGN waves (each (BM/WGM) x (BN/WGN)),
@@ -126,7 +142,8 @@ struct TileLoop {
         for (int r = 0; r < M::NACC; ++r) acc[a][b][r] = T(0);
   }
 
-  // Global -> register staging of stage kt.
+  // Global -> register staging of stage kt (KA / KB2: operand kinds of A
+  // and B, one staged chunk per quadrant a sum reads).
   // LOAD_FULL: the whole stage is inside both operands' valid extents and
   // every access is a 16-byte vector load (no masks, no branches, so the
   // loads of the next stage stay in flight while the MFMAs of this one run).
@@ -137,10 +154,13 @@ struct TileLoop {
   // per element, from the element itself when it is valid and from the
   // operand's first element otherwise, with the validity applied at the LDS
   // write in the same way (the operands are nonempty: see product).
-  template <int MODE>
+  template <int MODE, int KA, int KB2>
   static __device__ __forceinline__ void load_tile(const Operand<T>& A, const Operand<T>& B, int i0, int j0,
-                                                   int kt, chunk_t (&ra)[NA], chunk_t (&rbk)[NB][E],
+                                                   int kt, chunk_t (&ra)[NA][popc4(kind_quads(KA))],
+                                                   chunk_t (&rbk)[NB][E][popc4(kind_quads(KB2))],
                                                    uint64_t& amask, uint64_t& bmask) {
+    constexpr int QA = kind_quads(KA), NQA = popc4(QA);
+    constexpr int QB = kind_quads(KB2), NQB = popc4(QB);
     const int tid = threadIdx.x;
     const int k0 = kt * BK;
 #pragma unroll
@@ -151,17 +171,22 @@ struct TileLoop {
       const int gr = i0 + row, gc = k0 + kc * E;
       const T* p = A.p + (int64_t)gr * A.ld + gc;
       if (MODE == LOAD_FULL) {
-        ra[i] = *reinterpret_cast<const chunk_t*>(p);
+#pragma unroll
+        for (int j = 0; j < NQA; ++j) ra[i][j] = *reinterpret_cast<const chunk_t*>(p + A.q[nth_quad(QA, j)]);
       } else if (MODE == LOAD_EDGE_VEC) {
         const bool ok = gr < A.vrows && gc < A.vcols;
-        ra[i] = *reinterpret_cast<const chunk_t*>(ok ? p : A.p);
+        const T* s = ok ? p : A.p;
+#pragma unroll
+        for (int j = 0; j < NQA; ++j) ra[i][j] = *reinterpret_cast<const chunk_t*>(s + A.q[nth_quad(QA, j)]);
         const uint64_t bit = 1ull << i;
         amask = ok ? (amask | bit) : (amask & ~bit);
       } else {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           const bool ok = gr < A.vrows && gc + e < A.vcols;
-          ra[i][e] = *(ok ? p + e : A.p);
+          const T* s = ok ? p + e : A.p;
+#pragma unroll
+          for (int j = 0; j < NQA; ++j) ra[i][j][e] = s[A.q[nth_quad(QA, j)]];
           const uint64_t bit = 1ull << (i * E + e);
           amask = ok ? (amask | bit) : (amask & ~bit);
         }
@@ -178,17 +203,24 @@ struct TileLoop {
         const int gr = k0 + kc * E + rr;
         const T* p = B.p + (int64_t)gr * B.ld + gc;
         if (MODE == LOAD_FULL) {
-          rbk[i][rr] = *reinterpret_cast<const chunk_t*>(p);
+#pragma unroll
+          for (int j = 0; j < NQB; ++j)
+            rbk[i][rr][j] = *reinterpret_cast<const chunk_t*>(p + B.q[nth_quad(QB, j)]);
         } else if (MODE == LOAD_EDGE_VEC) {
           const bool ok = gr < B.vrows && gc < B.vcols;
-          rbk[i][rr] = *reinterpret_cast<const chunk_t*>(ok ? p : B.p);
+          const T* s = ok ? p : B.p;
+#pragma unroll
+          for (int j = 0; j < NQB; ++j)
+            rbk[i][rr][j] = *reinterpret_cast<const chunk_t*>(s + B.q[nth_quad(QB, j)]);
           const uint64_t bit = 1ull << (i * E + rr);
           bmask = ok ? (bmask | bit) : (bmask & ~bit);
         } else {
 #pragma unroll
           for (int e = 0; e < E; ++e) {
             const bool ok = gr < B.vrows && gc + e < B.vcols;
-            rbk[i][rr][e] = *(ok ? p + e : B.p);
+            const T* s = ok ? p + e : B.p;
+#pragma unroll
+            for (int j = 0; j < NQB; ++j) rbk[i][rr][j][e] = s[B.q[nth_quad(QB, j)]];
             const uint64_t bit = 1ull << ((i * E + rr) * E + e);
             bmask = ok ? (bmask | bit) : (bmask & ~bit);
           }
@@ -197,17 +229,27 @@ struct TileLoop {
     }
   }
 
-  template <int MODE>
-  static __device__ __forceinline__ void store_tile(Smem& sm, int buf, const chunk_t (&ra)[NA],
-                                                    const chunk_t (&rbk)[NB][E], uint64_t amask,
-                                                    uint64_t bmask) {
+  template <int MODE, int KA, int KB2>
+  static __device__ __forceinline__ void store_tile(Smem& sm, int buf,
+                                                    const chunk_t (&ra)[NA][popc4(kind_quads(KA))],
+                                                    const chunk_t (&rbk)[NB][E][popc4(kind_quads(KB2))],
+                                                    uint64_t amask, uint64_t bmask) {
+    constexpr int QA = kind_quads(KA), NQA = popc4(QA);
+    constexpr int QB = kind_quads(KB2), NQB = popc4(QB);
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int q = tid + NT * i;
       if (NCH_A % NT != 0 && q >= NCH_A) break;
       const int row = q / BKC, kc = q % BKC;
-      chunk_t v = ra[i];
+      chunk_t v;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        T x[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int j = 0; j < NQA; ++j) x[nth_quad(QA, j)] = ra[i][j][e];
+        v[e] = combine<KA>(x);
+      }
       if (MODE == LOAD_EDGE_VEC) {
         if (!((amask >> i) & 1)) v = chunk_t{};
       } else if (MODE == LOAD_MASKED) {
@@ -227,10 +269,13 @@ struct TileLoop {
         chunk_t t;
 #pragma unroll
         for (int rr = 0; rr < E; ++rr) {
+          T x[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+          for (int j = 0; j < NQB; ++j) x[nth_quad(QB, j)] = rbk[i][rr][j][c];
           bool ok = true;
           if (MODE == LOAD_EDGE_VEC) ok = (bmask >> (i * E + rr)) & 1;
           if (MODE == LOAD_MASKED) ok = (bmask >> ((i * E + rr) * E + c)) & 1;
-          t[rr] = ok ? rbk[i][rr][c] : T(0);
+          t[rr] = ok ? combine<KB2>(x) : T(0);
         }
         sm.Bs[buf][kc][swz_b<E>(cb * E + c)] = t;
       }
@@ -274,27 +319,28 @@ struct TileLoop {
   // every wave finished reading it before the barrier that ended stage t-1,
   // and it is read again only after the barrier that ends stage t.  The loop
   // ends with a barrier, so the next product may reuse the LDS at once.
-  template <int MODE>
+  template <int MODE, int KA, int KB2>
   static __device__ __forceinline__ void main_loop(Smem& sm, const Operand<T>& A, const Operand<T>& B, int i0,
                                                    int j0, int ktiles, Acc& acc) {
-    chunk_t ra[NA];
-    chunk_t rbk[NB][E];  // E rows (k) of E columns
+    chunk_t ra[NA][popc4(kind_quads(KA))];
+    chunk_t rbk[NB][E][popc4(kind_quads(KB2))];  // E rows (k) of E columns, per quadrant
     uint64_t amask = 0, bmask = 0;
-    load_tile<MODE>(A, B, i0, j0, 0, ra, rbk, amask, bmask);
-    store_tile<MODE>(sm, 0, ra, rbk, amask, bmask);
+    load_tile<MODE, KA, KB2>(A, B, i0, j0, 0, ra, rbk, amask, bmask);
+    store_tile<MODE, KA, KB2>(sm, 0, ra, rbk, amask, bmask);
     __syncthreads();
     for (int kt = 0; kt < ktiles; ++kt) {
       const int buf = kt & 1;
       const bool more = kt + 1 < ktiles;
-      if (more) load_tile<MODE>(A, B, i0, j0, kt + 1, ra, rbk, amask, bmask);
+      if (more) load_tile<MODE, KA, KB2>(A, B, i0, j0, kt + 1, ra, rbk, amask, bmask);
       compute<0, KMID>(sm, buf, acc);
-      if (more) store_tile<MODE>(sm, buf ^ 1, ra, rbk, amask, bmask);
+      if (more) store_tile<MODE, KA, KB2>(sm, buf ^ 1, ra, rbk, amask, bmask);
       compute<KMID, KB>(sm, buf, acc);
       __syncthreads();
     }
   }
 
-  // acc += A[i0 : i0 + BM, 0 : K] B[0 : K, j0 : j0 + BN].
+  // acc += A[i0 : i0 + BM, 0 : K] B[0 : K, j0 : j0 + BN] (A and B of kinds KA, KB2).
+  template <int KA = OK_PLAIN, int KB2 = OK_PLAIN>
   static __device__ __forceinline__ void product(Smem& sm, const Operand<T>& A, const Operand<T>& B, int i0,
                                                  int j0, int K, Acc& acc) {
     const int ktiles = (K + BK - 1) / BK;
@@ -307,11 +353,11 @@ struct TileLoop {
     const bool edge_vec = A.vec && B.vec && A.vrows > 0 && A.vcols > 0 && B.vrows > 0 && B.vcols > 0 &&
                           A.vcols % E == 0 && B.vcols % E == 0;
     if (interior)
-      main_loop<LOAD_FULL>(sm, A, B, i0, j0, ktiles, acc);
+      main_loop<LOAD_FULL, KA, KB2>(sm, A, B, i0, j0, ktiles, acc);
     else if (edge_vec)
-      main_loop<LOAD_EDGE_VEC>(sm, A, B, i0, j0, ktiles, acc);
+      main_loop<LOAD_EDGE_VEC, KA, KB2>(sm, A, B, i0, j0, ktiles, acc);
     else
-      main_loop<LOAD_MASKED>(sm, A, B, i0, j0, ktiles, acc);
+      main_loop<LOAD_MASKED, KA, KB2>(sm, A, B, i0, j0, ktiles, acc);
   }
 };
 

@@ -10,6 +10,11 @@
 // The products are ordered so that at most three tile accumulators are
 // live; every sum is rounded in the order of the separate U pass, so the
 // result has the same bits as the three-step path (products, then U).
+//
+// FUSED: the operands S1..S4 and T1..T4 are also formed in the tile loader
+// from the quadrants of the subproblem's A and B blocks (gemm_tile.h), so
+// the level runs with no temporaries at all: A and B are read, the four C
+// quadrants written, nothing else touches memory.
 #include <hip/hip_runtime.h>
 
 #include "desc.h"
@@ -23,7 +28,20 @@ namespace {
 
 using namespace gemm_detail;
 
-template <int BM, int BN, int BKC, int WGM, int WGN>
+// Operand kinds of P1 .. P7 when the sums are formed in the loader:
+// P1 = A11 B11, P2 = A12 B21, P3 = S4 B22, P4 = A22 T4, P5 = S1 T1,
+// P6 = S2 T2, P7 = S3 T3.
+__host__ __device__ constexpr int wino_akind(int p) {
+  return p == 2 ? OK_S4 : p == 4 ? OK_S1 : p == 5 ? OK_S2 : p == 6 ? OK_S3 : OK_PLAIN;
+}
+__host__ __device__ constexpr int wino_bkind(int p) {
+  return p == 3 ? OK_T4 : p == 4 ? OK_T1 : p == 5 ? OK_T2 : p == 6 ? OK_T3 : OK_PLAIN;
+}
+
+template <int P>
+using PIdx = std::integral_constant<int, P>;
+
+template <int BM, int BN, int BKC, int WGM, int WGN, bool FUSED>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_wino_kernel(KernelBases kb,
                                                                    const WinoLeafDesc* __restrict__ descs,
                                                                    int ndesc, int remap) {
@@ -39,9 +57,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_wino_kernel(KernelBases k
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
 
-  auto prod = [&](int p, Acc& acc) {
+  // a[p], b[p]: the operands of P(p+1); with FUSED, the parent block for a sum
+  auto prod = [&](auto ptag, Acc& acc) {
+    constexpr int p = decltype(ptag)::value;
+    constexpr int ka = FUSED ? wino_akind(p) : OK_PLAIN;
+    constexpr int kb2 = FUSED ? wino_bkind(p) : OK_PLAIN;
     TL::zero(acc);
-    TL::product(sm, operand<float>(kb, D.a[p]), operand<float>(kb, D.b[p]), i0, j0, D.k, acc);
+    const Operand<float> A =
+        ka == OK_PLAIN ? operand<float>(kb, D.a[p]) : operand_sum<float>(kb, D.a[p], D.m, D.k);
+    const Operand<float> B =
+        kb2 == OK_PLAIN ? operand<float>(kb, D.b[p]) : operand_sum<float>(kb, D.b[p], D.k, D.n);
+    TL::template product<ka, kb2>(sm, A, B, i0, j0, D.k, acc);
   };
   // v(a, b) gives the 16 values of MFMA tile (a, b) this lane stores; an
   // accumulating top level stores fma(beta, Cold, v) instead.
@@ -76,30 +102,35 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_wino_kernel(KernelBases k
   };
 
   Acc X, Y, Z;
-  prod(0, X);                                                    // P1
-  prod(1, Y);                                                    // P2
+  prod(PIdx<0>{}, X);                                            // P1
+  prod(PIdx<1>{}, Y);                                            // P2
   store(D.c[0], [&](int a, int b) { return X[a][b] + Y[a][b]; });  // C11 = U1
-  prod(5, Y);                                                    // P6
+  prod(PIdx<5>{}, Y);                                            // P6
   add_to(X, Y);                                                  // X = U2
-  prod(6, Y);                                                    // P7
+  prod(PIdx<6>{}, Y);                                            // P7
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
     for (int b = 0; b < FN; ++b) Y[a][b] = X[a][b] + Y[a][b];    // Y = U3
-  prod(4, Z);                                                    // P5
+  prod(PIdx<4>{}, Z);                                            // P5
   store(D.c[3], [&](int a, int b) { return Y[a][b] + Z[a][b]; });  // C22 = U7
   add_to(X, Z);                                                  // X = U4
-  prod(2, Z);                                                    // P3
+  prod(PIdx<2>{}, Z);                                            // P3
   add_to(X, Z);                                                  // X = U5
   store(D.c[1], [&](int a, int b) { return X[a][b]; });          // C12
-  prod(3, Z);                                                    // P4
+  prod(PIdx<3>{}, Z);                                            // P4
   store(D.c[2], [&](int a, int b) { return Y[a][b] - Z[a][b]; });  // C21 = U6
 }
 
 template <int BM, int BN, int BKC, int WGM, int WGN>
-hipError_t launch_cfg(const KernelBases& kb, const WinoLeafDesc* d, int n, int tiles, int remap, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_wino_kernel<BM, BN, BKC, WGM, WGN>), dim3(tiles), dim3(64 * WGM * WGN), 0, s, kb, d,
-                     n, remap);
+hipError_t launch_cfg(int fused, const KernelBases& kb, const WinoLeafDesc* d, int n, int tiles, int remap,
+                      hipStream_t s) {
+  if (fused)
+    hipLaunchKernelGGL((gemm_wino_kernel<BM, BN, BKC, WGM, WGN, true>), dim3(tiles), dim3(64 * WGM * WGN), 0, s,
+                       kb, d, n, remap);
+  else
+    hipLaunchKernelGGL((gemm_wino_kernel<BM, BN, BKC, WGM, WGN, false>), dim3(tiles), dim3(64 * WGM * WGN), 0, s,
+                       kb, d, n, remap);
   return hipGetLastError();
 }
 
@@ -112,13 +143,13 @@ GemmCfg gemm_wino_cfg(int cfg) {
   }
 }
 
-hipError_t launch_gemm_wino(int cfg, const KernelBases& kb, const WinoLeafDesc* d, int n, int tiles, int remap,
-                            hipStream_t s) {
+hipError_t launch_gemm_wino(int cfg, int fused, const KernelBases& kb, const WinoLeafDesc* d, int n, int tiles,
+                            int remap, hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
   switch (cfg) {
-    case 1: return launch_cfg<128, 128, 8, 4, 2>(kb, d, n, tiles, remap, s);
-    case 2: return launch_cfg<64, 128, 8, 2, 2>(kb, d, n, tiles, remap, s);
-    default: return launch_cfg<128, 128, 8, 2, 2>(kb, d, n, tiles, remap, s);
+    case 1: return launch_cfg<128, 128, 8, 4, 2>(fused, kb, d, n, tiles, remap, s);
+    case 2: return launch_cfg<64, 128, 8, 2, 2>(fused, kb, d, n, tiles, remap, s);
+    default: return launch_cfg<128, 128, 8, 2, 2>(fused, kb, d, n, tiles, remap, s);
   }
 }
 

@@ -42,7 +42,7 @@ hipError_t launch_gemm_fused(int cfg, const KernelBases& kb, const GemmDesc* d, 
 // combinations per output tile (WinoLeafDesc); cfg as gemm_wino_cfg.
 constexpr int kNumWinoCfg = 3;
 GemmCfg gemm_wino_cfg(int cfg);
-hipError_t launch_gemm_wino(int cfg, const KernelBases& kb, const WinoLeafDesc* d, int n, int tiles, int remap,
+hipError_t launch_gemm_wino(int cfg, int fused, const KernelBases& kb, const WinoLeafDesc* d, int n, int tiles, int remap,
                             hipStream_t s);
 // remap: 1 = XCD-contiguous tile order (launches of equal problems),
 // 0 = hardware round-robin (unequal problems, sorted longest first).

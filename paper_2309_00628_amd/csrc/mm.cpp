@@ -192,6 +192,7 @@ struct Builder {
   std::vector<GemmDesc> gm;
   std::vector<char> gm_fusable;  // descriptor satisfies the fused loader's preconditions
   std::vector<WinoLeafDesc> wl;  // last-level subproblems of the current launch
+  bool wl_fused = false;         // ... whose S/T sums are formed in the loader
   std::vector<EwPart> sp;        // split parts of the current launch
   int sp_grid = 0;
   bool gm_spl = false;           // the pending GEMM descriptors read SPL operands
@@ -441,11 +442,13 @@ struct Builder {
     txt << "JOIN\n";
   }
 
-  // One last-level Winograd subproblem C = A B with its S/T sums already
-  // formed: operands of P1 .. P7 and the output quadrants.
+  // One last-level Winograd subproblem C = A B: operands of P1 .. P7 (with
+  // fused, the parent blocks A, B in place of S1..S4, T1..T4, whose sums the
+  // loader forms) and the output quadrants.
   void wino(const MView (&a)[7], const MView (&bop)[7], const MView (&c)[4], int64_t m, int64_t n, int64_t k,
-            bool acc = false) {
-    if (!ew.empty() || !gm.empty()) flush();
+            bool acc = false, bool fused = false) {
+    if (!ew.empty() || !gm.empty() || (!wl.empty() && wl_fused != fused)) flush();
+    wl_fused = fused;
     WinoLeafDesc d;
     std::memset(&d, 0, sizeof d);
     for (int i = 0; i < 7; ++i) {
@@ -520,13 +523,14 @@ struct Builder {
       d.tiles_n = (int32_t)ceil_div(d.n, gc.bn);
       d.tile_start = grid;
       grid += d.tiles_m * d.tiles_n;
-      txt << "WINO " << d.m << " " << d.n << " " << d.k << " " << d.acc << " |";
+      txt << "WINO " << d.m << " " << d.n << " " << d.k << " " << d.acc << " " << (wl_fused ? 1 : 0) << " |";
       for (int i = 0; i < 7; ++i) txt << " " << vs(d.a[i]) << " " << vs(d.b[i]);
       txt << " |";
       for (int i = 0; i < 4; ++i) txt << " " << vs(d.c[i]);
       txt << "\n";
     }
-    OpRec r{OP_WINO, kernel_dtype(P.dtype), P.table.size(), (int)wl.size(), grid, cfg, 1, 0, cur_stream};
+    OpRec r{OP_WINO, kernel_dtype(P.dtype), P.table.size(), (int)wl.size(), grid, cfg, 1, wl_fused ? 1 : 0,
+            cur_stream};
     const size_t bytes = wl.size() * sizeof(WinoLeafDesc);
     P.table.resize(round_up(P.table.size() + bytes, 256));
     std::memcpy(P.table.data() + r.off, wl.data(), bytes);
@@ -534,6 +538,7 @@ struct Builder {
     txt << "LAUNCH WINO " << wl.size() << " " << grid << " " << cfg << (cur_stream ? " aux" : "") << "\n";
     wl.clear();
     P.wino = true;
+    if (wl_fused) P.fused = true;
   }
 
   void emit_gemm(std::vector<GemmDesc>& group, bool fused) {
@@ -868,6 +873,7 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
     MView a[7], b[7], c[4];
     int64_t m, n, k;
     bool acc;
+    bool fused;
   };
   std::vector<WinoSub> wl_pending;  // last-level subproblems (leaf_u)
   // The S/T passes run on the auxiliary stream while the leaf products whose
@@ -883,6 +889,10 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
     std::vector<Sub> next;
     next.reserve(subs.size() * 7);
     std::vector<std::array<MView, 11>> uargs;
+    // fused last level with MM_PLAN_FUSE: no temporaries at all (every
+    // subproblem must meet the fused loader's preconditions)
+    bool leaf_fused = leaf_u && l == L - 1 && b.P.fuse;
+    for (const Sub& s : subs) leaf_fused = leaf_fused && can_fuse(b, s);
     for (const Sub& s : subs) {
       const int64_t hm = s.A.rows / 2, hk = s.A.cols / 2, hn = s.B.cols / 2;
       if (strassen) {
@@ -907,6 +917,18 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
                          b.quad(s.C, 0, 1), b.quad(s.C, 1, 0), b.quad(s.C, 1, 1)});
         continue;
       }
+      if (leaf_fused) {
+        // products, operand sums and U combinations of the last level in one kernel
+        const MView C11 = b.quad(s.C, 0, 0), C12 = b.quad(s.C, 0, 1), C21 = b.quad(s.C, 1, 0),
+                    C22 = b.quad(s.C, 1, 1);
+        wl_pending.push_back({{b.quad(s.A, 0, 0), b.quad(s.A, 0, 1), s.A, b.quad(s.A, 1, 1), s.A, s.A, s.A},
+                              {b.quad(s.B, 0, 0), b.quad(s.B, 1, 0), b.quad(s.B, 1, 1), s.B, s.B, s.B, s.B},
+                              {C11, C12, C21, C22},
+                              hm, hn, hk, l == 0 && b.P.accumulate, true});
+        if (s.A.base == MB_A || s.A.base == MB_B || s.B.base == MB_A || s.B.base == MB_B)
+          b.P.fused_reads_ab = true;
+        continue;
+      }
       if (l == L - 1 && leaf_u) {
         // products and U combinations of the last level in one kernel
         const MView A11 = b.quad(s.A, 0, 0), A12 = b.quad(s.A, 0, 1), A21 = b.quad(s.A, 1, 0),
@@ -921,7 +943,7 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
         wl_pending.push_back({{A11, A12, S[3], A22, S[0], S[1], S[2]},
                               {B11, B21, B22, T[3], T[0], T[1], T[2]},
                               {b.quad(s.C, 0, 0), b.quad(s.C, 0, 1), b.quad(s.C, 1, 0), b.quad(s.C, 1, 1)},
-                              hm, hn, hk, l == 0 && b.P.accumulate});
+                              hm, hn, hk, l == 0 && b.P.accumulate, false});
         continue;
       }
       if (l == L - 1 && b.P.spl) {  // (never with Strassen: handled above)
@@ -1011,7 +1033,7 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
   }
   b.flush();
   b.cur_stream = 0;
-  for (const WinoSub& w : wl_pending) b.wino(w.a, w.b, w.c, w.m, w.n, w.k, w.acc);
+  for (const WinoSub& w : wl_pending) b.wino(w.a, w.b, w.c, w.m, w.n, w.k, w.acc, w.fused);
   b.flush();
   auto plain = [](const Sub& s) {
     return s.A.base != MB_WS && s.B.base != MB_WS && s.akind == OK_PLAIN && s.bkind == OK_PLAIN;
@@ -1328,7 +1350,7 @@ int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEven
       if (op.type == OP_EW)
         e = launch_ew(op.kdtype, kb, (const EwPart*)d, op.count, op.grid, st);
       else if (op.type == OP_WINO)
-        e = launch_gemm_wino(op.cfg, kb, (const WinoLeafDesc*)d, op.count, op.grid, op.remap, st);
+        e = launch_gemm_wino(op.cfg, op.fused, kb, (const WinoLeafDesc*)d, op.count, op.grid, op.remap, st);
       else if (op.type == OP_SPLIT)
         e = launch_split(kb, (const EwPart*)d, op.count, op.grid, st);
       else
@@ -1459,7 +1481,6 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   // grouped schedule's last level; other dtypes and schedules ignore it
   P->leaf_u = (flags & MM_PLAN_LEAF_U) != 0 && dtype == MM_F32 && sched == MM_SCHED_GROUPED &&
               algo == MM_ALGO_WINOGRAD;
-  if (P->leaf_u && P->fuse) return fail(MM_E_INVALID, "MM_PLAN_FUSE and MM_PLAN_LEAF_U exclude each other");
   // on request, split-bfloat16 leaves of the grouped schedule and of the
   // plain product read operands split once by a split pass
   const int rs = resolve_sched(algo, sched);

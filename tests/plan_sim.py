@@ -96,11 +96,11 @@ def parse(text):
             outs = [_view(t) for t in rest[1].split()]
             cur.append(("SPLIT", dict(kind=kind, rows=rows, cols=cols, mode=mode, ins=ins, outs=outs)))
         elif h[0] == "WINO":
-            m, n, k, acc = map(int, h[1:])
+            m, n, k, acc, fused = map(int, h[1:])
             ops = [_view(t) for t in rest[0].split()]
             cs = [_view(t) for t in rest[1].split()]
             assert len(ops) == 14 and len(cs) == 4
-            cur.append(("WINO", dict(m=m, n=n, k=k, acc=acc, a=ops[0::2], b=ops[1::2], c=cs)))
+            cur.append(("WINO", dict(m=m, n=n, k=k, acc=acc, fused=fused, a=ops[0::2], b=ops[1::2], c=cs)))
         elif h[0] == "EW":
             kind, rows, cols, m0, m1 = map(int, h[1:])
             ins = [_view(t) for t in rest[0].split()] if rest[0] else []
@@ -415,7 +415,10 @@ def run(text, bufs, hazards=True, beta=1):
                     y = [t.T for t in y]
                 results.append([("spl", v, t) for v, t in zip(it["outs"], y)])
             elif kind == "WINO":
-                p = [mem.read(a) @ mem.read(b) for a, b in zip(it["a"], it["b"])]
+                # fused: P3..P7 read the parent blocks and form S4, S1..S3 / T4, T1..T3
+                ak, bk = ((0, 0, 4, 0, 1, 2, 3), (0, 0, 0, 8, 5, 6, 7)) if it["fused"] else ((0,) * 7, (0,) * 7)
+                p = [operand(mem.read(a), ka) @ operand(mem.read(b), kb)
+                     for a, b, ka, kb in zip(it["a"], it["b"], ak, bk)]
                 u2 = p[0] + p[5]
                 u3 = u2 + p[6]
                 u4 = u2 + p[4]

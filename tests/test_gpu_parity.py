@@ -413,6 +413,44 @@ def test_leaf_u_bitwise_equal_to_separate_u_pass(api, naive, m, n, k, levels):
     assert rel_fro(ref[torch.from_numpy(rows).cuda()].cpu().numpy(), naive.gemm_rows(A, B, rows)) < 1e-5
 
 
+@pytest.mark.parametrize("m,n,k,levels", [(1024, 1024, 1024, 1), (2048, 2048, 2048, 2), (3000, 3000, 3000, 1),
+                                          (640, 384, 1152, 3), (128, 96, 64, 1)])
+def test_zero_temporary_level_bitwise(api, naive, m, n, k, levels):
+    # LEAF_U with FUSE: S/T formed in the loader of the fused last level,
+    # bitwise equal to the separate passes for every tile configuration
+    A, B = inputs.pair("uniform", m, n, k, 51, np.float32)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    print(f"zero-temp {m}x{n}x{k} L={levels}", flush=True)
+    ref = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, leaf_u=False)
+    for tile in (None, 0, 1, 2):
+        C = torch.full((m, n), float("nan"), device="cuda")
+        api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, leaf_u=True, fuse=True,
+               tile=tile, out=C)
+        torch.cuda.synchronize()
+        p = api.get_plan("winograd", "grouped", m, n, k, 1, levels, "f32", k, n, n, False, At.device, tile,
+                         fuse=True, leaf_u=True)
+        assert p.info["leaf_u"] == 1 and p.info["fused"] == 1
+        assert torch.equal(C, ref), tile
+    rows = np.arange(0, m, max(1, m // 16))
+    assert rel_fro(ref[torch.from_numpy(rows).cuda()].cpu().numpy(), naive.gemm_rows(A, B, rows)) < 1e-5
+    # accumulating, and through an unaligned A (the plan then runs its unfused twin)
+    C0 = torch.from_numpy(inputs.uniform((m, n), 52, dtype=np.float32)).cuda()
+    want = ref + 0.5 * C0
+    C = C0.clone()
+    api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, leaf_u=True, fuse=True, out=C,
+           beta=0.5)
+    torch.cuda.synchronize()
+    assert torch.equal(C, api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels,
+                                 leaf_u=False, out=C0.clone(), beta=0.5))
+    assert rel_fro(C.cpu().numpy(), want.cpu().numpy().astype(np.float64)) < 1e-6
+    Abuf = torch.empty(m * k + 1, device="cuda")
+    Au = Abuf[1:].view(m, k)
+    Au.copy_(At)
+    C = api.mm(Au, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, leaf_u=True, fuse=True)
+    torch.cuda.synchronize()
+    assert torch.equal(C, ref)
+
+
 def test_leaf_u_integer_exact_and_strided(api, naive):
     # integer inputs: exact; operands inside larger row-major buffers
     m, n, k = 384, 320, 256

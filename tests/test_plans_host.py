@@ -324,13 +324,44 @@ def test_leaf_u_plan_shape(lib):
         assert info["ws_bytes"] < ref["ws_bytes"]
         assert sum(l.startswith("WINO") for l in text.splitlines()) == 7 ** (lv - 1)
         assert "GEMM" not in text
-    # other dtypes / schedules ignore the flag; it excludes the fused loader
+    # other dtypes / schedules ignore the flag
     _, info = L.describe("winograd", "grouped", 512, 512, 512, cutoff=64, dtype="f64", leaf_u=True)
     assert info["leaf_u"] == 0
     _, info = L.describe("winograd", "two_temp", 512, 512, 512, cutoff=64, leaf_u=True)
     assert info["leaf_u"] == 0
-    with pytest.raises(L.MMError):
-        L.describe("winograd", "grouped", 512, 512, 512, cutoff=1, levels=1, leaf_u=True, fuse=True)
+
+
+def test_zero_temporary_last_level(lib):
+    # MM_PLAN_LEAF_U with MM_PLAN_FUSE: the last level reads A and B blocks,
+    # forms S/T in the loader and writes C: one launch and no workspace at one
+    # level (the plan's workspace size still covers the unfused plan it runs
+    # when A or B is not 16-byte aligned); at L levels the last level's S/T
+    # temporaries and pass disappear
+    text, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=1, leaf_u=True, fuse=True)
+    assert info["launches"] == 1 and info["fused"] == 1 and info["leaf_u"] == 1
+    assert [l.split()[1] for l in text.splitlines() if l.startswith("LAUNCH")] == ["WINO"]
+    assert not any(tok.startswith(f"{plan_sim.MB_WS}:") for tok in text.split())
+    for lv in (2, 3):
+        text, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=lv, leaf_u=True,
+                                fuse=True)
+        assert info["launches"] == 2 * lv - 1 and info["fused"] == 1
+        assert sum(l.startswith("LAUNCH EW") for l in text.splitlines()) == 2 * (lv - 1)
+    # a last level with padding keeps the S/T pass
+    _, info = L.describe("winograd", "grouped", 1000, 777, 555, cutoff=1, levels=2, leaf_u=True, fuse=True)
+    assert info["fused"] == 0 and info["leaf_u"] == 1
+
+
+@pytest.mark.parametrize("m,n,k,levels", [(16, 16, 16, 1), (64, 64, 64, 2), (96, 40, 56, 2), (256, 128, 192, 3),
+                                          (1000, 777, 555, 2), (128, 64, 96, 1)])
+def test_zero_temporary_plan_is_exact(lib, m, n, k, levels):
+    A = inputs.integers((m, k), 29, dtype=np.int64)
+    B = inputs.integers((k, n), 30, dtype=np.int64)
+    text, info = L.describe("winograd", "grouped", m, n, k, cutoff=1, levels=levels, dtype="f32", leaf_u=True,
+                            fuse=True)
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    C = np.full(m * n, -(10**9), dtype=np.int64)
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
+    assert np.array_equal(C.reshape(m, n), A @ B)
 
 
 @pytest.mark.parametrize("m,n,k,levels", [(16, 16, 16, 1), (64, 64, 64, 2), (96, 40, 56, 2), (200, 136, 72, 3),
