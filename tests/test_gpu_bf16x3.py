@@ -55,7 +55,7 @@ def test_bf16x3_integer_exact(api, naive):
     A, B = inputs.pair("int", 256, 256, 256, 2, np.float32)
     ref = naive.gemm(A, B)
     for algo, sched, lv in [("naive", "auto", 0), ("winograd", "grouped", 2), ("winograd", "two_temp", 1),
-                            ("strassen", "dfs3", 1)]:
+                            ("strassen", "dfs3", 1), ("strassen", "grouped", 2)]:
         got = run(api, A, B, algo=algo, sched=sched, cutoff=1, levels=lv)
         assert np.array_equal(got.astype(np.float64), ref), (algo, sched, lv)
 
@@ -64,9 +64,9 @@ def test_bf16x3_integer_exact(api, naive):
 def test_winograd_bf16x3_gauss_rowscaled(api, naive, n, levels):
     A, B = inputs.pair("gauss_rowscaled", n, n, n, 3, np.float32)
     ref = naive.gemm(A, B)
-    for sched in ("grouped", "two_temp"):
-        err = rel_fro(run(api, A, B, algo="winograd", sched=sched, cutoff=1, levels=levels), ref)
-        print(f"bf16x3 winograd {sched} n={n} L={levels}: {err:.3e}", flush=True)
+    for algo, sched in (("winograd", "grouped"), ("winograd", "two_temp"), ("strassen", "grouped")):
+        err = rel_fro(run(api, A, B, algo=algo, sched=sched, cutoff=1, levels=levels), ref)
+        print(f"bf16x3 {algo} {sched} n={n} L={levels}: {err:.3e}", flush=True)
         assert err < 1e-5
 
 
