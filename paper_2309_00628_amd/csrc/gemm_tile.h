@@ -126,10 +126,39 @@ struct TileLoop {
   static_assert(BKC % M::KG == 0 && BKC <= BKC_MAX && 16 % BKC == 0, "k chunks");
   static_assert(NA * E <= 64 && NB * E * E <= 64, "one validity bit per staged element");
 
+  // A is staged row by row (BKC chunks per row, see a_idx); B as BKC planes
+  // of BN column chunks (swz_b).
   struct Smem {
-    chunk_t As[2][BKC][BM];
+    chunk_t As[2][BM * BKC];
     chunk_t Bs[2][BKC][BN];
   };
+
+  // LDS slot of chunk kc of tile row `row`: the chunks of a row are contiguous
+  // and their order is XOR-ed with bits of the row above log2(16 / BKC), so
+  // 16 consecutive rows at one chunk position (a fragment read) and 16
+  // consecutive chunks of the stores both fall in 16 distinct bank groups.
+  static __device__ __forceinline__ int a_idx(int row, int kc) {
+    return row * BKC + (kc ^ ((row / (16 / BKC)) & (BKC - 1)));
+  }
+
+  // Interior stages of a plain A load straight into LDS (global_load_lds,
+  // 16 bytes per lane, 64 consecutive slots per wave instruction), with no
+  // register staging or LDS stores; the lane that fills slot p loads the
+  // chunk that a_idx places there.
+  static constexpr bool DMA_A = NCH_A % NT == 0;
+  static __device__ __forceinline__ void dma_a(Smem& sm, int buf, const Operand<T>& A, int i0, int kt) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int base = (wave * NA + i) * 64;
+      const int p = base + lane;
+      const int row = p / BKC, slot = p % BKC;
+      const int kc = slot ^ ((row / (16 / BKC)) & (BKC - 1));
+      const T* src = A.p + (int64_t)(i0 + row) * A.ld + k0 + kc * E;
+      __builtin_amdgcn_global_load_lds(src, &sm.As[buf][base], 16, 0, 0);
+    }
+  }
 
   typedef acc_t Acc[FM][FN];
 
@@ -161,10 +190,12 @@ struct TileLoop {
                                                    uint64_t& amask, uint64_t& bmask) {
     constexpr int QA = kind_quads(KA), NQA = popc4(QA);
     constexpr int QB = kind_quads(KB2), NQB = popc4(QB);
+    constexpr bool A_IN_REGS = !(MODE == LOAD_FULL && KA == OK_PLAIN && DMA_A);
     const int tid = threadIdx.x;
     const int k0 = kt * BK;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
+      if (!A_IN_REGS) break;
       const int q = tid + NT * i;
       if (NCH_A % NT != 0 && q >= NCH_A) break;
       const int row = q / BKC, kc = q % BKC;
@@ -236,9 +267,11 @@ struct TileLoop {
                                                     uint64_t amask, uint64_t bmask) {
     constexpr int QA = kind_quads(KA), NQA = popc4(QA);
     constexpr int QB = kind_quads(KB2), NQB = popc4(QB);
+    constexpr bool A_IN_REGS = !(MODE == LOAD_FULL && KA == OK_PLAIN && DMA_A);
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
+      if (!A_IN_REGS) break;
       const int q = tid + NT * i;
       if (NCH_A % NT != 0 && q >= NCH_A) break;
       const int row = q / BKC, kc = q % BKC;
@@ -257,7 +290,7 @@ struct TileLoop {
         for (int e = 0; e < E; ++e)
           if (!((amask >> (i * E + e)) & 1)) v[e] = T(0);
       }
-      sm.As[buf][kc][swz_a<BKC>(row, kc)] = v;
+      sm.As[buf][a_idx(row, kc)] = v;
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -294,7 +327,7 @@ struct TileLoop {
     auto read_frags = [&](int kb2, chunk_t (&xa)[FM], chunk_t (&xb)[FN]) {
       const int plane = kb2 * M::KG + g;
 #pragma unroll
-      for (int a = 0; a < FM; ++a) xa[a] = sm.As[buf][plane][swz_a<BKC>(wm * WM + a * TM + t, plane)];
+      for (int a = 0; a < FM; ++a) xa[a] = sm.As[buf][a_idx(wm * WM + a * TM + t, plane)];
 #pragma unroll
       for (int b = 0; b < FN; ++b) xb[b] = sm.Bs[buf][plane][swz_b<E>(wn * WN + b * TM + t)];
     };
@@ -325,16 +358,23 @@ struct TileLoop {
     chunk_t ra[NA][popc4(kind_quads(KA))];
     chunk_t rbk[NB][E][popc4(kind_quads(KB2))];  // E rows (k) of E columns, per quadrant
     uint64_t amask = 0, bmask = 0;
+    constexpr bool DMA = MODE == LOAD_FULL && KA == OK_PLAIN && DMA_A;
+    if (DMA) dma_a(sm, 0, A, i0, 0);
     load_tile<MODE, KA, KB2>(A, B, i0, j0, 0, ra, rbk, amask, bmask);
     store_tile<MODE, KA, KB2>(sm, 0, ra, rbk, amask, bmask);
+    if (DMA) __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of this wave's direct loads are done
     __syncthreads();
     for (int kt = 0; kt < ktiles; ++kt) {
       const int buf = kt & 1;
       const bool more = kt + 1 < ktiles;
-      if (more) load_tile<MODE, KA, KB2>(A, B, i0, j0, kt + 1, ra, rbk, amask, bmask);
+      if (more) {
+        if (DMA) dma_a(sm, buf ^ 1, A, i0, kt + 1);
+        load_tile<MODE, KA, KB2>(A, B, i0, j0, kt + 1, ra, rbk, amask, bmask);
+      }
       compute<0, KMID>(sm, buf, acc);
       if (more) store_tile<MODE, KA, KB2>(sm, buf ^ 1, ra, rbk, amask, bmask);
       compute<KMID, KB>(sm, buf, acc);
+      if (DMA) __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
   }
