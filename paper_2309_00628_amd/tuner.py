@@ -129,7 +129,13 @@ def candidates(dtype, L_, tiles=None):
     return out
 
 
-def tune(m, n, k, dtype="f32", max_levels=3, reps=5, warmup=2, tiles=None, save=True, verbose=False, rounds=3):
+# An option (overlap, fused last level) is chosen only when it beats the
+# plans without options by more than this fraction: differences smaller than
+# the run-to-run spread of the timings are not evidence.
+OPTION_MARGIN = 0.01
+
+
+def tune(m, n, k, dtype="f32", max_levels=3, reps=5, warmup=2, tiles=None, save=True, verbose=False, rounds=5):
     """Measure the candidates for this size class and cache the fastest."""
     import numpy as np
     import torch
@@ -175,7 +181,10 @@ def tune(m, n, k, dtype="f32", max_levels=3, reps=5, warmup=2, tiles=None, save=
             L_, tile, ov, lu = key
             print(f"  {dtype} {m}x{n}x{k} L={L_} tile={tile} overlap={int(ov)} leaf_u={int(lu)}: "
                   f"{t:.3f} ms {2.0 * m * n * k / t / 1e9:.1f} TFLOP/s", flush=True)
-    t, L_, tile, ov, lu = min(results, key=lambda r: r[0])
+    def score(r):
+        return r[0] * (1.0 + OPTION_MARGIN if (r[3] or r[4]) else 1.0)
+
+    t, L_, tile, ov, lu = min(results, key=score)
     leaf = min(m, n, k) >> L_
     # the cutoff that stops the recursion after L_ halvings: the leaf order
     entry = {"levels": L_, "tile": tile, "overlap": ov, "leaf_u": lu, "cutoff": leaf if L_ else min(m, n, k),
@@ -191,7 +200,7 @@ def tune(m, n, k, dtype="f32", max_levels=3, reps=5, warmup=2, tiles=None, save=
                                "tflops": round(2.0 * m * n * k / t0 / 1e9, 2)}
     rec = [r for r in results if r[1] > 0]
     if rec:
-        t2, L2, tile2, ov2, lu2 = min(rec, key=lambda r: r[0])
+        t2, L2, tile2, ov2, lu2 = min(rec, key=score)
         entry["best_recursive"] = {"levels": L2, "tile": tile2, "overlap": ov2, "leaf_u": lu2,
                                    "ms": round(t2, 4), "tflops": round(2.0 * m * n * k / t2 / 1e9, 2)}
     arch = _arch()
