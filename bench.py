@@ -65,28 +65,38 @@ def _events(torch, n, stream):
 
 
 def time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup):
-    """Run warm-up steps, then exactly ``steps`` timed steps with events
-    before and after every launch, recorded on the stream the launch runs on.
+    """Run warm-up steps, then exactly ``steps`` timed steps with one event
+    before and one after each step (the wall time and per-step latencies),
+    then ``steps`` more with events before and after every launch, recorded
+    on the stream the launch runs on (the per-launch durations).  An event
+    between two launches of a step delays the second one a little, so the
+    step time is taken without them.
     Returns (wall ms per step, per-step ms list, per-launch ms lists, kinds)."""
     import ctypes
     lib = L.load()
     s = torch.cuda.current_stream()
     nops = plan.info["launches"]
     nev = 2 * nops
-    evsets = [_events(torch, nev, s) for _ in range(steps)]
-    ptrs = [(ctypes.c_void_p * nev)(*[e.cuda_event for e in evs]) for evs in evsets]
     wsp, wsb = (ws.data_ptr(), ws.numel()) if ws is not None else (None, 0)
+    args = (plan._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), wsp, wsb, s.cuda_stream)
     for _ in range(warmup):
-        L.check(lib.mm_plan_execute(plan._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), wsp, wsb,
-                                    s.cuda_stream))
+        L.check(lib.mm_plan_execute(*args))
+    steps_ev = [_events(torch, 2, s) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        L.check(lib.mm_plan_execute_timed(plan._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), wsp,
-                                          wsb, s.cuda_stream, ptrs[i], nev))
+        steps_ev[i][0].record(s)
+        L.check(lib.mm_plan_execute(*args))
+        steps_ev[i][1].record(s)
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3 / steps
-    step_ms = [evs[0].elapsed_time(evs[-1]) for evs in evsets]
+    step_ms = [a.elapsed_time(b) for a, b in steps_ev]
+    evsets = [_events(torch, nev, s) for _ in range(steps)]
+    ptrs = [(ctypes.c_void_p * nev)(*[e.cuda_event for e in evs]) for evs in evsets]
+    torch.cuda.synchronize()
+    for i in range(steps):
+        L.check(lib.mm_plan_execute_timed(*args, ptrs[i], nev))
+    torch.cuda.synchronize()
     per_op = [[evs[2 * j].elapsed_time(evs[2 * j + 1]) for evs in evsets] for j in range(nops)]
     kinds = [lib.mm_plan_op_kind(plan._ptr, j) for j in range(nops)]
     return wall_ms, step_ms, per_op, kinds
