@@ -205,10 +205,12 @@ def measured_traffic(kernel, grid):
     return None
 
 
-def gemm_roofline(res, n):
+def gemm_roofline(res, n, traffic=True):
     """Roofline of the dominant kernel: the leaf-product launch (plain GEMM
     group or fused last Winograd level) with the most flops, on the caller's
-    stream (not sharing the GPU with an overlapped S/T pass)."""
+    stream (not sharing the GPU with an overlapped S/T pass).  ``traffic``:
+    look up its measured HBM bytes (the counter summary covers the headline
+    Winograd plan only)."""
     launches = plan_launches(res["plan"], 4)
     best, kind, grid = None, 1, None
     for lau, d, k in zip(launches, res["per_op"], res["kinds"]):
@@ -219,7 +221,8 @@ def gemm_roofline(res, n):
     achieved = flops / (avg_ms * 1e-3) / 1e12
     kname = "gemm_wino_kernel" if kind == 4 else "gemm_kernel<float"
     return dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=measured_traffic(kname, grid),
+                frac=round(achieved / PEAK_FP32_TFLOPS, 4),
+                traffic=measured_traffic(kname, grid) if traffic else None,
                 kernel=("gemm_wino_kernel (last level: products + U in registers)" if kind == 4
                         else "gemm_kernel<float> (grouped leaf products)"),
                 flops_per_launch=flops, avg_launch_ms=round(avg_ms, 4), grid=grid)
@@ -541,7 +544,7 @@ def main():
                              "p50_ms": round(strs["p50"], 4), "p99_ms": round(strs["p99"], 4)},
         "vendor_hipblaslt_tflops": round(vendor_tflops, 3),
         "roofline": gemm_roofline(win, n),
-        "plain_gemm_roofline": gemm_roofline(plain, n),
+        "plain_gemm_roofline": gemm_roofline(plain, n, traffic=False),
         "addition_kernels": ew_bandwidth(win, n),
     }
 
