@@ -193,6 +193,15 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                                  fma(beta, Cold, x)); the depth-first schedules form A B in a
                                  workspace block of m x n (they use C as scratch) and add it
                                  in one more element-wise pass.  Not for batched plans. */
+#define MM_PLAN_TRANS_B 128u /* Strassen-Winograd, grouped schedule, float32: the last level's
+                               T pass writes T1..T4 and the B quadrants that are leaf operands
+                               (B11, B21, B22) transposed, in one transposing pass, so the
+                               leaf products stage B in 16-byte chunks along k exactly as they
+                               stage A (straight from memory into LDS in interior tiles).
+                               Results are bitwise the same; costs three more quarter-size
+                               blocks of workspace and writes per last-level block.  The last
+                               level's fused forms (MM_PLAN_LEAF_U, MM_PLAN_SPLIT_PASS) take
+                               precedence; it takes precedence over MM_PLAN_FUSE. */
 #define MM_PLAN_PEEL 64u /* grouped schedule: instead of reading A, B and C as if zero-padded to
                            multiples of 2^L g, run the recursion on the largest leading block
                            whose sides are such multiples (pm x pk times pk x pn) and cover
@@ -244,8 +253,8 @@ int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, s
 /* Kind of launch i of a plan: 0 element-wise block operations, 1 MFMA GEMM
  * group (leaf products), 2 fork to / 3 join of the plan's auxiliary stream,
  * 4 fused last Winograd level (MM_PLAN_LEAF_U), 5 split pass of the
- * split-bfloat16 leaves; plus 8 when the launch runs on the auxiliary
- * stream; -1 if i is out of range. */
+ * split-bfloat16 leaves, 6 transposing pass (MM_PLAN_TRANS_B); plus 8 when
+ * the launch runs on the auxiliary stream; -1 if i is out of range. */
 int mm_plan_op_kind(mm_plan_t plan, int i);
 
 /* Plan facts: info[0] workspace bytes, [1] levels L, [2..4] padded m, n, k,

@@ -49,7 +49,7 @@ class Plan:
 
     def __init__(self, algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None,
                  ldc=None, graph=False, device=None, tile=None, fuse=False, overlap=False, leaf_u=False,
-                 split_pass=False, accumulate=False, peel=False):
+                 split_pass=False, accumulate=False, peel=False, trans_b=False):
         lib = L.load()
         self.algo, self.sched, self.dtype = algo, sched, dtype
         self.m, self.n, self.k = m, n, k
@@ -68,7 +68,8 @@ class Plan:
                                        (L.MM_PLAN_LEAF_U if leaf_u else 0) |
                                        (L.MM_PLAN_SPLIT_PASS if split_pass else 0) |
                                        (L.MM_PLAN_ACCUMULATE if accumulate else 0) |
-                                       (L.MM_PLAN_PEEL if peel else 0),
+                                       (L.MM_PLAN_PEEL if peel else 0) |
+                                       (L.MM_PLAN_TRANS_B if trans_b else 0),
                                        ctypes.byref(self._ptr)))
         self.accumulate = accumulate
         info = (ctypes.c_int64 * L.NINFO)()
@@ -128,21 +129,22 @@ def workspace(nbytes, device, stream):
 
 
 def get_plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile=None,
-             fuse=False, overlap=False, leaf_u=False, split_pass=False, accumulate=False, peel=False):
+             fuse=False, overlap=False, leaf_u=False, split_pass=False, accumulate=False, peel=False,
+             trans_b=False):
     key = (str(device), algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, tile, fuse,
-           overlap, leaf_u, split_pass, accumulate, peel)
+           overlap, leaf_u, split_pass, accumulate, peel, trans_b)
     with _plans_lock:
         p = _plans.get(key)
         if p is None:
             p = Plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile, fuse,
-                     overlap, leaf_u, split_pass, accumulate, peel)
+                     overlap, leaf_u, split_pass, accumulate, peel, trans_b)
             _plans[key] = p
     return p
 
 
 def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None, out=None,
        graph=False, stream=None, clobber_inputs=False, tile=None, fuse=False, overlap=None, leaf_u=None,
-       split_pass=False, beta=None, peel=False):
+       split_pass=False, beta=None, peel=False, trans_b=None):
     """C = A @ B on the GPU by ``algo`` in {"naive", "strassen", "winograd"}.
 
     ``cutoff`` / ``levels`` control the recursion as in mm.h; when both are
@@ -157,7 +159,8 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
     ``split_pass``: MM_PLAN_SPLIT_PASS.  ``beta`` (needs ``out``): the
     accumulating form out = A @ B + beta * out (MM_PLAN_ACCUMULATE).  ``peel``:
     MM_PLAN_PEEL (grouped schedule: thin products for ragged edges instead of
-    zero padding).  The in-place
+    zero padding).  ``trans_b``: MM_PLAN_TRANS_B (None: the autotuner's choice
+    when it picks the recursion, else off).  The in-place
     schedule overwrites its operands, so unless ``clobber_inputs`` is set the
     wrapper hands it copies.
     """
@@ -196,12 +199,14 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
                 overlap = bool(ch.get("overlap", False))
             if leaf_u is None:
                 leaf_u = bool(ch.get("leaf_u", False))
+            if trans_b is None:
+                trans_b = bool(ch.get("trans_b", False))
     elif cutoff is None:
         cutoff = 1
     elif levels is None:
         levels = -1
     p = get_plan(algo, sched, m, n, k, cutoff, levels, dt, lda, ldb, ldc, graph, A.device, tile, fuse,
-                 bool(overlap), bool(leaf_u), bool(split_pass), beta is not None, bool(peel))
+                 bool(overlap), bool(leaf_u), bool(split_pass), beta is not None, bool(peel), bool(trans_b))
     with torch.cuda.device(A.device):
         p(A, B, C, stream=stream, beta=beta)
     return C

@@ -58,6 +58,8 @@ enum EwKind : int32_t {
   EW_STR_U = 19,      // i = P1..P7 ; o = C11 = ((P1+P4)-P5)+P7, C12 = P3+P5, C21 = P2+P4,
                       //              C22 = ((P1+P3)-P2)+P6
   EW_STR_U_ACC = 20,  // i = P1..P7 C11 C12 C21 C22 ; o = fma(beta, Cij, EW_STR_U's Cij)
+  // Transposing passes (trans kernel; every output holds the transpose):
+  EW_WINO_T_TR = 21,  // i = B11 B12 B21 B22 ; o = T1' T2' T3' T4' B11' B21' B22' (T as EW_WINO_T)
 };
 
 constexpr int kEwMaxIn = 11;
@@ -99,9 +101,11 @@ struct GemmOut {
 // OK_S1..OK_S4 / OK_T1..OK_T4: the view is the parent block and the operand
 // is the Winograd sum S_i of its A quadrants / T_i of its B quadrants
 // (Section 2.3), formed while the tile is staged (fused loader).
+// OK_TRANS (B only): the view holds the transpose of the operand (n x k, each
+// row one column of B), so B is staged like A, in 16-byte chunks along k.
 enum OperandKind : int32_t {
   OK_PLAIN = 0, OK_S1 = 1, OK_S2 = 2, OK_S3 = 3, OK_S4 = 4,
-  OK_T1 = 5, OK_T2 = 6, OK_T3 = 7, OK_T4 = 8
+  OK_T1 = 5, OK_T2 = 6, OK_T3 = 7, OK_T4 = 8, OK_TRANS = 9
 };
 
 struct GemmDesc {

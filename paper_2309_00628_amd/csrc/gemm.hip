@@ -27,7 +27,8 @@ namespace {
 
 using namespace gemm_detail;
 
-template <typename T, int BM, int BN, int BKC, int WGM, int WGN>
+// BT: every problem's B view holds B transposed (OK_TRANS).
+template <typename T, int BM, int BN, int BKC, int WGM, int WGN, bool BT>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
                                                               const GemmDesc* __restrict__ descs,
                                                               int ndesc, int remap) {
@@ -41,17 +42,33 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
 
   typename TL::Acc acc;
   TL::zero(acc);
-  TL::product(sm, operand<T>(kb, D.a), operand<T>(kb, D.b), tr.i0, tr.j0, D.k, acc);
+  TL::template product<OK_PLAIN, BT ? OK_TRANS : OK_PLAIN>(sm, operand<T>(kb, D.a), operand<T>(kb, D.b), tr.i0,
+                                                         tr.j0, D.k, acc);
 
   store_outputs<T, TL::TM, M::NACC, TL::FM, TL::FN, TL::WM, TL::WN>(
       kb, D, tr.i0, tr.j0, wave / WGN, wave % WGN, lane, acc, [](int l, int r) { return M::row(l, r); });
 }
 
-template <typename T, int BM, int BN, int BKC, int WGM, int WGN>
+template <typename T, int BM, int BN, int BKC, int WGM, int WGN, bool BT = false>
 hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BKC, WGM, WGN>), dim3(tiles), dim3(64 * WGM * WGN), 0, s, kb,
+  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BKC, WGM, WGN, BT>), dim3(tiles), dim3(64 * WGM * WGN), 0, s, kb,
                      d, n, remap);
   return hipGetLastError();
+}
+
+// float32 with B transposed in memory
+hipError_t launch_f32_bt(int cfg, const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap,
+                         hipStream_t s) {
+  switch (cfg) {
+    case 1: return launch_cfg<float, 256, 128, 8, 4, 2, true>(kb, d, n, tiles, remap, s);
+    case 2: return launch_cfg<float, 128, 256, 8, 2, 4, true>(kb, d, n, tiles, remap, s);
+    case 3: return launch_cfg<float, 256, 256, 8, 4, 2, true>(kb, d, n, tiles, remap, s);
+    case 4: return launch_cfg<float, 64, 128, 8, 2, 2, true>(kb, d, n, tiles, remap, s);
+    case 5: return launch_cfg<float, 128, 64, 8, 2, 2, true>(kb, d, n, tiles, remap, s);
+    case 6: return launch_cfg<float, 256, 128, 4, 2, 2, true>(kb, d, n, tiles, remap, s);
+    case 7: return launch_cfg<float, 128, 128, 4, 2, 2, true>(kb, d, n, tiles, remap, s);
+    default: return launch_cfg<float, 128, 128, 8, 4, 2, true>(kb, d, n, tiles, remap, s);
+  }
 }
 
 }  // namespace
@@ -82,6 +99,7 @@ hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc
   if (tiles <= 0) return hipSuccess;
   if (dtype == DT_BF16X3) return launch_gemm_bf16x3(cfg, kb, d, n, tiles, remap, s);
   if (dtype == DT_BF16X3_SPL) return launch_gemm_bf16s(cfg, kb, d, n, tiles, remap, s);
+  if (dtype == DT_F32_BT) return launch_f32_bt(cfg, kb, d, n, tiles, remap, s);
   if (dtype == DT_F64) {
     switch (cfg) {
       case 5: return launch_cfg<double, 128, 64, 8, 2, 2>(kb, d, n, tiles, remap, s);

@@ -127,11 +127,16 @@ struct TileLoop {
   static_assert(NA * E <= 64 && NB * E * E <= 64, "one validity bit per staged element");
 
   // A is staged row by row (BKC chunks per row, see a_idx); B as BKC planes
-  // of BN column chunks (swz_b).
+  // of BN column chunks (b_idx), or, when it is given transposed (OK_TRANS),
+  // column by column like A.
+  static constexpr int NCH_B = BN * BKC;             // chunks of B per stage
+  static constexpr int NBT = (NCH_B + NT - 1) / NT;  // ... per thread (transposed B)
+  static_assert(NBT <= NB * E && NBT * E <= 64, "staging of a transposed B");
   struct Smem {
     chunk_t As[2][BM * BKC];
-    chunk_t Bs[2][BKC][BN];
+    chunk_t Bs[2][BKC * BN];
   };
+  static __device__ __forceinline__ int b_idx(int col, int kc) { return kc * BN + swz_b<E>(col); }
 
   // LDS slot of chunk kc of tile row `row`: the chunks of a row are contiguous
   // and their order is XOR-ed with bits of the row above log2(16 / BKC), so
@@ -146,18 +151,31 @@ struct TileLoop {
   // register staging or LDS stores; the lane that fills slot p loads the
   // chunk that a_idx places there.
   static constexpr bool DMA_A = NCH_A % NT == 0;
-  static __device__ __forceinline__ void dma_a(Smem& sm, int buf, const Operand<T>& A, int i0, int kt) {
+  static constexpr bool DMA_B = NCH_B % NT == 0;  // (transposed B)
+  // R rows (of A, or of a transposed B when IS_B) at r0 of the operand,
+  // chunks of k0 + [0, BK), into LDS buffer buf in a_idx order.
+  template <int R, bool IS_B>
+  static __device__ __forceinline__ void dma_rows(Smem& sm, int buf, const Operand<T>& X, int r0, int k0) {
+    constexpr int PER = (R * BKC) / NT;  // instructions per thread
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int k0 = kt * BK;
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int base = (wave * NA + i) * 64;
+    for (int i = 0; i < PER; ++i) {
+      const int base = (wave * PER + i) * 64;
       const int p = base + lane;
       const int row = p / BKC, slot = p % BKC;
       const int kc = slot ^ ((row / (16 / BKC)) & (BKC - 1));
-      const T* src = A.p + (int64_t)(i0 + row) * A.ld + k0 + kc * E;
-      __builtin_amdgcn_global_load_lds(src, &sm.As[buf][base], 16, 0, 0);
+      const T* src = X.p + (int64_t)(r0 + row) * X.ld + k0 + kc * E;
+      if (IS_B)
+        __builtin_amdgcn_global_load_lds(src, &sm.Bs[buf][base], 16, 0, 0);
+      else
+        __builtin_amdgcn_global_load_lds(src, &sm.As[buf][base], 16, 0, 0);
     }
+  }
+  static __device__ __forceinline__ void dma_a(Smem& sm, int buf, const Operand<T>& A, int i0, int kt) {
+    dma_rows<BM, false>(sm, buf, A, i0, kt * BK);
+  }
+  static __device__ __forceinline__ void dma_b(Smem& sm, int buf, const Operand<T>& B, int j0, int kt) {
+    if constexpr (DMA_B) dma_rows<BN, true>(sm, buf, B, j0, kt * BK);
   }
 
   typedef acc_t Acc[FM][FN];
@@ -222,6 +240,36 @@ struct TileLoop {
           amask = ok ? (amask | bit) : (amask & ~bit);
         }
       }
+    }
+    if constexpr (KB2 == OK_TRANS) {
+      // B given transposed: chunk kc of row `col` of B^T (one column of B)
+      if (MODE == LOAD_FULL && DMA_B) return;  // loaded straight into LDS
+#pragma unroll
+      for (int i = 0; i < NBT; ++i) {
+        const int q = tid + NT * i;
+        if (NCH_B % NT != 0 && q >= NCH_B) break;
+        const int col = q / BKC, kc = q % BKC;
+        const int gr = j0 + col, gc = k0 + kc * E;
+        const T* p = B.p + (int64_t)gr * B.ld + gc;
+        chunk_t& dst = rbk[i / E][i % E][0];
+        if (MODE == LOAD_FULL) {
+          dst = *reinterpret_cast<const chunk_t*>(p);
+        } else if (MODE == LOAD_EDGE_VEC) {
+          const bool ok = gr < B.vrows && gc < B.vcols;
+          dst = *reinterpret_cast<const chunk_t*>(ok ? p : B.p);
+          const uint64_t bit = 1ull << i;
+          bmask = ok ? (bmask | bit) : (bmask & ~bit);
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const bool ok = gr < B.vrows && gc + e < B.vcols;
+            dst[e] = *(ok ? p + e : B.p);
+            const uint64_t bit = 1ull << (i * E + e);
+            bmask = ok ? (bmask | bit) : (bmask & ~bit);
+          }
+        }
+      }
+      return;
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -292,6 +340,25 @@ struct TileLoop {
       }
       sm.As[buf][a_idx(row, kc)] = v;
     }
+    if constexpr (KB2 == OK_TRANS) {
+      if (MODE == LOAD_FULL && DMA_B) return;
+#pragma unroll
+      for (int i = 0; i < NBT; ++i) {
+        const int q = tid + NT * i;
+        if (NCH_B % NT != 0 && q >= NCH_B) break;
+        const int col = q / BKC, kc = q % BKC;
+        chunk_t v = rbk[i / E][i % E][0];
+        if (MODE == LOAD_EDGE_VEC) {
+          if (!((bmask >> i) & 1)) v = chunk_t{};
+        } else if (MODE == LOAD_MASKED) {
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+            if (!((bmask >> (i * E + e)) & 1)) v[e] = T(0);
+        }
+        sm.Bs[buf][a_idx(col, kc)] = v;
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int q = tid + NT * i;
@@ -310,7 +377,7 @@ struct TileLoop {
           if (MODE == LOAD_MASKED) ok = (bmask >> ((i * E + rr) * E + c)) & 1;
           t[rr] = ok ? combine<KB2>(x) : T(0);
         }
-        sm.Bs[buf][kc][swz_b<E>(cb * E + c)] = t;
+        sm.Bs[buf][b_idx(cb * E + c, kc)] = t;
       }
     }
   }
@@ -318,7 +385,7 @@ struct TileLoop {
   // MFMAs of k-blocks [KLO, KHI) of one LDS stage (a k-block is KG * E k
   // values).  The fragments of k-block j+1 are read into a second register
   // set while the MFMAs of k-block j run.
-  template <int KLO, int KHI>
+  template <int KLO, int KHI, bool BTL>
   static __device__ __forceinline__ void compute(const Smem& sm, int buf, Acc& acc) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
@@ -329,7 +396,10 @@ struct TileLoop {
 #pragma unroll
       for (int a = 0; a < FM; ++a) xa[a] = sm.As[buf][a_idx(wm * WM + a * TM + t, plane)];
 #pragma unroll
-      for (int b = 0; b < FN; ++b) xb[b] = sm.Bs[buf][plane][swz_b<E>(wn * WN + b * TM + t)];
+      for (int b = 0; b < FN; ++b) {
+        const int col = wn * WN + b * TM + t;
+        xb[b] = sm.Bs[buf][BTL ? a_idx(col, plane) : b_idx(col, plane)];
+      }
     };
     read_frags(KLO, fa[0], fb[0]);
 #pragma unroll
@@ -358,23 +428,27 @@ struct TileLoop {
     chunk_t ra[NA][popc4(kind_quads(KA))];
     chunk_t rbk[NB][E][popc4(kind_quads(KB2))];  // E rows (k) of E columns, per quadrant
     uint64_t amask = 0, bmask = 0;
+    constexpr bool BTL = KB2 == OK_TRANS;
     constexpr bool DMA = MODE == LOAD_FULL && KA == OK_PLAIN && DMA_A;
+    constexpr bool DMAB = MODE == LOAD_FULL && BTL && DMA_B;
     if (DMA) dma_a(sm, 0, A, i0, 0);
+    if (DMAB) dma_b(sm, 0, B, j0, 0);
     load_tile<MODE, KA, KB2>(A, B, i0, j0, 0, ra, rbk, amask, bmask);
     store_tile<MODE, KA, KB2>(sm, 0, ra, rbk, amask, bmask);
-    if (DMA) __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of this wave's direct loads are done
+    if (DMA || DMAB) __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of this wave's direct loads are done
     __syncthreads();
     for (int kt = 0; kt < ktiles; ++kt) {
       const int buf = kt & 1;
       const bool more = kt + 1 < ktiles;
       if (more) {
         if (DMA) dma_a(sm, buf ^ 1, A, i0, kt + 1);
+        if (DMAB) dma_b(sm, buf ^ 1, B, j0, kt + 1);
         load_tile<MODE, KA, KB2>(A, B, i0, j0, kt + 1, ra, rbk, amask, bmask);
       }
-      compute<0, KMID>(sm, buf, acc);
+      compute<0, KMID, BTL>(sm, buf, acc);
       if (more) store_tile<MODE, KA, KB2>(sm, buf ^ 1, ra, rbk, amask, bmask);
-      compute<KMID, KB>(sm, buf, acc);
-      if (DMA) __builtin_amdgcn_s_waitcnt(0);
+      compute<KMID, KB, BTL>(sm, buf, acc);
+      if (DMA || DMAB) __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
   }
@@ -388,8 +462,11 @@ struct TileLoop {
     // an operand with no valid element is zero: nothing to add (and the
     // loaders may then read its first element)
     if (A.vrows <= 0 || A.vcols <= 0 || B.vrows <= 0 || B.vcols <= 0) return;
-    const bool interior = A.vec && B.vec && (i0 + BM <= A.vrows) && (j0 + BN <= B.vcols) && (K % BK == 0) &&
-                          (K <= A.vcols) && (K <= B.vrows);
+    // extents of B along n and k (a transposed B holds n rows of k)
+    constexpr bool BTL = KB2 == OK_TRANS;
+    const int bn = BTL ? B.vrows : B.vcols, bk = BTL ? B.vcols : B.vrows;
+    const bool interior = A.vec && B.vec && (i0 + BM <= A.vrows) && (j0 + BN <= bn) && (K % BK == 0) &&
+                          (K <= A.vcols) && (K <= bk);
     const bool edge_vec = A.vec && B.vec && A.vrows > 0 && A.vcols > 0 && B.vrows > 0 && B.vcols > 0 &&
                           A.vcols % E == 0 && B.vcols % E == 0;
     if (interior)

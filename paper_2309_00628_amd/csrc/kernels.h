@@ -9,8 +9,9 @@ namespace mm {
 // Element types the kernels compute in (the public dtype codes of mm.h map
 // onto these; the split-bfloat16 path keeps float32 buffers).
 // DT_BF16X3_SPL: refined split-bfloat16 leaves whose operands were split by
-// the split pass (SPL layout; B operands transposed).
-enum KDtype : int { DT_F64 = 0, DT_F32 = 1, DT_BF16X3 = 2, DT_BF16X3_SPL = 3 };
+// the split pass (SPL layout; B operands transposed).  DT_F32_BT: float32
+// products whose B views hold B transposed (OK_TRANS).
+enum KDtype : int { DT_F64 = 0, DT_F32 = 1, DT_BF16X3 = 2, DT_BF16X3_SPL = 3, DT_F32_BT = 4 };
 
 // Tile configurations of the MFMA GEMM kernel (rows x cols of C per
 // workgroup); the planner needs the geometry to count tiles.
@@ -32,6 +33,8 @@ hipError_t launch_gemm_bf16s(int cfg, const KernelBases& kb, const GemmDesc* d, 
                              int remap, hipStream_t s);
 // Split passes (EW_SPLIT, EW_WINO_S_SPL, EW_WINO_T_SPL parts; rows x cols is
 // the float32 input block, transposed = mode[0]).
+int trans_blocks(int rows, int cols);
+hipError_t launch_trans(const KernelBases& kb, const EwPart* dparts, int nparts, int blocks, hipStream_t s);
 int split_blocks(int rows, int cols, int transposed);
 hipError_t launch_split(const KernelBases& kb, const EwPart* dparts, int nparts, int blocks, hipStream_t s);
 // Float32 leaf products whose operands may be Winograd sums of parent

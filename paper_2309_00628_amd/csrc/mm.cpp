@@ -52,7 +52,8 @@ int ew_dtype(int dtype) { return dtype == MM_F64 ? DT_F64 : DT_F32; }
 // OP_WINO: last-level Winograd subproblems, products and U combinations in
 // one kernel (WinoLeafDesc).
 // OP_SPLIT: split passes of the split-bfloat16 leaves (split kernel).
-enum OpType { OP_EW = 0, OP_GEMM = 1, OP_FORK = 2, OP_JOIN = 3, OP_WINO = 4, OP_SPLIT = 5 };
+// OP_TRANS: element-wise passes with transposed outputs (trans kernel).
+enum OpType { OP_EW = 0, OP_GEMM = 1, OP_FORK = 2, OP_JOIN = 3, OP_WINO = 4, OP_SPLIT = 5, OP_TRANS = 6 };
 
 struct OpRec {
   int type;
@@ -86,6 +87,7 @@ struct Plan {
   bool spl = false;      // split-bfloat16 leaves read operands split by a split pass
   bool accumulate = false;  // C <- A B + beta C (beta given per execution)
   bool peel = false;        // grouped: peel ragged rows / columns / k instead of padding
+  bool trans_b = false;     // grouped Winograd float32: last-level B operands stored transposed
   int64_t pm = 0, pn = 0, pk = 0;  // peeled: the leading block the recursion runs on
   bool has_aux = false;  // some launches go to the auxiliary stream
   struct Aux {
@@ -131,6 +133,7 @@ namespace {
 // partial last wave; 64x128 tiles keep small launches spread over more CUs.
 int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
   if (kdtype == DT_F64) return 0;
+  if (kdtype == DT_F32_BT) kdtype = DT_F32;  // same tiles
   bool equal = true;
   for (const GemmDesc& g : group) equal = equal && g.m == group[0].m && g.n == group[0].n;
   if (!equal && kdtype == DT_F32 && group.size() > 1) {
@@ -191,6 +194,9 @@ struct Builder {
   int cur_stream = 0;  // stream the next launches go to (0 main, 1 auxiliary)
   std::vector<GemmDesc> gm;
   std::vector<char> gm_fusable;  // descriptor satisfies the fused loader's preconditions
+  std::vector<EwPart> tp;        // transposing passes of the current launch
+  std::ostringstream ew_txt, tp_txt;  // listing lines of the pending element-wise / transposing parts
+  int tp_grid = 0;
   std::vector<WinoLeafDesc> wl;  // last-level subproblems of the current launch
   bool wl_fused = false;         // ... whose S/T sums are formed in the loader
   std::vector<EwPart> sp;        // split parts of the current launch
@@ -289,11 +295,11 @@ struct Builder {
     p.blk_start = ew_grid;
     ew_grid += blocks;
     ew.push_back(p);
-    txt << "EW " << kind << " " << rows << " " << cols << " " << mode0 << " " << mode1 << " |";
-    for (const auto& v : ins) txt << " " << vs(v);
-    txt << " |";
-    for (const auto& v : outs) txt << " " << vs(v);
-    txt << "\n";
+    ew_txt << "EW " << kind << " " << rows << " " << cols << " " << mode0 << " " << mode1 << " |";
+    for (const auto& v : ins) ew_txt << " " << vs(v);
+    ew_txt << " |";
+    for (const auto& v : outs) ew_txt << " " << vs(v);
+    ew_txt << "\n";
   }
 
   // GEMM epilogue outputs
@@ -338,6 +344,36 @@ struct Builder {
     txt << " |";
     for (const auto& v : outs) txt << " " << vs(v);
     txt << "\n";
+  }
+
+  // A transposing pass over rows x cols inputs; every output is a cols x rows
+  // workspace block holding the transpose of the recipe's result.
+  void trans_part(int kind, int64_t rows, int64_t cols, std::initializer_list<MView> ins,
+                  std::initializer_list<MView> outs) {
+    if (!gm.empty() || !wl.empty() || !sp.empty()) flush();
+    EwPart p;
+    std::memset(&p, 0, sizeof p);
+    p.kind = kind;
+    p.rows = (int32_t)rows;
+    p.cols = (int32_t)cols;
+    p.nin = (int32_t)ins.size();
+    p.nout = (int32_t)outs.size();
+    int i = 0;
+    for (const auto& v : ins) p.in[i++] = v;
+    for (; i < kEwMaxIn; ++i) p.in[i] = none();
+    i = 0;
+    for (const auto& v : outs) p.out[i++] = v;
+    for (; i < kEwMaxOut; ++i) p.out[i] = none();
+    const int blocks = trans_blocks((int)rows, (int)cols);
+    if (blocks == 0) return;
+    p.blk_start = tp_grid;
+    tp_grid += blocks;
+    tp.push_back(p);
+    tp_txt << "TRANS " << kind << " " << rows << " " << cols << " |";
+    for (const auto& v : ins) tp_txt << " " << vs(v);
+    tp_txt << " |";
+    for (const auto& v : outs) tp_txt << " " << vs(v);
+    tp_txt << "\n";
   }
 
   // C = a b^T-stored: a is an m x k SPL matrix, bt the n x k SPL transpose of
@@ -386,7 +422,7 @@ struct Builder {
     g.b = b;
     g.m = akind == OK_PLAIN ? a.rows : a.rows / 2;
     g.k = akind == OK_PLAIN ? a.cols : a.cols / 2;
-    g.n = bkind == OK_PLAIN ? b.cols : b.cols / 2;
+    g.n = bkind == OK_PLAIN ? b.cols : (bkind == OK_TRANS ? b.rows : b.cols / 2);
     g.kinds = akind | (bkind << 8);
     g.nout = (int32_t)outs.size();
     int i = 0;
@@ -483,21 +519,51 @@ struct Builder {
       P.table.resize(round_up(P.table.size() + bytes, 256));
       std::memcpy(P.table.data() + r.off, ew.data(), bytes);
       P.ops.push_back(r);
+      txt << ew_txt.str();
+      ew_txt.str("");
       txt << "LAUNCH EW " << ew.size() << " " << ew_grid << (cur_stream ? " aux" : "") << "\n";
       ew.clear();
       ew_grid = 0;
     }
+    if (!tp.empty()) {
+      OpRec r{OP_TRANS, DT_F32, P.table.size(), (int)tp.size(), tp_grid, 0, 0, 0, cur_stream};
+      const size_t bytes = tp.size() * sizeof(EwPart);
+      P.table.resize(round_up(P.table.size() + bytes, 256));
+      std::memcpy(P.table.data() + r.off, tp.data(), bytes);
+      P.ops.push_back(r);
+      txt << tp_txt.str();
+      tp_txt.str("");
+      txt << "LAUNCH TRANS " << tp.size() << " " << tp_grid << (cur_stream ? " aux" : "") << "\n";
+      tp.clear();
+      tp_grid = 0;
+    }
     if (!gm.empty()) {
       // Products with operand sums (and the plain products of the same
-      // blocks) run in the fused kernel; everything else in the regular one.
-      bool any_fused = false;
-      for (const GemmDesc& g : gm) any_fused = any_fused || g.kinds != 0;
+      // blocks) run in the fused kernel, products whose B is stored
+      // transposed in the transposed-B kernel, everything else in the
+      // regular one.
+      auto sums = [](const GemmDesc& g) {
+        const int ak = g.kinds & 0xff, bk = g.kinds >> 8;
+        return (ak >= OK_S1 && ak <= OK_S4) || (bk >= OK_T1 && bk <= OK_T4);
+      };
+      bool any_fused = false, any_bt = false;
+      for (const GemmDesc& g : gm) {
+        any_fused = any_fused || sums(g);
+        any_bt = any_bt || (g.kinds >> 8) == OK_TRANS;
+      }
       if (any_fused) {
         std::vector<GemmDesc> f, r;
         for (size_t i = 0; i < gm.size(); ++i) (gm_fusable[i] ? f : r).push_back(gm[i]);
         gm.clear();
         gm_fusable.clear();
         emit_gemm(f, true);
+        emit_gemm(r, false);
+      } else if (any_bt) {
+        std::vector<GemmDesc> t, r;
+        for (const GemmDesc& g : gm) ((g.kinds >> 8) == OK_TRANS ? t : r).push_back(g);
+        gm.clear();
+        gm_fusable.clear();
+        emit_gemm(t, false, true);
         emit_gemm(r, false);
       } else {
         emit_gemm(gm, false);
@@ -541,9 +607,9 @@ struct Builder {
     if (wl_fused) P.fused = true;
   }
 
-  void emit_gemm(std::vector<GemmDesc>& group, bool fused) {
+  void emit_gemm(std::vector<GemmDesc>& group, bool fused, bool bt = false) {
     if (group.empty()) return;
-    const int kd = gm_spl ? DT_BF16X3_SPL : kernel_dtype(P.dtype);
+    const int kd = gm_spl ? DT_BF16X3_SPL : (bt ? DT_F32_BT : kernel_dtype(P.dtype));
     // Unequal problems: longest (largest k) first, round-robin over XCDs.
     bool equal = true;
     for (const GemmDesc& g : group)
@@ -554,16 +620,16 @@ struct Builder {
     // the fused kernel has 256x256, 128x128 and 64x128 tiles; its 128x128
     // tile runs one wave per SIMD, so 64x128 is the default below 256x256
     if (fused && cfg != 3 && (cfg != 0 || P.tile_cfg < 0)) cfg = 4;
-    if (P.tile_cfg < 0 && equal && !fused && kd == DT_F32 && (cfg == 0 || cfg == 3)) {
+    if (P.tile_cfg < 0 && equal && !fused && (kd == DT_F32 || kd == DT_F32_BT) && (cfg == 0 || cfg == 3)) {
       const int p3 = split_for_rounds(group);
       if (p3 > 0 && p3 < (int)group.size()) {
         std::vector<GemmDesc> big(group.begin(), group.begin() + p3), small(group.begin() + p3, group.end());
-        emit_gemm_cfg(big, false, 3, true);
-        emit_gemm_cfg(small, false, 0, true);
+        emit_gemm_cfg(big, false, 3, true, kd);
+        emit_gemm_cfg(small, false, 0, true, kd);
         return;
       }
     }
-    emit_gemm_cfg(group, fused, cfg, equal);
+    emit_gemm_cfg(group, fused, cfg, equal, kd);
   }
 
   // Equal float32 problems on the eight-wave tiles (one workgroup per CU):
@@ -590,8 +656,7 @@ struct Builder {
     return (int)best;
   }
 
-  void emit_gemm_cfg(std::vector<GemmDesc>& group, bool fused, int cfg, bool equal) {
-    const int kd = gm_spl ? DT_BF16X3_SPL : kernel_dtype(P.dtype);
+  void emit_gemm_cfg(std::vector<GemmDesc>& group, bool fused, int cfg, bool equal, int kd) {
     const GemmCfg gc = gemm_cfg(kd, cfg);
     int grid = 0;
     for (GemmDesc& g : group) {
@@ -613,7 +678,7 @@ struct Builder {
     std::memcpy(P.table.data() + r.off, group.data(), bytes);
     P.ops.push_back(r);
     txt << "LAUNCH GEMM " << group.size() << " " << grid << " " << cfg << (fused ? " fused" : "")
-        << (gm_spl ? " spl" : "") << (cur_stream ? " aux" : "") << "\n";
+        << (gm_spl ? " spl" : "") << (kd == DT_F32_BT ? " bt" : "") << (cur_stream ? " aux" : "") << "\n";
     if (fused) P.fused = true;
   }
 };
@@ -973,6 +1038,37 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
         next.push_back(leaf(S[0], T[0], Pt[4]));
         next.push_back(leaf(S[1], T[1], Pt[5]));
         next.push_back(leaf(S[2], T[2], Pt[6]));
+        uargs.push_back({Pt[0], Pt[1], Pt[2], Pt[3], Pt[4], Pt[5], Pt[6], b.quad(s.C, 0, 0),
+                         b.quad(s.C, 0, 1), b.quad(s.C, 1, 0), b.quad(s.C, 1, 1)});
+        continue;
+      }
+      if (l == L - 1 && b.P.trans_b) {
+        // B side of the leaves stored transposed: T1..T4 and the plain B
+        // quadrants come out of one transposing pass, and the leaves stage
+        // B in k-chunks like A (straight into LDS in interior tiles)
+        const MView A11 = b.quad(s.A, 0, 0), A12 = b.quad(s.A, 0, 1), A21 = b.quad(s.A, 1, 0),
+                    A22 = b.quad(s.A, 1, 1);
+        const MView B11 = b.quad(s.B, 0, 0), B12 = b.quad(s.B, 0, 1), B21 = b.quad(s.B, 1, 0),
+                    B22 = b.quad(s.B, 1, 1);
+        MView S[4], Tt[4], Pt[7];
+        for (auto& v : S) v = b.temp(hm, hk);
+        for (auto& v : Tt) v = b.temp(hn, hk);
+        const MView b11 = b.temp(hn, hk), b21 = b.temp(hn, hk), b22 = b.temp(hn, hk);
+        for (auto& v : Pt) v = b.temp(hm, hn);
+        b.ew_part(EW_WINO_S, hm, hk, {A11, A12, A21, A22}, {S[0], S[1], S[2], S[3]});
+        b.trans_part(EW_WINO_T_TR, hk, hn, {B11, B12, B21, B22}, {Tt[0], Tt[1], Tt[2], Tt[3], b11, b21, b22});
+        auto leaf = [](const MView& x, const MView& y, const MView& c) {
+          Sub r{x, y, c};
+          r.bkind = OK_TRANS;
+          return r;
+        };
+        next.push_back(leaf(A11, b11, Pt[0]));
+        next.push_back(leaf(A12, b21, Pt[1]));
+        next.push_back(leaf(S[3], b22, Pt[2]));
+        next.push_back(leaf(A22, Tt[3], Pt[3]));
+        next.push_back(leaf(S[0], Tt[0], Pt[4]));
+        next.push_back(leaf(S[1], Tt[1], Pt[5]));
+        next.push_back(leaf(S[2], Tt[2], Pt[6]));
         uargs.push_back({Pt[0], Pt[1], Pt[2], Pt[3], Pt[4], Pt[5], Pt[6], b.quad(s.C, 0, 0),
                          b.quad(s.C, 0, 1), b.quad(s.C, 1, 0), b.quad(s.C, 1, 1)});
         continue;
@@ -1353,6 +1449,8 @@ int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEven
         e = launch_gemm_wino(op.cfg, op.fused, kb, (const WinoLeafDesc*)d, op.count, op.grid, op.remap, st);
       else if (op.type == OP_SPLIT)
         e = launch_split(kb, (const EwPart*)d, op.count, op.grid, st);
+      else if (op.type == OP_TRANS)
+        e = launch_trans(kb, (const EwPart*)d, op.count, op.grid, st);
       else
         e = op.fused ? launch_gemm_fused(op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, st)
                      : launch_gemm(op.kdtype, op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, st);
@@ -1477,6 +1575,8 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   P->overlap = (flags & MM_PLAN_OVERLAP) != 0;
   P->accumulate = (flags & MM_PLAN_ACCUMULATE) != 0;
   P->peel = (flags & MM_PLAN_PEEL) != 0;
+  P->trans_b = (flags & MM_PLAN_TRANS_B) != 0 && dtype == MM_F32 && algo == MM_ALGO_WINOGRAD &&
+               resolve_sched(algo, sched) == MM_SCHED_GROUPED;
   // the fused Winograd leaf level computes in float32 and replaces the
   // grouped schedule's last level; other dtypes and schedules ignore it
   P->leaf_u = (flags & MM_PLAN_LEAF_U) != 0 && dtype == MM_F32 && sched == MM_SCHED_GROUPED &&

@@ -22,6 +22,8 @@ EW_COPY, EW_ADD, EW_SUB, EW_WINO_S, EW_WINO_T, EW_WINO_U, EW_TT_U = range(7)
 EW_IP_A, EW_IP_B, EW_IP_U, EW_DIST, EW_ZERO = 7, 8, 9, 10, 11
 EW_SPLIT, EW_WINO_S_SPL, EW_WINO_T_SPL, EW_WINO_U_ACC, EW_AXPBY = 12, 13, 14, 15, 16
 EW_STR_S, EW_STR_T, EW_STR_U, EW_STR_U_ACC = 17, 18, 19, 20
+EW_WINO_T_TR = 21
+OK_TRANS = 9
 GM_STORE, GM_ADD, GM_AXPBY = 1, 2, 3
 MB_A, MB_B, MB_C, MB_WS, MB_ABS = 0, 1, 2, 3, 4
 
@@ -90,6 +92,12 @@ def parse(text):
             continue
         head, *rest = [s.strip() for s in line.split("|")]
         h = head.split()
+        if h[0] == "TRANS":
+            kind, rows, cols = map(int, h[1:])
+            ins = [_view(t) for t in rest[0].split()]
+            outs = [_view(t) for t in rest[1].split()]
+            cur.append(("TRANS", dict(kind=kind, rows=rows, cols=cols, ins=ins, outs=outs)))
+            continue
         if h[0] == "SPLIT":
             kind, rows, cols, mode = map(int, h[1:])
             ins = [_view(t) for t in rest[0].split()]
@@ -154,7 +162,7 @@ def check_streams(launches):
 def _launch_footprint(kind, items):
     reads, writes = set(), set()
     for _, it in items:
-        if kind == "EW":
+        if kind in ("EW", "TRANS"):
             for v in it["ins"]:
                 reads |= _footprint(v)
             for v in it["outs"]:
@@ -324,6 +332,13 @@ def check_hazards(launch):
                         for x in common.tolist():
                             pi, po = pos_in[x], pos_out[x]
                             assert (pi // ci, pi % ci) == (po // co, po % co), "EW cross-element alias"
+        elif kind == "TRANS":
+            r, w = _launch_footprint("EW", [(kind, it)])
+            assert sum(len(_footprint(v)) for v in it["outs"]) == len(w), "TRANS outputs overlap"
+            assert not (w & r), "TRANS writes its own inputs"
+            for v in it["outs"]:
+                assert (v.rows, v.cols) == (it["cols"], it["rows"]), "TRANS output not transposed"
+                assert v.off % 4 == 0 and v.ld % 4 == 0, "TRANS output rows not 16-byte aligned"
         elif kind == "SPLIT":
             r, w = _launch_footprint(kind, [(kind, it)])
             assert sum(len(_spl_footprint(v)) for v in it["outs"]) == len(w), "SPLIT outputs overlap"
@@ -362,6 +377,8 @@ def operand(M, kind):
     its quadrants named by kind (1..4: S1..S4, 5..8: T1..T4)."""
     if kind == 0:
         return M
+    if kind == OK_TRANS:  # the view holds the transpose of the operand
+        return M.T
     r, c = M.shape[0] // 2, M.shape[1] // 2
     q11, q12, q21, q22 = M[:r, :c], M[:r, c:], M[r:, :c], M[r:, c:]
     if kind <= 4:
@@ -397,6 +414,14 @@ def run(text, bufs, hazards=True, beta=1):
                 else:
                     y = _recipe(it["kind"], x, it["mode"])
                 results.append(list(zip(it["outs"], y)))
+            elif kind == "TRANS":
+                x = [mem.read(v, (it["rows"], it["cols"])) for v in it["ins"]]
+                assert it["kind"] == EW_WINO_T_TR
+                b11, b12, b21, b22 = x
+                t1 = b12 - b11
+                t2 = b22 - t1
+                y = [t1, t2, b22 - b12, t2 - b21, b11, b21, b22]
+                results.append([(v, t.T) for v, t in zip(it["outs"], y)])
             elif kind == "SPLIT":
                 x = [mem.read(v, (it["rows"], it["cols"])) for v in it["ins"]]
                 if it["kind"] == EW_SPLIT:

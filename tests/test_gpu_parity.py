@@ -551,3 +551,28 @@ def test_accumulating_leaf_u_and_graph_bitwise(api):
     with pytest.raises(ValueError):
         api.Plan("naive", "auto", 8, 8, 8)(At[:8, :8].contiguous(), Bt[:8, :8].contiguous(),
                                            torch.empty(8, 8, device="cuda"), beta=2.0)
+
+
+@pytest.mark.parametrize("m,n,k,levels", [(1024, 1024, 1024, 1), (2048, 2048, 2048, 2), (3000, 3000, 3000, 1),
+                                          (1000, 777, 555, 2), (640, 384, 1152, 3), (130, 70, 90, 1)])
+def test_transposed_b_bitwise(api, naive, m, n, k, levels):
+    # MM_PLAN_TRANS_B: the last level's B operands written transposed by the
+    # transposing T pass and staged like A; bitwise equal to the default plan
+    # for every tile configuration, accumulating too
+    A, B = inputs.pair("uniform", m, n, k, 55, np.float32)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    print(f"trans_b {m}x{n}x{k} L={levels}", flush=True)
+    ref = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, trans_b=False)
+    for tile in (None, 0, 1, 3, 4, 7):
+        C = torch.full((m, n), float("nan"), device="cuda")
+        api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, trans_b=True, tile=tile, out=C)
+        torch.cuda.synchronize()
+        assert torch.equal(C, ref), tile
+    rows = np.arange(0, m, max(1, m // 16))
+    assert rel_fro(ref[torch.from_numpy(rows).cuda()].cpu().numpy(), naive.gemm_rows(A, B, rows)) < 1e-5
+    C0 = torch.from_numpy(inputs.uniform((m, n), 56, dtype=np.float32)).cuda()
+    C1, C2 = C0.clone(), C0.clone()
+    api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, trans_b=True, out=C1, beta=-0.5)
+    api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, trans_b=False, out=C2, beta=-0.5)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)

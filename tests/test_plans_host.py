@@ -500,3 +500,36 @@ def test_plain_product_copies_unaligned_operands(lib):
         text, info = L.describe("naive", "auto", *shape, dtype="f32")
         assert [l.split()[1] for l in text.splitlines() if l.startswith("LAUNCH")] == ["GEMM"]
         assert info["ws_bytes"] == 0
+
+
+@pytest.mark.parametrize("m,n,k,levels", [(16, 16, 16, 1), (64, 64, 64, 2), (96, 40, 56, 2), (200, 136, 72, 3),
+                                          (1000, 777, 555, 2), (130, 70, 90, 1), (8, 300, 64, 1)])
+def test_transposed_b_plan_is_exact(lib, m, n, k, levels):
+    # MM_PLAN_TRANS_B: the last level's T pass writes T1..T4 and B11, B21,
+    # B22 transposed and the leaves read them as transposed B operands
+    A = inputs.integers((m, k), 53, dtype=np.int64)
+    B = inputs.integers((k, n), 54, dtype=np.int64)
+    text, info = L.describe("winograd", "grouped", m, n, k, cutoff=1, levels=levels, dtype="f32", trans_b=True)
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    C = np.full(m * n, -(10**9), dtype=np.int64)
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
+    assert np.array_equal(C.reshape(m, n), A @ B)
+
+
+def test_transposed_b_plan_shape(lib):
+    for lv in (1, 2):
+        _, ref = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=lv)
+        text, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=lv, trans_b=True)
+        launches = [l.split() for l in text.splitlines() if l.startswith("LAUNCH")]
+        # the last level's S pass and transposing T pass are two launches
+        assert info["launches"] == ref["launches"] + 1
+        assert sum(w[1] == "TRANS" for w in launches) == 1
+        assert all("bt" in w for w in launches if w[1] == "GEMM")
+        # three more quarter blocks per last-level block
+        q = (4096 >> lv) ** 2 * 4
+        assert info["ws_bytes"] == ref["ws_bytes"] + 3 * q * 7 ** (lv - 1)
+    # other dtypes, algorithms and schedules ignore the flag
+    for args in (("winograd", "grouped", 512, 512, 512, 64, "f64"), ("strassen", "grouped", 512, 512, 512, 64, "f32"),
+                 ("winograd", "two_temp", 512, 512, 512, 64, "f32")):
+        text, _ = L.describe(*args[:5], cutoff=args[5], dtype=args[6], trans_b=True)
+        assert "TRANS" not in text
