@@ -126,7 +126,7 @@ def plan_launches(plan, esz):
         elif w[0] == "WINO":
             m, n, k = map(int, w[1:4])
             flops += 7 * 2.0 * m * n * k
-        elif w[0] == "EW":
+        elif w[0] in ("EW", "TRANS"):
             _, ins, outs = [x.strip() for x in line.split("|")]
             for tok in (ins + " " + outs).split():
                 if tok != "-":
@@ -136,14 +136,15 @@ def plan_launches(plan, esz):
 
 
 def tuned_leaf(tuner, n, levels):
-    """The autotuner's (tile, overlap, leaf_u) choice for an n x n x n
+    """The autotuner's (tile, overlap, leaf_u, trans_b) choice for an n x n x n
     float32 product at this level count (planner defaults when the cache
     holds another level count for the size class)."""
     ch = tuner.choose(n, n, n, "f32")
     for c in (ch, ch.get("best_recursive") or {}):
         if ch["source"] == "tuned" and c.get("levels") == levels:
-            return c["tile"], bool(c.get("overlap", False)), bool(c.get("leaf_u", False))
-    return None, False, False
+            return (c["tile"], bool(c.get("overlap", False)), bool(c.get("leaf_u", False)),
+                    bool(c.get("trans_b", False)))
+    return None, False, False, False
 
 
 def tuned_plain_tile(tuner, n, dtype="f32"):
@@ -162,9 +163,9 @@ def pct(xs, q):
 
 
 def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtype="f32", tile=None,
-                overlap=False, leaf_u=False):
+                overlap=False, leaf_u=False, trans_b=False):
     plan = api.Plan(algo, sched, n, n, n, cutoff=1, levels=levels, dtype=dtype, tile=tile, overlap=overlap,
-                    leaf_u=leaf_u)
+                    leaf_u=leaf_u, trans_b=trans_b)
     ws = torch.empty(max(plan.ws_bytes, 256), dtype=torch.uint8, device=A.device)
     C = torch.empty((n, n), dtype=A.dtype, device=A.device)
     wall, step_ms, per_op, kinds = time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup)
@@ -234,7 +235,7 @@ def ew_bandwidth(res, n):
     launches = plan_launches(res["plan"], 4)
     out = []
     for lau, d, k in zip(launches, res["per_op"], res["kinds"]):
-        if k % 8 == 0:
+        if k % 8 in (0, 6):  # element-wise and transposing passes
             ms = sum(d) / len(d)
             out.append(dict(stream="aux" if k >= 8 else "main", bytes=lau["bytes"], ms=round(ms, 4),
                             gbs=round(lau["bytes"] / (ms * 1e-3) / 1e9, 1)))
@@ -288,9 +289,9 @@ def profile_set(torch, api, L, inputs, tuner, args):
         ch = tuner.choose(n, n, n, "f32")
         rec = ch.get("best_recursive") if ch["source"] == "tuned" else None
         lv = ch["levels"] if ch["levels"] > 0 else (rec["levels"] if rec else 1)
-        t, o, u = tuned_leaf(tuner, n, lv)
+        t, o, u, tb = tuned_leaf(tuner, n, lv)
         w = run_product(torch, api, L, "winograd", "grouped", n, lv, A, B, args.steps, args.warmup, tile=t,
-                        overlap=o, leaf_u=u)
+                        overlap=o, leaf_u=u, trans_b=tb)
         out["winograd"] = {"levels": lv, "tflops": round(w["tflops"], 2)}
         torch.backends.cuda.matmul.allow_tf32 = False
         C = torch.empty((n, n), device="cuda")
@@ -488,9 +489,9 @@ def main():
     else:
         levels = args.levels
 
-    tile, overlap, leaf_u = tuned_leaf(tuner, n, levels)
+    tile, overlap, leaf_u, trans_b = tuned_leaf(tuner, n, levels)
     win = run_product(torch, api, L, "winograd", args.sched, n, levels, A, B, args.steps, args.warmup,
-                      tile=tile, overlap=overlap, leaf_u=leaf_u)
+                      tile=tile, overlap=overlap, leaf_u=leaf_u, trans_b=trans_b)
     print(f"# winograd L={levels}: {win['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
     if args.profile_only:
         print(json.dumps({"profile_only": True, "n": n, "levels": levels,
@@ -534,7 +535,7 @@ def main():
         "config": {"workload": f"square fp32 matmul n={n}, Strassen-Winograd {args.sched} "
                                f"L={levels} vs plain MFMA GEMM",
                    "n": n, "levels": levels, "schedule": args.sched, "leaf_tile_cfg": tile,
-                   "overlap": overlap, "leaf_u": leaf_u},
+                   "overlap": overlap, "leaf_u": leaf_u, "trans_b": trans_b},
         "p50_ms": round(win["p50"], 4),
         "p99_ms": round(win["p99"], 4),
         "plain_gemm": {"tflops": round(plain["tflops"], 3), "p50_ms": round(plain["p50"], 4),
@@ -565,9 +566,9 @@ def main():
                              tile=tuned_plain_tile(tuner, n2))
             e = {"plain_tflops": round(p2["tflops"], 3)}
             for lv in lvls:
-                t2, o2, u2 = tuned_leaf(tuner, n2, lv)
+                t2, o2, u2, b2 = tuned_leaf(tuner, n2, lv)
                 w2 = run_product(torch, api, L, "winograd", args.sched, n2, lv, A2, B2, 20, 10, tile=t2,
-                                 overlap=o2, leaf_u=u2)
+                                 overlap=o2, leaf_u=u2, trans_b=b2)
                 e[f"winograd_L{lv}_tflops"] = round(w2["tflops"], 3)
                 e[f"winograd_L{lv}_p99_ms"] = round(w2["p99"], 4)
                 s2 = run_product(torch, api, L, "strassen", "grouped", n2, lv, A2, B2, 20, 10,

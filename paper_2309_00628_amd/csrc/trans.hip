@@ -9,8 +9,9 @@
 //
 // A block covers 64 rows (k) x 64 columns (n) of the inputs, staged in LDS
 // with one padding column (conflict-free reads down a column); a thread then
-// produces 16 consecutive k of one column and writes them as four 16-byte
-// stores into row n of each output, so four lanes write 256 contiguous bytes.
+// produces 4 consecutive k of one column per pass, so the 16 lanes that share
+// a column write 256 contiguous bytes of that output row with one 16-byte
+// store each.
 #include <hip/hip_runtime.h>
 
 #include "desc.h"
@@ -73,14 +74,14 @@ __global__ __launch_bounds__(kThreads) void trans_kernel(KernelBases kb, const E
   }
   __syncthreads();
 
-  const int c = tid / 4, kq = tid % 4;  // column (n) and quarter of the 64 k
-  const int orow = c0 + c;               // output row
-  if (orow >= P.cols) return;
+  const int kq = tid % 16;  // 4 consecutive k: kq * 4 .. kq * 4 + 3
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
-    const int k = kq * 16 + 4 * g;  // first of 4 consecutive k
+    const int c = tid / 16 + 16 * g;  // column (n) of this pass
+    const int orow = c0 + c;          // output row
+    const int k = kq * 4;
     const int ocol = r0 + k;
-    if (ocol >= P.rows) break;
+    if (orow >= P.cols || ocol >= P.rows) continue;
     f32x4 y[kEwMaxOut];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
