@@ -124,6 +124,13 @@ struct GemmDesc {
 //   P1 = A11 B11, P2 = A12 B21, P3 = S4 B22, P4 = A22 T4,
 //   P5 = S1 T1,   P6 = S2 T2,   P7 = S3 T3,
 //   C11 = P1 + P2, C12 = U5, C21 = U6, C22 = U7.
+// A leaf product C = A B of order 1, 2 or 4 computed in registers by the
+// Strassen-Winograd formula of Section 2.3 unrolled down to scalars (the
+// unrolled base cases of Section 3): one thread per leaf.
+struct BaseDesc {
+  MView a, b, c;
+};
+
 struct WinoLeafDesc {
   MView a[7], b[7];    // operands of P1 .. P7
   MView c[4];          // C11 C12 C21 C22

@@ -53,7 +53,10 @@ int ew_dtype(int dtype) { return dtype == MM_F64 ? DT_F64 : DT_F32; }
 // one kernel (WinoLeafDesc).
 // OP_SPLIT: split passes of the split-bfloat16 leaves (split kernel).
 // OP_TRANS: element-wise passes with transposed outputs (trans kernel).
-enum OpType { OP_EW = 0, OP_GEMM = 1, OP_FORK = 2, OP_JOIN = 3, OP_WINO = 4, OP_SPLIT = 5, OP_TRANS = 6 };
+// OP_BASE: unrolled base cases, one leaf product per thread (BaseDesc).
+enum OpType {
+  OP_EW = 0, OP_GEMM = 1, OP_FORK = 2, OP_JOIN = 3, OP_WINO = 4, OP_SPLIT = 5, OP_TRANS = 6, OP_BASE = 7
+};
 
 struct OpRec {
   int type;
@@ -88,6 +91,7 @@ struct Plan {
   bool accumulate = false;  // C <- A B + beta C (beta given per execution)
   bool peel = false;        // grouped: peel ragged rows / columns / k instead of padding
   bool trans_b = false;     // grouped Winograd float32: last-level B operands stored transposed
+  bool unroll_base = false; // grouped Winograd: leaves of order 1, 2, 4 by the unrolled base cases
   int64_t pm = 0, pn = 0, pk = 0;  // peeled: the leading block the recursion runs on
   bool has_aux = false;  // some launches go to the auxiliary stream
   struct Aux {
@@ -196,6 +200,8 @@ struct Builder {
   std::vector<char> gm_fusable;  // descriptor satisfies the fused loader's preconditions
   std::vector<EwPart> tp;        // transposing passes of the current launch
   std::ostringstream ew_txt, tp_txt;  // listing lines of the pending element-wise / transposing parts
+  std::vector<BaseDesc> bl;      // unrolled base cases of the current launch
+  int bl_order = 0;
   int tp_grid = 0;
   std::vector<WinoLeafDesc> wl;  // last-level subproblems of the current launch
   bool wl_fused = false;         // ... whose S/T sums are formed in the loader
@@ -344,6 +350,16 @@ struct Builder {
     txt << " |";
     for (const auto& v : outs) txt << " " << vs(v);
     txt << "\n";
+  }
+
+  // Leaf product c = a b of order s (1, 2 or 4) by the unrolled base case.
+  void base(const MView& a, const MView& bop, const MView& c, int s) {
+    if (!ew.empty() || !gm.empty() || !wl.empty() || !sp.empty() || !tp.empty() || (!bl.empty() && bl_order != s))
+      flush();
+    bl_order = s;
+    P.leaves += 1;
+    bl.push_back(BaseDesc{a, bop, c});
+    txt << "BASE " << s << " | " << vs(a) << " " << vs(bop) << " " << vs(c) << "\n";
   }
 
   // A transposing pass over rows x cols inputs; every output is a cols x rows
@@ -503,6 +519,16 @@ struct Builder {
 
   void flush() {
     if (!wl.empty()) emit_wino();
+    if (!bl.empty()) {
+      const int blocks = base_blocks((int)bl.size());
+      OpRec r{OP_BASE, kernel_dtype(P.dtype), P.table.size(), (int)bl.size(), blocks, bl_order, 0, 0, cur_stream};
+      const size_t bytes = bl.size() * sizeof(BaseDesc);
+      P.table.resize(round_up(P.table.size() + bytes, 256));
+      std::memcpy(P.table.data() + r.off, bl.data(), bytes);
+      P.ops.push_back(r);
+      txt << "LAUNCH BASE " << bl.size() << " " << blocks << " " << bl_order << (cur_stream ? " aux" : "") << "\n";
+      bl.clear();
+    }
     if (!sp.empty()) {
       OpRec r{OP_SPLIT, DT_BF16X3_SPL, P.table.size(), (int)sp.size(), sp_grid, 0, 0, 0, cur_stream};
       const size_t bytes = sp.size() * sizeof(EwPart);
@@ -1144,9 +1170,21 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
       if (plain(s)) b.gemm(s.A, s.B, {Builder::store(s.C)}, s.akind, s.bkind, s.fusable);
     b.join();
   }
+  // unrolled base cases for leaves of order 1, 2 or 4 (all leaves of a
+  // grouped level have the same order)
+  int base_order = 0;
+  if (b.P.unroll_base && !subs.empty()) {
+    const int64_t o = subs[0].A.rows;
+    base_order = (o == 1 || o == 2 || o == 4) ? (int)o : 0;
+    for (const Sub& s : subs)
+      if (s.A.rows != o || s.A.cols != o || s.B.cols != o || s.akind != OK_PLAIN || s.bkind != OK_PLAIN || s.spl)
+        base_order = 0;
+  }
   for (const Sub& s : subs) {
     if (overlap && plain(s)) continue;
-    if (s.spl)
+    if (base_order)
+      b.base(s.A, s.B, s.C, base_order);
+    else if (s.spl)
       b.gemm_spl(s.A, s.B, {Builder::store(s.C)});
     else
       b.gemm(s.A, s.B, {Builder::store(s.C)}, s.akind, s.bkind, s.fusable);
@@ -1451,6 +1489,8 @@ int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEven
         e = launch_split(kb, (const EwPart*)d, op.count, op.grid, st);
       else if (op.type == OP_TRANS)
         e = launch_trans(kb, (const EwPart*)d, op.count, op.grid, st);
+      else if (op.type == OP_BASE)
+        e = launch_base(op.kdtype, op.cfg, kb, (const BaseDesc*)d, op.count, op.grid, st);
       else
         e = op.fused ? launch_gemm_fused(op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, st)
                      : launch_gemm(op.kdtype, op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, st);
@@ -1577,6 +1617,8 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   P->peel = (flags & MM_PLAN_PEEL) != 0;
   P->trans_b = (flags & MM_PLAN_TRANS_B) != 0 && dtype == MM_F32 && algo == MM_ALGO_WINOGRAD &&
                resolve_sched(algo, sched) == MM_SCHED_GROUPED;
+  P->unroll_base = (flags & MM_PLAN_UNROLL_BASE) != 0 && dtype != MM_BF16X3_REFINED &&
+                   algo == MM_ALGO_WINOGRAD && resolve_sched(algo, sched) == MM_SCHED_GROUPED;
   // the fused Winograd leaf level computes in float32 and replaces the
   // grouped schedule's last level; other dtypes and schedules ignore it
   P->leaf_u = (flags & MM_PLAN_LEAF_U) != 0 && dtype == MM_F32 && sched == MM_SCHED_GROUPED &&

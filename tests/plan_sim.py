@@ -92,6 +92,10 @@ def parse(text):
             continue
         head, *rest = [s.strip() for s in line.split("|")]
         h = head.split()
+        if h[0] == "BASE":
+            a, b, c = [_view(t) for t in rest[0].split()]
+            cur.append(("BASE", dict(order=int(h[1]), a=a, b=b, c=c)))
+            continue
         if h[0] == "TRANS":
             kind, rows, cols = map(int, h[1:])
             ins = [_view(t) for t in rest[0].split()]
@@ -167,6 +171,9 @@ def _launch_footprint(kind, items):
                 reads |= _footprint(v)
             for v in it["outs"]:
                 writes |= _footprint(v)
+        elif kind == "BASE":
+            reads |= _footprint(it["a"]) | _footprint(it["b"])
+            writes |= _footprint(it["c"])
         elif kind == "WINO":
             for v in it["a"] + it["b"]:
                 reads |= _footprint(v)
@@ -332,6 +339,11 @@ def check_hazards(launch):
                         for x in common.tolist():
                             pi, po = pos_in[x], pos_out[x]
                             assert (pi // ci, pi % ci) == (po // co, po % co), "EW cross-element alias"
+        elif kind == "BASE":
+            r, w = _footprint(it["a"]) | _footprint(it["b"]), _footprint(it["c"])
+            assert not (w & r), "BASE writes its own operands"
+            for v in (it["a"], it["b"], it["c"]):
+                assert v.rows == v.cols == it["order"], "BASE block of another order"
         elif kind == "TRANS":
             r, w = _launch_footprint("EW", [(kind, it)])
             assert sum(len(_footprint(v)) for v in it["outs"]) == len(w), "TRANS outputs overlap"
@@ -390,6 +402,35 @@ def operand(M, kind):
     return {5: t1, 6: t2, 7: q22 - q12, 8: t2 - q21}[kind]
 
 
+def unrolled_winograd(a, b):
+    """The 22-operation form of Section 2.3 applied down to scalars (orders
+    1, 2, 4): what an unrolled base case computes."""
+    n = a.shape[0]
+    if n == 1:
+        return a * b
+    h = n // 2
+    a11, a12, a21, a22 = a[:h, :h], a[:h, h:], a[h:, :h], a[h:, h:]
+    b11, b12, b21, b22 = b[:h, :h], b[:h, h:], b[h:, :h], b[h:, h:]
+    s1 = a21 + a22
+    s2 = s1 - a11
+    s3 = a11 - a21
+    s4 = a12 - s2
+    t1 = b12 - b11
+    t2 = b22 - t1
+    t3 = b22 - b12
+    t4 = t2 - b21
+    p = [unrolled_winograd(x, y) for x, y in ((a11, b11), (a12, b21), (s4, b22), (a22, t4), (s1, t1),
+                                              (s2, t2), (s3, t3))]
+    u2 = p[0] + p[5]
+    u3 = u2 + p[6]
+    c = np.empty_like(a)
+    c[:h, :h] = p[0] + p[1]
+    c[:h, h:] = (u2 + p[4]) + p[2]
+    c[h:, :h] = u3 - p[3]
+    c[h:, h:] = u3 + p[4]
+    return c
+
+
 def run(text, bufs, hazards=True, beta=1):
     mem = Memory(bufs)
     for launch in parse(text):
@@ -414,6 +455,8 @@ def run(text, bufs, hazards=True, beta=1):
                 else:
                     y = _recipe(it["kind"], x, it["mode"])
                 results.append(list(zip(it["outs"], y)))
+            elif kind == "BASE":
+                results.append([(it["c"], unrolled_winograd(mem.read(it["a"]), mem.read(it["b"])))])
             elif kind == "TRANS":
                 x = [mem.read(v, (it["rows"], it["cols"])) for v in it["ins"]]
                 assert it["kind"] == EW_WINO_T_TR

@@ -576,3 +576,41 @@ def test_transposed_b_bitwise(api, naive, m, n, k, levels):
     api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, trans_b=False, out=C2, beta=-0.5)
     torch.cuda.synchronize()
     assert torch.equal(C1, C2)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_unrolled_base_case_bitwise(api, naive, dt):
+    # leaves of order 2 and 4 by the unrolled base case give the bits of the
+    # plan recursing to scalar leaves (1x1 MFMA products)
+    npdt = np.float64 if dt == "f64" else np.float32
+    n = 64
+    A, B = inputs.pair("uniform", n, n, n, 59, npdt)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    ref = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=6)
+    for lv in (4, 5, 6):
+        p = api.Plan("winograd", "grouped", n, n, n, cutoff=1, levels=lv, dtype=dt, unroll_base=True)
+        assert "LAUNCH BASE" in p.describe()
+        C = torch.full((n, n), float("nan"), dtype=At.dtype, device="cuda")
+        ws = torch.empty(max(p.ws_bytes, 256), dtype=torch.uint8, device="cuda")
+        p(At, Bt, C, ws)
+        torch.cuda.synchronize()
+        assert torch.equal(C, ref), lv
+    tol = 1e-12 if dt == "f64" else 1e-5
+    assert rel_fro(ref.cpu().numpy(), naive.gemm(A, B)) < tol
+    # ragged (virtual padding): against the oracle, and exact on integers
+    m, n2, k = 28, 30, 26
+    for kind in ("uniform", "int"):
+        A, B = inputs.pair(kind, m, n2, k, 60, npdt)
+        got = gpu_mm(api, A, B, algo="winograd", sched="grouped", cutoff=1, levels=3, dtype=dt)
+        p = api.get_plan("winograd", "grouped", m, n2, k, 1, 3, dt, k, n2, n2, False, torch.device("cuda"))
+        At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        pb = api.Plan("winograd", "grouped", m, n2, k, cutoff=1, levels=3, dtype=dt, unroll_base=True)
+        C = torch.empty((m, n2), dtype=At.dtype, device="cuda")
+        ws = torch.empty(max(pb.ws_bytes, 256), dtype=torch.uint8, device="cuda")
+        pb(At, Bt, C, ws)
+        torch.cuda.synchronize()
+        if kind == "int":
+            assert np.array_equal(C.cpu().numpy().astype(np.float64), naive.gemm(A, B))
+        else:
+            assert rel_fro(C.cpu().numpy(), naive.gemm(A, B)) < tol
+        del p, got

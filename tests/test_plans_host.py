@@ -533,3 +533,26 @@ def test_transposed_b_plan_shape(lib):
                  ("winograd", "two_temp", 512, 512, 512, 64, "f32")):
         text, _ = L.describe(*args[:5], cutoff=args[5], dtype=args[6], trans_b=True)
         assert "TRANS" not in text
+
+
+@pytest.mark.parametrize("m,n,k,levels", [(8, 8, 8, 2), (8, 8, 8, 3), (16, 16, 16, 3), (32, 32, 32, 3),
+                                          (28, 30, 26, 3)])
+def test_unrolled_base_case_plan_is_exact(lib, m, n, k, levels):
+    # MM_PLAN_UNROLL_BASE: leaves of order 1, 2 or 4 by the unrolled base case
+    A = inputs.integers((m, k), 57, dtype=np.int64)
+    B = inputs.integers((k, n), 58, dtype=np.int64)
+    text, info = L.describe("winograd", "grouped", m, n, k, cutoff=1, levels=levels, dtype="f32",
+                            unroll_base=True)
+    assert "LAUNCH BASE" in text and "LAUNCH GEMM" not in text
+    assert info["leaves"] == 7 ** levels
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    C = np.full(m * n, -(10**9), dtype=np.int64)
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
+    assert np.array_equal(C.reshape(m, n), A @ B)
+
+
+def test_unrolled_base_case_only_for_tiny_leaves(lib):
+    text, _ = L.describe("winograd", "grouped", 512, 512, 512, cutoff=1, levels=2, unroll_base=True)
+    assert "BASE" not in text and "LAUNCH GEMM" in text
+    text, _ = L.describe("winograd", "grouped", 64, 64, 64, cutoff=1, levels=4, dtype="f64", unroll_base=True)
+    assert [l.split()[4] for l in text.splitlines() if l.startswith("LAUNCH BASE")] == ["4"]
