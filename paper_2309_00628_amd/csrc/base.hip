@@ -13,6 +13,10 @@
 #include "desc.h"
 #include "kernels.h"
 
+// Every product and sum is rounded on its own, as the separate passes and
+// MFMA tiles of the recursion round them: no multiply-add contraction.
+#pragma clang fp contract(off)
+
 namespace mm {
 
 namespace {
