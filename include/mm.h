@@ -216,6 +216,13 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                            A[:pm,pk:] B[pk:,:pn], C[:pm,pn:] = A[:pm,:] B[:,pn:], C[pm:,:] =
                            A[pm:,:] B.  No effect when every side is already such a multiple
                            or when a side of the leading block would be empty. */
+/* Plain product (MM_ALGO_NAIVE, or a recursion of zero levels): split k into
+ * s parts (2 .. 8, each a multiple of 64 long), run the s partial products
+ * in one grouped launch into workspace blocks and sum them in order in one
+ * element-wise pass (applying beta in accumulating plans).  For products
+ * whose C has too few tiles to fill the 256 compute units; the sum order
+ * differs from the unsplit product's, so the bits may differ too. */
+#define MM_PLAN_SPLIT_K(s) (((unsigned)(s) & 0xfu) << 16)
 /* Force the MFMA GEMM tile configuration c (0 .. 7) for every leaf launch
  * instead of the planner's choice.  float32: 0 128x128 (BK 32, 8 waves),
  * 1 256x128 (8 waves), 2 128x256 (8 waves), 3 256x256 (BK 32, 8 waves),

@@ -31,6 +31,11 @@ MM_PLAN_TRANS_B = 128
 MM_PLAN_UNROLL_BASE = 256
 
 
+def plan_split_k(s):
+    """MM_PLAN_SPLIT_K(s) flag bits (0 when s is None or 1: no split)."""
+    return 0 if not s or s <= 1 else (int(s) & 0xF) << 16
+
+
 def plan_tile(c):
     """MM_PLAN_TILE(c) flag bits (0 when c is None: planner's choice)."""
     return 0 if c is None else ((int(c) + 1) << 8)
@@ -124,7 +129,7 @@ def check(status):
 
 def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None, ldc=None,
              fuse=False, overlap=False, leaf_u=False, split_pass=False, accumulate=False, tile=None,
-             peel=False, trans_b=False, unroll_base=False):
+             peel=False, trans_b=False, unroll_base=False, split_k=None):
     """Host-only plan listing and facts (no device needed)."""
     lib = load()
     lda = max(k, 1) if lda is None else lda
@@ -135,7 +140,8 @@ def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, l
             DTYPES.get(dtype, dtype), (MM_PLAN_FUSE if fuse else 0) | (MM_PLAN_OVERLAP if overlap else 0) |
             (MM_PLAN_LEAF_U if leaf_u else 0) | (MM_PLAN_SPLIT_PASS if split_pass else 0) |
             (MM_PLAN_ACCUMULATE if accumulate else 0) | (MM_PLAN_PEEL if peel else 0) |
-            (MM_PLAN_TRANS_B if trans_b else 0) | (MM_PLAN_UNROLL_BASE if unroll_base else 0) | plan_tile(tile))
+            (MM_PLAN_TRANS_B if trans_b else 0) | (MM_PLAN_UNROLL_BASE if unroll_base else 0) | plan_split_k(split_k) |
+            plan_tile(tile))
     need = lib.mm_describe(*args, None, 0, info, NINFO)
     if need == 0:
         raise MMError(1, last_error())

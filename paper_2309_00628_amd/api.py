@@ -49,7 +49,8 @@ class Plan:
 
     def __init__(self, algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None,
                  ldc=None, graph=False, device=None, tile=None, fuse=False, overlap=False, leaf_u=False,
-                 split_pass=False, accumulate=False, peel=False, trans_b=False, unroll_base=False):
+                 split_pass=False, accumulate=False, peel=False, trans_b=False, unroll_base=False,
+                 split_k=None):
         lib = L.load()
         self.algo, self.sched, self.dtype = algo, sched, dtype
         self.m, self.n, self.k = m, n, k
@@ -70,7 +71,8 @@ class Plan:
                                        (L.MM_PLAN_ACCUMULATE if accumulate else 0) |
                                        (L.MM_PLAN_PEEL if peel else 0) |
                                        (L.MM_PLAN_TRANS_B if trans_b else 0) |
-                                       (L.MM_PLAN_UNROLL_BASE if unroll_base else 0),
+                                       (L.MM_PLAN_UNROLL_BASE if unroll_base else 0) |
+                                       L.plan_split_k(split_k),
                                        ctypes.byref(self._ptr)))
         self.accumulate = accumulate
         info = (ctypes.c_int64 * L.NINFO)()
@@ -131,21 +133,21 @@ def workspace(nbytes, device, stream):
 
 def get_plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile=None,
              fuse=False, overlap=False, leaf_u=False, split_pass=False, accumulate=False, peel=False,
-             trans_b=False):
+             trans_b=False, split_k=None):
     key = (str(device), algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, tile, fuse,
-           overlap, leaf_u, split_pass, accumulate, peel, trans_b)
+           overlap, leaf_u, split_pass, accumulate, peel, trans_b, split_k)
     with _plans_lock:
         p = _plans.get(key)
         if p is None:
             p = Plan(algo, sched, m, n, k, cutoff, levels, dtype, lda, ldb, ldc, graph, device, tile, fuse,
-                     overlap, leaf_u, split_pass, accumulate, peel, trans_b)
+                     overlap, leaf_u, split_pass, accumulate, peel, trans_b, split_k=split_k)
             _plans[key] = p
     return p
 
 
 def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None, out=None,
        graph=False, stream=None, clobber_inputs=False, tile=None, fuse=False, overlap=None, leaf_u=None,
-       split_pass=False, beta=None, peel=False, trans_b=None):
+       split_pass=False, beta=None, peel=False, trans_b=None, split_k=None):
     """C = A @ B on the GPU by ``algo`` in {"naive", "strassen", "winograd"}.
 
     ``cutoff`` / ``levels`` control the recursion as in mm.h; when both are
@@ -161,7 +163,8 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
     accumulating form out = A @ B + beta * out (MM_PLAN_ACCUMULATE).  ``peel``:
     MM_PLAN_PEEL (grouped schedule: thin products for ragged edges instead of
     zero padding).  ``trans_b``: MM_PLAN_TRANS_B (None: the autotuner's choice
-    when it picks the recursion, else off).  The in-place
+    when it picks the recursion, else off).  ``split_k``: MM_PLAN_SPLIT_K for
+    plain products (None: the autotuner's choice when it picks the levels).  The in-place
     schedule overwrites its operands, so unless ``clobber_inputs`` is set the
     wrapper hands it copies.
     """
@@ -190,6 +193,13 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
     if cutoff is None and levels is None:
         if algo == "naive":
             cutoff, levels = 1, 0
+            from . import tuner
+            ch = tuner.choose(m, n, k, dt)
+            bp = ch.get("best_plain") or (ch if ch.get("levels") == 0 else {})
+            if tile is None:
+                tile = bp.get("tile")
+            if split_k is None:
+                split_k = bp.get("split_k")
         else:
             from . import tuner
             ch = tuner.choose(m, n, k, dt)
@@ -202,12 +212,15 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
                 leaf_u = bool(ch.get("leaf_u", False))
             if trans_b is None:
                 trans_b = bool(ch.get("trans_b", False))
+            if split_k is None:
+                split_k = ch.get("split_k")
     elif cutoff is None:
         cutoff = 1
     elif levels is None:
         levels = -1
     p = get_plan(algo, sched, m, n, k, cutoff, levels, dt, lda, ldb, ldc, graph, A.device, tile, fuse,
-                 bool(overlap), bool(leaf_u), bool(split_pass), beta is not None, bool(peel), bool(trans_b))
+                 bool(overlap), bool(leaf_u), bool(split_pass), beta is not None, bool(peel), bool(trans_b),
+                 split_k)
     with torch.cuda.device(A.device):
         p(A, B, C, stream=stream, beta=beta)
     return C

@@ -60,6 +60,9 @@ enum EwKind : int32_t {
   EW_STR_U_ACC = 20,  // i = P1..P7 C11 C12 C21 C22 ; o = fma(beta, Cij, EW_STR_U's Cij)
   // Transposing passes (trans kernel; every output holds the transpose):
   EW_WINO_T_TR = 21,  // i = B11 B12 B21 B22 ; o = T1' T2' T3' T4' B11' B21' B22' (T as EW_WINO_T)
+  // Split-k plain products (mode[0] = number of partial products np):
+  EW_SUM = 22,        // i = X0 .. X(np-1) ; o0 = ((X0 + X1) + X2) + ...
+  EW_SUM_ACC = 23,    // i = X0 .. X(np-1) C ; o0 = fma(beta, C, EW_SUM's sum)
 };
 
 constexpr int kEwMaxIn = 11;

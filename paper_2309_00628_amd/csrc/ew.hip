@@ -90,8 +90,9 @@ __global__ __launch_bounds__(kThreads) void ew_kernel(KernelBases kb, const EwPa
   const int kind = P.kind, nout = P.nout;
   // with beta == 0 the old C (the trailing inputs of the accumulating
   // recipes) is not read
-  const bool drop_c = kb.beta == 0.0 && (kind == EW_WINO_U_ACC || kind == EW_STR_U_ACC || kind == EW_AXPBY);
-  const int nin = drop_c ? (kind == EW_AXPBY ? 1 : 7) : P.nin;
+  const bool drop_c = kb.beta == 0.0 && (kind == EW_WINO_U_ACC || kind == EW_STR_U_ACC || kind == EW_AXPBY ||
+                                         kind == EW_SUM_ACC);
+  const int nin = drop_c ? (kind == EW_AXPBY ? 1 : (kind == EW_SUM_ACC ? P.mode[0] : 7)) : P.nin;
   const T beta = drop_c ? T(0) : T(kb.beta);
   bool vec = true;
   for (int i = 0; i < nin; ++i)
@@ -194,6 +195,18 @@ __global__ __launch_bounds__(kThreads) void ew_kernel(KernelBases kb, const EwPa
           break;
         }
         case EW_AXPBY: y[0][e] = fma(beta, x[1][e], x[0][e]); break;  // x = X C
+        case EW_SUM:
+        case EW_SUM_ACC: {  // x = X0 .. X(np-1) (C)
+          const int np = P.mode[0];
+          T s = x[0][e], c = T(0);
+#pragma unroll
+          for (int i = 1; i < kEwMaxIn; ++i) {
+            if (i < np) s = s + x[i][e];
+            if (i == np) c = x[i][e];
+          }
+          y[0][e] = kind == EW_SUM_ACC ? fma(beta, c, s) : s;
+          break;
+        }
         case EW_STR_S: {  // x = A11 A12 A21 A22
           y[0][e] = x[0][e] + x[3][e];
           y[1][e] = x[2][e] + x[3][e];

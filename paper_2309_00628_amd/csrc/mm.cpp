@@ -92,6 +92,7 @@ struct Plan {
   bool peel = false;        // grouped: peel ragged rows / columns / k instead of padding
   bool trans_b = false;     // grouped Winograd float32: last-level B operands stored transposed
   bool unroll_base = false; // grouped Winograd: leaves of order 1, 2, 4 by the unrolled base cases
+  int split_k = 1;          // plain product: k split over this many partial products
   int64_t pm = 0, pn = 0, pk = 0;  // peeled: the leading block the recursion runs on
   bool has_aux = false;  // some launches go to the auxiliary stream
   struct Aux {
@@ -280,6 +281,10 @@ struct Builder {
   // ---- element-wise parts ------------------------------------------------
   void ew_part(int kind, int64_t rows, int64_t cols, std::initializer_list<MView> ins,
                std::initializer_list<MView> outs, int mode0 = 0, int mode1 = 0) {
+    ew_parts(kind, rows, cols, std::vector<MView>(ins), std::vector<MView>(outs), mode0, mode1);
+  }
+  void ew_parts(int kind, int64_t rows, int64_t cols, const std::vector<MView>& ins,
+                const std::vector<MView>& outs, int mode0 = 0, int mode1 = 0) {
     if (!gm.empty() || !wl.empty()) flush();
     EwPart p;
     std::memset(&p, 0, sizeof p);
@@ -1293,6 +1298,23 @@ int build_plan(Plan& P) {
         b.ew_part(EW_AXPBY, m, n, {b.view(MB_C, 0, P.ldc, m, n, 0, 0), C}, {C});
       else
         b.ew_part(EW_ZERO, m, n, {}, {C});
+    } else if (P.split_k > 1 && !P.spl && ceil_div(k, round_up(ceil_div(k, P.split_k), 64)) > 1) {
+      // split k: the parts' partial products run in one grouped launch (the
+      // whole GPU busy when C alone has few tiles), then one pass sums them
+      // in order (and applies beta)
+      const int64_t kc = round_up(ceil_div(k, P.split_k), 64);
+      const int np = (int)ceil_div(k, kc);
+      std::vector<MView> parts;
+      for (int i = 0; i < np; ++i) {
+        const int64_t k0 = i * kc, kl = std::min(kc, k - k0);
+        const MView Pi = b.temp(m, n);
+        parts.push_back(Pi);
+        b.gemm(b.view(MB_A, k0, P.lda, m, kl, m, kl), b.view(MB_B, k0 * P.ldb, P.ldb, kl, n, kl, n),
+               {Builder::store(Pi)});
+      }
+      b.flush();
+      if (P.accumulate) parts.push_back(b.view(MB_C, 0, P.ldc, m, n, m, n));
+      b.ew_parts(P.accumulate ? EW_SUM_ACC : EW_SUM, m, n, parts, std::vector<MView>{C}, np);
     } else if (P.dtype != MM_BF16X3_REFINED && (P.lda % b.E || P.ldb % b.E || k % b.E || n % b.E) &&
                m >= 64 && n >= 64 && k >= 64 && (double)m * n * k >= 134217728.0) {
       // Operands that cannot be read in 16-byte chunks (a leading dimension
@@ -1617,6 +1639,9 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   P->peel = (flags & MM_PLAN_PEEL) != 0;
   P->trans_b = (flags & MM_PLAN_TRANS_B) != 0 && dtype == MM_F32 && algo == MM_ALGO_WINOGRAD &&
                resolve_sched(algo, sched) == MM_SCHED_GROUPED;
+  P->split_k = (int)((flags >> 16) & 0xf);
+  if (P->split_k > 8) return fail(MM_E_INVALID, "MM_PLAN_SPLIT_K allows at most 8 parts");
+  if (P->split_k < 1) P->split_k = 1;
   P->unroll_base = (flags & MM_PLAN_UNROLL_BASE) != 0 && dtype != MM_BF16X3_REFINED &&
                    algo == MM_ALGO_WINOGRAD && resolve_sched(algo, sched) == MM_SCHED_GROUPED;
   // the fused Winograd leaf level computes in float32 and replaces the

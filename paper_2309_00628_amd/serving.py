@@ -158,14 +158,14 @@ class GpuExecutor:
         ch = tuner.choose(r.m, r.n, r.k, r.dtype)
         algo = "winograd" if ch["levels"] > 0 else "naive"
         return (algo, ch["levels"], ch["tile"], bool(ch.get("overlap", False)), bool(ch.get("leaf_u", False)),
-                bool(ch.get("trans_b", False)))
+                bool(ch.get("trans_b", False)), ch.get("split_k") if ch["levels"] == 0 else None)
 
     def plan(self, r):
         from . import api
-        algo, levels, tile, overlap, leaf_u, trans_b = self.choice(r)
+        algo, levels, tile, overlap, leaf_u, trans_b, split_k = self.choice(r)
         return api.get_plan(algo, "grouped" if levels else "auto", r.m, r.n, r.k, 1, levels, r.dtype,
                             max(r.k, 1), max(r.n, 1), max(r.n, 1), False, self.device, tile,
-                            overlap=overlap, leaf_u=leaf_u, trans_b=trans_b)
+                            overlap=overlap, leaf_u=leaf_u, trans_b=trans_b, split_k=split_k)
 
     def need_bytes(self, r):
         esz = 8 if r.dtype == "f64" else 4

@@ -80,7 +80,7 @@ def rule_of_thumb(m, n, k, dtype):
     while L < 2 and min(m, n, k) >> (L + 1) >= leaf:
         L += 1
     return {"levels": L, "tile": None, "cutoff": 1, "overlap": False, "leaf_u": False, "trans_b": False,
-            "source": "rule"}
+            "split_k": None, "source": "rule"}
 
 
 def choose(m, n, k, dtype="f32"):
@@ -119,17 +119,26 @@ TILES = {"f32": (None, 0, 3, 4), "bf16x3": (None, 0, 1, 3, 4), "f64": (None,)}
 LEAF_U_TILES = (None, 0, 1, 2)  # tiles of the fused last-level kernel (float32)
 
 
-def candidates(dtype, L_, tiles=None):
-    """(tile, overlap, leaf_u, trans_b) tuples tried at L_ levels."""
+def candidates(dtype, L_, tiles=None, k=None):
+    """Option sets tried at L_ levels: dicts of tile, overlap, leaf_u,
+    trans_b and split_k (the plain product's k split, when k allows it)."""
+    def c(tile, overlap=False, leaf_u=False, trans_b=False, split_k=None):
+        return dict(tile=tile, overlap=overlap, leaf_u=leaf_u, trans_b=trans_b, split_k=split_k)
     out = []
     for tile in (tiles or TILES.get(dtype, (None,))):
         for ov in ((False, True) if L_ else (False,)):
-            out.append((tile, ov, False, False))
+            out.append(c(tile, overlap=ov))
         if L_ and dtype == "f32":
-            out.append((tile, False, False, True))
+            out.append(c(tile, trans_b=True))
+    if L_ == 0 and dtype in ("f32", "bf16x3") and tiles is None and k is not None:
+        out += [c(None, split_k=s) for s in SPLIT_K if k >= 64 * s]
     if L_ and dtype == "f32" and tiles is None:
-        out += [(tile, False, True, False) for tile in LEAF_U_TILES]
+        out += [c(tile, leaf_u=True) for tile in LEAF_U_TILES]
     return out
+
+
+# k splits tried for the plain product (they pay when C has few tiles)
+SPLIT_K = (2, 4, 8)
 
 
 # An option (overlap, fused last level) is chosen only when it beats the
@@ -157,16 +166,16 @@ def tune(m, n, k, dtype="f32", max_levels=3, reps=5, warmup=2, tiles=None, save=
     for L_ in range(0, max_levels + 1):
         if L_ > 0 and min(m, n, k) >> L_ < 64:
             break
-        for tile, ov, lu, tb in candidates(dtype, L_, tiles):
+        for opt in candidates(dtype, L_, tiles, k):
             algo = "naive" if L_ == 0 else "winograd"
+            key = (L_, opt["tile"], opt["overlap"], opt["leaf_u"], opt["trans_b"], opt["split_k"])
             try:
-                p = api.Plan(algo, "grouped" if L_ else "auto", m, n, k, cutoff=1, levels=L_,
-                             dtype=dtype, tile=tile, overlap=ov, leaf_u=lu, trans_b=tb)
+                p = api.Plan(algo, "grouped" if L_ else "auto", m, n, k, cutoff=1, levels=L_, dtype=dtype, **opt)
             except Exception as e:  # an unsupported candidate is skipped
                 if verbose:
-                    print(f"  skip L={L_} tile={tile} overlap={ov} leaf_u={lu} trans_b={tb}: {e}")
+                    print(f"  skip L={L_} {opt}: {e}")
                 continue
-            cands.append(((L_, tile, ov, lu, tb), p))
+            cands.append((key, p))
     if not cands:
         raise RuntimeError("no tuning candidate")
     warm_until = time.perf_counter() + 0.1
@@ -181,16 +190,16 @@ def tune(m, n, k, dtype="f32", max_levels=3, reps=5, warmup=2, tiles=None, save=
         t = sorted(ts)[len(ts) // 2]
         results.append((t,) + key)
         if verbose:
-            L_, tile, ov, lu, tb = key
-            print(f"  {dtype} {m}x{n}x{k} L={L_} tile={tile} overlap={int(ov)} leaf_u={int(lu)} trans_b={int(tb)}: "
-                  f"{t:.3f} ms {2.0 * m * n * k / t / 1e9:.1f} TFLOP/s", flush=True)
+            L_, tile, ov, lu, tb, sk = key
+            print(f"  {dtype} {m}x{n}x{k} L={L_} tile={tile} overlap={int(ov)} leaf_u={int(lu)} trans_b={int(tb)} "
+                  f"split_k={sk}: {t:.3f} ms {2.0 * m * n * k / t / 1e9:.1f} TFLOP/s", flush=True)
     def score(r):
-        return r[0] * (1.0 + OPTION_MARGIN if (r[3] or r[4] or r[5]) else 1.0)
+        return r[0] * (1.0 + OPTION_MARGIN if (r[3] or r[4] or r[5] or r[6]) else 1.0)
 
-    t, L_, tile, ov, lu, tb = min(results, key=score)
+    t, L_, tile, ov, lu, tb, sk = min(results, key=score)
     leaf = min(m, n, k) >> L_
     # the cutoff that stops the recursion after L_ halvings: the leaf order
-    entry = {"levels": L_, "tile": tile, "overlap": ov, "leaf_u": lu, "trans_b": tb,
+    entry = {"levels": L_, "tile": tile, "overlap": ov, "leaf_u": lu, "trans_b": tb, "split_k": sk,
              "cutoff": leaf if L_ else min(m, n, k),
              "ms": round(t, 4), "tflops": round(2.0 * m * n * k / t / 1e9, 2),
              "shape": [m, n, k]}
@@ -199,12 +208,12 @@ def tune(m, n, k, dtype="f32", max_levels=3, reps=5, warmup=2, tiles=None, save=
     # product when it does not win)
     plain = [r for r in results if r[1] == 0]
     if plain:
-        t0, _, tile0, _, _, _ = min(plain, key=lambda r: r[0])
-        entry["best_plain"] = {"levels": 0, "tile": tile0, "ms": round(t0, 4),
+        t0, _, tile0, _, _, _, sk0 = min(plain, key=score)
+        entry["best_plain"] = {"levels": 0, "tile": tile0, "split_k": sk0, "ms": round(t0, 4),
                                "tflops": round(2.0 * m * n * k / t0 / 1e9, 2)}
     rec = [r for r in results if r[1] > 0]
     if rec:
-        t2, L2, tile2, ov2, lu2, tb2 = min(rec, key=score)
+        t2, L2, tile2, ov2, lu2, tb2, _ = min(rec, key=score)
         entry["best_recursive"] = {"levels": L2, "tile": tile2, "overlap": ov2, "leaf_u": lu2, "trans_b": tb2,
                                    "ms": round(t2, 4), "tflops": round(2.0 * m * n * k / t2 / 1e9, 2)}
     arch = _arch()
@@ -229,7 +238,8 @@ def main(argv=None):
         for n in [int(x) for x in args.n.split(",")]:
             e = tune(n, n, n, dt, max_levels=args.max_levels, reps=args.reps, verbose=True)
             print(f"{dt} n={n}: levels={e['levels']} tile={e['tile']} overlap={e['overlap']} "
-                  f"leaf_u={e['leaf_u']} trans_b={e['trans_b']} {e['tflops']} TFLOP/s", flush=True)
+                  f"leaf_u={e['leaf_u']} trans_b={e['trans_b']} split_k={e.get('split_k')} {e['tflops']} TFLOP/s",
+                  flush=True)
     if args.copy_to:
         shutil.copy(cache_path(), args.copy_to)
 

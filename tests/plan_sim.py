@@ -23,6 +23,7 @@ EW_IP_A, EW_IP_B, EW_IP_U, EW_DIST, EW_ZERO = 7, 8, 9, 10, 11
 EW_SPLIT, EW_WINO_S_SPL, EW_WINO_T_SPL, EW_WINO_U_ACC, EW_AXPBY = 12, 13, 14, 15, 16
 EW_STR_S, EW_STR_T, EW_STR_U, EW_STR_U_ACC = 17, 18, 19, 20
 EW_WINO_T_TR = 21
+EW_SUM, EW_SUM_ACC = 22, 23
 OK_TRANS = 9
 GM_STORE, GM_ADD, GM_AXPBY = 1, 2, 3
 MB_A, MB_B, MB_C, MB_WS, MB_ABS = 0, 1, 2, 3, 4
@@ -452,6 +453,12 @@ def run(text, bufs, hazards=True, beta=1):
                     y = [beta * c + v for c, v in zip(x[7:], u)]
                 elif it["kind"] == EW_AXPBY:
                     y = [beta * x[1] + x[0]]
+                elif it["kind"] in (EW_SUM, EW_SUM_ACC):
+                    npart = it["mode"][0]
+                    s = x[0]
+                    for v in x[1:npart]:
+                        s = s + v
+                    y = [beta * x[npart] + s if it["kind"] == EW_SUM_ACC else s]
                 else:
                     y = _recipe(it["kind"], x, it["mode"])
                 results.append(list(zip(it["outs"], y)))

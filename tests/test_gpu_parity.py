@@ -619,3 +619,25 @@ def test_unrolled_base_case_bitwise(api, naive, dt):
         else:
             assert rel_fro(C.cpu().numpy(), naive.gemm(A, B)) < tol
         del p, got
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64", "bf16x3"])
+@pytest.mark.parametrize("m,n,k,s", [(256, 256, 1024, 4), (300, 200, 777, 8), (512, 384, 2048, 2)])
+def test_split_k_plain_product(api, naive, dt, m, n, k, s):
+    # MM_PLAN_SPLIT_K against the oracle, exact on integers, accumulating
+    npdt = np.float64 if dt == "f64" else np.float32
+    tol = 1e-12 if dt == "f64" else 1e-5
+    A, B = inputs.pair("uniform", m, n, k, 64, npdt)
+    got = gpu_mm(api, A, B, algo="naive", dtype=dt, split_k=s)
+    assert rel_fro(got, naive.gemm(A, B)) < tol
+    Ai, Bi = inputs.pair("int", m, n, k, 65, npdt)
+    assert np.array_equal(gpu_mm(api, Ai, Bi, algo="naive", dtype=dt, split_k=s).astype(np.float64),
+                          naive.gemm(Ai, Bi))
+    C0 = inputs.uniform((m, n), 66, dtype=npdt)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    for beta in (0.5, 0.0):
+        C = torch.from_numpy(C0.copy()).cuda() if beta else torch.full((m, n), float("nan"), dtype=At.dtype,
+                                                                        device="cuda")
+        api.mm(At, Bt, algo="naive", dtype=dt, split_k=s, out=C, beta=beta)
+        torch.cuda.synchronize()
+        assert rel_fro(C.cpu().numpy(), naive.gemm(A, B) + beta * C0.astype(np.float64)) < tol

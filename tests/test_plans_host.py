@@ -556,3 +556,21 @@ def test_unrolled_base_case_only_for_tiny_leaves(lib):
     assert "BASE" not in text and "LAUNCH GEMM" in text
     text, _ = L.describe("winograd", "grouped", 64, 64, 64, cutoff=1, levels=4, dtype="f64", unroll_base=True)
     assert [l.split()[4] for l in text.splitlines() if l.startswith("LAUNCH BASE")] == ["4"]
+
+
+@pytest.mark.parametrize("m,n,k,s", [(64, 48, 256, 2), (100, 60, 300, 4), (33, 17, 1000, 8), (64, 64, 64, 4)])
+@pytest.mark.parametrize("acc", [False, True])
+def test_split_k_plans_are_exact(lib, m, n, k, s, acc):
+    # MM_PLAN_SPLIT_K: partial products over k ranges (multiples of 64) in one
+    # grouped launch, then one ordered sum (with beta when accumulating)
+    A = inputs.integers((m, k), 61, dtype=np.int64)
+    B = inputs.integers((k, n), 62, dtype=np.int64)
+    C0 = inputs.integers((m, n), 63, dtype=np.int64)
+    text, info = L.describe("naive", "auto", m, n, k, dtype="f32", split_k=s, accumulate=acc)
+    parts = -(-k // (-(-(-(-k // s)) // 64) * 64))
+    launches = [l.split()[1] for l in text.splitlines() if l.startswith("LAUNCH")]
+    assert launches == (["GEMM", "EW"] if parts > 1 else ["GEMM"])
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    C = C0.ravel().copy()
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws}, beta=3)
+    assert np.array_equal(C.reshape(m, n), A @ B + (3 * C0 if acc else 0))
