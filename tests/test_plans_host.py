@@ -574,3 +574,23 @@ def test_split_k_plans_are_exact(lib, m, n, k, s, acc):
     C = C0.ravel().copy()
     plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws}, beta=3)
     assert np.array_equal(C.reshape(m, n), A @ B + (3 * C0 if acc else 0))
+
+
+@pytest.mark.parametrize("m,n,k,levels", [(64, 48, 40, 2), (50, 70, 30, 1)])
+def test_option_combinations_are_exact(lib, m, n, k, levels):
+    # every combination of up to three grouped-schedule options gives the
+    # exact product (accumulating ones A B + 2 C) and hazard-free launches
+    import itertools
+    A = inputs.integers((m, k), 67, dtype=np.int64)
+    B = inputs.integers((k, n), 68, dtype=np.int64)
+    C0 = inputs.integers((m, n), 69, dtype=np.int64)
+    opts = ("overlap", "leaf_u", "fuse", "trans_b", "peel", "accumulate")
+    for r in range(4):
+        for combo in itertools.combinations(opts, r):
+            text, info = L.describe("winograd", "grouped", m, n, k, cutoff=1, levels=levels, dtype="f32",
+                                    **{o: True for o in combo})
+            ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+            C = C0.ravel().copy()
+            plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws}, beta=2)
+            want = A @ B + (2 * C0 if "accumulate" in combo else 0)
+            assert np.array_equal(C.reshape(m, n), want), combo
