@@ -641,3 +641,20 @@ def test_split_k_plain_product(api, naive, dt, m, n, k, s):
         api.mm(At, Bt, algo="naive", dtype=dt, split_k=s, out=C, beta=beta)
         torch.cuda.synchronize()
         assert rel_fro(C.cpu().numpy(), naive.gemm(A, B) + beta * C0.astype(np.float64)) < tol
+
+
+@pytest.mark.parametrize("m,n,k,levels", [(1024, 1024, 1024, 1), (1000, 777, 555, 2)])
+def test_option_combinations_bitwise(api, m, n, k, levels):
+    # pairs of the grouped options that keep the bits give the bits of the
+    # plain grouped plan
+    import itertools
+    A, B = inputs.pair("uniform", m, n, k, 70, np.float32)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    ref = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, overlap=False,
+                 leaf_u=False, trans_b=False)
+    for combo in itertools.combinations(("overlap", "leaf_u", "fuse", "trans_b"), 2):
+        kw = dict(overlap=False, leaf_u=False, trans_b=False, fuse=False)
+        kw.update({o: True for o in combo})
+        C = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(C, ref), combo
