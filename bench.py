@@ -174,8 +174,9 @@ def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtyp
 
 
 def source_digest():
-    """SHA-256 over the library sources (csrc/ and include/), to tell
-    whether stored counter results were taken with the kernels built now."""
+    """SHA-256 over the library sources (csrc/ and include/) and the build
+    script (compiler flags), to tell whether stored counter results were
+    taken with the kernels built now."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
@@ -185,6 +186,8 @@ def source_digest():
                 h.update(name.encode())
                 with open(os.path.join(root, d, name), "rb") as f:
                     h.update(f.read())
+    with open(os.path.join(root, "paper_2309_00628_amd", "build.py"), "rb") as f:
+        h.update(f.read())
     return h.hexdigest()
 
 

@@ -26,9 +26,16 @@ FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE,
          "-Wno-unused-command-line-argument"]
 
 
+# Per-source flags.  The leaf-product GEMM's K loop is scheduled with LLVM's
+# memory-clause strategy, which keeps its fragment reads together ahead of
+# the MFMAs that use them (measured +0.2 to +2 % over the default scheduler,
+# most for the 128x128 tiles).
+EXTRA = {"gemm.hip": ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]}
+
+
 def _compile(src):
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
