@@ -13,12 +13,15 @@ LIB = os.path.join(HERE, "_liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
+    # a private temporary per process, renamed into place: processes that
+    # build at the same time (parallel test workers) never see a partial file
+    tmp = f"{LIB}.{os.getpid()}.tmp"
     cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-std=c11", SRC, "-o", LIB + ".tmp"]
+           "-fPIC", "-shared", "-std=c11", SRC, "-o", tmp]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(tmp, LIB)
     return LIB
 
 

@@ -28,7 +28,7 @@ MM_PLAN_SPLIT_PASS = 16
 MM_PLAN_ACCUMULATE = 32
 MM_PLAN_PEEL = 64
 MM_PLAN_TRANS_B = 128
-MM_PLAN_UNROLL_BASE = 256
+MM_PLAN_UNROLL_BASE = 0x100000
 
 
 def plan_split_k(s):

@@ -74,6 +74,31 @@ def test_naive_gemm_unaligned_copies(api, naive, dtype, m, n, k):
     assert rel_fro(got, naive.gemm(A, B)) < tol
 
 
+@pytest.mark.parametrize("m,n,k", [(1024, 768, 512), (600, 520, 300), (1100, 260, 1000)])
+def test_every_float32_tile_configuration(api, naive, m, n, k):
+    # each float32 tile shape (MM_PLAN_TILE 0 .. 7) of the plain product and
+    # of a Winograd level: within tolerance of the oracle, and bitwise equal
+    # to each other (every tile shape accumulates k in the same order)
+    A, B = inputs.pair("uniform", m, n, k, 60, np.float32)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    ref = naive.gemm(A, B)
+    for algo, levels in (("naive", 0), ("winograd", 1)):
+        first = None
+        for tile in range(8):
+            print(f"tile {tile} {algo} {m}x{n}x{k}", flush=True)
+            C = torch.full((m, n), float("nan"), device="cuda")
+            if algo == "naive":
+                api.mm(At, Bt, algo="naive", tile=tile, out=C)
+            else:
+                api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=levels, tile=tile, out=C)
+            torch.cuda.synchronize()
+            assert rel_fro(C.cpu().numpy(), ref) < (2e-6 if levels == 0 else 1e-5), tile
+            if first is None:
+                first = C
+            else:
+                assert torch.equal(C, first), tile
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_naive_gemm_exact_on_integers(api, naive, dtype):
     A, B = inputs.pair("int", 300, 200, 250, 4, dtype)

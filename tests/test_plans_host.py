@@ -6,6 +6,8 @@ schedule must reproduce the oracle's product exactly, with no two operations
 of one launch conflicting, and the plan facts (levels, padding, workspace,
 launches) must follow the paper's formulas.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -556,6 +558,35 @@ def test_unrolled_base_case_only_for_tiny_leaves(lib):
     assert "BASE" not in text and "LAUNCH GEMM" in text
     text, _ = L.describe("winograd", "grouped", 64, 64, 64, cutoff=1, levels=4, dtype="f64", unroll_base=True)
     assert [l.split()[4] for l in text.splitlines() if l.startswith("LAUNCH BASE")] == ["4"]
+
+
+def test_plan_flag_fields_are_disjoint():
+    # the single-bit options, the tile field MM_PLAN_TILE (bits 8-15) and the
+    # k-split field MM_PLAN_SPLIT_K (bits 16-19) of include/mm.h share no bit
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mm.h")).read()
+    bits = {name: int(v, 0) for name, v in re.findall(r"#define (MM_PLAN_[A-Z_]+) (0x[0-9a-fA-F]+|[0-9]+)u", hdr)}
+    assert len(bits) >= 9
+    fields = {"TILE": 0xff << 8, "SPLIT_K": 0xf << 16}
+    seen = 0
+    for name, b in list(bits.items()) + list(fields.items()):
+        assert b and seen & b == 0, name
+        seen |= b
+    for name, b in bits.items():
+        assert getattr(L, name) == b, name
+    assert L.plan_tile(7) == 8 << 8 and L.plan_split_k(8) == 8 << 16
+
+
+def test_tile_choice_and_unrolled_base_are_independent(lib):
+    # forcing tile 0 (field value 1) leaves the MFMA leaves in place, and the
+    # unrolled base cases leave the planner's tile choice alone
+    text, _ = L.describe("winograd", "grouped", 16, 16, 16, cutoff=1, levels=2, tile=0)
+    assert "BASE" not in text and "LAUNCH GEMM" in text
+    for tile in (None, 3, 7):
+        a, _ = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=1, tile=tile)
+        b, _ = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=1, tile=tile,
+                          unroll_base=True)
+        assert a == b
 
 
 @pytest.mark.parametrize("m,n,k,s", [(64, 48, 256, 2), (100, 60, 300, 4), (33, 17, 1000, 8), (64, 64, 64, 4)])
