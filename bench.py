@@ -147,14 +147,14 @@ def tuned_leaf(tuner, n, levels):
     return None, False, False, False
 
 
-def tuned_plain_tile(tuner, n, dtype="f32"):
-    """The autotuner's fastest tile for the plain n x n x n product."""
+def tuned_plain(tuner, n, dtype="f32"):
+    """The autotuner's fastest (tile, k split) for the plain n x n x n product."""
     ch = tuner.choose(n, n, n, dtype)
     if ch["source"] != "tuned":
-        return None
+        return None, None
     if ch.get("best_plain"):
-        return ch["best_plain"]["tile"]
-    return ch["tile"] if ch["levels"] == 0 else None
+        return ch["best_plain"]["tile"], ch["best_plain"].get("split_k")
+    return (ch["tile"], ch.get("split_k")) if ch["levels"] == 0 else (None, None)
 
 
 def pct(xs, q):
@@ -163,9 +163,9 @@ def pct(xs, q):
 
 
 def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtype="f32", tile=None,
-                overlap=False, leaf_u=False, trans_b=False):
+                overlap=False, leaf_u=False, trans_b=False, split_k=None):
     plan = api.Plan(algo, sched, n, n, n, cutoff=1, levels=levels, dtype=dtype, tile=tile, overlap=overlap,
-                    leaf_u=leaf_u, trans_b=trans_b)
+                    leaf_u=leaf_u, trans_b=trans_b, split_k=split_k)
     ws = torch.empty(max(plan.ws_bytes, 256), dtype=torch.uint8, device=A.device)
     C = torch.empty((n, n), dtype=A.dtype, device=A.device)
     wall, step_ms, per_op, kinds = time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup)
@@ -286,8 +286,8 @@ def profile_set(torch, api, L, inputs, tuner, args):
     out = {"profile_set": args.profile_set, "n": n}
     if args.profile_set == "gemm":
         A, B = [torch.from_numpy(x).cuda() for x in inputs.pair("uniform", n, n, n, 0, np.float32)]
-        p = run_product(torch, api, L, "naive", "auto", n, 0, A, B, args.steps, args.warmup,
-                        tile=tuned_plain_tile(tuner, n))
+        pt, pk = tuned_plain(tuner, n)
+        p = run_product(torch, api, L, "naive", "auto", n, 0, A, B, args.steps, args.warmup, tile=pt, split_k=pk)
         out["plain_tflops"] = round(p["tflops"], 2)
         ch = tuner.choose(n, n, n, "f32")
         rec = ch.get("best_recursive") if ch["source"] == "tuned" else None
@@ -335,13 +335,13 @@ def bench_precision(torch, api, L, inputs, tuner, n=8192, steps=10, warmup=10, r
                                ("f32_winograd_L2", "winograd", 2, "f32"),
                                ("f32_plain", "naive", 0, "f32")):
         ch = tuner.choose(n, n, n, dt)
-        tile = None
+        tile, sk = None, None
         for c in (ch, ch.get("best_recursive") or {}, ch.get("best_plain") or {}):
             if ch["source"] == "tuned" and c.get("levels") == lv:
-                tile = c["tile"]
+                tile, sk = c["tile"], (c.get("split_k") if lv == 0 else None)
                 break
         r = run_product(torch, api, L, algo, "grouped" if lv else "auto", n, lv, A, B, steps, warmup,
-                        dtype=dt, tile=tile)
+                        dtype=dt, tile=tile, split_k=sk)
         out[name] = {"tflops": round(r["tflops"], 3), "p50_ms": round(r["p50"], 4),
                      "rel_err": rel_err(r["C"], sample, ref), "tile": tile}
         print(f"# precision {name}: {out[name]}", file=sys.stderr, flush=True)
@@ -501,9 +501,9 @@ def main():
                           "tflops": round(win["tflops"], 3),
                           "roofline": gemm_roofline(win, n)}), flush=True)
         return
-    plain_tile = tuned_plain_tile(tuner, n)
+    plain_tile, plain_split = tuned_plain(tuner, n)
     plain = run_product(torch, api, L, "naive", "auto", n, 0, A, B, args.steps, args.warmup,
-                        tile=plain_tile)
+                        tile=plain_tile, split_k=plain_split)
     print(f"# plain mfma gemm: {plain['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
     # Strassen (Section 2.2) breadth first at the same levels and leaf tile
     # (a tile of the fused leaf-level kernel names another kernel: then the default)
@@ -542,7 +542,7 @@ def main():
         "p50_ms": round(win["p50"], 4),
         "p99_ms": round(win["p99"], 4),
         "plain_gemm": {"tflops": round(plain["tflops"], 3), "p50_ms": round(plain["p50"], 4),
-                       "p99_ms": round(plain["p99"], 4)},
+                       "p99_ms": round(plain["p99"], 4), "tile": plain_tile, "split_k": plain_split},
         "speedup_vs_plain": round(win["tflops"] / plain["tflops"], 4),
         "strassen_grouped": {"levels": levels, "tflops": round(strs["tflops"], 3),
                              "p50_ms": round(strs["p50"], 4), "p99_ms": round(strs["p99"], 4)},
@@ -565,8 +565,8 @@ def main():
         for n2, lvls in ((3000, (1, 2)), (8192, (1, 2))):
             A2_np, B2_np = inputs.pair("uniform", n2, n2, n2, 1, np.float32)
             A2, B2 = torch.from_numpy(A2_np).cuda(), torch.from_numpy(B2_np).cuda()
-            p2 = run_product(torch, api, L, "naive", "auto", n2, 0, A2, B2, 20, 10,
-                             tile=tuned_plain_tile(tuner, n2))
+            pt2, pk2 = tuned_plain(tuner, n2)
+            p2 = run_product(torch, api, L, "naive", "auto", n2, 0, A2, B2, 20, 10, tile=pt2, split_k=pk2)
             e = {"plain_tflops": round(p2["tflops"], 3)}
             for lv in lvls:
                 t2, o2, u2, b2 = tuned_leaf(tuner, n2, lv)

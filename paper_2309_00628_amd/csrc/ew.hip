@@ -76,20 +76,21 @@ __device__ inline void store_chunk(const KernelBases& kb, const MView& v, int r,
   }
 }
 
-// Fast path of the Strassen-Winograd passes (S / T / U of Section 2.3) over
-// blocks whose every input and output is entirely valid and 16-byte
-// aligned: no bounds checks, and the loads of all of a thread's chunks are
-// issued before its first store (the stores could otherwise alias later
-// loads, which would serialise the chunks).  The arithmetic is that of the
+// Fast path of the Winograd passes (S / T / U of Section 2.3) and of
+// Strassen's (Section 2.2) over blocks whose every input and output is
+// entirely valid and 16-byte aligned: no bounds checks, and the loads of all
+// of a thread's chunks are issued before its first store (the stores could
+// otherwise alias later loads, which would serialise the chunks).  The arithmetic is that of the
 // general path, in the same order.  Measured (n = 4096 and 8192): S/T
 // passes at 5.2-5.5 TB/s (4.6-5.0 in the general path), U passes at
 // 5.6-6.1 TB/s (4.6-5.1).
 template <typename T, int KIND>
-__device__ __forceinline__ void wino_fast(const KernelBases& kb, const EwPart& P, int64_t first, int64_t total,
+__device__ __forceinline__ void pass_fast(const KernelBases& kb, const EwPart& P, int64_t first, int64_t total,
                                           int cpr) {
   constexpr int V = VecT<T>::N;
-  constexpr int NIN = KIND == EW_WINO_U ? 7 : 4;
-  constexpr int NOUT = 4;
+  constexpr bool U = KIND == EW_WINO_U || KIND == EW_STR_U;
+  constexpr int NIN = U ? 7 : 4;
+  constexpr int NOUT = (KIND == EW_STR_S || KIND == EW_STR_T) ? 5 : 4;
   typedef typename VecT<T>::type vt;
   const T* ip[NIN];
   T* op[NOUT];
@@ -116,7 +117,7 @@ __device__ __forceinline__ void wino_fast(const KernelBases& kb, const EwPart& P
 #pragma unroll
     for (int i = 0; i < NIN; ++i) {
       const vt* src = reinterpret_cast<const vt*>(ip[i] + at_in[it][i]);
-      x[it][i] = KIND == EW_WINO_U ? __builtin_nontemporal_load(src) : *src;
+      x[it][i] = U ? __builtin_nontemporal_load(src) : *src;
     }
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
@@ -136,6 +137,23 @@ __device__ __forceinline__ void wino_fast(const KernelBases& kb, const EwPart& P
         const T t3 = x[it][3][e] - x[it][1][e];
         const T t4 = t2 - x[it][2][e];
         y[0][e] = t1; y[1][e] = t2; y[2][e] = t3; y[3][e] = t4;
+      } else if (KIND == EW_STR_S) {  // x = A11 A12 A21 A22
+        y[0][e] = x[it][0][e] + x[it][3][e];
+        y[1][e] = x[it][2][e] + x[it][3][e];
+        y[2][e] = x[it][0][e] + x[it][1][e];
+        y[3][e] = x[it][2][e] - x[it][0][e];
+        y[4][e] = x[it][1][e] - x[it][3][e];
+      } else if (KIND == EW_STR_T) {  // x = B11 B12 B21 B22
+        y[0][e] = x[it][0][e] + x[it][3][e];
+        y[1][e] = x[it][1][e] - x[it][3][e];
+        y[2][e] = x[it][2][e] - x[it][0][e];
+        y[3][e] = x[it][0][e] + x[it][1][e];
+        y[4][e] = x[it][2][e] + x[it][3][e];
+      } else if (KIND == EW_STR_U) {  // x = P1..P7
+        y[0][e] = ((x[it][0][e] + x[it][3][e]) - x[it][4][e]) + x[it][6][e];
+        y[1][e] = x[it][2][e] + x[it][4][e];
+        y[2][e] = x[it][1][e] + x[it][3][e];
+        y[3][e] = ((x[it][0][e] + x[it][2][e]) - x[it][1][e]) + x[it][5][e];
       } else {  // x = P1..P7
         const T u1 = x[it][0][e] + x[it][1][e];
         const T u2 = x[it][0][e] + x[it][5][e];
@@ -193,13 +211,17 @@ __global__ __launch_bounds__(kThreads) void ew_kernel(KernelBases kb, const EwPa
   const int cpr = (P.cols + V - 1) / V;
   const int64_t total = (int64_t)P.rows * cpr;
   const int64_t first = (int64_t)(b - P.blk_start) * (kThreads * kItems) + threadIdx.x;
-  if ((kind == EW_WINO_S || kind == EW_WINO_T || kind == EW_WINO_U) && first < total && part_full<T>(kb, P)) {
-    if (kind == EW_WINO_S)
-      wino_fast<T, EW_WINO_S>(kb, P, first, total, cpr);
-    else if (kind == EW_WINO_T)
-      wino_fast<T, EW_WINO_T>(kb, P, first, total, cpr);
-    else
-      wino_fast<T, EW_WINO_U>(kb, P, first, total, cpr);
+  if ((kind == EW_WINO_S || kind == EW_WINO_T || kind == EW_WINO_U || kind == EW_STR_S || kind == EW_STR_T ||
+       kind == EW_STR_U) &&
+      first < total && part_full<T>(kb, P)) {
+    switch (kind) {
+      case EW_WINO_S: pass_fast<T, EW_WINO_S>(kb, P, first, total, cpr); break;
+      case EW_WINO_T: pass_fast<T, EW_WINO_T>(kb, P, first, total, cpr); break;
+      case EW_WINO_U: pass_fast<T, EW_WINO_U>(kb, P, first, total, cpr); break;
+      case EW_STR_S: pass_fast<T, EW_STR_S>(kb, P, first, total, cpr); break;
+      case EW_STR_T: pass_fast<T, EW_STR_T>(kb, P, first, total, cpr); break;
+      default: pass_fast<T, EW_STR_U>(kb, P, first, total, cpr); break;
+    }
     return;
   }
 
