@@ -92,6 +92,40 @@ __device__ __forceinline__ T combine(const T (&q)[4]) {
   return q[0];
 }
 
+// N consecutive floats accessed as one vector (N = 1, 2, 4).
+template <int N>
+struct FVec {
+  typedef float type __attribute__((ext_vector_type(N)));
+  static __device__ __forceinline__ float get(const type& v, int i) { return v[i]; }
+  static __device__ __forceinline__ void set(type& v, int i, float x) { v[i] = x; }
+};
+template <>
+struct FVec<1> {
+  typedef float type;
+  static __device__ __forceinline__ float get(float v, int) { return v; }
+  static __device__ __forceinline__ void set(float& v, int, float x) { v = x; }
+};
+
+// Store the N values x of one lane at p (N consecutive columns of one row,
+// ncols of them inside the valid extent), out = x or fma(ds, d, x) with d
+// read at q; vector accesses when vec (p, q 4N-byte aligned) and all N are valid.
+template <int N>
+__device__ __forceinline__ void store_group(float* p, const float* q, bool add, float ds, const float (&x)[N],
+                                            int ncols, bool vec) {
+  typedef FVec<N> FV;
+  if (vec && ncols >= N) {
+    typename FV::type v, d;
+    if (add) d = *reinterpret_cast<const typename FV::type*>(q);
+#pragma unroll
+    for (int b = 0; b < N; ++b) FV::set(v, b, add ? fma(ds, FV::get(d, b), x[b]) : x[b]);
+    *reinterpret_cast<typename FV::type*>(p) = v;
+  } else {
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+      if (b < ncols) p[b] = add ? fma(ds, q[b], x[b]) : x[b];
+  }
+}
+
 // Operand load modes of a tile's K loop (see the kernels).
 enum LoadMode : int { LOAD_FULL = 0, LOAD_EDGE_VEC = 1, LOAD_MASKED = 2 };
 
@@ -127,10 +161,14 @@ __device__ __forceinline__ TileRef locate_tile(const Desc* __restrict__ descs, i
   return TileRef{lo, tm * BM, tn * BN};
 }
 
-// Epilogue: every output of the descriptor gets C = s * acc,
-// C = D + s * acc or C = beta * D + s * acc at the positions this lane owns.  ROW(lane, r) gives the
-// row (within an MFMA tile of edge TM) of accumulator register r.
-template <typename T, int TM, int NACC, int FM, int FN, int WM, int WN, typename Acc, typename RowFn>
+// Epilogue: every output of the descriptor gets C = s * acc, C = D + s * acc
+// or C = beta * D + s * acc at the positions this lane owns.  ROW(lane, r)
+// gives the row (within an MFMA tile of edge TM) of accumulator register r;
+// lane t of tile b holds column b TM + t of the wave's columns, or FN t + b
+// with PERM (the interleaved columns of a tile loop that stages B as it lies
+// in memory).
+template <typename T, int TM, int NACC, int FM, int FN, int WM, int WN, bool PERM = false, typename Acc,
+          typename RowFn>
 __device__ __forceinline__ void store_outputs(const KernelBases& kb, const GemmDesc& D, int i0, int j0,
                                               int wm, int wn, int lane, const Acc (&acc)[FM][FN],
                                               RowFn rowfn) {
@@ -149,11 +187,31 @@ __device__ __forceinline__ void store_outputs(const KernelBases& kb, const GemmD
     const T* Dp = add ? resolve<T>(kb, dv) : nullptr;
     const int64_t ldc = cv.ld, ldd = add ? dv.ld : 0;
     const int crows = cv.vrows, ccols = cv.vcols;
+    if constexpr (PERM) {
+      // the lane's FN tiles hold FN consecutive columns of each row: one
+      // vector store (and load of D) per row
+      const bool vec = view_vec(kb, cv) && (!add || view_vec(kb, dv));
+      const int col0 = j0 + wn * WN + FN * t;
+      if (col0 >= ccols) continue;
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int r = 0; r < NACC; ++r) {
+          const int row = i0 + wm * WM + a * TM + rowfn(lane, r);
+          if (row >= crows) continue;
+          float x[FN];
+#pragma unroll
+          for (int b = 0; b < FN; ++b) x[b] = sg * acc[a][b][r];
+          store_group<FN>(Cp + (int64_t)row * ldc + col0, add ? Dp + (int64_t)row * ldd + col0 : nullptr, add,
+                          dscale, x, ccols - col0, vec);
+        }
+      continue;
+    }
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
       for (int b = 0; b < FN; ++b) {
-        const int col = j0 + wn * WN + b * TM + t;
+        const int col = j0 + wn * WN + (PERM ? FN * t + b : b * TM + t);
         const int rbase = i0 + wm * WM + a * TM;
         T* cpt = Cp + (int64_t)rbase * ldc + col;
         const T* dpt = add ? Dp + (int64_t)rbase * ldd + col : nullptr;

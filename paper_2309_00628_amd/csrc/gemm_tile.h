@@ -77,6 +77,7 @@ struct MT<double> {
 
 constexpr int BKC_MAX = 8;
 
+
 // One operand of a tile product: element (r, c) at p[r * ld + c], zero
 // outside [0, vrows) x [0, vcols); vec: p and ld allow 16-byte loads.  For an
 // operand sum p is the parent block's first element, (vrows, vcols) the
@@ -138,6 +139,25 @@ struct TileLoop {
   };
   static __device__ __forceinline__ int b_idx(int col, int kc) { return kc * BN + swz_b<E>(col); }
 
+  // float32 B that is not given transposed is staged as it lies in memory
+  // ("natural": BK rows of BN consecutive columns, no swizzle), and the
+  // columns of a wave's FN MFMA tiles are interleaved: lane t of tile b
+  // computes column FN t + b of the wave's WN columns, so one LDS read of FN
+  // consecutive floats of a row of B feeds the lane's FN tiles.  B then needs
+  // no transposition on the way into LDS (interior stages load straight into
+  // it), and every k pairing of the MFMAs is that of the k-chunked layout,
+  // so the products keep their bits.
+  static constexpr bool NATF = std::is_same<T, float>::value;
+  template <int KB2>
+  static constexpr bool nat_b() { return NATF && KB2 != OK_TRANS; }
+  static_assert(!NATF || FN == 1 || FN == 2 || FN == 4, "natural B: FN floats per LDS read");
+  // column (within the tile) of lane t's outputs in MFMA tile b of wave
+  // column wn, for B given transposed or not
+  template <bool BT>
+  static __device__ __forceinline__ int out_col(int wn, int b, int t) {
+    return wn * WN + ((NATF && !BT) ? FN * t + b : b * TM + t);
+  }
+
   // LDS slot of chunk kc of tile row `row`: the chunks of a row are contiguous
   // and their order is XOR-ed with bits of the row above log2(16 / BKC), so
   // 16 consecutive rows at one chunk position (a fragment read) and 16
@@ -176,6 +196,23 @@ struct TileLoop {
   }
   static __device__ __forceinline__ void dma_b(Smem& sm, int buf, const Operand<T>& B, int j0, int kt) {
     if constexpr (DMA_B) dma_rows<BN, true>(sm, buf, B, j0, kt * BK);
+  }
+  // Natural B (plain, interior stages): BK rows of BN columns at (kt BK, j0),
+  // 16 bytes per lane in LDS order.
+  static __device__ __forceinline__ void dma_bn(Smem& sm, int buf, const Operand<T>& B, int j0, int kt) {
+    if constexpr (DMA_B) {
+      constexpr int PER = NCH_B / NT;
+      constexpr int CPR = BN / E;  // chunks per row
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      const int k0 = kt * BK;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int base = (wave * PER + i) * 64;
+        const int p = base + lane;
+        const T* src = B.p + (int64_t)(k0 + p / CPR) * B.ld + j0 + (p % CPR) * E;
+        __builtin_amdgcn_global_load_lds(src, &sm.Bs[buf][base], 16, 0, 0);
+      }
+    }
   }
 
   typedef acc_t Acc[FM][FN];
@@ -240,6 +277,42 @@ struct TileLoop {
           amask = ok ? (amask | bit) : (amask & ~bit);
         }
       }
+    }
+    if constexpr (nat_b<KB2>()) {
+      // natural B: chunk cc (E columns) of row `row` (one k) of the stage
+      if (MODE == LOAD_FULL && KB2 == OK_PLAIN && DMA_B) return;  // loaded straight into LDS
+      constexpr int CPR = BN / E;
+#pragma unroll
+      for (int i = 0; i < NBT; ++i) {
+        const int q = tid + NT * i;
+        if (NCH_B % NT != 0 && q >= NCH_B) break;
+        const int row = q / CPR, cc = q % CPR;
+        const int gr = k0 + row, gc = j0 + cc * E;
+        const T* p = B.p + (int64_t)gr * B.ld + gc;
+        chunk_t (&dst)[NQB] = rbk[i / E][i % E];
+        if (MODE == LOAD_FULL) {
+#pragma unroll
+          for (int j = 0; j < NQB; ++j) dst[j] = *reinterpret_cast<const chunk_t*>(p + B.q[nth_quad(QB, j)]);
+        } else if (MODE == LOAD_EDGE_VEC) {
+          const bool ok = gr < B.vrows && gc < B.vcols;
+          const T* src = ok ? p : B.p;
+#pragma unroll
+          for (int j = 0; j < NQB; ++j) dst[j] = *reinterpret_cast<const chunk_t*>(src + B.q[nth_quad(QB, j)]);
+          const uint64_t bit = 1ull << i;
+          bmask = ok ? (bmask | bit) : (bmask & ~bit);
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const bool ok = gr < B.vrows && gc + e < B.vcols;
+            const T* src = ok ? p + e : B.p;
+#pragma unroll
+            for (int j = 0; j < NQB; ++j) dst[j][e] = src[B.q[nth_quad(QB, j)]];
+            const uint64_t bit = 1ull << (i * E + e);
+            bmask = ok ? (bmask | bit) : (bmask & ~bit);
+          }
+        }
+      }
+      return;
     }
     if constexpr (KB2 == OK_TRANS) {
       // B given transposed: chunk kc of row `col` of B^T (one column of B)
@@ -340,6 +413,31 @@ struct TileLoop {
       }
       sm.As[buf][a_idx(row, kc)] = v;
     }
+    if constexpr (nat_b<KB2>()) {
+      if (MODE == LOAD_FULL && KB2 == OK_PLAIN && DMA_B) return;
+#pragma unroll
+      for (int i = 0; i < NBT; ++i) {
+        const int q = tid + NT * i;
+        if (NCH_B % NT != 0 && q >= NCH_B) break;
+        chunk_t v;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          T x[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+          for (int j = 0; j < NQB; ++j) x[nth_quad(QB, j)] = rbk[i / E][i % E][j][e];
+          v[e] = combine<KB2>(x);
+        }
+        if (MODE == LOAD_EDGE_VEC) {
+          if (!((bmask >> i) & 1)) v = chunk_t{};
+        } else if (MODE == LOAD_MASKED) {
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+            if (!((bmask >> (i * E + e)) & 1)) v[e] = T(0);
+        }
+        sm.Bs[buf][q] = v;
+      }
+      return;
+    }
     if constexpr (KB2 == OK_TRANS) {
       if (MODE == LOAD_FULL && DMA_B) return;
 #pragma unroll
@@ -390,6 +488,36 @@ struct TileLoop {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
     const int g = lane / TM, t = lane % TM;
+    if constexpr (NATF && !BTL) {
+      // natural B: step s of k-block kb2 reads row (kb2 KG + g) E + s of the
+      // stage, FN consecutive columns (the lane's column in each of its FN
+      // tiles); the k pairing is that of the k-chunked A fragments
+      typedef FVec<(NATF ? FN : 1)> FV;
+      typedef typename FV::type bv_t;
+      const float* Bf = reinterpret_cast<const float*>(&sm.Bs[buf][0]) + wn * WN + FN * t;
+      chunk_t fa[2][FM];
+      bv_t fb[2][E];
+      auto read_frags = [&](int kb2, chunk_t (&xa)[FM], bv_t (&xb)[E]) {
+        const int plane = kb2 * M::KG + g;
+#pragma unroll
+        for (int a = 0; a < FM; ++a) xa[a] = sm.As[buf][a_idx(wm * WM + a * TM + t, plane)];
+#pragma unroll
+        for (int s = 0; s < E; ++s) xb[s] = *reinterpret_cast<const bv_t*>(Bf + (plane * E + s) * BN);
+      };
+      read_frags(KLO, fa[0], fb[0]);
+#pragma unroll
+      for (int kb2 = KLO; kb2 < KHI; ++kb2) {
+        const int cur = (kb2 - KLO) & 1;
+        if (kb2 + 1 < KHI) read_frags(kb2 + 1, fa[cur ^ 1], fb[cur ^ 1]);
+#pragma unroll
+        for (int s = 0; s < E; ++s)
+#pragma unroll
+          for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b) acc[a][b] = M::mfma(fa[cur][a][s], FV::get(fb[cur][s], b), acc[a][b]);
+      }
+      return;
+    }
     chunk_t fa[2][FM], fb[2][FN];
     auto read_frags = [&](int kb2, chunk_t (&xa)[FM], chunk_t (&xb)[FN]) {
       const int plane = kb2 * M::KG + g;
@@ -431,11 +559,13 @@ struct TileLoop {
     constexpr bool BTL = KB2 == OK_TRANS;
     constexpr bool DMA = MODE == LOAD_FULL && KA == OK_PLAIN && DMA_A;
     constexpr bool DMAB = MODE == LOAD_FULL && BTL && DMA_B;
+    constexpr bool DMABN = MODE == LOAD_FULL && nat_b<KB2>() && KB2 == OK_PLAIN && DMA_B;
     if (DMA) dma_a(sm, 0, A, i0, 0);
     if (DMAB) dma_b(sm, 0, B, j0, 0);
+    if (DMABN) dma_bn(sm, 0, B, j0, 0);
     load_tile<MODE, KA, KB2>(A, B, i0, j0, 0, ra, rbk, amask, bmask);
     store_tile<MODE, KA, KB2>(sm, 0, ra, rbk, amask, bmask);
-    if (DMA || DMAB) __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of this wave's direct loads are done
+    if (DMA || DMAB || DMABN) __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of this wave's direct loads are done
     __syncthreads();
     for (int kt = 0; kt < ktiles; ++kt) {
       const int buf = kt & 1;
@@ -443,12 +573,13 @@ struct TileLoop {
       if (more) {
         if (DMA) dma_a(sm, buf ^ 1, A, i0, kt + 1);
         if (DMAB) dma_b(sm, buf ^ 1, B, j0, kt + 1);
+        if (DMABN) dma_bn(sm, buf ^ 1, B, j0, kt + 1);
         load_tile<MODE, KA, KB2>(A, B, i0, j0, kt + 1, ra, rbk, amask, bmask);
       }
       compute<0, KMID, BTL>(sm, buf, acc);
       if (more) store_tile<MODE, KA, KB2>(sm, buf ^ 1, ra, rbk, amask, bmask);
       compute<KMID, KB, BTL>(sm, buf, acc);
-      if (DMA || DMAB) __builtin_amdgcn_s_waitcnt(0);
+      if (DMA || DMAB || DMABN) __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
   }

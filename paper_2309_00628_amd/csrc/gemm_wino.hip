@@ -73,26 +73,30 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_wino_kernel(KernelBases k
   // accumulating top level stores fma(beta, Cold, v) instead.
   const bool accum = D.acc && kb.beta != 0.0;
   const float beta = (float)kb.beta;
+  // (the lane's FN tiles hold FN consecutive columns of each row: one vector
+  // access per row)
   auto store = [&](const MView& cv, auto v) {
     float* __restrict__ Cp = resolve<float>(kb, cv);
     const int t = lane % TM;
+    const int col0 = j0 + TL::template out_col<false>(wn, 0, t);
+    if (col0 >= cv.vcols) return;
+    const bool vec = view_vec(kb, cv);
 #pragma unroll
-    for (int a = 0; a < FM; ++a)
+    for (int a = 0; a < FM; ++a) {
+      typename M::acc_t x[FN];
 #pragma unroll
-      for (int b = 0; b < FN; ++b) {
-        const typename M::acc_t x = v(a, b);
-        const int col = j0 + wn * TL::WN + b * TM + t;
-        const int rbase = i0 + wm * TL::WM + a * TM;
-        float* cpt = Cp + (int64_t)rbase * cv.ld + col;
+      for (int b = 0; b < FN; ++b) x[b] = v(a, b);
 #pragma unroll
-        for (int r = 0; r < M::NACC; ++r) {
-          const int rr = M::row(lane, r);
-          if (rbase + rr < cv.vrows && col < cv.vcols) {
-            float* q = cpt + (int64_t)rr * cv.ld;
-            *q = accum ? fma(beta, *q, x[r]) : x[r];
-          }
-        }
+      for (int r = 0; r < M::NACC; ++r) {
+        const int row = i0 + wm * TL::WM + a * TM + M::row(lane, r);
+        if (row >= cv.vrows) continue;
+        float y[FN];
+#pragma unroll
+        for (int b = 0; b < FN; ++b) y[b] = x[b][r];
+        float* p = Cp + (int64_t)row * cv.ld + col0;
+        store_group<FN>(p, p, accum, beta, y, cv.vcols - col0, vec);
       }
+    }
   };
   auto add_to = [](Acc& x, const Acc& y) {
 #pragma unroll
