@@ -13,6 +13,9 @@
 // operand fetch is one ds_read_b128 that feeds E MFMAs.  Row (A) and column
 // (B) indices are XOR-swizzled so that both the stores of the global tile and
 // the fragment reads touch 16 distinct 16-byte bank groups per 16 lanes.
+// float32 B (unless given transposed) is instead staged as it lies in
+// memory, with the columns of each wave's MFMA tiles interleaved so that
+// one read of FN consecutive floats feeds FN MFMAs (see nat_b below).
 //
 // Edges: operand reads outside a view's valid extent are zero (this is also
 // how quadrants of a zero-padded matrix are read without a copy).  Interior
