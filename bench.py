@@ -135,16 +135,12 @@ def plan_launches(plan, esz):
     return out
 
 
-def tuned_leaf(tuner, n, levels):
+def tuned_leaf(tuner, n, levels, dtype="f32"):
     """The autotuner's (tile, overlap, leaf_u, trans_b) choice for an n x n x n
-    float32 product at this level count (planner defaults when the cache
-    holds another level count for the size class)."""
-    ch = tuner.choose(n, n, n, "f32")
-    for c in (ch, ch.get("best_recursive") or {}):
-        if ch["source"] == "tuned" and c.get("levels") == levels:
-            return (c["tile"], bool(c.get("overlap", False)), bool(c.get("leaf_u", False)),
-                    bool(c.get("trans_b", False)))
-    return None, False, False, False
+    product at this level count (planner defaults when the tuner has not
+    measured that level count for the size class)."""
+    o = tuner.options_at(n, n, n, dtype, levels)
+    return o if o is not None else (None, False, False, False)
 
 
 def tuned_plain(tuner, n, dtype="f32"):
@@ -334,16 +330,15 @@ def bench_precision(torch, api, L, inputs, tuner, n=8192, steps=10, warmup=10, r
                                ("bf16x3_plain", "naive", 0, "bf16x3"),
                                ("f32_winograd_L2", "winograd", 2, "f32"),
                                ("f32_plain", "naive", 0, "f32")):
-        ch = tuner.choose(n, n, n, dt)
-        tile, sk = None, None
-        for c in (ch, ch.get("best_recursive") or {}, ch.get("best_plain") or {}):
-            if ch["source"] == "tuned" and c.get("levels") == lv:
-                tile, sk = c["tile"], (c.get("split_k") if lv == 0 else None)
-                break
+        if lv:
+            tile, ov, lu, tb = tuned_leaf(tuner, n, lv, dt)
+            sk = None
+        else:
+            (tile, sk), ov, lu, tb = tuned_plain(tuner, n, dt), False, False, False
         r = run_product(torch, api, L, algo, "grouped" if lv else "auto", n, lv, A, B, steps, warmup,
-                        dtype=dt, tile=tile, split_k=sk)
+                        dtype=dt, tile=tile, split_k=sk, overlap=ov, leaf_u=lu, trans_b=tb)
         out[name] = {"tflops": round(r["tflops"], 3), "p50_ms": round(r["p50"], 4),
-                     "rel_err": rel_err(r["C"], sample, ref), "tile": tile}
+                     "rel_err": rel_err(r["C"], sample, ref), "tile": tile, "overlap": ov}
         print(f"# precision {name}: {out[name]}", file=sys.stderr, flush=True)
         del r
     out["speedup_bf16x3_winograd_vs_f32_plain"] = round(out["bf16x3_winograd_L2"]["tflops"] /

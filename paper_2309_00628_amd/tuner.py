@@ -91,6 +91,23 @@ def choose(m, n, k, dtype="f32"):
     return rule_of_thumb(m, n, k, dtype)
 
 
+def options_at(m, n, k, dtype, levels):
+    """The tuner's (tile, overlap, leaf_u, trans_b) for a recursion of exactly
+    ``levels`` levels, or None when it has not measured that level count."""
+    ch = choose(m, n, k, dtype)
+    if ch.get("source") != "tuned":
+        return None
+    c = (ch.get("by_level") or {}).get(str(levels))
+    if c is None:
+        for c2 in (ch, ch.get("best_recursive") or {}):
+            if c2.get("levels") == levels:
+                c = c2
+                break
+    if c is None:
+        return None
+    return c.get("tile"), bool(c.get("overlap", False)), bool(c.get("leaf_u", False)), bool(c.get("trans_b", False))
+
+
 def _time_plan(plan, A, B, C, reps, warmup):
     import ctypes
 
@@ -216,6 +233,14 @@ def tune(m, n, k, dtype="f32", max_levels=3, reps=5, warmup=2, tiles=None, save=
         t2, L2, tile2, ov2, lu2, tb2, _ = min(rec, key=score)
         entry["best_recursive"] = {"levels": L2, "tile": tile2, "overlap": ov2, "leaf_u": lu2, "trans_b": tb2,
                                    "ms": round(t2, 4), "tflops": round(2.0 * m * n * k / t2 / 1e9, 2)}
+        # the fastest options at every level count measured (for callers
+        # that fix the levels)
+        by_level = {}
+        for lv in sorted({r[1] for r in rec}):
+            t3, _, tile3, ov3, lu3, tb3, _ = min((r for r in rec if r[1] == lv), key=score)
+            by_level[str(lv)] = {"tile": tile3, "overlap": ov3, "leaf_u": lu3, "trans_b": tb3,
+                                 "ms": round(t3, 4), "tflops": round(2.0 * m * n * k / t3 / 1e9, 2)}
+        entry["by_level"] = by_level
     arch = _arch()
     load_cache(arch)[class_key(dtype, m, n, k)] = entry
     if save:
