@@ -118,7 +118,9 @@ def plan_launches(plan, esz):
             out.append(dict(kind=line, stream=0, flops=0.0, bytes=0.0))
         elif w[0] == "LAUNCH":
             out.append(dict(kind=w[1], stream=1 if w[-1] == "aux" else 0, flops=flops, bytes=nbytes,
-                            grid=int(w[3]) if len(w) > 3 else 0))
+                            grid=int(w[3]) if len(w) > 3 else 0,
+                            cfg=int(w[4]) if w[1] in ("GEMM", "WINO") and len(w) > 4 else None,
+                            flags=w[5:]))
             flops, nbytes = 0.0, 0.0
         elif w[0] == "GEMM":
             m, n, k = map(int, w[1:4])
@@ -187,10 +189,27 @@ def source_digest():
     return h.hexdigest()
 
 
+# Template arguments of the float32 leaf kernels per tile configuration
+# (MM_PLAN_TILE in include/mm.h): BM, BN, BKC, WGM, WGN.
+GEMM_F32_TILES = {0: (128, 128, 8, 4, 2), 1: (256, 128, 8, 4, 2), 2: (128, 256, 8, 2, 4), 3: (256, 256, 8, 4, 2),
+                  4: (64, 128, 8, 2, 2), 5: (128, 64, 8, 2, 2), 6: (256, 128, 4, 2, 2), 7: (128, 128, 4, 2, 2)}
+WINO_TILES = {0: (128, 128, 8, 2, 2), 1: (128, 128, 8, 4, 2), 2: (64, 128, 8, 2, 2)}
+
+
+def launch_kernel_name(lau):
+    """The name rocprofv3 gives the kernel of a float32 leaf launch."""
+    if lau["kind"] == "WINO":
+        t = WINO_TILES.get(lau["cfg"], WINO_TILES[0])
+        return "gemm_wino_kernel<%d, %d, %d, %d, %d, %s>" % (t + ("true" if "fused" in lau["flags"] else "false",))
+    t = GEMM_F32_TILES.get(lau["cfg"], GEMM_F32_TILES[0])
+    return "gemm_kernel<float, %d, %d, %d, %d, %d, %s>" % (t + ("true" if "bt" in lau["flags"] else "false",))
+
+
 def measured_traffic(kernel, grid):
     """HBM bytes per launch of (kernel, grid) from the rocprofv3 counter
-    summary in profiles/hbm_traffic.json, or None when there is none or it
-    was taken with other kernel sources."""
+    summary in profiles/hbm_traffic.json (kernels named with their template
+    arguments), or None when there is none or it was taken with other kernel
+    sources."""
     p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic.json")
     try:
         with open(p) as f:
@@ -200,7 +219,7 @@ def measured_traffic(kernel, grid):
     if data.get("source_sha256") != source_digest():
         return None
     for e in data.get("launches", []):
-        if kernel in e["kernel"] and e["grid"] == grid:
+        if e["kernel"] == kernel and e["grid"] == grid:
             return e["bytes_per_launch"]
     return None
 
@@ -212,19 +231,19 @@ def gemm_roofline(res, n, traffic=True):
     look up its measured HBM bytes (the counter summary covers the headline
     Winograd plan only)."""
     launches = plan_launches(res["plan"], 4)
-    best, kind, grid = None, 1, None
+    best, kind, grid, top = None, 1, None, None
     for lau, d, k in zip(launches, res["per_op"], res["kinds"]):
         if k in (1, 4) and (best is None or lau["flops"] > best[0]):
-            kind, grid = k, lau["grid"]
+            kind, grid, top = k, lau["grid"], lau
             best = (lau["flops"], sum(d) / len(d))
     flops, avg_ms = best if best else (0.0, float("nan"))
     achieved = flops / (avg_ms * 1e-3) / 1e12
-    kname = "gemm_wino_kernel" if kind == 4 else "gemm_kernel<float"
+    kname = launch_kernel_name(top) if top is not None else None
     return dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / PEAK_FP32_TFLOPS, 4),
-                traffic=measured_traffic(kname, grid) if traffic else None,
-                kernel=("gemm_wino_kernel (last level: products + U in registers)" if kind == 4
-                        else "gemm_kernel<float> (grouped leaf products)"),
+                traffic=measured_traffic(kname, grid) if traffic and kname else None,
+                kernel=kname + (" (last level: products + U in registers)" if kind == 4
+                                else " (grouped leaf products)") if kname else None,
                 flops_per_launch=flops, avg_launch_ms=round(avg_ms, 4), grid=grid)
 
 

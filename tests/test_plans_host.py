@@ -625,3 +625,26 @@ def test_option_combinations_are_exact(lib, m, n, k, levels):
             plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws}, beta=2)
             want = A @ B + (2 * C0 if "accumulate" in combo else 0)
             assert np.array_equal(C.reshape(m, n), want), combo
+
+
+def test_bench_tile_table_matches_the_library(lib):
+    # bench.py names the kernel of a leaf launch from its tile configuration
+    # (to find its measured traffic); the tile edges it assumes must give the
+    # grid the library launches
+    import math
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    m, n = 1000, 700
+    for c, (bm, bn, bkc, wgm, wgn) in bench.GEMM_F32_TILES.items():
+        text, _ = L.describe("naive", "auto", m, n, 256, tile=c)
+        lau = [x for x in bench.plan_launches(type("P", (), {"describe": lambda self: text})(), 4)
+               if x["kind"] == "GEMM"]
+        assert len(lau) == 1 and lau[0]["cfg"] == c
+        assert lau[0]["grid"] == math.ceil(m / bm) * math.ceil(n / bn), c
+        assert bench.launch_kernel_name(lau[0]) == f"gemm_kernel<float, {bm}, {bn}, {bkc}, {wgm}, {wgn}, false>"
+    for c, (bm, bn, bkc, wgm, wgn) in bench.WINO_TILES.items():
+        text, _ = L.describe("winograd", "grouped", 2 * m, 2 * n, 512, cutoff=1, levels=1, leaf_u=True, tile=c)
+        lau = [x for x in bench.plan_launches(type("P", (), {"describe": lambda self: text})(), 4)
+               if x["kind"] == "WINO"]
+        assert len(lau) == 1 and lau[0]["grid"] == math.ceil(m / bm) * math.ceil(n / bn), c
