@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline and error check")
     ap.add_argument("--no-extra", action="store_true", help="skip the n=3000 / n=8192 side runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batch")
+    ap.add_argument("--no-schedules", action="store_true",
+                    help="skip the depth-first schedules (Two Temp, In-Place, Strassen DFS) at n=4096")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop runs")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the n=8192 split-bfloat16 precision runs")
@@ -365,6 +367,37 @@ def bench_precision(torch, api, L, inputs, tuner, n=8192, steps=10, warmup=10, r
     return out
 
 
+def bench_schedules(torch, api, L, A, B, n, rows=None, ref=None, steps=20, warmup=10):
+    """The paper's schedules beside the grouped one at the headline size:
+    Strassen-Winograd Two Temp (Table 2) and In-Place (Table 3), Strassen
+    depth first with three temporaries, and both grouped, at one and two
+    levels, with the workspace each needs.  The in-place schedule overwrites
+    its operands, so it is timed on copies (its run time does not depend on
+    the values) and its error is taken from one run on fresh copies."""
+    out = {}
+    for algo, sched in (("winograd", "two_temp"), ("winograd", "in_place"), ("winograd", "grouped"),
+                        ("strassen", "dfs3"), ("strassen", "grouped")):
+        for lv in (1, 2):
+            clob = sched == "in_place"
+            Ax, Bx = (A.clone(), B.clone()) if clob else (A, B)
+            r = run_product(torch, api, L, algo, sched, n, lv, Ax, Bx, steps, warmup)
+            e = {"tflops": round(r["tflops"], 3), "p50_ms": round(r["p50"], 4),
+                 "workspace_mib": round(r["plan"].ws_bytes / 2 ** 20, 1)}
+            if rows is not None:
+                C = r["C"]
+                if clob:
+                    Ax.copy_(A)
+                    Bx.copy_(B)
+                    ws = torch.empty(max(r["plan"].ws_bytes, 256), dtype=torch.uint8, device=A.device)
+                    r["plan"](Ax, Bx, C, ws)
+                    torch.cuda.synchronize()
+                e["rel_err"] = rel_err(C, rows, ref)
+            out[f"{algo}_{sched}_L{lv}"] = e
+            print(f"# schedule {algo} {sched} L={lv}: {e}", file=sys.stderr, flush=True)
+            del r, Ax, Bx
+    return out
+
+
 def bench_batched(torch, api, inputs, tuner, count=512, steps=10, warmup=3, seed=7):
     """512 independent float32 products, m, n, k log-uniform in [64, 2048]
     (multiples of 16), levels per size class from the tuner, run as one
@@ -573,6 +606,8 @@ def main():
         out["plain_rel_err"] = rel_err(plain["C"], rows, ref)
         out["strassen_grouped"]["rel_err"] = rel_err(strs["C"], rows, ref)
         out["rel_err_note"] = "relative Frobenius error vs the float64 oracle on the sampled rows"
+    if not args.no_schedules:
+        out["schedules"] = bench_schedules(torch, api, L, A, B, n, *((rows, ref) if not args.no_cpu else ()))
 
     if not args.no_extra:
         extra = {}
