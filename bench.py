@@ -398,6 +398,36 @@ def bench_schedules(torch, api, L, A, B, n, rows=None, ref=None, steps=20, warmu
     return out
 
 
+def bench_fp64_small(torch, api, L, inputs, n=512, cutoff=64, steps=50, warmup=10):
+    """float64, n = 512, uniform[-1, 1], recursion cutoff 64 (three levels):
+    the plain product and each algorithm / schedule (the depth-first one
+    also replayed from a captured hipGraph, which does not shorten it: its
+    ~1400 small launches depend on one another, so the time is their GPU-side
+    latency, not the host's launch cost), with the relative Frobenius error
+    against the oracle's full product."""
+    import numpy as np
+    from oracle import naive
+    A_np, B_np = inputs.pair("uniform", n, n, n, 0, np.float64)
+    ref = naive.gemm(A_np, B_np)
+    A, B = torch.from_numpy(A_np).cuda(), torch.from_numpy(B_np).cuda()
+    out = {"workload": f"square fp64 n={n}, uniform[-1,1], cutoff {cutoff}"}
+    for name, algo, sched, lv, graph in (("plain", "naive", "auto", 0, False),
+                                         ("winograd_grouped", "winograd", "grouped", -1, False),
+                                         ("winograd_two_temp", "winograd", "two_temp", -1, False),
+                                         ("winograd_two_temp_graph", "winograd", "two_temp", -1, True),
+                                         ("strassen_grouped", "strassen", "grouped", -1, False)):
+        plan = api.Plan(algo, sched, n, n, n, cutoff=cutoff if lv else 1, levels=lv, dtype="f64", graph=graph)
+        ws = torch.empty(max(plan.ws_bytes, 256), dtype=torch.uint8, device=A.device)
+        C = torch.empty((n, n), dtype=torch.float64, device=A.device)
+        wall, step_ms, _, _ = time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup)
+        got = C.cpu().numpy()
+        out[name] = {"levels": plan.info.get("levels"), "tflops": round(2.0 * n ** 3 / (wall * 1e-3) / 1e12, 3),
+                     "p50_ms": round(pct(step_ms, 50), 4),
+                     "rel_err": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+    print(f"# fp64 n={n}: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_batched(torch, api, inputs, tuner, count=512, steps=10, warmup=3, seed=7):
     """512 independent float32 products, m, n, k log-uniform in [64, 2048]
     (multiples of 16), levels per size class from the tuner, run as one
@@ -633,6 +663,7 @@ def main():
 
     if not args.no_precision:
         out["precision"] = bench_precision(torch, api, L, inputs, tuner)
+        out["fp64_small"] = bench_fp64_small(torch, api, L, inputs)
     if not args.no_batched:
         out["batched"] = bench_batched(torch, api, inputs, tuner)
         print(f"# batched: {out['batched']}", file=sys.stderr, flush=True)
