@@ -21,18 +21,21 @@ __device__ __forceinline__ bool view_vec(const KernelBases& kb, const MView& v) 
   return v.vec && (v.base == MB_ABS || ((kb.aligned >> v.base) & 1));
 }
 
-// LDS swizzles (16-byte chunks).  The tile stores and the fragment reads of
-// every configuration are conflict-free whether the LDS serves 8 or 16
-// lanes of a 128-bit access per cycle (checked exhaustively on the host for
-// every instantiated tile shape):
+// LDS swizzles (16-byte chunks).  gfx950's LDS serves a 128-bit access 16
+// lanes per cycle (64 banks); the tile stores and the fragment reads of
+// every instantiated tile shape touch 16 distinct bank groups per 16 lanes
+// (tests/test_lds_layout.py checks every float32 and float64 tile shape;
+// rocprofv3's SQ_LDS_BANK_CONFLICT reads 0 for these kernels):
 // A: a store phase covers 16/BKC consecutive rows x BKC chunks; the row is
 //    XOR-ed with kc ^ (row mod (16/BKC)) * BKC, a permutation within each
 //    aligned group of 16 rows, so the 32 consecutive rows a fragment read
 //    touches stay distinct.
-// B: 8 consecutive lanes store columns E*cb + c of 8 consecutive cb; the low
-//    bits are XOR-ed with a function of column bits 3 and up, so each group
-//    of 8 (and 16) lanes lands in distinct chunk slots, and reads of 32
-//    consecutive columns remain a permutation within aligned groups.
+// B (k-chunked, float64 and split-bfloat16): 8 consecutive lanes store
+//    columns E*cb + c of 8 consecutive cb; the low bits are XOR-ed with a
+//    function of column bits 3 and up, so each group of 8 (and 16) lanes
+//    lands in distinct chunk slots, and reads of 32 consecutive columns
+//    remain a permutation within aligned groups.  float32 B is staged as it
+//    lies in memory (gemm_tile.h): its reads are contiguous runs.
 template <int BKC>
 __device__ __forceinline__ int swz_a(int row, int kc) {
   return row ^ ((kc ^ ((row % (16 / BKC)) * BKC)) & 15);

@@ -174,7 +174,7 @@ struct TileLoop {
   // register staging or LDS stores; the lane that fills slot p loads the
   // chunk that a_idx places there.
   static constexpr bool DMA_A = NCH_A % NT == 0;
-  static constexpr bool DMA_B = NCH_B % NT == 0;  // (transposed B)
+  static constexpr bool DMA_B = NCH_B % NT == 0;  // (transposed or natural B)
   // R rows (of A, or of a transposed B when IS_B) at r0 of the operand,
   // chunks of k0 + [0, BK), into LDS buffer buf in a_idx order.
   template <int R, bool IS_B>
