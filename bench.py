@@ -194,7 +194,8 @@ def source_digest():
 # Template arguments of the float32 leaf kernels per tile configuration
 # (MM_PLAN_TILE in include/mm.h): BM, BN, BKC, WGM, WGN.
 GEMM_F32_TILES = {0: (128, 128, 8, 4, 2), 1: (256, 128, 8, 4, 2), 2: (128, 256, 8, 2, 4), 3: (256, 256, 8, 4, 2),
-                  4: (64, 128, 8, 2, 2), 5: (128, 64, 8, 2, 2), 6: (256, 128, 4, 2, 2), 7: (128, 128, 4, 2, 2)}
+                  4: (64, 128, 8, 2, 2), 5: (128, 64, 8, 2, 2), 6: (256, 128, 4, 2, 2), 7: (128, 128, 4, 2, 2),
+                  8: (64, 64, 8, 2, 2)}
 WINO_TILES = {0: (128, 128, 8, 2, 2), 1: (128, 128, 8, 4, 2), 2: (64, 128, 8, 2, 2)}
 
 

@@ -223,11 +223,11 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
  * whose C has too few tiles to fill the 256 compute units; the sum order
  * differs from the unsplit product's, so the bits may differ too. */
 #define MM_PLAN_SPLIT_K(s) (((unsigned)(s) & 0xfu) << 16)
-/* Force the MFMA GEMM tile configuration c (0 .. 7) for every leaf launch
+/* Force the MFMA GEMM tile configuration c (0 .. 8) for every leaf launch
  * instead of the planner's choice.  float32: 0 128x128 (BK 32, 8 waves),
  * 1 256x128 (8 waves), 2 128x256 (8 waves), 3 256x256 (BK 32, 8 waves),
  * 4 64x128, 5 128x64, 6 256x128 (BK 16, 4 waves), 7 128x128 (BK 16,
- * 4 waves); float64: 0 128x128, 5 128x64 (others fall back to 0);
+ * 4 waves), 8 64x64 (BK 32, 4 waves); float64: 0 128x128, 5 128x64 (others fall back to 0);
  * MM_BF16X3_REFINED: 0 128x128, 1 256x128 (8 waves), 3 256x256 (8 waves),
  * 4 64x128 (others fall back to 0), and with MM_PLAN_SPLIT_PASS 0, 1, 3
  * 256x256 (4 waves), 4, 5 256x128 (4 waves), 6 256x256 (8 waves).  With

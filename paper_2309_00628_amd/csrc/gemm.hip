@@ -67,6 +67,7 @@ hipError_t launch_f32_bt(int cfg, const KernelBases& kb, const GemmDesc* d, int 
     case 5: return launch_cfg<float, 128, 64, 8, 2, 2, true>(kb, d, n, tiles, remap, s);
     case 6: return launch_cfg<float, 256, 128, 4, 2, 2, true>(kb, d, n, tiles, remap, s);
     case 7: return launch_cfg<float, 128, 128, 4, 2, 2, true>(kb, d, n, tiles, remap, s);
+    case 8: return launch_cfg<float, 64, 64, 8, 2, 2, true>(kb, d, n, tiles, remap, s);
     default: return launch_cfg<float, 128, 128, 8, 4, 2, true>(kb, d, n, tiles, remap, s);
   }
 }
@@ -90,6 +91,7 @@ GemmCfg gemm_cfg(int dtype, int cfg) {
     case 5: return {128, 64};
     case 6: return {256, 128};
     case 7: return {128, 128};
+    case 8: return {64, 64};
     default: return {128, 128};
   }
 }
@@ -116,6 +118,9 @@ hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc
     case 5: return launch_cfg<float, 128, 64, 8, 2, 2>(kb, d, n, tiles, remap, s);
     case 6: return launch_cfg<float, 256, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
     case 7: return launch_cfg<float, 128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
+    // 64x64 with four waves (each 32x32): products too small to give the
+    // larger tiles a workgroup per compute unit
+    case 8: return launch_cfg<float, 64, 64, 8, 2, 2>(kb, d, n, tiles, remap, s);
 
     default: return launch_cfg<float, 128, 128, 8, 4, 2>(kb, d, n, tiles, remap, s);
   }

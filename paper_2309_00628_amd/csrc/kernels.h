@@ -18,7 +18,7 @@ enum KDtype : int { DT_F64 = 0, DT_F32 = 1, DT_BF16X3 = 2, DT_BF16X3_SPL = 3, DT
 struct GemmCfg {
   int bm, bn;
 };
-constexpr int kNumGemmCfg = 8;
+constexpr int kNumGemmCfg = 9;
 GemmCfg gemm_cfg(int dtype, int cfg);
 
 int ew_blocks(int rows, int cols, int dtype);

@@ -144,11 +144,11 @@ int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
   if (!equal && kdtype == DT_F32 && group.size() > 1) {
     // Unequal problems: minimise the padded work (tile area x k) over the
     // measured per-tile MFMA efficiency of each shape.
-    const int cand[4] = {0, 3, 4, 5};
-    const double eff[4] = {0.81, 0.87, 0.75, 0.72};
+    const int cand[5] = {0, 3, 4, 5, 8};
+    const double eff[5] = {0.81, 0.87, 0.75, 0.72, 0.74};
     int best = 0;
     double best_cost = 1e300;
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 5; ++i) {
       const GemmCfg gc = gemm_cfg(kdtype, cand[i]);
       double work = 0;
       for (const GemmDesc& g : group)
@@ -175,15 +175,18 @@ int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
     if (t256 >= 256) return 1;
     return t128 >= 256 ? 0 : 4;
   }
-  int64_t t256 = 0, t128 = 0;
+  int64_t t256 = 0, t128 = 0, t64x128 = 0;
   for (const GemmDesc& g : group) {
     t256 += ceil_div(g.m, 256) * ceil_div(g.n, 256);
     t128 += ceil_div(g.m, 128) * ceil_div(g.n, 128);
+    t64x128 += ceil_div(g.m, 64) * ceil_div(g.n, 128);
   }
   // whole rounds of 256 workgroups (one per CU) suit the eight-wave tiles
   if (t256 >= 1024 || (t256 >= 256 && t256 % 256 == 0)) return 3;
   if (t128 >= 2048 || (t128 >= 256 && t128 % 256 == 0)) return 0;
-  return 4;
+  // too few 64x128 tiles to give every CU one: 64x64 (measured at n = 512 ..
+  // 1024: 1.4-1.7x the 64x128 tile)
+  return t64x128 < 256 ? 8 : 4;
 }
 
 // ---------------------------------------------------------------------------

@@ -76,7 +76,7 @@ def test_naive_gemm_unaligned_copies(api, naive, dtype, m, n, k):
 
 @pytest.mark.parametrize("m,n,k", [(1024, 768, 512), (600, 520, 300), (1100, 260, 1000)])
 def test_every_float32_tile_configuration(api, naive, m, n, k):
-    # each float32 tile shape (MM_PLAN_TILE 0 .. 7) of the plain product and
+    # each float32 tile shape (MM_PLAN_TILE 0 .. 8) of the plain product and
     # of a Winograd level: within tolerance of the oracle, and bitwise equal
     # to each other (every tile shape accumulates k in the same order)
     A, B = inputs.pair("uniform", m, n, k, 60, np.float32)
@@ -84,7 +84,7 @@ def test_every_float32_tile_configuration(api, naive, m, n, k):
     ref = naive.gemm(A, B)
     for algo, levels in (("naive", 0), ("winograd", 1)):
         first = None
-        for tile in range(8):
+        for tile in range(9):
             print(f"tile {tile} {algo} {m}x{n}x{k}", flush=True)
             C = torch.full((m, n), float("nan"), device="cuda")
             if algo == "naive":

@@ -18,7 +18,7 @@ import pytest
 # (T, BM, BN, BKC, WGM, WGN) of every GEMM / fused-U tile loop instantiation
 F32_TILES = [(128, 128, 8, 4, 2), (256, 128, 8, 4, 2), (128, 256, 8, 2, 4), (256, 256, 8, 4, 2),
              (64, 128, 8, 2, 2), (128, 64, 8, 2, 2), (256, 128, 4, 2, 2), (128, 128, 4, 2, 2),
-             (128, 128, 8, 2, 2)]
+             (128, 128, 8, 2, 2), (64, 64, 8, 2, 2)]
 F64_TILES = [(128, 128, 8, 2, 2), (128, 64, 8, 2, 2)]
 MT = {"f32": dict(TM=32, KG=2, E=4), "f64": dict(TM=16, KG=4, E=2)}
 
