@@ -512,6 +512,7 @@ GemmCfg gemm_bf16x3_cfg(int cfg) {
     case 1: return {256, 128};
     case 3: return {256, 256};
     case 4: return {64, 128};
+    case 8: return {64, 64};
     default: return {128, 128};
   }
 }
@@ -526,6 +527,8 @@ hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d,
     case 1: return launch_cfg<256, 128, 4, 4, 2, true>(kb, d, n, tiles, remap, s);
     case 3: return launch_cfg<256, 256, 2, 4, 2, true>(kb, d, n, tiles, remap, s);
     case 4: return launch_cfg<64, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
+    // small products: one 32x32 tile per wave
+    case 8: return launch_cfg<64, 64, 4, 2, 2>(kb, d, n, tiles, remap, s);
     default: return launch_cfg<128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
   }
 }

@@ -165,15 +165,18 @@ int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
     // eight-wave tiles (two waves per SIMD) hide the split's vector work
     // behind the MFMAs, and the 256x256 tile splits each element for half as
     // many tiles as 256x128; smaller launches keep more CUs busy with 64x128.
-    int64_t t2x2 = 0, t256 = 0, t128 = 0;
+    int64_t t2x2 = 0, t256 = 0, t128 = 0, t64x128 = 0;
     for (const GemmDesc& g : group) {
       t2x2 += ceil_div(g.m, 256) * ceil_div(g.n, 256);
       t256 += ceil_div(g.m, 256) * ceil_div(g.n, 128);
       t128 += ceil_div(g.m, 128) * ceil_div(g.n, 128);
+      t64x128 += ceil_div(g.m, 64) * ceil_div(g.n, 128);
     }
     if (kdtype == DT_BF16X3 && t2x2 >= 512) return 3;
     if (t256 >= 256) return 1;
-    return t128 >= 256 ? 0 : 4;
+    if (t128 >= 256) return 0;
+    // (the in-loader split kernel also has 64x64 tiles for small products)
+    return kdtype == DT_BF16X3 && t64x128 < 256 ? 8 : 4;
   }
   int64_t t256 = 0, t128 = 0, t64x128 = 0;
   for (const GemmDesc& g : group) {
