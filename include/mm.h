@@ -21,10 +21,13 @@
  *            MM_F32: float in, float out, float MFMA products, float sums.
  *            MM_BF16X3_REFINED: float in and out; block sums in float; every
  *            leaf product splits each float operand x into bfloat16 parts
- *            x = hi + lo + res (res formed in double), multiplies the parts
- *            with bfloat16 MFMA into a float accumulator: three main
- *            products hi*hi + hi*lo + lo*hi plus one correction
- *            lo*lo + res*hi + hi*res.  Relative Frobenius error is about
+ *            x = hi + lo + res, multiplies the parts with bfloat16 MFMA
+ *            into a float accumulator: three main products
+ *            hi*hi + hi*lo + lo*hi plus one correction
+ *            lo*lo + res*hi + hi*res.  The residual x - hi - lo is formed
+ *            in float: both subtractions are exact there (x - hi fits in 16
+ *            significant bits, x - hi - lo in 8), so it has the same bits a
+ *            double residual would have.  Relative Frobenius error is about
  *            1e-6 on well-scaled inputs (float32 level).
  * Asynchrony Every call only enqueues work on `stream` (a hipStream_t; NULL
  *            is the legacy default stream) and returns.  Faults inside
