@@ -4,17 +4,25 @@ plain MFMA GEMM of the same library, on one MI355X, with the relative error
 against the float64 oracle and p50/p99 step latency.
 
 Workload (one "step" = one whole product, every kernel of the path):
-square float32 C = A x B, n = 4096, entries i.i.d. U[-1, 1] from a fixed
-seed, Strassen-Winograd with the grouped schedule.  The plain MFMA GEMM
-(mm_naive) runs the same product for comparison.  Inputs are resident in HBM
-before timing starts.
+square float32 C = A x B, n = 8192, entries i.i.d. U[-1, 1] from a fixed
+seed, Strassen-Winograd with two levels (grouped schedule, the autotuner's
+options for two levels).  The plain MFMA GEMM (mm_naive) and hipBLASLt
+(torch.matmul, context only) run the same product.  Inputs are resident in
+HBM before timing starts.
+
+Timing: the GPU first runs the plain product for a fixed wall time (clocks
+settle under MFMA load), then W untimed steps of each contender, then the K
+timed steps of each contender in R interleaved rounds (the order rotates
+from round to round, so no contender always runs first).  ``value`` is
+2 n^3 K over the summed wall time of the K Winograd steps; per-round rates
+and their medians are reported for all three.
 
 Printed: one JSON line (rank 0).  ``roofline`` is for the dominant kernel,
-the grouped MFMA leaf GEMM launch: algorithmic flops of one launch
-(7^L leaf products of 2 (n/2^L)^3 flops) over that launch's average duration,
+the grouped MFMA leaf GEMM launch with the most flops: algorithmic flops of
+one launch (its leaf products' 2mnk) over that launch's average duration,
 measured with HIP events recorded around each launch on the stream the
-kernels run on, during the timed steps.  ``cpu_baseline`` is the oracle (the
-double-precision triple loop) timed on the host on a sample of output rows.
+kernels run on.  ``cpu_baseline`` is the oracle (the double-precision triple
+loop) timed on the host on samples of output rows.
 """
 import argparse
 import json
@@ -27,29 +35,33 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+PEAK_BF16_TFLOPS = 2516.6  # MI355X dense BF16 matrix peak
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    # enough untimed steps for the GPU clocks to settle under MFMA load
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--levels", type=int, default=None, help="recursion levels (default: tuned)")
+    ap.add_argument("--steps", type=int, default=25)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--rounds", type=int, default=5, help="interleaved timing rounds")
+    ap.add_argument("--warm-seconds", type=float, default=2.5,
+                    help="wall time of plain products run before anything is timed")
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--levels", type=int, default=2)
     ap.add_argument("--sched", default="grouped")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline and error check")
-    ap.add_argument("--no-extra", action="store_true", help="skip the n=3000 / n=8192 side runs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the n=4096 / n=3000 side runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batch")
     ap.add_argument("--no-schedules", action="store_true",
                     help="skip the depth-first schedules (Two Temp, In-Place, Strassen DFS) at n=4096")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop runs")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the n=8192 split-bfloat16 precision runs")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="host time for the oracle baseline table (all sizes, 1 thread and all cores)")
     ap.add_argument("--profile-only", action="store_true",
-                    help="run only the timed Winograd steps (for rocprofv3 runs)")
+                    help="run only the Winograd steps of the headline (for rocprofv3 runs)")
     ap.add_argument("--profile-set", choices=("gemm", "bf16x3"), default=None,
                     help="for rocprofv3 runs at --n: 'gemm' = the plain float32 product, the fastest "
                          "Winograd plan and torch.matmul (hipBLASLt); 'bf16x3' = the refined "
@@ -66,42 +78,111 @@ def _events(torch, n, stream):
     return evs
 
 
-def time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup):
-    """Run warm-up steps, then exactly ``steps`` timed steps with one event
-    before and one after each step (the wall time and per-step latencies),
-    then ``steps`` more with events before and after every launch, recorded
-    on the stream the launch runs on (the per-launch durations).  An event
-    between two launches of a step delays the second one a little, so the
-    step time is taken without them.
-    Returns (wall ms per step, per-step ms list, per-launch ms lists, kinds)."""
+class Contender:
+    """One product to time: ``step()`` enqueues one whole product on the
+    current stream."""
+
+    def __init__(self, name, step, plan=None, C=None):
+        self.name, self.step, self.plan, self.C = name, step, plan, C
+        self.wall_s = 0.0
+        self.steps = 0
+        self.step_ms = []
+        self.round_tflops = []
+
+
+def plan_contender(torch, L, name, plan, A, B, C, ws):
+    lib = L.load()
+    wsp, wsb = (ws.data_ptr(), ws.numel()) if ws is not None else (None, 0)
+    args = (plan._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), wsp, wsb)
+
+    def step():
+        L.check(lib.mm_plan_execute(*args, torch.cuda.current_stream().cuda_stream))
+    c = Contender(name, step, plan, C)
+    c.args = args
+    c.ws = ws          # the plan reads and writes it: keep it allocated
+    return c
+
+
+def warm_gpu(torch, step, seconds):
+    """Run ``step`` until ``seconds`` of wall time have passed (the GPU's
+    clocks settle under sustained MFMA load)."""
+    t_end = time.perf_counter() + seconds
+    while time.perf_counter() < t_end:
+        for _ in range(4):
+            step()
+        torch.cuda.synchronize()
+
+
+def timed_rounds(torch, contenders, steps, rounds, flops):
+    """``steps`` timed steps of every contender, split over ``rounds``
+    interleaved rounds; in round r the contenders run in an order rotated by
+    r.  Each round's block of steps is bracketed by device synchronisations;
+    events around every step give the per-step latencies."""
+    s = torch.cuda.current_stream()
+    per_round = [steps // rounds + (1 if r < steps % rounds else 0) for r in range(rounds)]
+    for r, cnt in enumerate(per_round):
+        if cnt == 0:
+            continue
+        order = contenders[r % len(contenders):] + contenders[:r % len(contenders)]
+        for c in order:
+            evs = [_events(torch, 2, s) for _ in range(cnt)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for e0, e1 in evs:
+                e0.record(s)
+                c.step()
+                e1.record(s)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            c.wall_s += dt
+            c.steps += cnt
+            c.step_ms += [e0.elapsed_time(e1) for e0, e1 in evs]
+            c.round_tflops.append(flops * cnt / dt / 1e12)
+    for c in contenders:
+        c.tflops = flops * c.steps / c.wall_s / 1e12
+        c.wall_ms = c.wall_s * 1e3 / c.steps
+        c.median_round_tflops = sorted(c.round_tflops)[len(c.round_tflops) // 2]
+
+
+def launch_times(torch, L, c, steps):
+    """Per-launch durations of a plan contender: ``steps`` more products,
+    each with events before and after every launch, recorded on the stream
+    that launch runs on (mm_plan_execute_timed).  Returns (per-launch ms
+    lists, launch kinds)."""
     import ctypes
     lib = L.load()
     s = torch.cuda.current_stream()
-    nops = plan.info["launches"]
+    nops = c.plan.info["launches"]
     nev = 2 * nops
-    wsp, wsb = (ws.data_ptr(), ws.numel()) if ws is not None else (None, 0)
-    args = (plan._ptr, A.data_ptr(), B.data_ptr(), C.data_ptr(), wsp, wsb, s.cuda_stream)
-    for _ in range(warmup):
-        L.check(lib.mm_plan_execute(*args))
-    steps_ev = [_events(torch, 2, s) for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        steps_ev[i][0].record(s)
-        L.check(lib.mm_plan_execute(*args))
-        steps_ev[i][1].record(s)
-    torch.cuda.synchronize()
-    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
-    step_ms = [a.elapsed_time(b) for a, b in steps_ev]
     evsets = [_events(torch, nev, s) for _ in range(steps)]
     ptrs = [(ctypes.c_void_p * nev)(*[e.cuda_event for e in evs]) for evs in evsets]
     torch.cuda.synchronize()
     for i in range(steps):
-        L.check(lib.mm_plan_execute_timed(*args, ptrs[i], nev))
+        L.check(lib.mm_plan_execute_timed(*c.args, s.cuda_stream, ptrs[i], nev))
     torch.cuda.synchronize()
     per_op = [[evs[2 * j].elapsed_time(evs[2 * j + 1]) for evs in evsets] for j in range(nops)]
-    kinds = [lib.mm_plan_op_kind(plan._ptr, j) for j in range(nops)]
-    return wall_ms, step_ms, per_op, kinds
+    kinds = [lib.mm_plan_op_kind(c.plan._ptr, j) for j in range(nops)]
+    return per_op, kinds
+
+
+def time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup):
+    """Warm-up steps, then exactly ``steps`` timed steps with one event before
+    and one after each step (wall time and per-step latencies), then
+    ``steps`` more with events around every launch (per-launch durations).
+    An event between two launches of a step delays the second one a little,
+    so the step time is taken without them.
+    Returns (wall ms per step, per-step ms list, per-launch ms lists, kinds)."""
+    c = plan_contender(torch, L, "plan", plan, A, B, C, ws)
+    for _ in range(warmup):
+        c.step()
+    timed_rounds(torch, [c], steps, 1, 2.0)
+    per_op, kinds = launch_times(torch, L, c, steps)
+    return c.wall_ms, c.step_ms, per_op, kinds
+
+
+# Element-wise recipes of the plan listing (EwKind in csrc/desc.h).
+EW_RECIPES = {0: "copy", 1: "add", 2: "sub", 3: "winograd S", 4: "winograd T", 5: "winograd U", 11: "zero",
+              15: "winograd U (accumulate)", 17: "strassen S", 18: "strassen T", 19: "strassen U", 22: "k-split sum"}
 
 
 def plan_launches(plan, esz):
@@ -111,7 +192,7 @@ def plan_launches(plan, esz):
     subproblem) and algorithmic HBM bytes (EW: every valid input element read
     once, every valid output element written once), read off the plan
     listing."""
-    out, flops, nbytes = [], 0.0, 0.0
+    out, flops, nbytes, ekinds = [], 0.0, 0.0, set()
     for line in plan.describe().splitlines():
         w = line.split()
         if not w:
@@ -122,8 +203,8 @@ def plan_launches(plan, esz):
             out.append(dict(kind=w[1], stream=1 if w[-1] == "aux" else 0, flops=flops, bytes=nbytes,
                             grid=int(w[3]) if len(w) > 3 else 0,
                             cfg=int(w[4]) if w[1] in ("GEMM", "WINO") and len(w) > 4 else None,
-                            flags=w[5:]))
-            flops, nbytes = 0.0, 0.0
+                            flags=w[5:], recipes=sorted(ekinds)))
+            flops, nbytes, ekinds = 0.0, 0.0, set()
         elif w[0] == "GEMM":
             m, n, k = map(int, w[1:4])
             flops += 2.0 * m * n * k
@@ -131,6 +212,7 @@ def plan_launches(plan, esz):
             m, n, k = map(int, w[1:4])
             flops += 7 * 2.0 * m * n * k
         elif w[0] in ("EW", "TRANS"):
+            ekinds.add(EW_RECIPES.get(int(w[1]), w[1]) if w[0] == "EW" else "transpose")
             _, ins, outs = [x.strip() for x in line.split("|")]
             for tok in (ins + " " + outs).split():
                 if tok != "-":
@@ -258,43 +340,86 @@ def ew_bandwidth(res, n):
     for lau, d, k in zip(launches, res["per_op"], res["kinds"]):
         if k % 8 in (0, 6):  # element-wise and transposing passes
             ms = sum(d) / len(d)
-            out.append(dict(stream="aux" if k >= 8 else "main", bytes=lau["bytes"], ms=round(ms, 4),
-                            gbs=round(lau["bytes"] / (ms * 1e-3) / 1e9, 1)))
+            gbs = lau["bytes"] / (ms * 1e-3) / 1e9
+            out.append(dict(recipes=lau["recipes"], stream="aux" if k >= 8 else "main", bytes=lau["bytes"],
+                            ms=round(ms, 4),
+                            gbs=round(gbs, 1), hbm_frac=round(gbs / PEAK_HBM_GBS, 3)))
     return out
 
 
-def cpu_baseline(A_np, B_np, seconds):
-    """The oracle (double triple loop, all host cores) on a sample of rows,
-    repeated until about ``seconds`` of host time have been spent."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(inputs, big, seconds):
+    """The oracle (double-precision triple loop) timed on the host: at
+    n = 512, 3000, 4096 and the headline n, with one thread and with all of
+    them, three runs each over a sample of output rows sized so that the
+    whole table takes about ``seconds`` of host time.  ``big`` = (A, B) of
+    the headline product.  ``value`` is the all-core rate at the headline n."""
     import numpy as np
     from oracle import naive
-    n = A_np.shape[0]
-    rows = 8
-    t0 = time.perf_counter()
-    naive.gemm_rows(A_np, B_np, np.arange(rows))
-    dt = time.perf_counter() - t0
-    rows = int(max(8, min(n, rows * seconds / max(dt, 1e-3))))
-    sample = np.linspace(0, n - 1, rows).astype(np.int64)
-    reps, spent = 0, 0.0
-    while True:
-        t0 = time.perf_counter()
-        ref = naive.gemm_rows(A_np, B_np, sample)
-        spent += time.perf_counter() - t0
-        reps += 1
-        if spent >= 0.8 * seconds or rows < n:
-            break
-    flops = 2.0 * rows * n * n * reps
-    return dict(value=round(flops / spent / 1e12, 6), unit="TFLOP/s", cores=naive.max_threads(),
-                kind="oracle",
-                sample=f"{reps} pass(es) over {rows} of {n} output rows of the n={n} product "
-                       f"({spent:.1f} s, float64 triple loop)"), sample, ref
+    nth = naive.max_threads()
+    nbig = big[0].shape[0]
+    sizes = sorted({512, 3000, 4096, nbig})
+    per_run = seconds / (len(sizes) * 2 * 3)
+    table = []
+    for n in sizes:
+        A_np, B_np = big if n == nbig else inputs.pair("uniform", n, n, n, 0, np.float32)
+        for th in (1, nth):
+            # calibrate the row count so one run takes about per_run seconds
+            r0 = th
+            t0 = time.perf_counter()
+            naive.gemm_rows(A_np, B_np, np.arange(r0), threads=th)
+            dt = max(time.perf_counter() - t0, 1e-4)
+            rows = int(min(n, max(th, r0 * per_run / dt)))
+            rows = max(th, rows // th * th) if rows < n else n
+            sample = np.linspace(0, n - 1, rows).astype(np.int64)
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                naive.gemm_rows(A_np, B_np, sample, threads=th)
+                ts.append(time.perf_counter() - t0)
+            p50, p99 = pct(ts, 50), pct(ts, 99)
+            table.append(dict(n=n, threads=th, rows=rows, runs=3, p50_s=round(p50, 4), p99_s=round(p99, 4),
+                              gflops=round(2.0 * rows * n * n / p50 / 1e9, 3)))
+            print(f"# oracle n={n} threads={th}: {table[-1]}", file=sys.stderr, flush=True)
+    head = [t for t in table if t["n"] == nbig and t["threads"] == nth][0]
+    return dict(value=round(head["gflops"] / 1e3, 6), unit="TFLOP/s", cores=nth, kind="oracle",
+                cpu=cpu_model(),
+                sample=f"{head['rows']} of {nbig} output rows of the n={nbig} product per run, 3 runs, "
+                       f"{nth} threads (p50 run {head['p50_s']} s); the table gives n = "
+                       f"{', '.join(str(s) for s in sizes)} at 1 and {nth} threads",
+                table=table)
+
+
+def sample_rows(n, count=64):
+    """Output rows checked against the oracle: ``count`` rows spread over
+    the matrix, always including the first and the last."""
+    import numpy as np
+    return np.unique(np.r_[0, np.linspace(0, n - 1, count).astype(np.int64), n - 1])
 
 
 def rel_err(C, rows, ref):
+    """Relative Frobenius error of C's rows ``rows`` against the oracle's."""
     import numpy as np
     import torch
     got = C[torch.from_numpy(rows).to(C.device)].double().cpu().numpy()
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def oracle_rows(A_np, B_np, rows):
+    from oracle import naive
+    return naive.gemm_rows(A_np, B_np, rows)
 
 
 def profile_set(torch, api, L, inputs, tuner, args):
@@ -334,6 +459,21 @@ def profile_set(torch, api, L, inputs, tuner, args):
     print(json.dumps(out), flush=True)
 
 
+def leaf_roofline(res, dt):
+    """Roofline of a product's dominant leaf launch; the split-bfloat16 leaves
+    run six bfloat16 MFMA products per float product, against the BF16 peak."""
+    rl = gemm_roofline(res, 0, traffic=False)
+    if dt != "bf16x3":
+        return rl
+    lau = [x for x, k in zip(plan_launches(res["plan"], 4), res["kinds"]) if k in (1, 9)]
+    top = max(lau, key=lambda x: x["flops"]) if lau else None
+    bf = 6.0 * rl["flops_per_launch"]
+    ach = bf / (rl["avg_launch_ms"] * 1e-3) / 1e12
+    return dict(rl, achieved=round(ach, 2), peak=PEAK_BF16_TFLOPS, frac=round(ach / PEAK_BF16_TFLOPS, 4),
+                flops_per_launch=bf, kernel=f"gemm_bf16x3_kernel (tile cfg {top['cfg'] if top else None}, "
+                                            "6 bf16 products per leaf product)")
+
+
 def bench_precision(torch, api, L, inputs, tuner, n=8192, steps=10, warmup=10, rows=48):
     """n = 8192, A and B Gaussian with rows scaled by 10^u, u ~ U[-3, 3]:
     split-bfloat16 refined leaves under two Winograd levels (and plain), the
@@ -360,7 +500,8 @@ def bench_precision(torch, api, L, inputs, tuner, n=8192, steps=10, warmup=10, r
         r = run_product(torch, api, L, algo, "grouped" if lv else "auto", n, lv, A, B, steps, warmup,
                         dtype=dt, tile=tile, split_k=sk, overlap=ov, leaf_u=lu, trans_b=tb)
         out[name] = {"tflops": round(r["tflops"], 3), "p50_ms": round(r["p50"], 4),
-                     "rel_err": rel_err(r["C"], sample, ref), "tile": tile, "overlap": ov}
+                     "rel_err": rel_err(r["C"], sample, ref), "tile": tile, "overlap": ov,
+                     "roofline": leaf_roofline(r, dt)}
         print(f"# precision {name}: {out[name]}", file=sys.stderr, flush=True)
         del r
     out["speedup_bf16x3_winograd_vs_f32_plain"] = round(out["bf16x3_winograd_L2"]["tflops"] /
@@ -429,10 +570,50 @@ def bench_fp64_small(torch, api, L, inputs, n=512, cutoff=64, steps=50, warmup=1
     return out
 
 
-def bench_batched(torch, api, inputs, tuner, count=512, steps=10, warmup=3, seed=7):
+def bench_d2(torch, api, L, inputs, tuner, with_ref=True):
+    """Square float32 n = 4096 and n = 3000 (not a power of two; with L <= 3
+    levels 3000 = 8 * 375 needs no padding): the plain MFMA GEMM, then
+    Strassen-Winograd and Strassen at one and two levels, each with its
+    relative error against the oracle on sampled rows (first and last row
+    included)."""
+    import numpy as np
+    out = {}
+    arrays = {}
+    for n2 in (4096, 3000):
+        A2_np, B2_np = inputs.pair("uniform", n2, n2, n2, 1, np.float32)
+        A2, B2 = torch.from_numpy(A2_np).cuda(), torch.from_numpy(B2_np).cuda()
+        rows = sample_rows(n2)
+        ref = oracle_rows(A2_np, B2_np, rows) if with_ref else None
+        pt2, pk2 = tuned_plain(tuner, n2)
+        p2 = run_product(torch, api, L, "naive", "auto", n2, 0, A2, B2, 20, 10, tile=pt2, split_k=pk2)
+        e = {"plain": {"tflops": round(p2["tflops"], 3), "p99_ms": round(p2["p99"], 4)}}
+        if with_ref:
+            e["plain"]["rel_err"] = rel_err(p2["C"], rows, ref)
+        for lv in (1, 2):
+            t2, o2, u2, b2 = tuned_leaf(tuner, n2, lv)
+            w2 = run_product(torch, api, L, "winograd", "grouped", n2, lv, A2, B2, 20, 10, tile=t2,
+                             overlap=o2, leaf_u=u2, trans_b=b2)
+            s2 = run_product(torch, api, L, "strassen", "grouped", n2, lv, A2, B2, 20, 10,
+                             tile=None if u2 else t2)
+            for name, r in ((f"winograd_L{lv}", w2), (f"strassen_L{lv}", s2)):
+                e[name] = {"tflops": round(r["tflops"], 3), "p50_ms": round(r["p50"], 4),
+                           "p99_ms": round(r["p99"], 4), "padded_order": r["plan"].info.get("M")}
+                if with_ref:
+                    e[name]["rel_err"] = rel_err(r["C"], rows, ref)
+            e[f"winograd_L{lv}"]["speedup_vs_plain"] = round(w2["tflops"] / p2["tflops"], 4)
+            del w2, s2
+        out[str(n2)] = e
+        arrays[n2] = (A2_np, B2_np, A2, B2, rows, ref)
+        print(f"# d2 n={n2}: {e}", file=sys.stderr, flush=True)
+    return out, arrays
+
+
+def bench_batched(torch, api, inputs, tuner, count=512, steps=10, warmup=3, seed=7, check=True):
     """512 independent float32 products, m, n, k log-uniform in [64, 2048]
     (multiples of 16), levels per size class from the tuner, run as one
-    level-synchronous batched plan replayed from a hipGraph."""
+    batched plan replayed from a hipGraph; the relative error of a sample of
+    problems (sampled rows, every one against the oracle) is reported."""
+    import numpy as np
     shapes = inputs.batched_shapes(count, seed)
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
@@ -460,6 +641,24 @@ def bench_batched(torch, api, inputs, tuner, count=512, steps=10, warmup=3, seed
         return (time.perf_counter() - t0) * 1e3 / reps, e0.elapsed_time(e1) / reps
 
     wall, dev = timed(plan, steps)
+    out = {"workload": f"{count} fp32 products, m,n,k log-uniform in [64,2048] (x16), uniform[-1,1]",
+           "tflops": round(flops / (wall * 1e-3) / 1e12, 3), "ms_per_batch": round(wall, 4),
+           "device_ms_per_batch": round(dev, 4), "launches_per_batch": plan.info["launches"],
+           "levels_histogram": {str(l): levels.count(l) for l in sorted(set(levels))}, "graph": True}
+    if check:
+        # every problem with a recursion level, the largest problems, and an
+        # even spread over the rest
+        vol = np.array([m * n * k for (m, n, k) in shapes])
+        pick = set(np.argsort(-vol)[:4].tolist()) | {i for i, l in enumerate(levels) if l > 0}
+        pick |= set(np.linspace(0, count - 1, 12).astype(int).tolist())
+        errs = []
+        for i in sorted(pick)[:32]:
+            m, n, k = shapes[i]
+            rows = sample_rows(m, 8)
+            ref = oracle_rows(As[i].cpu().numpy(), Bs[i].cpu().numpy(), rows)
+            errs.append(rel_err(Cs[i], rows, ref))
+        out["rel_err_max"] = max(errs)
+        out["rel_err_checked_problems"] = len(errs)
     naive_plans = [api.get_plan("naive", "auto", m, n, k, 1, 0, "f32", k, n, n, False, As[0].device)
                    for (m, n, k) in shapes]
 
@@ -472,44 +671,68 @@ def bench_batched(torch, api, inputs, tuner, count=512, steps=10, warmup=3, seed
             torch.matmul(a, b, out=c)
     wall_n, _ = timed(loop_naive, 3)
     wall_t, _ = timed(loop_torch, 3)
-    return {"workload": f"{count} fp32 products, m,n,k log-uniform in [64,2048] (x16), uniform[-1,1]",
-            "tflops": round(flops / (wall * 1e-3) / 1e12, 3), "ms_per_batch": round(wall, 4),
-            "device_ms_per_batch": round(dev, 4), "launches_per_batch": plan.info["launches"],
-            "levels_histogram": {str(l): levels.count(l) for l in sorted(set(levels))},
-            "loop_of_mm_naive_tflops": round(flops / (wall_n * 1e-3) / 1e12, 3),
-            "loop_of_torch_matmul_tflops": round(flops / (wall_t * 1e-3) / 1e12, 3),
-            "graph": True}
+    out["loop_of_mm_naive_tflops"] = round(flops / (wall_n * 1e-3) / 1e12, 3)
+    out["loop_of_torch_matmul_tflops"] = round(flops / (wall_t * 1e-3) / 1e12, 3)
+    return out
 
 
-def bench_serving(torch, inputs, count=160, budget_gib=32, slots=4, seed=11):
+def bench_serving(torch, inputs, count=160, budget_gib=32, slots=4, seed=11, check=True):
     """Poisson arrivals, square n: 70% in [256,1024], 25% in [1024,4096],
     5% = 8192; dtype 50/50 float32 / split-bfloat16 refined; HBM-budget
-    admission, one stream and workspace per slot."""
+    admission into one device arena of the budget's size, one stream per
+    slot (one executor for every run).  The outputs of a sample of requests
+    of the untimed warm-up run are checked against the oracle on sampled
+    rows (a request's result is the same in every run: plans depend only on
+    its shape and dtype)."""
+    import numpy as np
     from paper_2309_00628_amd import serving
     dev = torch.device("cuda", 0)
     base = inputs.serving_trace(count, seed, qps=1.0)
     reqs = serving.make_requests(base, dev)
     torch.cuda.synchronize()
+    ex = serving.GpuExecutor(slots, budget_gib << 30, keep_outputs=False)
+    # requests whose outputs are kept for the error check: a spread over
+    # the trace covering both dtypes and the three size bands
+    keep = set()
+    for band in ((256, 1024), (1025, 4096), (8192, 8192)):
+        for dt in ("f32", "bf16x3"):
+            ids = [i for i, t in enumerate(base) if band[0] <= t["n"] <= band[1] and t["dtype"] == dt]
+            keep |= set(ids[:2])
 
-    def run(qps):
+    def run(qps, keep_ids=()):
         for r, t in zip(reqs, base):
             r.arrival = 0.0 if qps is None else t["t"] / qps
             r.t_admit = r.t_done = -1.0
             r.error = ""
             r.C = None
-        ex = serving.GpuExecutor(slots, keep_outputs=False)
+        ex.keep_rids = set(keep_ids)
         srv = serving.Server(ex, budget_gib << 30, n_slots=slots)
         done, wall = srv.run(reqs)
         torch.cuda.synchronize()
         st = serving.summarize(done, wall)
         st["max_concurrent"] = srv.max_running
+        st["peak_reserved_gib"] = round(srv.peak_reserved / 2 ** 30, 3)
         return st
 
-    run(None)                                   # warm-up: plans, workspaces
-    sat = run(None)
+    run(None, keep if check else ())            # warm-up (plans; sample outputs kept for the check)
     out = {"workload": f"{count} requests, n: 70% U[256,1024], 25% U[1024,4096], 5% 8192; "
                        "dtype 50/50 f32 / bf16x3; Poisson arrivals",
-           "hbm_budget_gib": budget_gib, "slots": slots, "saturation": sat, "load": {}}
+           "hbm_budget_gib": budget_gib, "slots": slots, "load": {}}
+    if check:
+        errs = {}
+        for i in sorted(keep):
+            r = reqs[i]
+            if r.C is None:
+                continue
+            rows = sample_rows(r.m, 8)
+            ref = oracle_rows(r.A[torch.from_numpy(rows).to(dev)].cpu().numpy(), r.B.cpu().numpy(),
+                              np.arange(len(rows)))
+            errs[f"{r.dtype}_n{r.n}_id{i}"] = rel_err(r.C, rows, ref)
+            r.C = None
+        out["rel_err_sample"] = errs
+        out["rel_err_max"] = max(errs.values()) if errs else None
+    sat = run(None)
+    out["saturation"] = sat
     for f in (0.25, 0.5, 0.75, 0.9):
         qps = f * sat["req_per_s"]
         st = run(qps)
@@ -545,131 +768,123 @@ def main():
     if args.profile_set:
         profile_set(torch, api, L, inputs, tuner, args)
         return
-    n = args.n
+    n, lv = args.n, args.levels
+    flops = 2.0 * n ** 3
     A_np, B_np = inputs.pair("uniform", n, n, n, 0, np.float32)
     A = torch.from_numpy(A_np).cuda()
     B = torch.from_numpy(B_np).cuda()
-    print(f"# bench n={n} fp32, steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    print(f"# bench n={n} fp32 L={lv}, steps={args.steps} warmup={args.warmup} rounds={args.rounds}",
+          file=sys.stderr, flush=True)
 
-    # level choice: the tuner's cached choice for this size class; without one
-    # time L = 1..3 briefly and keep the fastest
-    ch = tuner.choose(n, n, n, "f32")
-    rec = ch.get("best_recursive") if ch["source"] == "tuned" else None
-    if args.levels is None and ch["source"] == "tuned" and ch["levels"] > 0:
-        levels = ch["levels"]
-    elif args.levels is None and rec:
-        levels = rec["levels"]  # the plain product won the size class; time the best recursion
-    elif args.levels is None:
-        best = None
-        for lv in (1, 2, 3):
-            r = run_product(torch, api, L, "winograd", args.sched, n, lv, A, B, 5, 2)
-            print(f"# tune L={lv}: {r['tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
-            if best is None or r["tflops"] > best[1]:
-                best = (lv, r["tflops"])
-        levels = best[0]
-    else:
-        levels = args.levels
+    def plan_and_buffers(plan):
+        ws = torch.empty(max(plan.ws_bytes, 256), dtype=torch.uint8, device="cuda")
+        return ws, torch.empty((n, n), dtype=torch.float32, device="cuda")
 
-    tile, overlap, leaf_u, trans_b = tuned_leaf(tuner, n, levels)
-    win = run_product(torch, api, L, "winograd", args.sched, n, levels, A, B, args.steps, args.warmup,
-                      tile=tile, overlap=overlap, leaf_u=leaf_u, trans_b=trans_b)
-    print(f"# winograd L={levels}: {win['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    tile, overlap, leaf_u, trans_b = tuned_leaf(tuner, n, lv)
+    wplan = api.Plan("winograd", args.sched, n, n, n, cutoff=1, levels=lv, tile=tile, overlap=overlap,
+                     leaf_u=leaf_u, trans_b=trans_b)
+    win = plan_contender(torch, L, "winograd", wplan, A, B, *reversed(plan_and_buffers(wplan)))
     if args.profile_only:
-        print(json.dumps({"profile_only": True, "n": n, "levels": levels,
-                          "tflops": round(win["tflops"], 3),
-                          "roofline": gemm_roofline(win, n)}), flush=True)
+        warm_gpu(torch, win.step, args.warm_seconds)
+        timed_rounds(torch, [win], args.steps, 1, flops)
+        per_op, kinds = launch_times(torch, L, win, args.steps)
+        print(json.dumps({"profile_only": True, "n": n, "levels": lv, "tflops": round(win.tflops, 3),
+                          "roofline": gemm_roofline(dict(plan=wplan, per_op=per_op, kinds=kinds), n)}),
+              flush=True)
         return
     plain_tile, plain_split = tuned_plain(tuner, n)
-    plain = run_product(torch, api, L, "naive", "auto", n, 0, A, B, args.steps, args.warmup,
-                        tile=plain_tile, split_k=plain_split)
-    print(f"# plain mfma gemm: {plain['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
-    # Strassen (Section 2.2) breadth first at the same levels and leaf tile
-    # (a tile of the fused leaf-level kernel names another kernel: then the default)
-    strs = run_product(torch, api, L, "strassen", "grouped", n, levels, A, B, 20, 10,
-                       tile=None if leaf_u else tile)
-    print(f"# strassen L={levels}: {strs['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
-
-    # vendor GEMM (hipBLASLt through torch.matmul) as context only
+    pplan = api.Plan("naive", "auto", n, n, n, cutoff=1, levels=0, tile=plain_tile, split_k=plain_split)
+    plain = plan_contender(torch, L, "plain", pplan, A, B, *reversed(plan_and_buffers(pplan)))
     torch.backends.cuda.matmul.allow_tf32 = False
-    for _ in range(3):
-        torch.matmul(A, B)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        torch.matmul(A, B)
-    torch.cuda.synchronize()
-    vendor_tflops = 2.0 * n ** 3 / ((time.perf_counter() - t0) / args.steps) / 1e12
+    Cv = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    vendor = Contender("hipblaslt", lambda: torch.matmul(A, B, out=Cv), None, Cv)
+    contenders = [win, plain, vendor]
+
+    warm_gpu(torch, plain.step, args.warm_seconds)
+    for c in contenders:
+        for _ in range(args.warmup):
+            c.step()
+    timed_rounds(torch, contenders, args.steps, args.rounds, flops)
+    for c in contenders:
+        print(f"# {c.name}: {c.tflops:.2f} TFLOP/s (rounds {[round(x, 1) for x in c.round_tflops]})",
+              file=sys.stderr, flush=True)
+    w_ops, w_kinds = launch_times(torch, L, win, args.steps)
+    p_ops, p_kinds = launch_times(torch, L, plain, args.steps)
+    wres = dict(plan=wplan, per_op=w_ops, kinds=w_kinds)
+    pres = dict(plan=pplan, per_op=p_ops, kinds=p_kinds)
+    # Strassen (Section 2.2) breadth first at the same levels (context)
+    strs = run_product(torch, api, L, "strassen", "grouped", n, lv, A, B, 20, 5, tile=None if leaf_u else tile)
+    print(f"# strassen L={lv}: {strs['tflops']:.2f} TFLOP/s", file=sys.stderr, flush=True)
+
+    def summary(c):
+        return {"tflops": round(c.tflops, 3), "median_round_tflops": round(c.median_round_tflops, 3),
+                "round_tflops": [round(x, 2) for x in c.round_tflops],
+                "p50_ms": round(pct(c.step_ms, 50), 4), "p99_ms": round(pct(c.step_ms, 99), 4)}
 
     out = {
         "metric": "effective TFLOP/s (2mnk/t) Winograd vs plain GEMM at stated rel. err; p99 ms",
-        "value": round(win["tflops"], 3),
+        "value": round(win.tflops, 3),
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(win["wall_ms"], 4),
+        "ms_per_step": round(win.wall_ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (uniform[-1,1], seeded)",
-        "config": {"workload": f"square fp32 matmul n={n}, Strassen-Winograd {args.sched} "
-                               f"L={levels} vs plain MFMA GEMM",
-                   "n": n, "levels": levels, "schedule": args.sched, "leaf_tile_cfg": tile,
+        "config": {"workload": f"square fp32 matmul n={n}, Strassen-Winograd {args.sched} L={lv} "
+                               f"vs plain MFMA GEMM",
+                   "n": n, "levels": lv, "schedule": args.sched, "leaf_tile_cfg": tile,
                    "overlap": overlap, "leaf_u": leaf_u, "trans_b": trans_b},
-        "p50_ms": round(win["p50"], 4),
-        "p99_ms": round(win["p99"], 4),
-        "plain_gemm": {"tflops": round(plain["tflops"], 3), "p50_ms": round(plain["p50"], 4),
-                       "p99_ms": round(plain["p99"], 4), "tile": plain_tile, "split_k": plain_split},
-        "speedup_vs_plain": round(win["tflops"] / plain["tflops"], 4),
-        "strassen_grouped": {"levels": levels, "tflops": round(strs["tflops"], 3),
+        "timing": {"warm_seconds": args.warm_seconds, "rounds": args.rounds,
+                   "note": "K steps per contender in R interleaved rounds, order rotated per round"},
+        "p50_ms": round(pct(win.step_ms, 50), 4),
+        "p99_ms": round(pct(win.step_ms, 99), 4),
+        "winograd": summary(win),
+        "plain_gemm": dict(summary(plain), tile=plain_tile, split_k=plain_split),
+        "hipblaslt": summary(vendor),
+        "speedup_vs_plain": round(win.tflops / plain.tflops, 4),
+        "speedup_vs_plain_median_round": round(win.median_round_tflops / plain.median_round_tflops, 4),
+        "speedup_vs_hipblaslt": round(win.tflops / vendor.tflops, 4),
+        "strassen_grouped": {"levels": lv, "tflops": round(strs["tflops"], 3),
                              "p50_ms": round(strs["p50"], 4), "p99_ms": round(strs["p99"], 4)},
-        "vendor_hipblaslt_tflops": round(vendor_tflops, 3),
-        "roofline": gemm_roofline(win, n),
-        "plain_gemm_roofline": gemm_roofline(plain, n, traffic=False),
-        "addition_kernels": ew_bandwidth(win, n),
+        "roofline": gemm_roofline(wres, n),
+        "plain_gemm_roofline": gemm_roofline(pres, n, traffic=False),
+        "addition_kernels": ew_bandwidth(wres, n),
     }
-
     if not args.no_cpu:
-        cb, rows, ref = cpu_baseline(A_np, B_np, args.cpu_seconds)
-        out["cpu_baseline"] = cb
-        out["rel_err"] = rel_err(win["C"], rows, ref)
-        out["plain_rel_err"] = rel_err(plain["C"], rows, ref)
+        rows = sample_rows(n)
+        ref = oracle_rows(A_np, B_np, rows)
+        out["rel_err"] = rel_err(win.C, rows, ref)
+        out["plain_gemm"]["rel_err"] = rel_err(plain.C, rows, ref)
+        out["hipblaslt"]["rel_err"] = rel_err(vendor.C, rows, ref)
         out["strassen_grouped"]["rel_err"] = rel_err(strs["C"], rows, ref)
-        out["rel_err_note"] = "relative Frobenius error vs the float64 oracle on the sampled rows"
-    if not args.no_schedules:
-        out["schedules"] = bench_schedules(torch, api, L, A, B, n, *((rows, ref) if not args.no_cpu else ()))
+        out["rel_err_note"] = (f"relative Frobenius error vs the float64 oracle on {len(rows)} sampled rows "
+                               "(first and last included)")
+    del strs
+    for c in contenders:
+        c.C = None
+    del win, plain, vendor, contenders, Cv
 
     if not args.no_extra:
-        extra = {}
-        for n2, lvls in ((3000, (1, 2)), (8192, (1, 2))):
-            A2_np, B2_np = inputs.pair("uniform", n2, n2, n2, 1, np.float32)
-            A2, B2 = torch.from_numpy(A2_np).cuda(), torch.from_numpy(B2_np).cuda()
-            pt2, pk2 = tuned_plain(tuner, n2)
-            p2 = run_product(torch, api, L, "naive", "auto", n2, 0, A2, B2, 20, 10, tile=pt2, split_k=pk2)
-            e = {"plain_tflops": round(p2["tflops"], 3)}
-            for lv in lvls:
-                t2, o2, u2, b2 = tuned_leaf(tuner, n2, lv)
-                w2 = run_product(torch, api, L, "winograd", args.sched, n2, lv, A2, B2, 20, 10, tile=t2,
-                                 overlap=o2, leaf_u=u2, trans_b=b2)
-                e[f"winograd_L{lv}_tflops"] = round(w2["tflops"], 3)
-                e[f"winograd_L{lv}_p99_ms"] = round(w2["p99"], 4)
-                s2 = run_product(torch, api, L, "strassen", "grouped", n2, lv, A2, B2, 20, 10,
-                                 tile=None if u2 else t2)
-                e[f"strassen_L{lv}_tflops"] = round(s2["tflops"], 3)
-            extra[str(n2)] = e
-            print(f"# extra n={n2}: {e}", file=sys.stderr, flush=True)
-            del A2, B2
-        out["extra"] = extra
-
+        out["d2"], arrays = bench_d2(torch, api, L, inputs, tuner, with_ref=not args.no_cpu)
+        if not args.no_schedules:
+            A4_np, B4_np, A4, B4, rows4, ref4 = arrays[4096]
+            out["schedules"] = bench_schedules(torch, api, L, A4, B4, 4096,
+                                               *((rows4, ref4) if not args.no_cpu else ()))
+        del arrays
     if not args.no_precision:
         out["precision"] = bench_precision(torch, api, L, inputs, tuner)
         out["fp64_small"] = bench_fp64_small(torch, api, L, inputs)
     if not args.no_batched:
-        out["batched"] = bench_batched(torch, api, inputs, tuner)
+        out["batched"] = bench_batched(torch, api, inputs, tuner, check=not args.no_cpu)
         print(f"# batched: {out['batched']}", file=sys.stderr, flush=True)
     if not args.no_serving:
-        out["serving"] = bench_serving(torch, inputs)
+        out["serving"] = bench_serving(torch, inputs, check=not args.no_cpu)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(inputs, (A_np, B_np), args.cpu_seconds)
 
     print(json.dumps(out), flush=True)
 

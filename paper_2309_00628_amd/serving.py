@@ -3,11 +3,18 @@
 Requests (C = A B with operands already resident on the device) arrive over
 time.  The loop admits them first-come first-served whenever a slot is free
 and the HBM budget has room for what the request needs while it runs (its
-output C and its plan's workspace).  A slot is a HIP stream with its own
-device-resident workspace, so admitted requests overlap on the device; a
-request finishing frees its slot and its budget, and the next queued request
-is admitted at once, while the others are still running (continuous
-batching, not a queue in front of one product at a time).
+output C and its plan's workspace).  A slot is a HIP stream, so admitted
+requests overlap on the device; a request finishing frees its slot and its
+budget, and the next queued request is admitted at once, while the others
+are still running (continuous batching, not a queue in front of one product
+at a time).
+
+The budget is enforced on the device, not only in the books: the GPU
+executor allocates one arena of exactly the budget's size when it is built
+and places every running request's output and workspace in it (first fit,
+256-byte aligned, freed blocks merged with their neighbours).  A request is
+admitted only when both blocks can be placed, so the executor's device
+memory never exceeds the budget, whatever the mix and however long it runs.
 
 Each request runs the library's product for its size: Strassen-Winograd with
 the autotuner's levels and tile for its size class and dtype (float32 or the
@@ -95,7 +102,8 @@ class Server:
                     free.append(slot)
                     done.append(r)
                     progressed = True
-            while queue and free and self.reserved + queue[0].need_bytes <= self.budget:
+            while (queue and free and self.reserved + queue[0].need_bytes <= self.budget and
+                   self._reserve(queue[0])):
                 r = queue.popleft()
                 r.slot = free.pop()
                 self.reserved += r.need_bytes
@@ -107,6 +115,7 @@ class Server:
                 except Exception as e:          # a failed request frees its slot
                     r.error = str(e)
                     r.t_done = self.clock() - t0
+                    self.ex.release(r)
                     self.reserved -= r.need_bytes
                     free.append(r.slot)
                     done.append(r)
@@ -124,6 +133,54 @@ class Server:
                     time.sleep(self.idle_sleep)
         wall = self.clock() - t0
         return done, wall
+
+    def _reserve(self, r):
+        """Ask the executor to place the request's memory (executors without
+        an arena always can)."""
+        reserve = getattr(self.ex, "reserve", None)
+        return True if reserve is None else bool(reserve(r))
+
+
+class Arena:
+    """First-fit allocator of byte ranges in a buffer of ``capacity`` bytes:
+    host bookkeeping only (offsets), ``align``-byte aligned blocks, freed
+    blocks merged with free neighbours."""
+
+    def __init__(self, capacity, align=256):
+        self.capacity = int(capacity)
+        self.align = int(align)
+        self.free_list = [(0, self.capacity)] if self.capacity > 0 else []   # sorted (offset, size)
+        self.used = {}                                                      # offset -> size
+
+    def alloc(self, nbytes):
+        size = max(self.align, -(-int(nbytes) // self.align) * self.align)
+        for i, (off, sz) in enumerate(self.free_list):
+            if sz >= size:
+                if sz == size:
+                    del self.free_list[i]
+                else:
+                    self.free_list[i] = (off + size, sz - size)
+                self.used[off] = size
+                return off
+        return None
+
+    def free(self, off):
+        size = self.used.pop(off)
+        fl = self.free_list
+        i = 0
+        while i < len(fl) and fl[i][0] < off:
+            i += 1
+        fl.insert(i, (off, size))
+        if i + 1 < len(fl) and fl[i][0] + fl[i][1] == fl[i + 1][0]:       # merge with the next
+            fl[i] = (fl[i][0], fl[i][1] + fl[i + 1][1])
+            del fl[i + 1]
+        if i > 0 and fl[i - 1][0] + fl[i - 1][1] == fl[i][0]:             # and the previous
+            fl[i - 1] = (fl[i - 1][0], fl[i - 1][1] + fl[i][1])
+            del fl[i]
+
+    @property
+    def used_bytes(self):
+        return sum(self.used.values())
 
 
 def summarize(done, wall):
@@ -143,15 +200,27 @@ def summarize(done, wall):
 
 
 class GpuExecutor:
-    """Runs requests on the current GPU through libmm, one HIP stream per slot."""
+    """Runs requests on the current GPU through libmm, one HIP stream per slot,
+    every running request's output and workspace placed in one device arena
+    of ``arena_bytes`` (give it the server's budget).
 
-    def __init__(self, n_slots, device=None, keep_outputs=True):
+    Outputs are views into the arena while their request runs.  When a
+    request completes, its blocks return to the arena; its output is first
+    copied out (and the copy waited for) if ``keep_outputs`` is set or its id
+    is in ``keep_rids``, else it is dropped (the caller has consumed it)."""
+
+    def __init__(self, n_slots, arena_bytes, device=None, keep_outputs=True):
         import torch
+        from . import api  # noqa: F401  (loads libmm before any stream is made)
         self.torch = torch
         self.keep_outputs = keep_outputs
+        self.keep_rids = set()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_slots)]
+        self.arena = Arena(arena_bytes)
+        self.buf = torch.empty(max(int(arena_bytes), 256), dtype=torch.uint8, device=self.device)
         self.events = {}
+        self.blocks = {}
 
     def choice(self, r):
         from . import tuner
@@ -167,23 +236,45 @@ class GpuExecutor:
                             max(r.k, 1), max(r.n, 1), max(r.n, 1), False, self.device, tile,
                             overlap=overlap, leaf_u=leaf_u, trans_b=trans_b, split_k=split_k)
 
-    def need_bytes(self, r):
+    def _sizes(self, r):
         esz = 8 if r.dtype == "f64" else 4
-        return r.m * r.n * esz + self.plan(r).ws_bytes
+        return r.m * r.n * esz, self.plan(r).ws_bytes
+
+    def need_bytes(self, r):
+        c, w = self._sizes(r)
+        a = self.arena.align
+        return -(-c // a) * a + (-(-w // a) * a if w else 0)
+
+    def reserve(self, r):
+        """Place the request's output and workspace in the arena (False, with
+        nothing held, when they do not fit now)."""
+        c, w = self._sizes(r)
+        oc = self.arena.alloc(c)
+        if oc is None:
+            return False
+        ow = None
+        if w:
+            ow = self.arena.alloc(w)
+            if ow is None:
+                self.arena.free(oc)
+                return False
+        self.blocks[r.rid] = (oc, c, ow, w)
+        return True
 
     def submit(self, r):
-        from . import api
         torch = self.torch
         s = self.streams[r.slot]
         p = self.plan(r)
+        if r.rid not in self.blocks and not self.reserve(r):
+            raise RuntimeError("request does not fit in the arena")
+        oc, c, ow, w = self.blocks[r.rid]
+        tdt = torch.float32 if r.dtype != "f64" else torch.float64
+        r.C = self.buf[oc:oc + c].view(tdt).view(r.m, r.n)
+        ws = self.buf[ow:ow + w] if w else None
         s.wait_stream(torch.cuda.current_stream(self.device))   # operands were made there
-        with torch.cuda.stream(s):
-            r.C = torch.empty((r.m, r.n), dtype=torch.float32 if r.dtype != "f64" else torch.float64,
-                              device=self.device)
-            ws = api.workspace(p.ws_bytes, self.device, s) if p.ws_bytes else None
-            p(r.A, r.B, r.C, ws=ws, stream=s)
-            ev = torch.cuda.Event()
-            ev.record(s)
+        p(r.A, r.B, r.C, ws=ws, stream=s)
+        ev = torch.cuda.Event()
+        ev.record(s)
         self.events[r.rid] = ev
         r.info = {"algo": p.algo, "levels": p.info["levels"]}
 
@@ -191,9 +282,20 @@ class GpuExecutor:
         return self.events[r.rid].query()
 
     def release(self, r):
-        self.events.pop(r.rid, None)
-        if not self.keep_outputs:
+        ev = self.events.pop(r.rid, None)
+        if r.C is not None and (self.keep_outputs or r.rid in self.keep_rids) and ev is not None:
+            # copy the output out of the arena before its block is reused
+            cur = self.torch.cuda.current_stream(self.device)
+            cur.wait_event(ev)
+            r.C = r.C.clone()
+            cur.synchronize()
+        else:
             r.C = None
+        blk = self.blocks.pop(r.rid, None)
+        if blk is not None:
+            self.arena.free(blk[0])
+            if blk[2] is not None:
+                self.arena.free(blk[2])
 
 
 def make_requests(trace, device, keep_outputs=True):

@@ -93,3 +93,59 @@ def test_failed_launch_becomes_an_error_response_and_frees_its_slot():
     errs = sorted(r.rid for r in done if r.error)
     assert errs == [2, 7]
     assert len(done) == 20 and srv.reserved == 0
+
+
+def test_arena_blocks_never_overlap_and_merge_back():
+    """The serving arena's first-fit allocator on a random sequence of
+    allocations and frees: blocks are aligned, inside the buffer, disjoint,
+    and once everything is freed the free list is one block again."""
+    import random
+
+    from paper_2309_00628_amd.serving import Arena
+    rnd = random.Random(5)
+    a = Arena(1 << 20, align=256)
+    live = {}
+    for step in range(4000):
+        if live and (rnd.random() < 0.45 or len(live) > 40):
+            off = rnd.choice(sorted(live))
+            a.free(off)
+            del live[off]
+        else:
+            nb = rnd.choice([1, 255, 256, 257, 4096, 65536, 300000])
+            off = a.alloc(nb)
+            if off is None:
+                assert sum(sz for _, sz in a.free_list) < 1 << 20
+                continue
+            size = -(-nb // 256) * 256
+            assert off % 256 == 0 and 0 <= off and off + size <= 1 << 20
+            for o, s in live.items():
+                assert off + size <= o or o + s <= off
+            live[off] = size
+        assert a.used_bytes == sum(live.values())
+    for off in list(live):
+        a.free(off)
+    assert a.free_list == [(0, 1 << 20)] and a.used_bytes == 0
+
+
+def test_admission_waits_when_the_arena_is_fragmented():
+    """An executor that can refuse to place a request (fragmented arena):
+    the server keeps it queued, in order, until a completion makes room."""
+    class Fragmented(FakeExecutor):
+        def __init__(self):
+            super().__init__(rate_flops=1e11, ws_bytes=lambda r: 0)
+            self.refusals = 0
+
+        def reserve(self, r):
+            # refuse while anything is running
+            if self.running:
+                self.refusals += 1
+                return False
+            return True
+
+    reqs = [Request(rid=i, m=256, n=256, k=256, dtype="f32", arrival=0.0) for i in range(5)]
+    ex = Fragmented()
+    srv = Server(ex, 1 << 30, n_slots=4)
+    done, _ = srv.run(reqs)
+    assert len(done) == 5 and all(not r.error for r in done)
+    assert srv.max_running == 1 and ex.refusals > 0
+    assert srv.admit_order == [0, 1, 2, 3, 4]
