@@ -306,6 +306,32 @@ int mm_batched(int count, const int64_t* mnk, void* const* A, void* const* B, vo
                int dtype, const int* cutoff, const int* levels, void* ws, size_t ws_bytes,
                hipStream_t stream);
 
+/* ---- no device allocation --------------------------------------------- */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * library holds one static scratch array of MM_NOALLOC_SCRATCH_BYTES on each
+ * GPU it runs on, from the load of its code object until the process ends. */
+#define MM_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define MM_NOALLOC_TABLE_BYTES (4u << 20) /* of which: the plan's descriptor table */
+
+/* mm_winograd without any device allocation: the Two Temp schedule (Section
+ * 3.3, Table 2), its descriptor table and workspace in the static scratch
+ * array of the current device (the table is copied there with an
+ * asynchronous host-to-device copy on `stream` at every call).  Same
+ * arguments, results within the float tolerance of mm_winograd's (bitwise
+ * equal where both pad to the same blocks).  Returns MM_E_WORKSPACE, with
+ * nothing enqueued, when the product's workspace exceeds
+ * MM_NOALLOC_SCRATCH_BYTES - MM_NOALLOC_TABLE_BYTES (60 MiB: for example
+ * float32 n <= 5400 with one level, n = 4096 with two) or its table exceeds
+ * MM_NOALLOC_TABLE_BYTES.  Calls share the device's array and it keeps the
+ * last call's contents (nothing in it needs to start at zero): calls that
+ * overlap on one device, on different streams, race; serialise them on one
+ * stream.  Allocates only host memory (the plan, on the first call of each
+ * shape). */
+int mm_winograd_noalloc(int64_t m, int64_t n, int64_t k, const void* A, const void* B, void* C, int cutoff,
+                        int levels, int dtype, hipStream_t stream);
+
 /* ---- diagnostics ------------------------------------------------------ */
 
 /* Host-only: build the plan mm_plan_create would build (same flags),

@@ -71,6 +71,7 @@ _SIGS = {
     "mm_naive": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_int, c_vp]),
     "mm_strassen": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_int, c_int, c_int, c_vp]),
     "mm_winograd": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_int, c_int, c_int, c_vp]),
+    "mm_winograd_noalloc": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_int, c_int, c_int, c_vp]),
     "mm_gemm_ex": (c_int, [c_int, c_int, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,
                            c_int, c_int, c_int, c_vp, c_sz, c_vp]),
     "mm_workspace_size": (c_sz, [c_int, c_int, c_i64, c_i64, c_i64, c_int, c_int, c_int]),

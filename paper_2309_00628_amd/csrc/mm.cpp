@@ -26,6 +26,7 @@
 #include "mm.h"
 #include "desc.h"
 #include "kernels.h"
+#include "internal.h"
 
 struct mm_plan_s;
 
@@ -1479,8 +1480,11 @@ int aux_for(Plan& P, hipStream_t s, Plan::Aux** out) {
 
 // events (timed execution): events[2i] / events[2i+1] are recorded before /
 // after launch i on the stream that launch runs on.
+// table: the device copy of the plan's descriptor table to read (default:
+// the one the plan uploaded).
 int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEvent_t* events = nullptr,
-            double beta = 1.0) {
+            double beta = 1.0, const void* table = nullptr) {
+  const void* dtab = table ? table : P.dtable;
   KernelBases kb;
   kb.beta = beta;
   kb.p[MB_A] = A;
@@ -1508,7 +1512,7 @@ int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEven
       if (hipEventRecord(ax->join, ax->aux) != hipSuccess || hipStreamWaitEvent(s, ax->join, 0) != hipSuccess)
         return fail(MM_E_HIP, "join of the auxiliary stream failed");
     } else {
-      const void* d = (const char*)P.dtable + op.off;
+      const void* d = (const char*)dtab + op.off;
       if (op.type == OP_EW)
         e = launch_ew(op.kdtype, kb, (const EwPart*)d, op.count, op.grid, st);
       else if (op.type == OP_WINO)
@@ -1745,6 +1749,10 @@ int short_form(int algo, int64_t m, int64_t n, int64_t k, const void* A, const v
   return execute(*P, (void*)A, (void*)B, C, ws, P->ws_bytes, s);
 }
 
+// Plans of the entry point that allocates nothing: host only (their table is
+// copied into the caller's memory at every call), keyed like the short forms.
+std::map<std::string, std::unique_ptr<Plan>> g_host_plans;
+
 // ---------------------------------------------------------------------------
 // Batches: every problem planned with the grouped schedule on absolute
 // addresses, then merged stage by stage across problems.
@@ -1861,6 +1869,53 @@ int build_batched(Plan& P, int count, const int64_t* mnk, void* const* A, void* 
 }
 
 }  // namespace
+
+int set_error(int code, const char* msg) { return fail(code, msg); }
+
+int run_in_memory(int algo, int sched, int64_t m, int64_t n, int64_t k, const void* A, const void* B, void* C,
+                  int cutoff, int levels, int dtype, void* table, size_t table_cap, void* ws, size_t ws_cap,
+                  hipStream_t s) {
+  int rc = check_enums(algo, sched, dtype);
+  if (rc != MM_OK) return rc;
+  const int64_t lda = std::max<int64_t>(k, 1), ldb = std::max<int64_t>(n, 1);
+  rc = check_args(m, n, k, A, lda, B, ldb, C, ldb, dtype);
+  if (rc != MM_OK) return rc;
+  if (m == 0 || n == 0) return MM_OK;
+  int dev = 0;
+  rc = check_device(&dev);
+  if (rc != MM_OK) return rc;
+  char key[256];
+  std::snprintf(key, sizeof key, "%d|%d|%d|%lld|%lld|%lld|%d|%d|%d", dev, algo, sched, (long long)m,
+                (long long)n, (long long)k, cutoff, levels, dtype);
+  Plan* P = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_host_plans.find(key);
+    if (it == g_host_plans.end()) {
+      std::unique_ptr<Plan> np;
+      rc = make_plan(algo, sched, m, n, k, lda, ldb, ldb, cutoff, levels, dtype, 0, &np);
+      if (rc != MM_OK) return rc;
+      np->device = dev;
+      it = g_host_plans.emplace(key, std::move(np)).first;
+    }
+    P = it->second.get();
+  }
+  if (P->has_aux || P->unfused) return fail(MM_E_UNSUPPORTED, "schedule needs plan-owned resources");
+  if (P->table.size() > table_cap)
+    return fail(MM_E_WORKSPACE, "descriptor table of " + std::to_string(P->table.size()) +
+                                    " bytes exceeds the static scratch's table area of " +
+                                    std::to_string(table_cap));
+  if (P->ws_bytes > ws_cap)
+    return fail(MM_E_WORKSPACE, "workspace of " + std::to_string(P->ws_bytes) +
+                                    " bytes exceeds the static scratch's workspace area of " +
+                                    std::to_string(ws_cap));
+  if (P->ops.empty()) return MM_OK;
+  if (!P->table.empty() &&
+      hipMemcpyAsync(table, P->table.data(), P->table.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(MM_E_HIP, "copy of the descriptor table failed");
+  return enqueue(*P, (void*)A, (void*)B, C, ws, s, nullptr, 1.0, table);
+}
+
 }  // namespace mm
 
 struct mm_plan_s {
