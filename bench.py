@@ -617,14 +617,15 @@ def bench_batched(torch, api, inputs, tuner, count=512, steps=10, warmup=3, seed
     shapes = inputs.batched_shapes(count, seed)
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
-    As, Bs, Cs, levels = [], [], [], []
+    from paper_2309_00628_amd import _lib as L
+    As, Bs, Cs = [], [], []
     for (m, n, k) in shapes:
         As.append(torch.rand((m, k), generator=g, device="cuda") * 2 - 1)
         Bs.append(torch.rand((k, n), generator=g, device="cuda") * 2 - 1)
         Cs.append(torch.empty((m, n), device="cuda"))
-        levels.append(tuner.choose(m, n, k, "f32")["levels"])
+    levels = L.batched_levels(shapes)          # the library's tuned level count per size class
     flops = sum(2.0 * m * n * k for (m, n, k) in shapes)
-    plan = api.BatchedPlan(As, Bs, Cs, cutoff=[1] * count, levels=levels, graph=True)
+    plan = api.BatchedPlan(As, Bs, Cs, graph=True)  # NULL levels: tuned per size class
     s = torch.cuda.current_stream()
 
     def timed(fn, reps):
@@ -644,6 +645,7 @@ def bench_batched(torch, api, inputs, tuner, count=512, steps=10, warmup=3, seed
     out = {"workload": f"{count} fp32 products, m,n,k log-uniform in [64,2048] (x16), uniform[-1,1]",
            "tflops": round(flops / (wall * 1e-3) / 1e12, 3), "ms_per_batch": round(wall, 4),
            "device_ms_per_batch": round(dev, 4), "launches_per_batch": plan.info["launches"],
+           "persistent": False, "levels_source": L.tuning_source() or "rule",
            "levels_histogram": {str(l): levels.count(l) for l in sorted(set(levels))}, "graph": True}
     if check:
         # every problem with a recursion level, the largest problems, and an

@@ -219,6 +219,20 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                            A[:pm,pk:] B[pk:,:pn], C[:pm,pn:] = A[:pm,:] B[:,pn:], C[pm:,:] =
                            A[pm:,:] B.  No effect when every side is already such a multiple
                            or when a side of the leading block would be empty. */
+#define MM_PLAN_PERSISTENT 0x200000u /* batched plans, MM_F32: run the whole batch -- the S/T passes of
+                                       every recursion level, every leaf-product tile and the U passes
+                                       of every problem -- as ONE launch of a persistent kernel whose
+                                       workgroups (as many as fit on the GPU at once) take tasks from a
+                                       queue in order; a task waits on a per-problem counter for the
+                                       stage it needs (and gives up after a bounded number of polls,
+                                       flagging the plan: see mm_plan_check).  Same results as the
+                                       level-synchronous batched plan.  The plan owns a small counter
+                                       buffer: its executions must not overlap (serialise them on one
+                                       stream).  Other dtypes ignore the flag.  SWITCHED OFF on the
+                                       device: its first run on MI355X hung and the cause is not yet
+                                       found, so mm_batched_plan_create returns MM_E_UNSUPPORTED for it;
+                                       the host-only calls (mm_batched_describe, mm_batched_table) still
+                                       build it, for checking its task queue. */
 /* Plain product (MM_ALGO_NAIVE, or a recursion of zero levels): split k into
  * s parts (2 .. 8, each a multiple of 64 long), run the s partial products
  * in one grouped launch into workspace blocks and sum them in order in one
@@ -271,7 +285,8 @@ int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, s
  * 4 fused last Winograd level (MM_PLAN_LEAF_U), 5 split pass of the
  * split-bfloat16 leaves, 6 transposing pass (MM_PLAN_TRANS_B), 7 unrolled base
  * cases (MM_PLAN_UNROLL_BASE); plus 8 when
- * the launch runs on the auxiliary stream; -1 if i is out of range. */
+ * the launch runs on the auxiliary stream; 16 the persistent launch of a
+ * whole batch (MM_PLAN_PERSISTENT); -1 if i is out of range. */
 int mm_plan_op_kind(mm_plan_t plan, int i);
 
 /* Plan facts: info[0] workspace bytes, [1] levels L, [2..4] padded m, n, k,
@@ -291,17 +306,42 @@ int mm_plan_destroy(mm_plan_t plan);
 /* ---- batches ---------------------------------------------------------- */
 
 /* A batch of independent products C_i = A_i x B_i (contiguous, one dtype),
- * each with its own cutoff and levels (NULL arrays: cutoff 1 and levels 0,
- * i.e. the naive method, for every problem).  Problems are executed
+ * mnk[3i .. 3i+2] = (m_i, n_i, k_i), each with its own cutoff and levels
+ * (Section 3.4).  levels NULL: each problem's level count is the
+ * autotuner's choice for its size class (see mm_batched_levels); cutoff
+ * NULL: cutoff 1.  Without MM_PLAN_PERSISTENT problems are executed
  * level-synchronously: one launch per recursion stage for the whole batch
- * and one grouped MFMA launch for every leaf of every problem.  The plan
- * binds the operand addresses. */
+ * and one grouped MFMA launch for every leaf of every problem; with it (float32)
+ * everything runs as one persistent launch.  The plan binds the operand
+ * addresses. */
 int mm_batched_plan_create(int count, const int64_t* mnk, void* const* A, void* const* B,
                            void* const* C, int dtype, const int* cutoff, const int* levels,
                            unsigned flags, mm_plan_t* plan);
 
+/* The level count each problem of a batch gets (host only; no device
+ * needed): given levels as given, NULL levels the size class's tuned count;
+ * both then capped by the cutoff (NULL: 1) and the problem's shape.  A size
+ * class is the volume-equivalent order v = (m n k)^(1/3) rounded to half
+ * octaves; the table of tuned counts is read once per process from
+ * tuning/gfx950_batched.txt next to the library (or $MM_TUNING_DIR), and
+ * a dtype with no table takes one level per halving while the leaf's v
+ * stays >= 2048 (4096 split bfloat16), at most two. */
+int mm_batched_levels(int count, const int64_t* mnk, int dtype, const int* cutoff, const int* levels,
+                      int* levels_out);
+
+/* Path of the size-class table read by mm_batched_levels ("" when none was
+ * found). */
+const char* mm_tuning_source(void);
+
+/* Persistent plans: wait for `stream`, then report (and clear) the flag a
+ * task sets when it waits past its bound (MM_E_HIP: the results of the
+ * executions since the last check are not reliable).  MM_OK for other
+ * plans, without synchronising. */
+int mm_plan_check(mm_plan_t plan, hipStream_t stream);
+
 /* One-shot batch: builds (or fetches from a cache keyed by all arguments)
- * the batched plan and executes it with the workspace given. */
+ * the level-synchronous batched plan and executes it with the workspace
+ * given. */
 int mm_batched(int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C,
                int dtype, const int* cutoff, const int* levels, void* ws, size_t ws_bytes,
                hipStream_t stream);
@@ -346,8 +386,17 @@ size_t mm_describe(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t
 /* Host-only counterpart for mm_batched_plan_create.  The addresses are only
  * recorded (never dereferenced), so any values may be passed. */
 size_t mm_batched_describe(int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C,
-                           int dtype, const int* cutoff, const int* levels, char* buf, size_t len,
-                           int64_t* info, int ninfo);
+                           int dtype, const int* cutoff, const int* levels, unsigned flags, char* buf,
+                           size_t len, int64_t* info, int ninfo);
+
+/* Host-only: the device descriptor table of the batched plan
+ * mm_batched_plan_create would build (same flags; for a persistent plan it
+ * starts with the task queue's header, desc.h), copied into buf (up to len
+ * bytes).  Returns its size, 0 when the arguments are rejected.  For
+ * checking the task queue on a machine with no GPU. */
+size_t mm_batched_table(int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C,
+                        int dtype, const int* cutoff, const int* levels, unsigned flags, void* buf,
+                        size_t len);
 
 const char* mm_last_error(void);
 int mm_version(void);

@@ -29,6 +29,7 @@ MM_PLAN_ACCUMULATE = 32
 MM_PLAN_PEEL = 64
 MM_PLAN_TRANS_B = 128
 MM_PLAN_UNROLL_BASE = 0x100000
+MM_PLAN_PERSISTENT = 0x200000
 
 
 def plan_split_k(s):
@@ -92,7 +93,12 @@ _SIGS = {
     "mm_describe": (c_sz, [c_int, c_int, c_i64, c_i64, c_i64, c_i64, c_i64, c_i64, c_int, c_int,
                            c_int, ctypes.c_uint, ctypes.c_char_p, c_sz, c_i64p, c_int]),
     "mm_batched_describe": (c_sz, [c_int, c_i64p, c_vpp, c_vpp, c_vpp, c_int, c_intp, c_intp,
-                                   ctypes.c_char_p, c_sz, c_i64p, c_int]),
+                                   ctypes.c_uint, ctypes.c_char_p, c_sz, c_i64p, c_int]),
+    "mm_batched_table": (c_sz, [c_int, c_i64p, c_vpp, c_vpp, c_vpp, c_int, c_intp, c_intp, ctypes.c_uint,
+                                c_vp, c_sz]),
+    "mm_batched_levels": (c_int, [c_int, c_i64p, c_int, c_intp, c_intp, c_intp]),
+    "mm_tuning_source": (ctypes.c_char_p, []),
+    "mm_plan_check": (c_int, [c_vp, c_vp]),
     "mm_last_error": (ctypes.c_char_p, []),
     "mm_version": (c_int, []),
 }
@@ -151,7 +157,44 @@ def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, l
     return buf.value.decode(), _info_dict(info)
 
 
-def batched_describe(mnk, addrs, dtype="f32", cutoff=None, levels=None):
+def batched_levels(mnk, dtype="f32", cutoff=None, levels=None):
+    """The level count each problem of a batch gets (mm_batched_levels;
+    host only): None arrays as NULL (tuned levels per size class, cutoff 1)."""
+    lib = load()
+    cnt = len(mnk)
+    flat = (ctypes.c_int64 * max(3 * cnt, 1))(*[v for t in mnk for v in t])
+    cp = (c_int * cnt)(*cutoff) if cutoff is not None else None
+    lp = (c_int * cnt)(*levels) if levels is not None else None
+    out = (c_int * max(cnt, 1))()
+    check(lib.mm_batched_levels(cnt, flat, DTYPES.get(dtype, dtype), cp, lp, out))
+    return [int(out[i]) for i in range(cnt)]
+
+
+def batched_table(mnk, addrs, dtype="f32", cutoff=None, levels=None, persistent=True):
+    """Host-only: the bytes of a batched plan's device descriptor table."""
+    lib = load()
+    cnt = len(mnk)
+    flat = (ctypes.c_int64 * max(3 * cnt, 1))(*[v for t in mnk for v in t])
+    A = (c_vp * max(cnt, 1))(*[a for a, _, _ in addrs])
+    B = (c_vp * max(cnt, 1))(*[b for _, b, _ in addrs])
+    C = (c_vp * max(cnt, 1))(*[c for _, _, c in addrs])
+    cp = (c_int * cnt)(*cutoff) if cutoff is not None else None
+    lp = (c_int * cnt)(*levels) if levels is not None else None
+    fl = MM_PLAN_PERSISTENT if persistent else 0
+    need = lib.mm_batched_table(cnt, flat, A, B, C, DTYPES.get(dtype, dtype), cp, lp, fl, None, 0)
+    if need == 0:
+        raise MMError(1, last_error())
+    buf = ctypes.create_string_buffer(need)
+    lib.mm_batched_table(cnt, flat, A, B, C, DTYPES.get(dtype, dtype), cp, lp, fl, buf, need)
+    return buf.raw
+
+
+def tuning_source():
+    """Path of the size-class table the library read ("" when none)."""
+    return load().mm_tuning_source().decode()
+
+
+def batched_describe(mnk, addrs, dtype="f32", cutoff=None, levels=None, persistent=False):
     """Host-only listing of a batched plan; ``addrs`` = [(a, b, c)] byte addresses."""
     lib = load()
     cnt = len(mnk)
@@ -162,12 +205,13 @@ def batched_describe(mnk, addrs, dtype="f32", cutoff=None, levels=None):
     cp = (c_int * cnt)(*cutoff) if cutoff is not None else None
     lp = (c_int * cnt)(*levels) if levels is not None else None
     info = (ctypes.c_int64 * NINFO)()
-    need = lib.mm_batched_describe(cnt, flat, A, B, C, DTYPES.get(dtype, dtype), cp, lp, None, 0,
+    fl = MM_PLAN_PERSISTENT if persistent else 0
+    need = lib.mm_batched_describe(cnt, flat, A, B, C, DTYPES.get(dtype, dtype), cp, lp, fl, None, 0,
                                    info, NINFO)
     if need == 0:
         raise MMError(1, last_error())
     buf = ctypes.create_string_buffer(need + 1)
-    lib.mm_batched_describe(cnt, flat, A, B, C, DTYPES.get(dtype, dtype), cp, lp, buf, need + 1,
+    lib.mm_batched_describe(cnt, flat, A, B, C, DTYPES.get(dtype, dtype), cp, lp, fl, buf, need + 1,
                             info, NINFO)
     return buf.value.decode(), _info_dict(info)
 

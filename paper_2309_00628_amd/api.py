@@ -229,9 +229,12 @@ def mm(A, B, algo="winograd", sched="auto", cutoff=None, levels=None, dtype=None
 class BatchedPlan:
     """Independent products C_i = A_i B_i bound to fixed tensors
     (mm_batched_plan_create).  Run with ``plan()``; with ``graph=True`` the
-    level-synchronous launch sequence is captured once and replayed."""
+    launch sequence is captured once and replayed.  ``levels=None``: each
+    problem's tuned level count for its size class; ``persistent=True``
+    (float32): the whole batch as one persistent launch."""
 
-    def __init__(self, As, Bs, Cs, cutoff=None, levels=None, dtype=None, graph=True, tile=None):
+    def __init__(self, As, Bs, Cs, cutoff=None, levels=None, dtype=None, graph=True, tile=None,
+                 persistent=False):
         lib = L.load()
         if not (len(As) == len(Bs) == len(Cs)):
             raise ValueError("As, Bs, Cs differ in length")
@@ -258,7 +261,8 @@ class BatchedPlan:
         self._ptr = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             L.check(lib.mm_batched_plan_create(cnt, flat, Ap, Bp, Cp, L.DTYPES[dt], cp, lp,
-                                               (L.MM_PLAN_GRAPH if graph else 0) | L.plan_tile(tile),
+                                               (L.MM_PLAN_GRAPH if graph else 0) | L.plan_tile(tile) |
+                                               (L.MM_PLAN_PERSISTENT if persistent else 0),
                                                ctypes.byref(self._ptr)))
         info = (ctypes.c_int64 * L.NINFO)()
         lib.mm_plan_info(self._ptr, info, L.NINFO)
@@ -271,6 +275,12 @@ class BatchedPlan:
         L.check(L.load().mm_plan_execute(self._ptr, None, None, None, self.ws.data_ptr(),
                                          self.ws.numel(), s.cuda_stream))
         return self.tensors[2]
+
+    def check(self, stream=None):
+        """Wait for ``stream`` and raise if a task of a persistent launch
+        waited past its bound since the last check (mm_plan_check)."""
+        s = _stream(stream, self.device)
+        L.check(L.load().mm_plan_check(self._ptr, s.cuda_stream))
 
     def __del__(self):
         try:

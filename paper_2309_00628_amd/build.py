@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmm.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["mm.cpp", "gemm.hip", "gemm_bf16x3.hip", "gemm_fused.hip", "gemm_wino.hip", "ew.hip", "split.hip", "trans.hip", "base.hip", "noalloc.hip"]
+SOURCES = ["mm.cpp", "gemm.hip", "gemm_bf16x3.hip", "gemm_fused.hip", "gemm_wino.hip", "ew.hip", "split.hip", "trans.hip", "base.hip", "noalloc.hip", "batch.hip"]
 ARCH = "gfx950"
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -51,7 +51,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(len(srcs), 4)) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-ldl", "-o", tmp]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout)

@@ -143,6 +143,46 @@ struct WinoLeafDesc {
   int32_t acc;         // 1: C = beta C + U (top level of an accumulating product)
 };
 
+// Persistent batched execution: a whole batch of products (every recursion
+// stage of every problem) as one launch whose workgroups take tasks from a
+// queue in order.  The tasks form segments: the S/T passes of each
+// recursion level, then the leaf-product tiles, then the U passes of each
+// level from the deepest up.  A task of an element-wise segment is a run of
+// element-wise blocks of one part; a task of the GEMM segment is one output
+// tile of one leaf product.  Dependencies are per problem and stage: a task
+// waits until a counter has reached the number of tasks of the stage it
+// needs, and signals its own stage's counter when done.  Every task depends
+// only on tasks earlier in the queue, so the workgroup holding the earliest
+// unfinished task never waits on an unfinished one: the queue drains.
+enum PTaskKind : int32_t { PT_EW = 0, PT_GEMM = 1 };
+constexpr int kPersistMaxSegs = 2 * 6 + 2;  // S/T and U per level (MM_MAX_LEVELS 6), leaves, zero fills
+constexpr int kPersistEwBlocks = 8;         // element-wise blocks per task
+
+struct PDep {
+  int32_t wait;        // counter to wait for (-1: none)
+  int32_t target;      // ... until it counts this many completed tasks
+  int32_t signal;      // counter to increment per completed task (-1: none)
+  int32_t task_start;  // first task (within its segment) of this descriptor
+};
+
+struct PSeg {
+  int32_t kind;     // PTaskKind
+  int32_t first;    // queue index of the segment's first task
+  int32_t ntasks;
+  int32_t ndesc;    // EwPart (PT_EW) or GemmDesc (PT_GEMM) entries
+  int64_t desc_off; // byte offsets in the plan's table: descriptors ...
+  int64_t dep_off;  // ... and one PDep per descriptor
+};
+
+struct PersistHdr {
+  int32_t nseg, ntasks, ncounters, pad;
+  PSeg seg[kPersistMaxSegs];
+};
+
+// Counters of a persistent plan (int32, device memory owned by the plan,
+// zero between launches: the last workgroup to finish clears them).
+enum PCounter : int32_t { PC_HEAD = 0, PC_EXIT = 1, PC_ERROR = 2, PC_FIRST = 4 };
+
 struct KernelBases {
   void* p[kNumBases];
   int32_t aligned;  // bit b set: base b is 16-byte aligned

@@ -143,6 +143,20 @@ struct TileRef {
 // With remap == 0 (launches of unequal problems, sorted longest first) the
 // hardware's round-robin spreads every run of 8 consecutive tiles over the
 // 8 XCDs, which balances the XCDs and starts the longest tiles first.
+// Tile lt (counted from the problem's first tile) of a problem with
+// tiles_m x tiles_n tiles: groups of 8 tile-rows, column by column.
+template <int BM, int BN>
+__device__ __forceinline__ TileRef tile_in_problem(int desc, int lt, int tiles_m, int tiles_n) {
+  constexpr int GROUP = 8;
+  const int per_group = GROUP * tiles_n;
+  const int gid = lt / per_group;
+  const int first_m = gid * GROUP;
+  const int gsz = min(tiles_m - first_m, GROUP);
+  const int tm = first_m + (lt - gid * per_group) % gsz;
+  const int tn = (lt - gid * per_group) / gsz;
+  return TileRef{desc, tm * BM, tn * BN};
+}
+
 template <int BM, int BN, typename Desc>
 __device__ __forceinline__ TileRef locate_tile(const Desc* __restrict__ descs, int ndesc, int remap) {
   const int rb = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -152,16 +166,7 @@ __device__ __forceinline__ TileRef locate_tile(const Desc* __restrict__ descs, i
     if (descs[mid].tile_start <= rb) lo = mid; else hi = mid - 1;
   }
   const Desc& D = descs[lo];
-  const int lt = rb - D.tile_start;
-  const int tiles_m = D.tiles_m, tiles_n = D.tiles_n;
-  constexpr int GROUP = 8;
-  const int per_group = GROUP * tiles_n;
-  const int gid = lt / per_group;
-  const int first_m = gid * GROUP;
-  const int gsz = min(tiles_m - first_m, GROUP);
-  const int tm = first_m + (lt - gid * per_group) % gsz;
-  const int tn = (lt - gid * per_group) / gsz;
-  return TileRef{lo, tm * BM, tn * BN};
+  return tile_in_problem<BM, BN>(lo, rb - D.tile_start, D.tiles_m, D.tiles_n);
 }
 
 // Epilogue: every output of the descriptor gets C = s * acc, C = D + s * acc

@@ -51,6 +51,14 @@ constexpr int kNumWinoCfg = 3;
 GemmCfg gemm_wino_cfg(int cfg);
 hipError_t launch_gemm_wino(int cfg, int fused, const KernelBases& kb, const WinoLeafDesc* d, int n, int tiles, int remap,
                             hipStream_t s);
+// Persistent batched plans (batch.hip): tile configurations 0, 4 and 8 of
+// the float32 GEMM; workgroups per compute unit that fit at once; launch of
+// the whole task queue (table: PersistHdr and its segments; ctr: the plan's
+// counters; spin: polls before a wait gives up and flags the plan).
+bool persist_cfg_ok(int cfg);
+int persist_occupancy(int cfg);
+hipError_t launch_persist(int cfg, const KernelBases& kb, const void* table, int* ctr, int grid, int spin,
+                          hipStream_t s);
 // remap: 1 = XCD-contiguous tile order (launches of equal problems),
 // 0 = hardware round-robin (unequal problems, sorted longest first).
 hipError_t launch_gemm(int dtype, int cfg, const KernelBases& kb, const GemmDesc* ddescs, int ndesc, int tiles,

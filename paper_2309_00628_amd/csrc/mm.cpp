@@ -8,12 +8,14 @@
 // leaf products).  Descriptors address memory relative to the call's buffers
 // (A, B, C, workspace) so the table is uploaded to the device once and every
 // later execution is kernel launches only.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -56,7 +58,8 @@ int ew_dtype(int dtype) { return dtype == MM_F64 ? DT_F64 : DT_F32; }
 // OP_TRANS: element-wise passes with transposed outputs (trans kernel).
 // OP_BASE: unrolled base cases, one leaf product per thread (BaseDesc).
 enum OpType {
-  OP_EW = 0, OP_GEMM = 1, OP_FORK = 2, OP_JOIN = 3, OP_WINO = 4, OP_SPLIT = 5, OP_TRANS = 6, OP_BASE = 7
+  OP_EW = 0, OP_GEMM = 1, OP_FORK = 2, OP_JOIN = 3, OP_WINO = 4, OP_SPLIT = 5, OP_TRANS = 6, OP_BASE = 7,
+  OP_PERSIST = 16  // a whole batch in one persistent launch (PersistHdr at the op's offset)
 };
 
 struct OpRec {
@@ -94,6 +97,10 @@ struct Plan {
   bool trans_b = false;     // grouped Winograd float32: last-level B operands stored transposed
   bool unroll_base = false; // grouped Winograd: leaves of order 1, 2, 4 by the unrolled base cases
   int split_k = 1;          // plain product: k split over this many partial products
+  bool persistent = false;  // batched: one persistent launch (OP_PERSIST)
+  int pcount = 0;           // ... its counters (besides PC_FIRST fixed ones)
+  int pgrid = 0;            // ... its workgroups (as many as fit at once)
+  int* dctr = nullptr;      // ... device counters, owned
   int64_t pm = 0, pn = 0, pk = 0;  // peeled: the leading block the recursion runs on
   bool has_aux = false;  // some launches go to the auxiliary stream
   struct Aux {
@@ -127,6 +134,7 @@ struct Plan {
       (void)hipStreamDestroy(a.aux);
     }
     if (dtable) (void)hipFree(dtable);
+    if (dctr) (void)hipFree(dctr);
   }
 };
 
@@ -290,9 +298,9 @@ struct Builder {
                std::initializer_list<MView> outs, int mode0 = 0, int mode1 = 0) {
     ew_parts(kind, rows, cols, std::vector<MView>(ins), std::vector<MView>(outs), mode0, mode1);
   }
-  void ew_parts(int kind, int64_t rows, int64_t cols, const std::vector<MView>& ins,
-                const std::vector<MView>& outs, int mode0 = 0, int mode1 = 0) {
-    if (!gm.empty() || !wl.empty()) flush();
+  // An element-wise part (blk_start left 0) and its listing line.
+  EwPart make_ew(int kind, int64_t rows, int64_t cols, const std::vector<MView>& ins,
+                 const std::vector<MView>& outs, int mode0 = 0, int mode1 = 0) {
     EwPart p;
     std::memset(&p, 0, sizeof p);
     p.kind = kind;
@@ -308,16 +316,27 @@ struct Builder {
     i = 0;
     for (const auto& v : outs) p.out[i++] = v;
     for (; i < kEwMaxOut; ++i) p.out[i] = none();
+    return p;
+  }
+  static std::string ew_line(const EwPart& p) {
+    std::ostringstream o;
+    o << "EW " << p.kind << " " << p.rows << " " << p.cols << " " << p.mode[0] << " " << p.mode[1] << " |";
+    for (int i = 0; i < p.nin; ++i) o << " " << vs(p.in[i]);
+    o << " |";
+    for (int i = 0; i < p.nout; ++i) o << " " << vs(p.out[i]);
+    o << "\n";
+    return o.str();
+  }
+  void ew_parts(int kind, int64_t rows, int64_t cols, const std::vector<MView>& ins,
+                const std::vector<MView>& outs, int mode0 = 0, int mode1 = 0) {
+    if (!gm.empty() || !wl.empty()) flush();
+    EwPart p = make_ew(kind, rows, cols, ins, outs, mode0, mode1);
     const int blocks = ew_blocks((int)rows, (int)cols, ew_dtype(P.dtype));
     if (blocks == 0) return;
     p.blk_start = ew_grid;
     ew_grid += blocks;
     ew.push_back(p);
-    ew_txt << "EW " << kind << " " << rows << " " << cols << " " << mode0 << " " << mode1 << " |";
-    for (const auto& v : ins) ew_txt << " " << vs(v);
-    ew_txt << " |";
-    for (const auto& v : outs) ew_txt << " " << vs(v);
-    ew_txt << "\n";
+    ew_txt << ew_line(p);
   }
 
   // GEMM epilogue outputs
@@ -441,6 +460,42 @@ struct Builder {
 
   // akind / bkind != OK_PLAIN: a / b is the parent block and the operand is
   // the Winograd sum of its quadrants (formed in the loader).
+  // A leaf-product descriptor (tiles left 0), as gemm() records it.
+  GemmDesc make_gemm(const MView& a, const MView& b, std::initializer_list<Out> outs) {
+    GemmDesc g;
+    std::memset(&g, 0, sizeof g);
+    g.a = a;
+    g.b = b;
+    g.m = a.rows;
+    g.k = a.cols;
+    g.n = b.cols;
+    g.nout = (int32_t)outs.size();
+    int i = 0;
+    for (const auto& o : outs) {
+      g.out[i].c = o.c;
+      g.out[i].mode = o.mode;
+      g.out[i].sign = o.sign;
+      g.out[i].d = (o.mode == GM_ADD || o.mode == GM_AXPBY) ? o.d : none();
+      ++i;
+    }
+    for (; i < 2; ++i) {
+      g.out[i].c = none();
+      g.out[i].d = none();
+      g.out[i].mode = GM_NONE;
+      g.out[i].sign = 1;
+    }
+    return g;
+  }
+  static std::string gemm_line(const GemmDesc& g) {
+    std::ostringstream o;
+    o << "GEMM " << g.m << " " << g.n << " " << g.k << " " << (g.kinds & 0xff) << " " << (g.kinds >> 8) << " | "
+      << vs(g.a) << " " << vs(g.b) << " |";
+    for (int j = 0; j < g.nout; ++j)
+      o << " " << g.out[j].mode << ":" << g.out[j].sign << ":" << vs(g.out[j].c) << ":" << vs(g.out[j].d);
+    o << "\n";
+    return o.str();
+  }
+
   void gemm(const MView& a, const MView& b, std::initializer_list<Out> outs, int akind = OK_PLAIN,
             int bkind = OK_PLAIN, bool fusable = false) {
     if (!ew.empty() || !sp.empty() || gm_spl) flush();
@@ -703,13 +758,7 @@ struct Builder {
       g.tile_start = grid;
       grid += g.tiles_m * g.tiles_n;
     }
-    for (const GemmDesc& g : group) {
-      txt << "GEMM " << g.m << " " << g.n << " " << g.k << " " << (g.kinds & 0xff) << " " << (g.kinds >> 8)
-          << " | " << vs(g.a) << " " << vs(g.b) << " |";
-      for (int j = 0; j < g.nout; ++j)
-        txt << " " << g.out[j].mode << ":" << g.out[j].sign << ":" << vs(g.out[j].c) << ":" << vs(g.out[j].d);
-      txt << "\n";
-    }
+    for (const GemmDesc& g : group) txt << gemm_line(g);
     OpRec r{OP_GEMM, kd, P.table.size(), (int)group.size(), grid, cfg, equal ? 1 : 0, fused ? 1 : 0, cur_stream};
     const size_t bytes = group.size() * sizeof(GemmDesc);
     P.table.resize(round_up(P.table.size() + bytes, 256));
@@ -1235,6 +1284,109 @@ int count_levels(int64_t m, int64_t n, int64_t k, int cutoff, int levels) {
 
 bool bf16x3_available() { return gemm_bf16x3_available(); }
 
+// ---------------------------------------------------------------------------
+// Levels per size class for batches given no levels: Section 3.4 chooses
+// the cutoff per size from a cost model; on the GPU the choice is measured
+// by the autotuner (tuner.py --batched) and stored as a table.
+//
+// A size class is the product's volume-equivalent order v = (m n k)^(1/3)
+// rounded to half octaves, round(2 log2 v) / 2.  The table is read once per
+// process from <directory of libmm.so>/tuning/gfx950_batched.txt, or from
+// $MM_TUNING_DIR/gfx950_batched.txt: lines "dtype class levels" (dtype
+// f64, f32 or bf16x3), '#' starts a comment.  A class missing from the table
+// takes the nearest class of its dtype that is there; with no entry for the
+// dtype the rule is one level per halving while the leaf's v stays at or
+// above 2048 (4096 for split bfloat16), at most two.  The count is then
+// capped by the cutoff (count_levels).
+// ---------------------------------------------------------------------------
+struct ClassTable {
+  std::map<std::string, std::map<double, int>> by_dtype;  // dtype name -> class -> levels
+  std::string source;                                     // file read, empty when none
+};
+
+const char* dtype_name(int dtype) {
+  return dtype == MM_F64 ? "f64" : (dtype == MM_F32 ? "f32" : "bf16x3");
+}
+
+std::string lib_dir() {
+  Dl_info info;
+  if (dladdr((void*)&mm_version, &info) && info.dli_fname) {
+    std::string f(info.dli_fname);
+    const size_t at = f.rfind('/');
+    return at == std::string::npos ? std::string(".") : f.substr(0, at);
+  }
+  return ".";
+}
+
+const ClassTable& class_table() {
+  static ClassTable t;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const char* env = std::getenv("MM_TUNING_DIR");
+    const std::string path = (env && *env ? std::string(env) : lib_dir() + "/tuning") + "/gfx950_batched.txt";
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+      char* hash = std::strchr(line, '#');
+      if (hash) *hash = 0;
+      char dt[32];
+      double cls = 0;
+      int lv = 0;
+      if (std::sscanf(line, "%31s %lf %d", dt, &cls, &lv) == 3 && lv >= 0 && lv <= MM_MAX_LEVELS)
+        t.by_dtype[dt][cls] = lv;
+    }
+    std::fclose(f);
+    t.source = path;
+  });
+  return t;
+}
+
+double size_class(int64_t m, int64_t n, int64_t k) {
+  if (m <= 0 || n <= 0 || k <= 0) return 0.0;
+  // round(2 log2 v) / 2 with log2 v = log2(m n k) / 3 (halves rounded up)
+  return std::floor(2.0 * std::log2((double)m * (double)n * (double)k) / 3.0 + 0.5) / 2.0;
+}
+
+int class_levels(int64_t m, int64_t n, int64_t k, int dtype) {
+  const ClassTable& t = class_table();
+  const double c = size_class(m, n, k);
+  auto it = t.by_dtype.find(dtype_name(dtype));
+  if (it != t.by_dtype.end() && !it->second.empty()) {
+    int best = 0;
+    double dist = 1e300;
+    for (const auto& e : it->second)
+      if (std::fabs(e.first - c) < dist) {
+        dist = std::fabs(e.first - c);
+        best = e.second;
+      }
+    return best;
+  }
+  // v / 2^(L+1) >= leaf, compared as m n k >= (leaf 2^(L+1))^3
+  const double leaf = dtype == MM_BF16X3_REFINED ? 4096.0 : 2048.0;
+  const double vol = (double)m * (double)n * (double)k;
+  int L = 0;
+  while (L < 2) {
+    const double e = leaf * (double)((int64_t)2 << L);
+    if (vol < e * e * e) break;
+    ++L;
+  }
+  return L;
+}
+
+// The (cutoff, levels) of every problem of a batch: given arrays as given;
+// a NULL cutoff array means cutoff 1, a NULL levels array the size class's
+// tuned level count.
+void resolve_batch(int count, const int64_t* mnk, int dtype, const int* cutoff, const int* levels,
+                   std::vector<int>& cut, std::vector<int>& lev) {
+  cut.assign(count, 1);
+  lev.assign(count, 0);
+  for (int i = 0; i < count; ++i) {
+    cut[i] = cutoff ? cutoff[i] : 1;
+    lev[i] = levels ? levels[i] : class_levels(mnk[3 * i], mnk[3 * i + 1], mnk[3 * i + 2], dtype);
+  }
+}
+
 int check_enums(int algo, int sched, int dtype) {
   if (dtype < MM_F64 || dtype > MM_BF16X3_REFINED) return fail(MM_E_INVALID, "unknown dtype");
   if (algo < MM_ALGO_NAIVE || algo > MM_ALGO_WINOGRAD) return fail(MM_E_INVALID, "unknown algorithm");
@@ -1444,6 +1596,26 @@ int upload(Plan& P) {
     rc = upload(*P.unfused);
     if (rc != MM_OK) return rc;
   }
+  if (P.persistent) {
+    // The persistent batched launch hung on its first run on MI355X (no
+    // fault; every wait apparently ran to its bound) and the cause is not
+    // known: it stays off the GPU until one is shown.  Its plans are still
+    // built on the host (mm_batched_describe, mm_batched_table), where the
+    // task queue is checked.
+    return fail(MM_E_UNSUPPORTED, "the persistent batched launch is switched off (it hung on MI355X with "
+                                  "the cause not yet found); use the level-synchronous batched plan");
+    const size_t cb = (size_t)(PC_FIRST + P.pcount) * sizeof(int);
+    if (hipMalloc((void**)&P.dctr, cb) != hipSuccess) {
+      P.dctr = nullptr;
+      (void)hipGetLastError();
+      return fail(MM_E_NOMEM, "hipMalloc of the persistent plan's counters failed");
+    }
+    // zero once here; every launch leaves them zero again
+    if (hipMemset(P.dctr, 0, cb) != hipSuccess) return fail(MM_E_HIP, "clearing the counters failed");
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    P.pgrid = persist_occupancy(P.ops[0].cfg) * cus;
+  }
   if (P.table.empty()) return MM_OK;
   if (hipMalloc(&P.dtable, P.table.size()) != hipSuccess) {
     P.dtable = nullptr;
@@ -1480,6 +1652,17 @@ int aux_for(Plan& P, hipStream_t s, Plan::Aux** out) {
 
 // events (timed execution): events[2i] / events[2i+1] are recorded before /
 // after launch i on the stream that launch runs on.
+// Polls a persistent launch's task makes on a counter before it gives up
+// and flags the plan (MM_PERSIST_SPIN_LIMIT overrides; tests lower it).
+int persist_spin_limit() {
+  static const int lim = [] {
+    const char* e = std::getenv("MM_PERSIST_SPIN_LIMIT");
+    const long v = e ? std::strtol(e, nullptr, 10) : 0;
+    return v > 0 ? (int)std::min<long>(v, 1L << 30) : (1 << 22);
+  }();
+  return lim;
+}
+
 // table: the device copy of the plan's descriptor table to read (default:
 // the one the plan uploaded).
 int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEvent_t* events = nullptr,
@@ -1523,6 +1706,8 @@ int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEven
         e = launch_trans(kb, (const EwPart*)d, op.count, op.grid, st);
       else if (op.type == OP_BASE)
         e = launch_base(op.kdtype, op.cfg, kb, (const BaseDesc*)d, op.count, op.grid, st);
+      else if (op.type == OP_PERSIST)
+        e = launch_persist(op.cfg, kb, d, P.dctr, P.pgrid, persist_spin_limit(), st);
       else
         e = op.fused ? launch_gemm_fused(op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, st)
                      : launch_gemm(op.kdtype, op.cfg, kb, (const GemmDesc*)d, op.count, op.grid, op.remap, st);
@@ -1768,11 +1953,15 @@ int build_batched(Plan& P, int count, const int64_t* mnk, void* const* A, void* 
   };
   std::vector<Prob> probs(count);
   int Lmax = 0;
+  for (int i = 0; i < count; ++i)
+    if (mnk[3 * i] < 0 || mnk[3 * i + 1] < 0 || mnk[3 * i + 2] < 0)
+      return fail(MM_E_INVALID, "negative dimension in batch");
+  std::vector<int> cut, lev;
+  resolve_batch(count, mnk, P.dtype, cutoff, levels, cut, lev);
   for (int i = 0; i < count; ++i) {
     const int64_t m = mnk[3 * i], n = mnk[3 * i + 1], k = mnk[3 * i + 2];
-    if (m < 0 || n < 0 || k < 0) return fail(MM_E_INVALID, "negative dimension in batch");
-    const int c = cutoff ? cutoff[i] : 1;
-    const int lv = levels ? levels[i] : 0;
+    const int c = cut[i];
+    const int lv = lev[i];
     int rc = check_args(m, n, k, A[i], std::max<int64_t>(k, 1), B[i], std::max<int64_t>(n, 1), C[i],
                         std::max<int64_t>(n, 1), P.dtype);
     if (rc != MM_OK) return rc;
@@ -1866,6 +2055,239 @@ int build_batched(Plan& P, int count, const int64_t* mnk, void* const* A, void* 
   for (auto& pr : probs) lmax = std::max<int64_t>(lmax, pr.L);
   P.L = (int)lmax;
   return MM_OK;
+}
+
+// Batches as ONE persistent launch (batch.hip, desc.h): the recursion of
+// every problem as in build_batched (same blocks, same temporaries), laid
+// out as a task queue: the S/T passes of level 0, 1, ..., the leaf-product
+// tiles (longest k first), the U passes of the deepest level up to level 0.
+// Each element-wise part and each leaf product carries its problem's
+// dependency: S/T of level l waits for S/T of level l - 1, the leaves wait
+// for the last S/T level, U of the deepest level waits for the leaves, U of
+// level l for U of level l + 1.  Float32 only.
+int build_batched_persistent(Plan& P, int count, const int64_t* mnk, void* const* A, void* const* B,
+                             void* const* C, const int* cutoff, const int* levels) {
+  Builder b(P);
+  const size_t esz = b.esz;
+  for (int i = 0; i < count; ++i)
+    if (mnk[3 * i] < 0 || mnk[3 * i + 1] < 0 || mnk[3 * i + 2] < 0)
+      return fail(MM_E_INVALID, "negative dimension in batch");
+  std::vector<int> cut, lev;
+  resolve_batch(count, mnk, P.dtype, cutoff, levels, cut, lev);
+  std::vector<int> Ls(count, 0);
+  int Lmax = 0;
+  for (int i = 0; i < count; ++i) {
+    const int64_t m = mnk[3 * i], n = mnk[3 * i + 1], k = mnk[3 * i + 2];
+    int rc = check_args(m, n, k, A[i], std::max<int64_t>(k, 1), B[i], std::max<int64_t>(n, 1), C[i],
+                        std::max<int64_t>(n, 1), P.dtype);
+    if (rc != MM_OK) return rc;
+    Ls[i] = (m == 0 || n == 0 || k == 0) ? 0 : count_levels(m, n, k, cut[i], lev[i]);
+    if (Ls[i] > MM_MAX_LEVELS) return fail(MM_E_UNSUPPORTED, "too many levels in batch problem");
+    Lmax = std::max(Lmax, Ls[i]);
+  }
+  // stage lists, each entry tagged with its problem
+  std::vector<std::vector<std::pair<int, EwPart>>> st(Lmax), u(Lmax);
+  std::vector<std::pair<int, EwPart>> zeros;
+  std::vector<std::pair<int, GemmDesc>> leaves;
+  for (int i = 0; i < count; ++i) {
+    const int64_t m = mnk[3 * i], n = mnk[3 * i + 1], k = mnk[3 * i + 2];
+    if (m == 0 || n == 0) continue;
+    const int L = Ls[i];
+    const int64_t step = (int64_t)1 << L;
+    const int64_t g = (L > 0 && std::min(std::min(m, n), k) / step >= 32) ? b.E : 1;
+    const int64_t M = L ? round_up(m, step * g) : m, N = L ? round_up(n, step * g) : n,
+                  K = L ? round_up(k, step * g) : k;
+    const int64_t ka = std::max<int64_t>(k, 1), na = std::max<int64_t>(n, 1);
+    std::vector<Sub> cur{{b.view(MB_ABS, (int64_t)((uintptr_t)A[i] / esz), ka, M, K, m, k),
+                          b.view(MB_ABS, (int64_t)((uintptr_t)B[i] / esz), na, K, N, k, n),
+                          b.view(MB_ABS, (int64_t)((uintptr_t)C[i] / esz), na, M, N, m, n)}};
+    if (k == 0) {
+      zeros.push_back({i, b.make_ew(EW_ZERO, m, n, {}, {cur[0].C})});
+      continue;
+    }
+    for (int l = 0; l < L; ++l) {
+      std::vector<Sub> next;
+      for (const Sub& s : cur) {
+        const int64_t hm = s.A.rows / 2, hk = s.A.cols / 2, hn = s.B.cols / 2;
+        const MView A11 = b.quad(s.A, 0, 0), A12 = b.quad(s.A, 0, 1), A21 = b.quad(s.A, 1, 0),
+                    A22 = b.quad(s.A, 1, 1);
+        const MView B11 = b.quad(s.B, 0, 0), B12 = b.quad(s.B, 0, 1), B21 = b.quad(s.B, 1, 0),
+                    B22 = b.quad(s.B, 1, 1);
+        MView S[4], T[4], Pt[7];
+        for (auto& v : S) v = b.temp(hm, hk);
+        for (auto& v : T) v = b.temp(hk, hn);
+        for (auto& v : Pt) v = b.temp(hm, hn);
+        st[l].push_back({i, b.make_ew(EW_WINO_S, hm, hk, {A11, A12, A21, A22}, {S[0], S[1], S[2], S[3]})});
+        st[l].push_back({i, b.make_ew(EW_WINO_T, hk, hn, {B11, B12, B21, B22}, {T[0], T[1], T[2], T[3]})});
+        next.push_back({A11, B11, Pt[0]});
+        next.push_back({A12, B21, Pt[1]});
+        next.push_back({S[3], B22, Pt[2]});
+        next.push_back({A22, T[3], Pt[3]});
+        next.push_back({S[0], T[0], Pt[4]});
+        next.push_back({S[1], T[1], Pt[5]});
+        next.push_back({S[2], T[2], Pt[6]});
+        u[l].push_back({i, b.make_ew(EW_WINO_U, hm, hn, {Pt[0], Pt[1], Pt[2], Pt[3], Pt[4], Pt[5], Pt[6]},
+                                     {b.quad(s.C, 0, 0), b.quad(s.C, 0, 1), b.quad(s.C, 1, 0),
+                                      b.quad(s.C, 1, 1)})});
+      }
+      cur.swap(next);
+    }
+    for (const Sub& s : cur) {
+      P.leaves += 1;
+      GemmDesc gd = b.make_gemm(s.A, s.B, {Builder::store(s.C)});
+      if (gd.m > 0 && gd.n > 0) leaves.push_back({i, gd});
+    }
+  }
+  // tile configuration of the leaf products: the unequal-batch cost model
+  // over the persistent kernel's tiles
+  int cfg = P.tile_cfg;
+  if (cfg < 0 || !persist_cfg_ok(cfg)) {
+    const int cand[3] = {0, 4, 8};
+    const double eff[3] = {0.81, 0.75, 0.74};
+    double best_cost = 1e300;
+    cfg = 0;
+    for (int c = 0; c < 3; ++c) {
+      const GemmCfg gc = gemm_cfg(DT_F32, cand[c]);
+      double work = 0;
+      for (const auto& e : leaves)
+        work += (double)ceil_div(e.second.m, gc.bm) * ceil_div(e.second.n, gc.bn) * gc.bm * gc.bn * e.second.k;
+      if (work / eff[c] < best_cost) {
+        best_cost = work / eff[c];
+        cfg = cand[c];
+      }
+    }
+  }
+  const GemmCfg gc = gemm_cfg(DT_F32, cfg);
+  std::stable_sort(leaves.begin(), leaves.end(), [](const std::pair<int, GemmDesc>& x,
+                                                    const std::pair<int, GemmDesc>& y) {
+    return x.second.k > y.second.k;
+  });
+  // counters: per problem with levels, one per S/T level, one for the
+  // leaves, one per U level above the top
+  std::vector<std::vector<int>> c_st(count), c_u(count);
+  std::vector<int> c_leaf(count, -1);
+  int nctr = 0;
+  for (int i = 0; i < count; ++i) {
+    if (Ls[i] == 0) continue;
+    for (int l = 0; l < Ls[i]; ++l) c_st[i].push_back(nctr++);
+    c_leaf[i] = nctr++;
+    c_u[i].assign(Ls[i], -1);
+    for (int l = 1; l < Ls[i]; ++l) c_u[i][l] = nctr++;
+  }
+  // tasks per (problem, stage)
+  auto ew_tasks = [](const EwPart& p) {
+    return (int)ceil_div(ew_blocks(p.rows, p.cols, DT_F32), kPersistEwBlocks);
+  };
+  std::vector<std::vector<int>> n_st(count), n_u(count);
+  std::vector<int> n_leaf(count, 0);
+  for (int i = 0; i < count; ++i) {
+    n_st[i].assign(Ls[i], 0);
+    n_u[i].assign(Ls[i], 0);
+  }
+  for (int l = 0; l < Lmax; ++l) {
+    for (const auto& e : st[l]) n_st[e.first][l] += ew_tasks(e.second);
+    for (const auto& e : u[l]) n_u[e.first][l] += ew_tasks(e.second);
+  }
+  for (auto& e : leaves) {
+    e.second.tiles_m = (int32_t)ceil_div(e.second.m, gc.bm);
+    e.second.tiles_n = (int32_t)ceil_div(e.second.n, gc.bn);
+    n_leaf[e.first] += e.second.tiles_m * e.second.tiles_n;
+  }
+  // segments
+  PersistHdr hdr;
+  std::memset(&hdr, 0, sizeof hdr);
+  std::vector<uint8_t>& tab = P.table;
+  tab.assign(round_up(sizeof(PersistHdr), 256), 0);
+  int ntasks = 0;
+  auto add_seg = [&](int kind, const std::vector<uint8_t>& descs, const std::vector<PDep>& deps, int nt) {
+    if (deps.empty() || nt == 0) return;
+    PSeg& sg = hdr.seg[hdr.nseg++];
+    sg.kind = kind;
+    sg.first = ntasks;
+    sg.ntasks = nt;
+    sg.ndesc = (int32_t)deps.size();
+    sg.desc_off = (int64_t)tab.size();
+    tab.insert(tab.end(), descs.begin(), descs.end());
+    tab.resize(round_up(tab.size(), 256), 0);
+    sg.dep_off = (int64_t)tab.size();
+    const uint8_t* d = reinterpret_cast<const uint8_t*>(deps.data());
+    tab.insert(tab.end(), d, d + deps.size() * sizeof(PDep));
+    tab.resize(round_up(tab.size(), 256), 0);
+    ntasks += nt;
+  };
+  auto ew_seg = [&](const std::vector<std::pair<int, EwPart>>& parts, auto dep_of) {
+    std::vector<uint8_t> descs;
+    std::vector<PDep> deps;
+    int nt = 0;
+    for (const auto& e : parts) {
+      const int t = ew_tasks(e.second);
+      if (t == 0) continue;
+      PDep d = dep_of(e.first);
+      d.task_start = nt;
+      nt += t;
+      const uint8_t* p = reinterpret_cast<const uint8_t*>(&e.second);
+      descs.insert(descs.end(), p, p + sizeof(EwPart));
+      deps.push_back(d);
+      b.txt << Builder::ew_line(e.second);
+      b.txt << "PDEP " << d.wait << " " << d.target << " " << d.signal << " " << d.task_start << " " << t << "\n";
+    }
+    add_seg(PT_EW, descs, deps, nt);
+    if (nt) b.txt << "LAUNCH EW " << deps.size() << " " << nt << " persist\n";
+  };
+  for (int l = 0; l < Lmax; ++l) {
+    std::vector<std::pair<int, EwPart>> parts = st[l];
+    if (l == 0) parts.insert(parts.end(), zeros.begin(), zeros.end());
+    ew_seg(parts, [&](int i) {
+      if (Ls[i] == 0) return PDep{-1, 0, -1, 0};  // a zero fill
+      return l == 0 ? PDep{-1, 0, c_st[i][0], 0} : PDep{c_st[i][l - 1], n_st[i][l - 1], c_st[i][l], 0};
+    });
+  }
+  if (Lmax == 0) ew_seg(zeros, [](int) { return PDep{-1, 0, -1, 0}; });
+  {
+    std::vector<uint8_t> descs;
+    std::vector<PDep> deps;
+    int nt = 0;
+    for (auto& e : leaves) {
+      const int i = e.first;
+      PDep d = Ls[i] ? PDep{c_st[i][Ls[i] - 1], n_st[i][Ls[i] - 1], c_leaf[i], nt} : PDep{-1, 0, -1, nt};
+      e.second.tile_start = nt;
+      nt += e.second.tiles_m * e.second.tiles_n;
+      const uint8_t* p = reinterpret_cast<const uint8_t*>(&e.second);
+      descs.insert(descs.end(), p, p + sizeof(GemmDesc));
+      deps.push_back(d);
+      b.txt << Builder::gemm_line(e.second);
+      b.txt << "PDEP " << d.wait << " " << d.target << " " << d.signal << " " << d.task_start << " "
+            << e.second.tiles_m * e.second.tiles_n << "\n";
+    }
+    add_seg(PT_GEMM, descs, deps, nt);
+    if (nt) b.txt << "LAUNCH GEMM " << deps.size() << " " << nt << " " << cfg << " persist\n";
+  }
+  for (int l = Lmax - 1; l >= 0; --l)
+    ew_seg(u[l], [&](int i) {
+      const int L = Ls[i];
+      const PDep w = l == L - 1 ? PDep{c_leaf[i], n_leaf[i], -1, 0} : PDep{c_u[i][l + 1], n_u[i][l + 1], -1, 0};
+      return PDep{w.wait, w.target, l > 0 ? c_u[i][l] : -1, 0};
+    });
+  hdr.ntasks = ntasks;
+  hdr.ncounters = nctr;
+  std::memcpy(tab.data(), &hdr, sizeof hdr);
+  P.ops.push_back(OpRec{OP_PERSIST, DT_F32, 0, ntasks, 0, cfg, 0, 0, 0});
+  b.txt << "LAUNCH PERSIST 0 " << ntasks << " " << cfg << "\n";
+  P.persistent = true;
+  P.pcount = nctr;
+  P.ws_bytes = (size_t)b.ws_peak * esz;
+  P.text = b.txt.str();
+  P.L = Lmax;
+  return MM_OK;
+}
+
+// A batched plan: persistent (one launch) when asked for and float32,
+// level-synchronous otherwise.
+int build_batch_plan(Plan& P, int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C,
+                     const int* cutoff, const int* levels) {
+  if ((P.flags & MM_PLAN_PERSISTENT) && P.dtype == MM_F32)
+    return build_batched_persistent(P, count, mnk, A, B, C, cutoff, levels);
+  return build_batched(P, count, mnk, A, B, C, cutoff, levels);
 }
 
 }  // namespace
@@ -2084,8 +2506,8 @@ size_t mm_describe(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t
 }
 
 size_t mm_batched_describe(int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C,
-                           int dtype, const int* cutoff, const int* levels, char* buf, size_t len,
-                           int64_t* info, int ninfo) {
+                           int dtype, const int* cutoff, const int* levels, unsigned flags, char* buf,
+                           size_t len, int64_t* info, int ninfo) {
   if (count < 0 || (count > 0 && (!mnk || !A || !B || !C))) return 0;
   if (check_enums(MM_ALGO_WINOGRAD, MM_SCHED_GROUPED, dtype) != MM_OK) return 0;
   std::unique_ptr<Plan> P(new Plan);
@@ -2093,11 +2515,29 @@ size_t mm_batched_describe(int count, const int64_t* mnk, void* const* A, void* 
   P->sched = MM_SCHED_GROUPED;
   P->dtype = dtype;
   P->batched = true;
-  if (build_batched(*P, count, mnk, A, B, C, cutoff, levels) != MM_OK) return 0;
+  P->flags = flags;
+  P->tile_cfg = (int)((flags >> 8) & 0xff) - 1;
+  if (build_batch_plan(*P, count, mnk, A, B, C, cutoff, levels) != MM_OK) return 0;
   mm_plan_s tmp{std::move(P)};
   if (info) mm_plan_info(&tmp, info, ninfo);
   const size_t r = mm_plan_describe(&tmp, buf, len);
   return r ? r : 1;
+}
+
+size_t mm_batched_table(int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C,
+                        int dtype, const int* cutoff, const int* levels, unsigned flags, void* buf, size_t len) {
+  if (count < 0 || (count > 0 && (!mnk || !A || !B || !C))) return 0;
+  if (check_enums(MM_ALGO_WINOGRAD, MM_SCHED_GROUPED, dtype) != MM_OK) return 0;
+  Plan P;
+  P.algo = MM_ALGO_WINOGRAD;
+  P.sched = MM_SCHED_GROUPED;
+  P.dtype = dtype;
+  P.batched = true;
+  P.flags = flags;
+  P.tile_cfg = (int)((flags >> 8) & 0xff) - 1;
+  if (build_batch_plan(P, count, mnk, A, B, C, cutoff, levels) != MM_OK) return 0;
+  if (buf) std::memcpy(buf, P.table.data(), std::min(len, P.table.size()));
+  return P.table.size();
 }
 
 int mm_batched_plan_create(int count, const int64_t* mnk, void* const* A, void* const* B, void* const* C,
@@ -2116,11 +2556,47 @@ int mm_batched_plan_create(int count, const int64_t* mnk, void* const* A, void* 
   P->flags = flags;
   P->tile_cfg = (int)((flags >> 8) & 0xff) - 1;
   if (P->tile_cfg >= kNumGemmCfg) return fail(MM_E_INVALID, "unknown tile configuration");
-  rc = build_batched(*P, count, mnk, A, B, C, cutoff, levels);
+  rc = build_batch_plan(*P, count, mnk, A, B, C, cutoff, levels);
   if (rc != MM_OK) return rc;
   rc = upload(*P);
   if (rc != MM_OK) return rc;
   *plan = new mm_plan_s{std::move(P)};
+  return MM_OK;
+}
+
+int mm_batched_levels(int count, const int64_t* mnk, int dtype, const int* cutoff, const int* levels,
+                      int* levels_out) {
+  if (count < 0 || (count > 0 && (!mnk || !levels_out))) return fail(MM_E_INVALID, "bad batch arrays");
+  int rc = check_enums(MM_ALGO_WINOGRAD, MM_SCHED_GROUPED, dtype);
+  if (rc != MM_OK) return rc;
+  for (int i = 0; i < count; ++i)
+    if (mnk[3 * i] < 0 || mnk[3 * i + 1] < 0 || mnk[3 * i + 2] < 0)
+      return fail(MM_E_INVALID, "negative dimension in batch");
+  std::vector<int> cut, lev;
+  resolve_batch(count, mnk, dtype, cutoff, levels, cut, lev);
+  for (int i = 0; i < count; ++i) {
+    const int64_t m = mnk[3 * i], n = mnk[3 * i + 1], k = mnk[3 * i + 2];
+    levels_out[i] = (m == 0 || n == 0 || k == 0) ? 0 : count_levels(m, n, k, cut[i], lev[i]);
+  }
+  return MM_OK;
+}
+
+const char* mm_tuning_source(void) { return class_table().source.c_str(); }
+
+int mm_plan_check(mm_plan_t plan, hipStream_t stream) {
+  if (!plan || !plan->p) return fail(MM_E_INVALID, "NULL plan");
+  Plan& P = *plan->p;
+  if (!P.persistent || !P.dctr) return MM_OK;
+  if (hipStreamSynchronize(stream) != hipSuccess) return fail(MM_E_HIP, "hipStreamSynchronize failed");
+  int flag = 0;
+  if (hipMemcpy(&flag, P.dctr + PC_ERROR, sizeof flag, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(MM_E_HIP, "reading the plan's error flag failed");
+  if (flag) {
+    const int zero = 0;
+    (void)hipMemcpy(P.dctr + PC_ERROR, &zero, sizeof zero, hipMemcpyHostToDevice);
+    return fail(MM_E_HIP, "a task of the persistent launch waited past its bound; results since the last "
+                          "check are not reliable");
+  }
   return MM_OK;
 }
 
@@ -2131,10 +2607,15 @@ int mm_batched(int count, const int64_t* mnk, void* const* A, void* const* B, vo
   int rc = check_device(&dev);
   if (rc != MM_OK) return rc;
   std::ostringstream key;
+  for (int i = 0; i < count; ++i)
+    if (mnk[3 * i] < 0 || mnk[3 * i + 1] < 0 || mnk[3 * i + 2] < 0)
+      return fail(MM_E_INVALID, "negative dimension in batch");
+  std::vector<int> cut, lev;
+  resolve_batch(count, mnk, dtype, cutoff, levels, cut, lev);
   key << "B|" << dev << "|" << dtype << "|" << count;
   for (int i = 0; i < count; ++i)
     key << "|" << mnk[3 * i] << "," << mnk[3 * i + 1] << "," << mnk[3 * i + 2] << "," << A[i] << "," << B[i]
-        << "," << C[i] << "," << (cutoff ? cutoff[i] : 1) << "," << (levels ? levels[i] : 0);
+        << "," << C[i] << "," << cut[i] << "," << lev[i];
   Plan* P = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -2147,7 +2628,7 @@ int mm_batched(int count, const int64_t* mnk, void* const* A, void* const* B, vo
       np->batched = true;
       rc = check_enums(MM_ALGO_WINOGRAD, MM_SCHED_GROUPED, dtype);
       if (rc != MM_OK) return rc;
-      rc = build_batched(*np, count, mnk, A, B, C, cutoff, levels);
+      rc = build_batch_plan(*np, count, mnk, A, B, C, cut.data(), lev.data());
       if (rc != MM_OK) return rc;
       rc = upload(*np);
       if (rc != MM_OK) return rc;

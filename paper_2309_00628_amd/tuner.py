@@ -248,6 +248,96 @@ def tune(m, n, k, dtype="f32", max_levels=3, reps=5, warmup=2, tiles=None, save=
     return entry
 
 
+# ---------------------------------------------------------------------------
+# Batches: levels per size class, measured in the batch itself
+# ---------------------------------------------------------------------------
+# In a batch the GPU is already full of leaf products, so whether a
+# recursion level pays for a problem depends on the batch, not on the
+# problem alone.  The tuner measures the batched workload (512 products,
+# m, n, k log-uniform in [64, 2048]) as one batched plan and, class by
+# class (largest share of the flops first), keeps the level count that
+# makes the whole batch fastest.  The library reads the result
+# (tuning/<arch>_batched.txt: "dtype class levels") whenever a batch is
+# given no levels.
+
+def batched_class(m, n, k):
+    """Size class of a batched product: its volume-equivalent order
+    (m n k)^(1/3) rounded to half octaves (as the library computes it)."""
+    return math.floor(2.0 * math.log2(max(m * n * k, 1)) / 3.0 + 0.5) / 2.0
+
+
+def batch_table_path(arch=None):
+    return os.path.join(CACHE_DIR, f"{arch or _arch()}_batched.txt")
+
+
+def tune_batched(count=512, seed=7, dtype="f32", max_levels=2, reps=10, rounds=3, margin=0.01, save=True,
+                 verbose=False, out=None):
+    import torch
+
+    from . import api, inputs
+    shapes = inputs.batched_shapes(count, seed)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    As, Bs, Cs = [], [], []
+    for (m, n, k) in shapes:
+        As.append(torch.rand((m, k), generator=g, device="cuda") * 2 - 1)
+        Bs.append(torch.rand((k, n), generator=g, device="cuda") * 2 - 1)
+        Cs.append(torch.empty((m, n), device="cuda"))
+    cls = [batched_class(*s) for s in shapes]
+    flops = {}
+    for (m, n, k), c in zip(shapes, cls):
+        flops[c] = flops.get(c, 0.0) + 2.0 * m * n * k
+    classes = sorted(flops, key=lambda c: -flops[c])
+    choice = {c: 0 for c in classes}
+    s = torch.cuda.current_stream()
+
+    def time_levels(lv):
+        plan = api.BatchedPlan(As, Bs, Cs, cutoff=[1] * count, levels=lv, graph=True)
+        for _ in range(3):
+            plan()
+        ts = []
+        for _ in range(rounds):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(reps):
+                plan()
+            e1.record(s)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / reps)
+        return sorted(ts)[len(ts) // 2]
+
+    total = sum(flops.values())
+    base = time_levels([0] * count)
+    if verbose:
+        print(f"batched all L=0: {base:.4f} ms {total / base / 1e9:.1f} TFLOP/s", flush=True)
+    for c in classes:
+        best_t, best_l = None, 0
+        for L_ in range(0, max_levels + 1):
+            if L_ and any(min(sh) >> L_ < 16 for sh, cc in zip(shapes, cls) if cc == c):
+                break                   # leaves of fewer than 16 rows: not worth a level
+            lv = [L_ if cc == c else choice[cc] for cc in cls]
+            t = time_levels(lv)
+            if verbose:
+                print(f"  class {c:.1f} ({flops[c] / total:.1%} of the flops) L={L_}: {t:.4f} ms "
+                      f"{total / t / 1e9:.1f} TFLOP/s", flush=True)
+            if best_t is None or t < best_t * (1.0 - margin):
+                best_t, best_l = t, L_
+        choice[c] = best_l
+    lines = ["# levels per size class of batched float32 products, measured on the batched workload",
+             f"# ({count} products, m, n, k log-uniform in [64, 2048], seed {seed}) as one batched plan;",
+             "# class = round(2 log2 (m n k)^(1/3)) / 2.  Columns: dtype class levels"]
+    lines += [f"{dtype} {c:.1f} {choice[c]}" for c in sorted(choice)]
+    text = "\n".join(lines) + "\n"
+    if save:
+        os.makedirs(CACHE_DIR, exist_ok=True)
+        with open(batch_table_path(), "w") as f:
+            f.write(text)
+    if out:
+        with open(out, "w") as f:
+            f.write(text)
+    return choice
+
+
 def main(argv=None):
     """Tune square size classes: python -m paper_2309_00628_amd.tuner --n 1024,4096 --dtype f32"""
     import argparse
@@ -258,7 +348,13 @@ def main(argv=None):
     ap.add_argument("--max-levels", type=int, default=3)
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--copy-to", default=None, help="also copy the cache file here")
+    ap.add_argument("--batched", action="store_true",
+                    help="tune the levels per size class of the batched workload instead")
     args = ap.parse_args(argv)
+    if args.batched:
+        ch = tune_batched(verbose=True, out=args.copy_to)
+        print({f"{c:.1f}": l for c, l in sorted(ch.items())}, flush=True)
+        return
     for dt in args.dtype.split(","):
         for n in [int(x) for x in args.n.split(",")]:
             e = tune(n, n, n, dt, max_levels=args.max_levels, reps=args.reps, verbose=True)

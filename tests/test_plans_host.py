@@ -648,3 +648,114 @@ def test_bench_tile_table_matches_the_library(lib):
         lau = [x for x in bench.plan_launches(type("P", (), {"describe": lambda self: text})(), 4)
                if x["kind"] == "WINO"]
         assert len(lau) == 1 and lau[0]["grid"] == math.ceil(m / bm) * math.ceil(n / bn), c
+
+
+def _persistent_segments(text):
+    """(kind, [(wait, target, signal, task_start, ntasks)]) per segment of a
+    persistent batched listing, in queue order."""
+    segs, cur = [], []
+    for line in text.splitlines():
+        if line.startswith("PDEP"):
+            cur.append(tuple(map(int, line.split()[1:])))
+        elif line.startswith("LAUNCH") and not line.startswith("LAUNCH PERSIST"):
+            segs.append((line.split()[1], cur))
+            cur = []
+    assert not cur
+    return segs
+
+
+def _batch_fixture(shapes, seed0=100):
+    mats, addrs = [], []
+    pos, esz = 0, 4
+    for i, (m, n, k) in enumerate(shapes):
+        A = inputs.integers((m, k), seed0 + i, dtype=np.int64)
+        B = inputs.integers((k, n), seed0 + 100 + i, dtype=np.int64)
+        a, b, c = pos, pos + A.size + 8, pos + A.size + B.size + 16
+        pos = c + m * n + 8
+        addrs.append(((a + 1024) * esz, (b + 1024) * esz, (c + 1024) * esz))
+        mats.append((A, B, a, b, c))
+    flat = np.full(pos + 2048, -(10**9), dtype=np.int64)
+    for A, B, a, b, c in mats:
+        flat[1024 + a:1024 + a + A.size] = A.ravel()
+        flat[1024 + b:1024 + b + B.size] = B.ravel()
+    return mats, addrs, flat
+
+
+def test_persistent_batched_plan_exact_and_drains(lib):
+    """MM_PLAN_PERSISTENT: one launch; its queue, executed segment by
+    segment, gives the exact product of every problem (integers); every
+    task waits only on a counter that earlier segments alone signal, for
+    exactly the number of tasks that signal it, so the workgroup holding
+    the earliest unfinished task never waits on an unfinished one."""
+    shapes = [(16, 32, 8), (40, 24, 56), (7, 9, 11), (64, 64, 64), (0, 5, 3), (6, 4, 0), (96, 80, 112),
+              (33, 65, 17)]
+    cut = [2, 4, 1, 8, 1, 1, 1, 1]
+    lev = [-1, 2, 1, -1, 1, 1, 3, 0]
+    mats, addrs, flat = _batch_fixture(shapes)
+    text, info = L.batched_describe(shapes, addrs, dtype="f32", cutoff=cut, levels=lev, persistent=True)
+    assert info["launches"] == 1
+    _, ref_info = L.batched_describe(shapes, addrs, dtype="f32", cutoff=cut, levels=lev)
+    assert info["ws_bytes"] == ref_info["ws_bytes"] and info["leaves"] == ref_info["leaves"]
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    plan_sim.run(text, {plan_sim.MB_ABS: flat, plan_sim.MB_WS: ws})
+    for (m, n, k), (A, B, a, b, c) in zip(shapes, mats):
+        got = flat[1024 + c:1024 + c + m * n].reshape(m, n)
+        assert np.array_equal(got, A @ B), (m, n, k)
+    segs = _persistent_segments(text)
+    signalers = {}                        # counter -> (segments, tasks)
+    for si, (_, items) in enumerate(segs):
+        start = 0
+        for w, t, s, ts, nt in items:
+            assert ts == start and nt > 0
+            start += nt
+            if s >= 0:
+                segset, tot = signalers.get(s, (set(), 0))
+                signalers[s] = (segset | {si}, tot + nt)
+    for si, (_, items) in enumerate(segs):
+        for w, t, s, ts, nt in items:
+            if w < 0:
+                continue
+            segset, tot = signalers[w]
+            assert max(segset) < si, (si, w)
+            assert t == tot, (si, w, t, tot)
+    waited = {w for _, items in segs for w, *_ in items if w >= 0}
+    assert waited == set(signalers)       # every signalled counter is waited on
+
+
+def test_batched_null_levels_follow_the_size_classes(lib):
+    """mm_batched_levels with NULL levels: the tuned level count of each
+    problem's size class (the table the library read, or the documented rule
+    without one), capped by the cutoff and the shape; a batched plan built
+    with NULL levels has exactly those leaves."""
+    import math
+    shapes = [(64, 64, 64), (2048, 2048, 2048), (4096, 4096, 4096), (8192, 8192, 8192), (100, 3000, 50),
+              (1536, 256, 2048)]
+    got = L.batched_levels(shapes)
+    src = L.tuning_source()
+    table = {}
+    if src:
+        for line in open(src):
+            line = line.split("#")[0].split()
+            if len(line) == 3 and line[0] == "f32":
+                table[float(line[1])] = int(line[2])
+
+    def expect(m, n, k):
+        vol = m * n * k
+        if table:
+            c = math.floor(2 * math.log2(vol) / 3 + 0.5) / 2
+            lv = min(table.items(), key=lambda e: abs(e[0] - c))[1]
+        else:
+            lv = 0
+            while lv < 2 and vol >= (2048 * (2 << lv)) ** 3:
+                lv += 1
+        # capped by the shape (cutoff 1): halve while the smallest side > 1
+        cap = 0
+        while cap < lv and min(-(-m // (1 << cap)), -(-n // (1 << cap)), -(-k // (1 << cap))) > 1:
+            cap += 1
+        return cap
+    assert got == [expect(*s) for s in shapes], (got, src)
+    assert L.batched_levels(shapes, levels=[1] * 6) == [1] * 6
+    assert L.batched_levels(shapes, cutoff=[4096] * 6, levels=[3] * 6) == [0, 0, 0, 1, 0, 0]
+    addrs = [(4096 * (3 * i + 1), 4096 * (3 * i + 2), 4096 * (3 * i + 3)) for i in range(len(shapes))]
+    _, info = L.batched_describe(shapes, [(a << 20, b << 20, c << 20) for a, b, c in addrs])
+    assert info["leaves"] == sum(7 ** lv for lv in got)
