@@ -50,20 +50,38 @@ __device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
 }
 __device__ __forceinline__ int row32(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Round a pair of floats to bfloat16 (nearest even) with one packed
+// conversion; element 0 lands in the low half of the returned word.
+__device__ __forceinline__ unsigned cvt_pair(float a, float b) {
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+}
+// The two bfloat16 halves of a packed word as floats (exact: a bfloat16 is
+// the top half of a float).
+__device__ __forceinline__ float lo_half(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float hi_half(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+
 // Split 8 floats into their bfloat16 hi, lo and residual parts (both
-// differences are exact, see above).
+// differences are exact, see above), two elements per conversion.
 __device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo, bf16x8& rs) {
+  u32x4 H, Lw, R;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const __bf16 h = (__bf16)x[e];
-    const float hf = (float)h;
-    const float d1 = x[e] - hf;
-    const __bf16 l = (__bf16)d1;
-    const float d2 = d1 - (float)l;
-    hi[e] = h;
-    lo[e] = l;
-    rs[e] = (__bf16)d2;
+  for (int p = 0; p < 4; ++p) {
+    const float x0 = x[2 * p], x1 = x[2 * p + 1];
+    const unsigned h = cvt_pair(x0, x1);
+    const float d0 = x0 - lo_half(h), d1 = x1 - hi_half(h);
+    const unsigned l = cvt_pair(d0, d1);
+    const float e0 = d0 - lo_half(l), e1 = d1 - hi_half(l);
+    H[p] = h;
+    Lw[p] = l;
+    R[p] = cvt_pair(e0, e1);
   }
+  hi = __builtin_bit_cast(bf16x8, H);
+  lo = __builtin_bit_cast(bf16x8, Lw);
+  rs = __builtin_bit_cast(bf16x8, R);
 }
 
 constexpr int KC = 8;  // k values per 16-byte chunk (bfloat16)
@@ -297,6 +315,231 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
                                                [](int l, int r) { return row32(l, r); });
 }
 
+// The same products on a 256 x 256 tile with eight waves (two per SIMD, each
+// 128 x 64), software-pipelined so that the split's vector work runs under
+// the MFMAs of the same wave.  Each thread stages one 8-float chunk of A
+// and one 8-row column of B per stage (EBB = 1 column per block), so the
+// split work is the same in every wave.  During stage t the registers hold
+// stage t+1 (loaded during stage t-1): it is split into the other LDS
+// buffer between the MFMAs of the first two rows of 32 x 32 tiles, after
+// which the loads of stage t+2 are issued into the same registers, to
+// arrive while the last two rows and the next stage's first rows compute.
+// The steady-state loop (stages that both split and load) is one basic
+// block, so the compiler can interleave the split with the MFMAs; the last
+// two stages are peeled.  A stage holds 16 k (one MFMA k-step); the six
+// products of a tile are issued in the order of the kernel above and the
+// LDS layout is the same (swz_b depends only on the column), so both
+// kernels give the same bits.  Tiles that are not entirely inside both
+// operands (and products whose k is not a multiple of 16) take a plain
+// masked loop.
+template <int BM, int BN, int WGM, int WGN, int EBB>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(KernelBases kb,
+                                                                    const GemmDesc* __restrict__ descs,
+                                                                    int ndesc, int remap) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int TM = 32;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / TM, FN = WN / TM;
+  constexpr int BKC = 2;
+  constexpr int BK = BKC * KC;
+  constexpr int NCH_A = BM * BKC;           // 8-float chunks of A per stage
+  constexpr int NA = NCH_A / NT;
+  constexpr int NBLK_B = BKC * (BN / EBB);  // 8 x EBB blocks of B per stage
+  constexpr int NB = NBLK_B / NT;
+  constexpr int NPART = NA + NB * EBB;      // split calls per thread and stage
+  static_assert(NCH_A % NT == 0 && NBLK_B % NT == 0 && NA >= 1 && NB >= 1, "whole chunks per thread");
+  static_assert(FM >= 2 * NPART / 2 && FM % 2 == 0, "split spread over the first half of the tile rows");
+
+  __shared__ bf16x8 As[2][3][BKC][BM];
+  __shared__ bf16x8 Bs[2][3][BKC][BN];
+
+  const TileRef tr = locate_tile<BM, BN>(descs, ndesc, remap);
+  const GemmDesc& D = descs[tr.desc];
+  const int i0 = tr.i0, j0 = tr.j0;
+  const MView av = D.a, bv = D.b;
+  const float* __restrict__ Ap = resolve<float>(kb, av);
+  const float* __restrict__ Bp = resolve<float>(kb, bv);
+  const int64_t lda = av.ld, ldb = bv.ld;
+  const bool avec = view_vec(kb, av), bvec = view_vec(kb, bv);
+  const int K = D.k;
+  const int ktiles = (K + BK - 1) / BK;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int g = lane / TM, t = lane % TM;
+
+  float sa[NA][8];          // staged A chunks of one stage
+  float sb[NB][8][EBB];     // staged B blocks of one stage
+
+  auto load_full = [&](int kt) {
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + NT * i;
+      const int row = q / BKC, kc = q % BKC;
+      const float* p = Ap + (int64_t)(i0 + row) * lda + k0 + kc * KC;
+      const f32x4 u = *reinterpret_cast<const f32x4*>(p);
+      const f32x4 w = *reinterpret_cast<const f32x4*>(p + 4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        sa[i][e] = u[e];
+        sa[i][4 + e] = w[e];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + NT * i;
+      const int kc = q / (BN / EBB), cb = q % (BN / EBB);
+#pragma unroll
+      for (int rr = 0; rr < KC; ++rr) {
+        const float* p = Bp + (int64_t)(k0 + kc * KC + rr) * ldb + j0 + cb * EBB;
+        if constexpr (EBB == 2) {
+          const f32x2 u = *reinterpret_cast<const f32x2*>(p);
+          sb[i][rr][0] = u[0];
+          sb[i][rr][1] = u[1];
+        } else {
+          sb[i][rr][0] = *p;
+        }
+      }
+    }
+  };
+  auto load_masked = [&](int kt) {
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + NT * i;
+      const int row = q / BKC, kc = q % BKC;
+      const int gr = i0 + row, gc = k0 + kc * KC;
+      const float* p = Ap + (int64_t)gr * lda + gc;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sa[i][e] = (gr < av.vrows && gc + e < av.vcols) ? p[e] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + NT * i;
+      const int kc = q / (BN / EBB), cb = q % (BN / EBB);
+#pragma unroll
+      for (int rr = 0; rr < KC; ++rr) {
+        const int gr = k0 + kc * KC + rr;
+#pragma unroll
+        for (int c = 0; c < EBB; ++c) {
+          const int gc = j0 + cb * EBB + c;
+          sb[i][rr][c] = (gr < bv.vrows && gc < bv.vcols) ? Bp[(int64_t)gr * ldb + gc] : 0.f;
+        }
+      }
+    }
+  };
+  // Split call j (0 .. NPART - 1: the A chunks, then the B columns) of the
+  // staged stage into LDS buffer buf.
+  auto split_part = [&](int buf, int j) {
+    bf16x8 h, l, r;
+    if (j < NA) {
+      const int q = tid + NT * j;
+      const int row = q / BKC, kc = q % BKC;
+      split8(sa[j], h, l, r);
+      const int sr = swz_a<BKC>(row, kc);
+      As[buf][0][kc][sr] = h;
+      As[buf][1][kc][sr] = l;
+      As[buf][2][kc][sr] = r;
+    } else {
+      const int i = (j - NA) / EBB, c = (j - NA) % EBB;
+      const int q = tid + NT * i;
+      const int kc = q / (BN / EBB), cb = q % (BN / EBB);
+      float col[8];
+#pragma unroll
+      for (int rr = 0; rr < KC; ++rr) col[rr] = sb[i][rr][c];
+      split8(col, h, l, r);
+      const int sc = swz_b<EB>(cb * EBB + c);
+      Bs[buf][0][kc][sc] = h;
+      Bs[buf][1][kc][sc] = l;
+      Bs[buf][2][kc][sc] = r;
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  // The MFMAs of one stage from LDS buffer buf.  SPLIT: the staged stage is
+  // split into buffer nbuf between the first FM/2 rows of tiles; LOAD: then
+  // stage kt_next is loaded into the staging registers.
+  auto stage = [&](auto split_tag, auto load_tag, int buf, int nbuf, int kt_next) {
+    constexpr bool SPLIT = decltype(split_tag)::value;
+    constexpr bool LOAD = decltype(load_tag)::value;
+    bf16x8 fb[3][FN];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) fb[p][b] = Bs[buf][p][g][swz_b<EB>(wn * WN + b * TM + t)];
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      bf16x8 fa[3];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) fa[p] = As[buf][p][g][swz_a<BKC>(wm * WM + a * TM + t, g)];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[1], fb[1][b], acc[a][b]);  // lo  * lo
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[2], fb[0][b], acc[a][b]);  // res * hi
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[0], fb[2][b], acc[a][b]);  // hi  * res
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[1], fb[0][b], acc[a][b]);  // lo  * hi
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[0], fb[1][b], acc[a][b]);  // hi  * lo
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[0], fb[0][b], acc[a][b]);  // hi  * hi
+      if constexpr (SPLIT) {
+#pragma unroll
+        for (int j = 0; j < NPART; ++j)
+          if (j * (FM / 2) / NPART == a) split_part(nbuf, j);
+      }
+      if constexpr (LOAD) {
+        if (a == FM / 2 - 1) load_full(kt_next);
+      }
+    }
+  };
+  typedef std::integral_constant<bool, true> yes;
+  typedef std::integral_constant<bool, false> no;
+
+  const bool interior = avec && bvec && (i0 + BM <= av.vrows) && (j0 + BN <= bv.vcols) && (K % BK == 0) &&
+                        (K <= av.vcols) && (K <= bv.vrows);
+  if (ktiles > 0 && interior) {
+    load_full(0);
+#pragma unroll
+    for (int j = 0; j < NPART; ++j) split_part(0, j);
+    if (ktiles > 1) load_full(1);
+    __syncthreads();
+    int kt = 0;
+    for (; kt + 2 < ktiles; ++kt) {
+      stage(yes{}, yes{}, kt & 1, (kt & 1) ^ 1, kt + 2);
+      __syncthreads();
+    }
+    if (kt + 1 < ktiles) {
+      stage(yes{}, no{}, kt & 1, (kt & 1) ^ 1, 0);
+      __syncthreads();
+      ++kt;
+    }
+    stage(no{}, no{}, kt & 1, 0, 0);
+  } else if (ktiles > 0) {
+    for (int kt = 0; kt < ktiles; ++kt) {
+      load_masked(kt);
+#pragma unroll
+      for (int j = 0; j < NPART; ++j) split_part(0, j);
+      __syncthreads();
+      stage(no{}, no{}, 0, 0, 0);
+      __syncthreads();
+    }
+  }
+
+  store_outputs<float, TM, 16, FM, FN, WM, WN>(kb, D, i0, j0, wm, wn, lane, acc,
+                                               [](int l, int r) { return row32(l, r); });
+}
+
 // The same products from operands already split by the split pass (SPL
 // layout, desc.h): a is the m x k A operand, b the n x k transpose of the B
 // operand, each a run of 48-byte chunks (hi, lo, res of 8 consecutive k).
@@ -485,6 +728,13 @@ hipError_t launch_spl(const KernelBases& kb, const GemmDesc* d, int n, int tiles
   return hipGetLastError();
 }
 
+template <int BM, int BN, int WGM, int WGN, int EBB>
+hipError_t launch_pipe(const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_bf16p_kernel<BM, BN, WGM, WGN, EBB>), dim3(tiles), dim3(64 * WGM * WGN), 0, s, kb, d,
+                     n, remap);
+  return hipGetLastError();
+}
+
 template <int BM, int BN, int BKC, int WGM, int WGN, bool LATE = false>
 hipError_t launch_cfg(const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap, hipStream_t s) {
   hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN, BKC, WGM, WGN, LATE>), dim3(tiles), dim3(64 * WGM * WGN), 0, s,
@@ -512,6 +762,7 @@ GemmCfg gemm_bf16x3_cfg(int cfg) {
     case 1: return {256, 128};
     case 3: return {256, 256};
     case 4: return {64, 128};
+    case 6: return {256, 256};
     case 8: return {64, 64};
     default: return {128, 128};
   }
@@ -527,6 +778,8 @@ hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d,
     case 1: return launch_cfg<256, 128, 4, 4, 2, true>(kb, d, n, tiles, remap, s);
     case 3: return launch_cfg<256, 256, 2, 4, 2, true>(kb, d, n, tiles, remap, s);
     case 4: return launch_cfg<64, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
+    // eight waves of 128 x 64, split pipelined under the MFMAs
+    case 6: return launch_pipe<256, 256, 2, 4, 1>(kb, d, n, tiles, remap, s);
     // small products: one 32x32 tile per wave
     case 8: return launch_cfg<64, 64, 4, 2, 2>(kb, d, n, tiles, remap, s);
     default: return launch_cfg<128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);

@@ -181,7 +181,9 @@ int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
       t128 += ceil_div(g.m, 128) * ceil_div(g.n, 128);
       t64x128 += ceil_div(g.m, 64) * ceil_div(g.n, 128);
     }
-    if (kdtype == DT_BF16X3 && t2x2 >= 512) return 3;
+    // (the in-loader split's 256x256 tile: the pipelined eight-wave kernel,
+    // measured 9 % faster than the other 256x256 kernel at n = 8192)
+    if (kdtype == DT_BF16X3 && t2x2 >= 512) return 6;
     if (t256 >= 256) return 1;
     if (t128 >= 256) return 0;
     // (the in-loader split kernel also has 64x64 tiles for small products)
@@ -714,7 +716,7 @@ struct Builder {
     // tile runs one wave per SIMD, so 64x128 is the default below 256x256
     if (fused && cfg != 3 && (cfg != 0 || P.tile_cfg < 0)) cfg = 4;
     if (P.tile_cfg < 0 && equal && !fused && (kd == DT_F32 || kd == DT_F32_BT) && (cfg == 0 || cfg == 3)) {
-      const int p3 = split_for_rounds(group);
+      const int p3 = split_for_rounds(group, 0.87, 0.84);
       if (p3 > 0 && p3 < (int)group.size()) {
         std::vector<GemmDesc> big(group.begin(), group.begin() + p3), small(group.begin() + p3, group.end());
         emit_gemm_cfg(big, false, 3, true, kd);
@@ -722,20 +724,31 @@ struct Builder {
         return;
       }
     }
+    if (P.tile_cfg < 0 && equal && kd == DT_BF16X3 && cfg == 6) {
+      // split-bfloat16: the pipelined 256x256 tile and the 128x128 tile
+      // (measured MFMA fractions 0.54 and about 0.45)
+      const int p6 = split_for_rounds(group, 0.54, 0.45);
+      if (p6 > 0 && p6 < (int)group.size()) {
+        std::vector<GemmDesc> big(group.begin(), group.begin() + p6), small(group.begin() + p6, group.end());
+        emit_gemm_cfg(big, false, 6, true, kd);
+        emit_gemm_cfg(small, false, 0, true, kd);
+        return;
+      }
+    }
     emit_gemm_cfg(group, fused, cfg, equal, kd);
   }
 
-  // Equal float32 problems on the eight-wave tiles (one workgroup per CU):
-  // how many of them to give 256x256 tiles, the rest 128x128, so that both
-  // launches fill whole rounds of 256 workgroups.  Time model per problem
-  // class: rounds x tile work / measured tile efficiency (0.87 for 256x256,
-  // 0.84 for 128x128).  Returns the count, or -1 when one tile shape for
-  // all is as good.
-  static int split_for_rounds(const std::vector<GemmDesc>& group) {
+  // Equal problems on the eight-wave tiles (one workgroup per CU): how many
+  // of them to give 256x256 tiles, the rest 128x128, so that both launches
+  // fill whole rounds of 256 workgroups.  Time model per problem class:
+  // rounds x tile work / measured tile efficiency (e256 for 256x256, e128
+  // for 128x128; float32: 0.87 and 0.84).  Returns the count, or -1 when one
+  // tile shape for all is as good.
+  static int split_for_rounds(const std::vector<GemmDesc>& group, double e256, double e128) {
     const int64_t P = (int64_t)group.size();
     const int64_t m = group[0].m, n = group[0].n;
     const int64_t T3 = ceil_div(m, 256) * ceil_div(n, 256), T0 = ceil_div(m, 128) * ceil_div(n, 128);
-    const double t3 = 256.0 * 256.0 / 0.87, t0 = 128.0 * 128.0 / 0.84;
+    const double t3 = 256.0 * 256.0 / e256, t0 = 128.0 * 128.0 / e128;
     auto cost = [&](int64_t p) {
       return (double)ceil_div(p * T3, 256) * t3 + (double)ceil_div((P - p) * T0, 256) * t0;
     };
