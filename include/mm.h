@@ -206,11 +206,12 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                                level's fused forms (MM_PLAN_LEAF_U, MM_PLAN_SPLIT_PASS) take
                                precedence; it takes precedence over MM_PLAN_FUSE. */
 #define MM_PLAN_UNROLL_BASE 0x100000u /* Strassen-Winograd, grouped schedule, float32 / float64: when the
-                                         leaves are of order 1, 2 or 4 (the recursion run down to tiny
-                                         blocks, as in Section 3's experiments), compute them with the
-                                         unrolled base cases (one thread per leaf, the 22-operation form
-                                         unrolled to scalars in registers) instead of MFMA tiles.  Gives
-                                         the same bits as the plan with log2(order) more levels. */
+                                         leaves are of order 1, 2, 4 or 8 (the recursion run down to tiny
+                                         blocks, as in Section 3's experiments with win2x2, win4x4 and
+                                         win8x8), compute them with the unrolled base cases (one thread
+                                         per leaf, the 22-operation form unrolled to scalars in
+                                         registers) instead of MFMA tiles.  Gives the same bits as the
+                                         plan with log2(order) more levels. */
 #define MM_PLAN_PEEL 64u /* grouped schedule: instead of reading A, B and C as if zero-padded to
                            multiples of 2^L g, run the recursion on the largest leading block
                            whose sides are such multiples (pm x pk times pk x pn) and cover

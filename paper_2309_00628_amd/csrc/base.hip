@@ -1,8 +1,10 @@
-// Unrolled base cases of the Strassen-Winograd recursion: each thread
-// computes one small leaf product C = A B (order S = 1, 2 or 4) entirely in
-// registers by the 22-operation form of Section 2.3, unrolled down to
-// scalars (S = 4: two levels, the seven 2 x 2 products each unrolled once
-// more).  The sums and products are taken in the order the grouped schedule
+// Unrolled base cases of the Strassen-Winograd recursion (the paper's
+// win2x2, win4x4 and win8x8 of Section 3): each thread computes one small
+// leaf product C = A B (order S = 1, 2, 4 or 8) in registers by the
+// 22-operation form of Section 2.3, unrolled down to scalars (S = 4: two
+// levels, the seven 2 x 2 products each unrolled once more; S = 8: three
+// levels, 343 scalar products, held partly in scratch: the 8 x 8 case is for
+// completeness and exactness, not speed).  The sums and products are taken in the order the grouped schedule
 // uses level by level, so a plan whose leaves are of order S gives the same
 // bits as the plan with log2(S) more levels and scalar leaves.
 //
@@ -120,6 +122,7 @@ hipError_t launch_t(int s, const KernelBases& kb, const BaseDesc* d, int count, 
   switch (s) {
     case 1: hipLaunchKernelGGL((base_kernel<T, 1>), dim3(blocks), dim3(kThreads), 0, st, kb, d, count); break;
     case 2: hipLaunchKernelGGL((base_kernel<T, 2>), dim3(blocks), dim3(kThreads), 0, st, kb, d, count); break;
+    case 8: hipLaunchKernelGGL((base_kernel<T, 8>), dim3(blocks), dim3(kThreads), 0, st, kb, d, count); break;
     default: hipLaunchKernelGGL((base_kernel<T, 4>), dim3(blocks), dim3(kThreads), 0, st, kb, d, count); break;
   }
   return hipGetLastError();

@@ -33,7 +33,7 @@ hipError_t launch_gemm_bf16s(int cfg, const KernelBases& kb, const GemmDesc* d, 
                              int remap, hipStream_t s);
 // Split passes (EW_SPLIT, EW_WINO_S_SPL, EW_WINO_T_SPL parts; rows x cols is
 // the float32 input block, transposed = mode[0]).
-// Unrolled base cases: count leaves of order s (1, 2 or 4) in one launch.
+// Unrolled base cases: count leaves of order s (1, 2, 4 or 8) in one launch.
 int base_blocks(int count);
 hipError_t launch_base(int dtype, int s, const KernelBases& kb, const BaseDesc* d, int count, int blocks,
                        hipStream_t st);

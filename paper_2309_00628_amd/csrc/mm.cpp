@@ -95,7 +95,7 @@ struct Plan {
   bool accumulate = false;  // C <- A B + beta C (beta given per execution)
   bool peel = false;        // grouped: peel ragged rows / columns / k instead of padding
   bool trans_b = false;     // grouped Winograd float32: last-level B operands stored transposed
-  bool unroll_base = false; // grouped Winograd: leaves of order 1, 2, 4 by the unrolled base cases
+  bool unroll_base = false; // grouped Winograd: leaves of order 1, 2, 4, 8 by the unrolled base cases
   int split_k = 1;          // plain product: k split over this many partial products
   bool persistent = false;  // batched: one persistent launch (OP_PERSIST)
   int pcount = 0;           // ... its counters (besides PC_FIRST fixed ones)
@@ -1244,12 +1244,12 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
       if (plain(s)) b.gemm(s.A, s.B, {Builder::store(s.C)}, s.akind, s.bkind, s.fusable);
     b.join();
   }
-  // unrolled base cases for leaves of order 1, 2 or 4 (all leaves of a
+  // unrolled base cases for leaves of order 1, 2, 4 or 8 (all leaves of a
   // grouped level have the same order)
   int base_order = 0;
   if (b.P.unroll_base && !subs.empty()) {
     const int64_t o = subs[0].A.rows;
-    base_order = (o == 1 || o == 2 || o == 4) ? (int)o : 0;
+    base_order = (o == 1 || o == 2 || o == 4 || o == 8) ? (int)o : 0;
     for (const Sub& s : subs)
       if (s.A.rows != o || s.A.cols != o || s.B.cols != o || s.akind != OK_PLAIN || s.bkind != OK_PLAIN || s.spl)
         base_order = 0;

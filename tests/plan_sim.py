@@ -407,7 +407,7 @@ def operand(M, kind):
 
 def unrolled_winograd(a, b):
     """The 22-operation form of Section 2.3 applied down to scalars (orders
-    1, 2, 4): what an unrolled base case computes."""
+    1, 2, 4, 8): what an unrolled base case computes."""
     n = a.shape[0]
     if n == 1:
         return a * b

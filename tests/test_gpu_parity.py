@@ -8,6 +8,7 @@ computes a sample of rows, which it does exactly as it would in the full
 product.
 """
 import ctypes
+import itertools
 
 import numpy as np
 import pytest
@@ -605,14 +606,15 @@ def test_transposed_b_bitwise(api, naive, m, n, k, levels):
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 def test_unrolled_base_case_bitwise(api, naive, dt):
-    # leaves of order 2 and 4 by the unrolled base case give the bits of the
-    # plan recursing to scalar leaves (1x1 MFMA products)
+    # leaves of order 8, 4 and 2 by the unrolled base case (win8x8, win4x4,
+    # win2x2) give the bits of the plan recursing to scalar leaves (1x1 MFMA
+    # products), i.e. of the plan with three, two and one more levels
     npdt = np.float64 if dt == "f64" else np.float32
     n = 64
     A, B = inputs.pair("uniform", n, n, n, 59, npdt)
     At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
     ref = api.mm(At, Bt, algo="winograd", sched="grouped", cutoff=1, levels=6)
-    for lv in (4, 5, 6):
+    for lv in (3, 4, 5, 6):
         p = api.Plan("winograd", "grouped", n, n, n, cutoff=1, levels=lv, dtype=dt, unroll_base=True)
         assert "LAUNCH BASE" in p.describe()
         C = torch.full((n, n), float("nan"), dtype=At.dtype, device="cuda")
@@ -626,10 +628,12 @@ def test_unrolled_base_case_bitwise(api, naive, dt):
     err = rel_fro(ref.cpu().numpy(), naive.gemm(A, B))
     print(f"unrolled base {dt}: six-level error {err:.3e}", flush=True)
     assert err < (1e-11 if dt == "f64" else 1e-4)
-    tol = 1e-12 if dt == "f64" else 1e-5
-    # ragged (virtual padding): against the oracle, and exact on integers
-    m, n2, k = 28, 30, 26
-    for kind in ("uniform", "int"):
+    # ragged (virtual padding; leaves of order 4 and 8, i.e. five and six
+    # levels down to scalars): against the oracle, the six-level case with
+    # the deep plan's slack, and exact on integers
+    for (m, n2, k), kind in itertools.product(((28, 30, 26), (60, 62, 58)), ("uniform", "int")):
+        deep = m > 32
+        tol = (1e-11 if deep else 1e-12) if dt == "f64" else (1e-4 if deep else 1e-5)
         A, B = inputs.pair(kind, m, n2, k, 60, npdt)
         got = gpu_mm(api, A, B, algo="winograd", sched="grouped", cutoff=1, levels=3, dtype=dt)
         p = api.get_plan("winograd", "grouped", m, n2, k, 1, 3, dt, k, n2, n2, False, torch.device("cuda"))

@@ -538,9 +538,9 @@ def test_transposed_b_plan_shape(lib):
 
 
 @pytest.mark.parametrize("m,n,k,levels", [(8, 8, 8, 2), (8, 8, 8, 3), (16, 16, 16, 3), (32, 32, 32, 3),
-                                          (28, 30, 26, 3)])
+                                          (28, 30, 26, 3), (16, 16, 16, 1), (64, 64, 64, 3), (60, 62, 58, 3)])
 def test_unrolled_base_case_plan_is_exact(lib, m, n, k, levels):
-    # MM_PLAN_UNROLL_BASE: leaves of order 1, 2 or 4 by the unrolled base case
+    # MM_PLAN_UNROLL_BASE: leaves of order 1, 2, 4 or 8 by the unrolled base case
     A = inputs.integers((m, k), 57, dtype=np.int64)
     B = inputs.integers((k, n), 58, dtype=np.int64)
     text, info = L.describe("winograd", "grouped", m, n, k, cutoff=1, levels=levels, dtype="f32",
@@ -558,6 +558,10 @@ def test_unrolled_base_case_only_for_tiny_leaves(lib):
     assert "BASE" not in text and "LAUNCH GEMM" in text
     text, _ = L.describe("winograd", "grouped", 64, 64, 64, cutoff=1, levels=4, dtype="f64", unroll_base=True)
     assert [l.split()[4] for l in text.splitlines() if l.startswith("LAUNCH BASE")] == ["4"]
+    text, _ = L.describe("winograd", "grouped", 64, 64, 64, cutoff=1, levels=3, dtype="f64", unroll_base=True)
+    assert [l.split()[4] for l in text.splitlines() if l.startswith("LAUNCH BASE")] == ["8"]
+    text, _ = L.describe("winograd", "grouped", 128, 128, 128, cutoff=1, levels=3, unroll_base=True)
+    assert "BASE" not in text              # leaves of 16: MFMA tiles
 
 
 def test_plan_flag_fields_are_disjoint():
