@@ -245,9 +245,9 @@ def pct(xs, q):
 
 
 def run_product(torch, api, L, algo, sched, n, levels, A, B, steps, warmup, dtype="f32", tile=None,
-                overlap=False, leaf_u=False, trans_b=False, split_k=None):
+                overlap=False, leaf_u=False, trans_b=False, split_k=None, pad_to=None):
     plan = api.Plan(algo, sched, n, n, n, cutoff=1, levels=levels, dtype=dtype, tile=tile, overlap=overlap,
-                    leaf_u=leaf_u, trans_b=trans_b, split_k=split_k)
+                    leaf_u=leaf_u, trans_b=trans_b, split_k=split_k, pad_to=pad_to)
     ws = torch.empty(max(plan.ws_bytes, 256), dtype=torch.uint8, device=A.device)
     C = torch.empty((n, n), dtype=A.dtype, device=A.device)
     wall, step_ms, per_op, kinds = time_plan(torch, api, L, plan, A, B, C, ws, steps, warmup)
@@ -572,10 +572,11 @@ def bench_fp64_small(torch, api, L, inputs, n=512, cutoff=64, steps=50, warmup=1
 
 def bench_d2(torch, api, L, inputs, tuner, with_ref=True):
     """Square float32 n = 4096 and n = 3000 (not a power of two; with L <= 3
-    levels 3000 = 8 * 375 needs no padding): the plain MFMA GEMM, then
-    Strassen-Winograd and Strassen at one and two levels, each with its
-    relative error against the oracle on sampled rows (first and last row
-    included)."""
+    levels 3000 = 8 * 375 needs no padding beyond the vector width): the
+    plain MFMA GEMM, then Strassen-Winograd and Strassen at one and two
+    levels, and for n = 3000 Winograd padded to 3072 at one to three levels,
+    each with its relative error against the oracle on sampled rows (first
+    and last row included)."""
     import numpy as np
     out = {}
     arrays = {}
@@ -602,6 +603,17 @@ def bench_d2(torch, api, L, inputs, tuner, with_ref=True):
                     e[name]["rel_err"] = rel_err(r["C"], rows, ref)
             e[f"winograd_L{lv}"]["speedup_vs_plain"] = round(w2["tflops"] / p2["tflops"], 4)
             del w2, s2
+        if n2 == 3000:
+            # the same product zero-padded (virtually) to 3072 = 3 x 2^10, so
+            # that the leaves are multiples of the tile edges
+            for lv in (1, 2, 3):
+                r = run_product(torch, api, L, "winograd", "grouped", n2, lv, A2, B2, 20, 10, pad_to=1024)
+                e[f"winograd_L{lv}_pad3072"] = {"tflops": round(r["tflops"], 3), "p50_ms": round(r["p50"], 4),
+                                                "padded_order": r["plan"].info.get("M"),
+                                                "speedup_vs_plain": round(r["tflops"] / p2["tflops"], 4)}
+                if with_ref:
+                    e[f"winograd_L{lv}_pad3072"]["rel_err"] = rel_err(r["C"], rows, ref)
+                del r
         out[str(n2)] = e
         arrays[n2] = (A2_np, B2_np, A2, B2, rows, ref)
         print(f"# d2 n={n2}: {e}", file=sys.stderr, flush=True)

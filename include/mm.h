@@ -234,6 +234,14 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                                        found, so mm_batched_plan_create returns MM_E_UNSUPPORTED for it;
                                        the host-only calls (mm_batched_describe, mm_batched_table) still
                                        build it, for checking its task queue. */
+/* Recursive plans: pad m, n and k up to multiples of 2^q as well as of 2^L
+ * (q = 0 .. 15; 0: no extra padding).  For example MM_PLAN_PAD(7) takes
+ * n = 3000 to 3072, giving leaves of 1536 / 768 / 384 (tile multiples)
+ * instead of 1500 / 750 / 375 (Section 3.1 pads to a power of two; 3000 needs
+ * no padding at all for up to three levels).  The grouped schedule pads
+ * virtually (no copies); the depth-first schedules copy.  Ignored with
+ * MM_PLAN_PEEL and for zero levels. */
+#define MM_PLAN_PAD(q) (((unsigned)(q) & 0xfu) << 24)
 /* Plain product (MM_ALGO_NAIVE, or a recursion of zero levels): split k into
  * s parts (2 .. 8, each a multiple of 64 long), run the s partial products
  * in one grouped launch into workspace blocks and sum them in order in one

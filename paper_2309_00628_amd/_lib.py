@@ -37,6 +37,17 @@ def plan_split_k(s):
     return 0 if not s or s <= 1 else (int(s) & 0xF) << 16
 
 
+def plan_pad(mult):
+    """MM_PLAN_PAD(q) flag bits for padding to a multiple of ``mult`` (a
+    power of two; None or 1: no extra padding)."""
+    if not mult or mult <= 1:
+        return 0
+    q = int(mult).bit_length() - 1
+    if 1 << q != int(mult) or q > 15:
+        raise ValueError("pad multiple must be a power of two up to 2^15")
+    return q << 24
+
+
 def plan_tile(c):
     """MM_PLAN_TILE(c) flag bits (0 when c is None: planner's choice)."""
     return 0 if c is None else ((int(c) + 1) << 8)
@@ -136,7 +147,7 @@ def check(status):
 
 def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None, ldc=None,
              fuse=False, overlap=False, leaf_u=False, split_pass=False, accumulate=False, tile=None,
-             peel=False, trans_b=False, unroll_base=False, split_k=None):
+             peel=False, trans_b=False, unroll_base=False, split_k=None, pad_to=None):
     """Host-only plan listing and facts (no device needed)."""
     lib = load()
     lda = max(k, 1) if lda is None else lda
@@ -148,7 +159,7 @@ def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, l
             (MM_PLAN_LEAF_U if leaf_u else 0) | (MM_PLAN_SPLIT_PASS if split_pass else 0) |
             (MM_PLAN_ACCUMULATE if accumulate else 0) | (MM_PLAN_PEEL if peel else 0) |
             (MM_PLAN_TRANS_B if trans_b else 0) | (MM_PLAN_UNROLL_BASE if unroll_base else 0) | plan_split_k(split_k) |
-            plan_tile(tile))
+            plan_tile(tile) | plan_pad(pad_to))
     need = lib.mm_describe(*args, None, 0, info, NINFO)
     if need == 0:
         raise MMError(1, last_error())

@@ -97,6 +97,7 @@ struct Plan {
   bool trans_b = false;     // grouped Winograd float32: last-level B operands stored transposed
   bool unroll_base = false; // grouped Winograd: leaves of order 1, 2, 4, 8 by the unrolled base cases
   int split_k = 1;          // plain product: k split over this many partial products
+  int64_t pad_mult = 1;     // recursive plans: pad m, n, k to multiples of this too (MM_PLAN_PAD)
   bool persistent = false;  // batched: one persistent launch (OP_PERSIST)
   int pcount = 0;           // ... its counters (besides PC_FIRST fixed ones)
   int pgrid = 0;            // ... its workgroups (as many as fit at once)
@@ -1433,9 +1434,10 @@ int build_plan(Plan& P) {
   const int64_t step = (int64_t)1 << P.L;
   int64_t g = 1;
   if (P.sched == MM_SCHED_GROUPED && P.L > 0 && std::min(std::min(m, n), k) / step >= 32) g = b.E;
-  P.M = round_up(m, step * g);
-  P.N = round_up(n, step * g);
-  P.K = round_up(k, step * g);
+  const int64_t mult = std::max<int64_t>(step * g, P.pad_mult);
+  P.M = round_up(m, mult);
+  P.N = round_up(n, mult);
+  P.K = round_up(k, mult);
   // Peeling: the recursion runs on the largest leading block whose sides are
   // multiples of 2^L g and thin products cover the rest (when every side of
   // that block is nonempty; otherwise the plan pads).
@@ -1848,6 +1850,7 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   P->trans_b = (flags & MM_PLAN_TRANS_B) != 0 && dtype == MM_F32 && algo == MM_ALGO_WINOGRAD &&
                resolve_sched(algo, sched) == MM_SCHED_GROUPED;
   P->split_k = (int)((flags >> 16) & 0xf);
+  P->pad_mult = (int64_t)1 << ((flags >> 24) & 0xf);
   if (P->split_k > 8) return fail(MM_E_INVALID, "MM_PLAN_SPLIT_K allows at most 8 parts");
   if (P->split_k < 1) P->split_k = 1;
   P->unroll_base = (flags & MM_PLAN_UNROLL_BASE) != 0 && dtype != MM_BF16X3_REFINED &&

@@ -186,3 +186,28 @@ def test_batched_workload_graph_replay(api, naive):
         ratio = elem_ratio(got, ref, A, B, rows, lv, M, N)
         assert err < 1e-5, (i, shapes[i], lv, err)
         assert ratio < elem_bound(lv), (i, shapes[i], lv, ratio)
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_fp32_3000_padded_to_3072(api, naive, levels):
+    """n = 3000 zero-padded (virtually) to 3072 (MM_PLAN_PAD): within
+    tolerance of the oracle on sampled rows, first and last included, and
+    no element of the padding written."""
+    n = 3000
+    A, B = inputs.pair("uniform", n, n, n, 44, np.float32)
+    rows = np.unique(np.r_[0, inputs.rng(45).choice(n, 30, replace=False), n - 1])
+    ref = naive.gemm_rows(A, B, rows)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    p = api.Plan("winograd", "grouped", n, n, n, cutoff=1, levels=levels, pad_to=1024, ldc=n + 16)
+    assert p.info["M"] == 3072
+    Cw = torch.full((n, n + 16), 7.0, device="cuda")
+    C = Cw[:, :n]
+    ws = torch.empty(max(p.ws_bytes, 256), dtype=torch.uint8, device="cuda")
+    p(At, Bt, C, ws)
+    torch.cuda.synchronize()
+    got = C[torch.from_numpy(rows).cuda()].cpu().numpy()
+    err = rel_fro(got, ref)
+    print(f"n=3000 padded to 3072 L={levels}: rel err {err:.3e}", flush=True)
+    assert err < 1e-5
+    assert bool(torch.all(Cw[:, n:] == 7.0))
+    assert elem_ratio(got, ref, A, B, rows, levels, 3072, 3072) < elem_bound(levels)

@@ -565,20 +565,21 @@ def test_unrolled_base_case_only_for_tiny_leaves(lib):
 
 
 def test_plan_flag_fields_are_disjoint():
-    # the single-bit options, the tile field MM_PLAN_TILE (bits 8-15) and the
-    # k-split field MM_PLAN_SPLIT_K (bits 16-19) of include/mm.h share no bit
+    # the single-bit options, the tile field MM_PLAN_TILE (bits 8-15), the
+    # k-split field MM_PLAN_SPLIT_K (bits 16-19) and the padding field
+    # MM_PLAN_PAD (bits 24-27) of include/mm.h share no bit
     import re
     hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mm.h")).read()
     bits = {name: int(v, 0) for name, v in re.findall(r"#define (MM_PLAN_[A-Z_]+) (0x[0-9a-fA-F]+|[0-9]+)u", hdr)}
     assert len(bits) >= 9
-    fields = {"TILE": 0xff << 8, "SPLIT_K": 0xf << 16}
+    fields = {"TILE": 0xff << 8, "SPLIT_K": 0xf << 16, "PAD": 0xf << 24}
     seen = 0
     for name, b in list(bits.items()) + list(fields.items()):
         assert b and seen & b == 0, name
         seen |= b
     for name, b in bits.items():
         assert getattr(L, name) == b, name
-    assert L.plan_tile(7) == 8 << 8 and L.plan_split_k(8) == 8 << 16
+    assert L.plan_tile(7) == 8 << 8 and L.plan_split_k(8) == 8 << 16 and L.plan_pad(128) == 7 << 24
 
 
 def test_tile_choice_and_unrolled_base_are_independent(lib):
@@ -763,3 +764,29 @@ def test_batched_null_levels_follow_the_size_classes(lib):
     addrs = [(4096 * (3 * i + 1), 4096 * (3 * i + 2), 4096 * (3 * i + 3)) for i in range(len(shapes))]
     _, info = L.batched_describe(shapes, [(a << 20, b << 20, c << 20) for a, b, c in addrs])
     assert info["leaves"] == sum(7 ** lv for lv in got)
+
+
+@pytest.mark.parametrize("sched", ["grouped", "two_temp"])
+def test_pad_to_a_multiple_is_exact(lib, sched):
+    """MM_PLAN_PAD: n = 3000 needs no padding for up to three levels (the
+    grouped schedule rounds to 2^L times the 16-byte vector width: 3008),
+    and with the flag pads to 3072 (multiples of 2^7); the padded plans are
+    exact on integers (simulated), for the virtual padding of the grouped
+    schedule and the copies of the depth-first one."""
+    _, info = L.describe("winograd", "two_temp", 3000, 3000, 3000, cutoff=1, levels=3)
+    assert info["M"] == 3000 and info["leaf_rows"] == 375
+    _, info = L.describe("winograd", "grouped", 3000, 3000, 3000, cutoff=1, levels=3)
+    assert info["M"] == 3008 and info["leaf_rows"] == 376
+    _, info = L.describe("winograd", "grouped", 3000, 3000, 3000, cutoff=1, levels=3, pad_to=128)
+    assert info["M"] == info["N"] == info["K"] == 3072 and info["leaf_rows"] == 384
+    _, info = L.describe("winograd", "grouped", 3000, 3000, 3000, cutoff=1, levels=0, pad_to=128)
+    assert info["M"] == 3000                       # no levels: nothing to pad
+    m, n, k = 40, 36, 44
+    A = inputs.integers((m, k), 71, dtype=np.int64)
+    B = inputs.integers((k, n), 72, dtype=np.int64)
+    text, info = L.describe("winograd", sched, m, n, k, cutoff=1, levels=2, pad_to=32)
+    assert info["M"] == info["N"] == info["K"] == 64
+    ws = np.full(max(info["ws_bytes"] // 4, 1), 10**9, dtype=np.int64)
+    C = np.full(m * n, -(10**9), dtype=np.int64)
+    plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
+    assert np.array_equal(C.reshape(m, n), A @ B)
