@@ -78,7 +78,7 @@ def elem_ratio(got, ref, A, B, rows, L, M, N):
 # level (every level adds block sums of up to four terms before and after
 # the products).  With uniform inputs |c_ij| / (alpha_i beta_j) ~ 3/sqrt(n),
 # so at n = 8192 the plain product's bound flags a relative error of about
-# 1e-3 in a single element; the observed maxima are listed in the design doc.
+# 1e-3 in a single element; each case prints its observed maximum.
 def elem_bound(L):
     return 64.0 * 2 ** L
 
