@@ -546,6 +546,154 @@ struct TileLoop {
     }
   }
 
+  // Interior tiles whose operands both load straight into LDS (plain A,
+  // float32 B as it lies in memory).  Two LDS stages of BK k values.  An MFMA
+  // step is one k value of every MFMA tile of the wave (FM x FN MFMAs); a
+  // stage holds KB * E steps.  The fragments of step i+1 are read while the
+  // MFMAs of step i run (two register sets, alternating with the step; A's
+  // chunk covers the E steps of a k-block, B's read one step).  The loads of
+  // stage t+1 are issued one per step during the first steps of stage t,
+  // between MFMAs (issued together right after the barrier they held the
+  // waves up at their issue); they go into the buffer freed by the barrier of
+  // stage t-1.  The barrier that hands a stage over sits before the stage's
+  // last step, once every wave holds that step's fragments and its own loads
+  // of the next stage have landed; the next stage's first fragments are read
+  // while the last MFMAs of this one run.  No wave waits for LDS with an
+  // empty matrix pipeline.  The same MFMAs in the same order as the other
+  // loops: the bits do not change.
+  //
+  // The loads are buffer loads (a resource over the stage's first element,
+  // 32-bit per-lane byte offsets fixed for the whole loop): the compiler then
+  // counts the fragment reads exactly (with the global form it waits for
+  // every outstanding LDS read), and the per-stage address arithmetic is
+  // scalar.  Row offsets must fit in 32 bits: leading dimensions below
+  // kDirectLdMax.  The barrier is a bare s_barrier after an explicit wait.
+  static constexpr int64_t kDirectLdMax = int64_t(1) << 21;
+  static constexpr int DPA = BM * BKC / NT, DPB = BN * BKC / NT;  // loads per lane per stage
+  // Whether operands of kinds KA, KB2 take this loop in interior tiles.
+  template <int KA, int KB2>
+  static constexpr bool direct_kind() {
+    return KA == OK_PLAIN && KB2 == OK_PLAIN && NATF && DMA_A && DMA_B && KB % 2 == 0 && DPA + DPB < KB * E &&
+           DPA * NT == BM * BKC && DPB * NT == BN * BKC;
+  }
+  static __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const T* p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), 0, -1, 0x00020000);
+  }
+  static __device__ __forceinline__ __attribute__((address_space(3))) void* lds(const chunk_t* p) {
+    return (__attribute__((address_space(3))) void*)(p);
+  }
+  static __device__ __forceinline__ void bare_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  }
+  static __device__ __forceinline__ void main_loop_direct(Smem& sm, const Operand<T>& A, const Operand<T>& B,
+                                                          int i0, int j0, int ktiles, Acc& acc) {
+    static_assert(direct_kind<OK_PLAIN, OK_PLAIN>(),
+                  "float32, whole loads per lane, even k-blocks per stage, a stage's loads spread over all but "
+                  "its last step");
+    constexpr int STEPS = KB * E;
+    constexpr int CPR = BN / E;
+    typedef FVec<FN> FV;
+    typedef typename FV::type bv_t;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int g = lane / TM, t = lane % TM;
+    // byte offsets of this lane's chunks in a stage (A in a_idx order, B as
+    // it lies in memory), from the stage's first element
+    uint32_t oa[DPA], ob[DPB];
+#pragma unroll
+    for (int i = 0; i < DPA; ++i) {
+      const int p = (wave * DPA + i) * 64 + lane;
+      const int row = p / BKC, slot = p % BKC;
+      const int kc = slot ^ ((row / (16 / BKC)) & (BKC - 1));
+      oa[i] = (uint32_t)(((int64_t)row * A.ld + kc * E) * (int64_t)sizeof(T));
+    }
+#pragma unroll
+    for (int i = 0; i < DPB; ++i) {
+      const int p = (wave * DPB + i) * 64 + lane;
+      ob[i] = (uint32_t)(((int64_t)(p / CPR) * B.ld + (p % CPR) * E) * (int64_t)sizeof(T));
+    }
+    // load i (0 <= i < DPA + DPB: A's first) of this lane's share of stage
+    // kt, into LDS buffer kt & 1
+    auto load_part = [&](int kt, int i) {
+      const int buf = kt & 1;
+      if (i < DPA) {
+        const __amdgpu_buffer_rsrc_t ra = rsrc(A.p + (int64_t)i0 * A.ld + (int64_t)kt * BK);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, lds(&sm.As[buf][(wave * DPA + i) * 64]), 16, oa[i], 0, 0, 0);
+      } else {
+        const int j = i - DPA;
+        const __amdgpu_buffer_rsrc_t rb = rsrc(B.p + (int64_t)kt * BK * B.ld + j0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, lds(&sm.Bs[buf][(wave * DPB + j) * 64]), 16, ob[j], 0, 0, 0);
+      }
+    };
+    chunk_t fa[2][FM];
+    bv_t fb[2];
+    auto read_a = [&](int buf, int kb2, chunk_t (&xa)[FM]) {
+      const int plane = kb2 * M::KG + g;
+#pragma unroll
+      for (int a = 0; a < FM; ++a) xa[a] = sm.As[buf][a_idx(wm * WM + a * TM + t, plane)];
+    };
+    auto read_b = [&](int buf, int step, bv_t& xb) {
+      const int plane = (step / E) * M::KG + g;
+      const float* Bf = reinterpret_cast<const float*>(&sm.Bs[buf][0]) + wn * WN + FN * t;
+      xb = *reinterpret_cast<const bv_t*>(Bf + (plane * E + step % E) * BN);
+    };
+#pragma unroll
+    for (int i = 0; i < DPA + DPB; ++i) load_part(0, i);
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's part of stage 0 has landed
+    bare_barrier();
+    read_a(0, 0, fa[0]);
+    read_b(0, 0, fb[0]);
+    for (int kt = 0; kt < ktiles; ++kt) {
+      const int buf = kt & 1;
+      const bool more = kt + 1 < ktiles;
+#pragma unroll
+      for (int step = 0; step < STEPS; ++step) {
+        const int kb2 = step / E, s = step % E;
+        const int ca = kb2 & 1, cb = step & 1;
+        // MFMAs [m0, m1) of this step, in the order of the other loops
+        auto mfmas = [&](int m0, int m1) {
+#pragma unroll
+          for (int m = m0; m < m1; ++m)
+            acc[m / FN][m % FN] = M::mfma(fa[ca][m / FN][s], FV::get(fb[cb], m % FN), acc[m / FN][m % FN]);
+        };
+        if (step + 1 < STEPS) {
+          if (s == E - 1) read_a(buf, kb2 + 1, fa[ca ^ 1]);
+          read_b(buf, step + 1, fb[cb ^ 1]);
+          __builtin_amdgcn_sched_barrier(0);
+          if (step < DPA + DPB) {
+            // one load of stage kt+1 per step
+            mfmas(0, (FM * FN) / 2);
+            __builtin_amdgcn_sched_barrier(0);
+            if (more) load_part(kt + 1, step);
+            __builtin_amdgcn_sched_barrier(0);
+            mfmas((FM * FN) / 2, FM * FN);
+          } else {
+            mfmas(0, FM * FN);
+          }
+        } else {
+          // this step's fragments read, stage kt+1 landed (this wave's part)
+          __builtin_amdgcn_s_waitcnt(0);
+          bare_barrier();
+          // half of the step's MFMAs first, so the matrix core has work while
+          // the next stage's first fragments are read
+          mfmas(0, (FM * FN) / 2);
+          __builtin_amdgcn_sched_barrier(0);
+          if (more) {
+            read_a(buf ^ 1, 0, fa[ca ^ 1]);
+            read_b(buf ^ 1, 0, fb[cb ^ 1]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+          mfmas((FM * FN) / 2, FM * FN);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    // Every wave read its last fragments before the last stage's barrier,
+    // and no load is in flight: the LDS may be reused at once.
+  }
+
   // Pipeline: the global loads of stage t+1 are issued first; the stage is
   // written to the other LDS buffer halfway through the MFMAs of stage t, so
   // the wait for those loads and the LDS writes overlap the second half of
@@ -556,6 +704,12 @@ struct TileLoop {
   template <int MODE, int KA, int KB2>
   static __device__ __forceinline__ void main_loop(Smem& sm, const Operand<T>& A, const Operand<T>& B, int i0,
                                                    int j0, int ktiles, Acc& acc) {
+    if constexpr (MODE == LOAD_FULL && direct_kind<KA, KB2>()) {
+      if (A.ld < kDirectLdMax && B.ld < kDirectLdMax) {
+        main_loop_direct(sm, A, B, i0, j0, ktiles, acc);
+        return;
+      }
+    }
     chunk_t ra[NA][popc4(kind_quads(KA))];
     chunk_t rbk[NB][E][popc4(kind_quads(KB2))];  // E rows (k) of E columns, per quadrant
     uint64_t amask = 0, bmask = 0;
