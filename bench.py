@@ -211,6 +211,15 @@ def plan_launches(plan, esz):
         elif w[0] == "WINO":
             m, n, k = map(int, w[1:4])
             flops += 7 * 2.0 * m * n * k
+        elif w[0] == "EW2":
+            # two levels in one pass: S/T read the parent block and write three
+            # quarters of each upper sum and the 28 lower sums; U reads the 49
+            # lower products and writes the four C quadrants
+            kind, R, C = map(int, w[1:4])
+            ekinds.add(("winograd S" if kind == 0 else "winograd T" if kind == 1 else "winograd U")
+                       + " (two levels)")
+            blk = R * C * esz
+            nbytes += (16 + 12 + 28) * blk if kind in (0, 1) else (49 + 16) * blk
         elif w[0] in ("EW", "TRANS"):
             ekinds.add(EW_RECIPES.get(int(w[1]), w[1]) if w[0] == "EW" else "transpose")
             _, ins, outs = [x.strip() for x in line.split("|")]
@@ -338,10 +347,10 @@ def ew_bandwidth(res, n):
     launches = plan_launches(res["plan"], 4)
     out = []
     for lau, d, k in zip(launches, res["per_op"], res["kinds"]):
-        if k % 8 in (0, 6):  # element-wise and transposing passes
+        if k % 8 in (0, 6) or k in (18, 26):  # element-wise, transposing and two-level passes
             ms = sum(d) / len(d)
             gbs = lau["bytes"] / (ms * 1e-3) / 1e9
-            out.append(dict(recipes=lau["recipes"], stream="aux" if k >= 8 else "main", bytes=lau["bytes"],
+            out.append(dict(recipes=lau["recipes"], stream="aux" if k in (8, 14, 26) else "main", bytes=lau["bytes"],
                             ms=round(ms, 4),
                             gbs=round(gbs, 1), hbm_frac=round(gbs / PEAK_HBM_GBS, 3)))
     return out

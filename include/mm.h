@@ -220,6 +220,12 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
                            A[:pm,pk:] B[pk:,:pn], C[:pm,pn:] = A[:pm,:] B[:,pn:], C[pm:,:] =
                            A[pm:,:] B.  No effect when every side is already such a multiple
                            or when a side of the leading block would be empty. */
+#define MM_PLAN_LEVEL_PASSES 0x400000u /* Strassen-Winograd, grouped schedule: one pre-addition
+ * (S/T) and one post-addition (U) pass per recursion level.  By default two
+ * consecutive levels whose blocks are entirely valid (no zero padding) and
+ * split into whole 16-byte chunks share one pass each way, which keeps the
+ * upper level's sums and products in registers instead of HBM (the same
+ * bits); this flag asks for the level-by-level passes instead. */
 #define MM_PLAN_PERSISTENT 0x200000u /* batched plans, MM_F32: run the whole batch -- the S/T passes of
                                        every recursion level, every leaf-product tile and the U passes
                                        of every problem -- as ONE launch of a persistent kernel whose
@@ -296,7 +302,9 @@ int mm_plan_execute_timed(mm_plan_t plan, void* A, void* B, void* C, void* ws, s
  * split-bfloat16 leaves, 6 transposing pass (MM_PLAN_TRANS_B), 7 unrolled base
  * cases (MM_PLAN_UNROLL_BASE); plus 8 when
  * the launch runs on the auxiliary stream; 16 the persistent launch of a
- * whole batch (MM_PLAN_PERSISTENT); -1 if i is out of range. */
+ * whole batch (MM_PLAN_PERSISTENT); 18 (26 on the auxiliary stream) a pass
+ * that forms two recursion levels' pre- or post-additions at once (see
+ * MM_PLAN_LEVEL_PASSES); -1 if i is out of range. */
 int mm_plan_op_kind(mm_plan_t plan, int i);
 
 /* Plan facts: info[0] workspace bytes, [1] levels L, [2..4] padded m, n, k,

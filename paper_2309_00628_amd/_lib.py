@@ -30,6 +30,7 @@ MM_PLAN_PEEL = 64
 MM_PLAN_TRANS_B = 128
 MM_PLAN_UNROLL_BASE = 0x100000
 MM_PLAN_PERSISTENT = 0x200000
+MM_PLAN_LEVEL_PASSES = 0x400000
 
 
 def plan_split_k(s):
@@ -147,7 +148,7 @@ def check(status):
 
 def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None, ldc=None,
              fuse=False, overlap=False, leaf_u=False, split_pass=False, accumulate=False, tile=None,
-             peel=False, trans_b=False, unroll_base=False, split_k=None, pad_to=None):
+             peel=False, trans_b=False, unroll_base=False, split_k=None, pad_to=None, level_passes=False):
     """Host-only plan listing and facts (no device needed)."""
     lib = load()
     lda = max(k, 1) if lda is None else lda
@@ -159,7 +160,7 @@ def describe(algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, l
             (MM_PLAN_LEAF_U if leaf_u else 0) | (MM_PLAN_SPLIT_PASS if split_pass else 0) |
             (MM_PLAN_ACCUMULATE if accumulate else 0) | (MM_PLAN_PEEL if peel else 0) |
             (MM_PLAN_TRANS_B if trans_b else 0) | (MM_PLAN_UNROLL_BASE if unroll_base else 0) | plan_split_k(split_k) |
-            plan_tile(tile) | plan_pad(pad_to))
+            plan_tile(tile) | plan_pad(pad_to) | (MM_PLAN_LEVEL_PASSES if level_passes else 0))
     need = lib.mm_describe(*args, None, 0, info, NINFO)
     if need == 0:
         raise MMError(1, last_error())

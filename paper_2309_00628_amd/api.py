@@ -50,7 +50,7 @@ class Plan:
     def __init__(self, algo, sched, m, n, k, cutoff=1, levels=-1, dtype="f32", lda=None, ldb=None,
                  ldc=None, graph=False, device=None, tile=None, fuse=False, overlap=False, leaf_u=False,
                  split_pass=False, accumulate=False, peel=False, trans_b=False, unroll_base=False,
-                 split_k=None, pad_to=None):
+                 split_k=None, pad_to=None, level_passes=False):
         lib = L.load()
         self.algo, self.sched, self.dtype = algo, sched, dtype
         self.m, self.n, self.k = m, n, k
@@ -72,7 +72,8 @@ class Plan:
                                        (L.MM_PLAN_PEEL if peel else 0) |
                                        (L.MM_PLAN_TRANS_B if trans_b else 0) |
                                        (L.MM_PLAN_UNROLL_BASE if unroll_base else 0) |
-                                       L.plan_split_k(split_k) | L.plan_pad(pad_to),
+                                       L.plan_split_k(split_k) | L.plan_pad(pad_to) |
+                                       (L.MM_PLAN_LEVEL_PASSES if level_passes else 0),
                                        ctypes.byref(self._ptr)))
         self.accumulate = accumulate
         info = (ctypes.c_int64 * L.NINFO)()

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmm.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["mm.cpp", "gemm.hip", "gemm_bf16x3.hip", "gemm_fused.hip", "gemm_wino.hip", "ew.hip", "split.hip", "trans.hip", "base.hip", "noalloc.hip", "batch.hip"]
+SOURCES = ["mm.cpp", "gemm.hip", "gemm_bf16x3.hip", "gemm_fused.hip", "gemm_wino.hip", "ew.hip", "ew2.hip", "split.hip", "trans.hip", "base.hip", "noalloc.hip", "batch.hip"]
 ARCH = "gfx950"
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

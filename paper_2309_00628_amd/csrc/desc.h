@@ -88,6 +88,34 @@ struct EwPart {
   MView out[kEwMaxOut];
 };
 
+// Two consecutive recursion levels of Section 2.3's block form in one pass
+// (grouped schedule, blocks entirely valid).  rows x cols is one block of
+// the lower level (the position grid of the pass); the upper level's blocks
+// are twice that, its parent block four times.
+//  EW2_S (EW2_T): from the parent block X (quadrants A11 A12 A21 A22, or
+//    B11 B12 B21 B22) the sums S1..S4 (T1..T4) of the upper level, kept in
+//    registers and written in `top` only where the lower level reads them as
+//    plain operands (quadrants 11, 12, 22 of an A-side sum; 11, 21, 22 of a
+//    B-side sum), and, for each of the seven operands of the upper level's
+//    products (A11 A12 S4 A22 S1 S2 S3, or B11 B21 B22 T4 T1 T2 T3), its own
+//    sums S1..S4 (T1..T4), written in low[o][0..3].
+//  EW2_U: from the 49 lower-level products (low[q][c]: product c of the
+//    upper-level product q), each upper-level product's four quadrants
+//    (U1 U5 U6 U7 of its seven, in registers), and from those the parent's
+//    C11 C12 C21 C22 (top[0..3]).
+// Per element the operations and their order are those of the two separate
+// passes, so the results are bitwise the same.
+enum Ew2Kind : int32_t { EW2_S = 0, EW2_T = 1, EW2_U = 2 };
+
+struct Ew2Part {
+  int32_t kind;
+  int32_t rows, cols;
+  int32_t blk_start;  // first block of this part in the launch
+  MView x;            // EW2_S / EW2_T: the parent block (2 rows*2 x 2 cols*2)
+  MView top[4];
+  MView low[7][7];    // EW2_S / EW2_T use low[o][0..3]
+};
+
 // GEMM epilogue: out = sign * acc (store), out = d + sign * acc (add), or
 // out = fma(beta, d, sign * acc) (axpby; beta from KernelBases, d not read
 // when beta == 0).

@@ -22,6 +22,11 @@ constexpr int kNumGemmCfg = 9;
 GemmCfg gemm_cfg(int dtype, int cfg);
 
 int ew_blocks(int rows, int cols, int dtype);
+// Two recursion levels of pre- or post-additions in one pass (ew2.hip): the
+// blocks of parts of rows x cols lower-level positions, and the launch.
+int ew2_blocks(int rows, int cols, int dtype);
+hipError_t launch_ew2(int dtype, const KernelBases& kb, const Ew2Part* dparts, int nparts, int blocks,
+                      hipStream_t s);
 hipError_t launch_ew(int dtype, const KernelBases& kb, const EwPart* dparts, int nparts, int blocks,
                      hipStream_t s);
 bool gemm_bf16x3_available();

@@ -59,7 +59,8 @@ int ew_dtype(int dtype) { return dtype == MM_F64 ? DT_F64 : DT_F32; }
 // OP_BASE: unrolled base cases, one leaf product per thread (BaseDesc).
 enum OpType {
   OP_EW = 0, OP_GEMM = 1, OP_FORK = 2, OP_JOIN = 3, OP_WINO = 4, OP_SPLIT = 5, OP_TRANS = 6, OP_BASE = 7,
-  OP_PERSIST = 16  // a whole batch in one persistent launch (PersistHdr at the op's offset)
+  OP_PERSIST = 16,  // a whole batch in one persistent launch (PersistHdr at the op's offset)
+  OP_EW2 = 18       // two recursion levels of pre- or post-additions in one pass (Ew2Part)
 };
 
 struct OpRec {
@@ -94,6 +95,7 @@ struct Plan {
   bool spl = false;      // split-bfloat16 leaves read operands split by a split pass
   bool accumulate = false;  // C <- A B + beta C (beta given per execution)
   bool peel = false;        // grouped: peel ragged rows / columns / k instead of padding
+  bool level_passes = false; // grouped Winograd: one pre- and one post-addition pass per level
   bool trans_b = false;     // grouped Winograd float32: last-level B operands stored transposed
   bool unroll_base = false; // grouped Winograd: leaves of order 1, 2, 4, 8 by the unrolled base cases
   int split_k = 1;          // plain product: k split over this many partial products
@@ -228,6 +230,8 @@ struct Builder {
   int sp_grid = 0;
   bool gm_spl = false;           // the pending GEMM descriptors read SPL operands
   int gm_grid = 0;
+  std::vector<Ew2Part> e2;  // pending two-level passes
+  int e2_grid = 0;
   std::ostringstream txt;
 
   explicit Builder(Plan& p) : P(p), esz(elem_size(p.dtype)), E(16 / (int64_t)elem_size(p.dtype)) {}
@@ -332,7 +336,7 @@ struct Builder {
   }
   void ew_parts(int kind, int64_t rows, int64_t cols, const std::vector<MView>& ins,
                 const std::vector<MView>& outs, int mode0 = 0, int mode1 = 0) {
-    if (!gm.empty() || !wl.empty()) flush();
+    if (!e2.empty() || !gm.empty() || !wl.empty()) flush();
     EwPart p = make_ew(kind, rows, cols, ins, outs, mode0, mode1);
     const int blocks = ew_blocks((int)rows, (int)cols, ew_dtype(P.dtype));
     if (blocks == 0) return;
@@ -340,6 +344,33 @@ struct Builder {
     ew_grid += blocks;
     ew.push_back(p);
     ew_txt << ew_line(p);
+  }
+
+  // A two-level pre- or post-addition pass (desc.h, Ew2Part) over rows x
+  // cols lower-level positions; low holds 7 x 4 (S, T) or 7 x 7 (U) views.
+  void ew2_part(int kind, int64_t rows, int64_t cols, const MView& x, const MView (&top)[4],
+                const std::vector<std::vector<MView>>& low) {
+    if (!ew.empty() || !gm.empty() || !wl.empty() || !sp.empty() || !tp.empty() || !bl.empty()) flush();
+    Ew2Part p;
+    std::memset(&p, 0, sizeof p);
+    p.kind = kind;
+    p.rows = (int32_t)rows;
+    p.cols = (int32_t)cols;
+    p.x = kind == EW2_U ? none() : x;
+    for (int k = 0; k < 4; ++k) p.top[k] = top[k];
+    for (int q = 0; q < 7; ++q)
+      for (int i = 0; i < 7; ++i) p.low[q][i] = i < (int)low[q].size() ? low[q][i] : none();
+    const int blocks = ew2_blocks((int)rows, (int)cols, ew_dtype(P.dtype));
+    if (blocks == 0) return;
+    p.blk_start = e2_grid;
+    e2_grid += blocks;
+    e2.push_back(p);
+    txt << "EW2 " << kind << " " << rows << " " << cols << " | " << vs(p.x) << " |";
+    for (int k = 0; k < 4; ++k) txt << " " << vs(p.top[k]);
+    txt << " |";
+    for (int q = 0; q < 7; ++q)
+      for (int i = 0; i < (kind == EW2_U ? 7 : 4); ++i) txt << " " << vs(p.low[q][i]);
+    txt << "\n";
   }
 
   // GEMM epilogue outputs
@@ -359,7 +390,7 @@ struct Builder {
   // transpose.
   void split_part(int kind, int64_t rows, int64_t cols, bool transposed, std::initializer_list<MView> ins,
                   std::initializer_list<MView> outs) {
-    if (!ew.empty() || !gm.empty() || !wl.empty()) flush();
+    if (!e2.empty() || !ew.empty() || !gm.empty() || !wl.empty()) flush();
     EwPart p;
     std::memset(&p, 0, sizeof p);
     p.kind = kind;
@@ -388,7 +419,8 @@ struct Builder {
 
   // Leaf product c = a b of order s (1, 2 or 4) by the unrolled base case.
   void base(const MView& a, const MView& bop, const MView& c, int s) {
-    if (!ew.empty() || !gm.empty() || !wl.empty() || !sp.empty() || !tp.empty() || (!bl.empty() && bl_order != s))
+    if (!e2.empty() || !ew.empty() || !gm.empty() || !wl.empty() || !sp.empty() || !tp.empty() ||
+        (!bl.empty() && bl_order != s))
       flush();
     bl_order = s;
     P.leaves += 1;
@@ -400,7 +432,7 @@ struct Builder {
   // workspace block holding the transpose of the recipe's result.
   void trans_part(int kind, int64_t rows, int64_t cols, std::initializer_list<MView> ins,
                   std::initializer_list<MView> outs) {
-    if (!gm.empty() || !wl.empty() || !sp.empty()) flush();
+    if (!e2.empty() || !gm.empty() || !wl.empty() || !sp.empty()) flush();
     EwPart p;
     std::memset(&p, 0, sizeof p);
     p.kind = kind;
@@ -429,7 +461,7 @@ struct Builder {
   // C = a b^T-stored: a is an m x k SPL matrix, bt the n x k SPL transpose of
   // the B operand.
   void gemm_spl(const MView& a, const MView& bt, std::initializer_list<Out> outs) {
-    if (!ew.empty() || !sp.empty() || (!gm.empty() && !gm_spl)) flush();
+    if (!e2.empty() || !ew.empty() || !sp.empty() || (!gm.empty() && !gm_spl)) flush();
     gm_spl = true;
     GemmDesc g;
     std::memset(&g, 0, sizeof g);
@@ -501,7 +533,7 @@ struct Builder {
 
   void gemm(const MView& a, const MView& b, std::initializer_list<Out> outs, int akind = OK_PLAIN,
             int bkind = OK_PLAIN, bool fusable = false) {
-    if (!ew.empty() || !sp.empty() || gm_spl) flush();
+    if (!e2.empty() || !ew.empty() || !sp.empty() || gm_spl) flush();
     GemmDesc g;
     std::memset(&g, 0, sizeof g);
     g.a = a;
@@ -569,7 +601,7 @@ struct Builder {
   // loader forms) and the output quadrants.
   void wino(const MView (&a)[7], const MView (&bop)[7], const MView (&c)[4], int64_t m, int64_t n, int64_t k,
             bool acc = false, bool fused = false) {
-    if (!ew.empty() || !gm.empty() || (!wl.empty() && wl_fused != fused)) flush();
+    if (!e2.empty() || !ew.empty() || !gm.empty() || (!wl.empty() && wl_fused != fused)) flush();
     wl_fused = fused;
     WinoLeafDesc d;
     std::memset(&d, 0, sizeof d);
@@ -588,6 +620,16 @@ struct Builder {
   }
 
   void flush() {
+    if (!e2.empty()) {
+      OpRec r{OP_EW2, ew_dtype(P.dtype), P.table.size(), (int)e2.size(), e2_grid, 0, 0, 0, cur_stream};
+      const size_t bytes = e2.size() * sizeof(Ew2Part);
+      P.table.resize(round_up(P.table.size() + bytes, 256));
+      std::memcpy(P.table.data() + r.off, e2.data(), bytes);
+      P.ops.push_back(r);
+      txt << "LAUNCH EW2 " << e2.size() << " " << e2_grid << (cur_stream ? " aux" : "") << "\n";
+      e2.clear();
+      e2_grid = 0;
+    }
     if (!wl.empty()) emit_wino();
     if (!bl.empty()) {
       const int blocks = base_blocks((int)bl.size());
@@ -1051,7 +1093,33 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
     b.fork();
     b.cur_stream = 1;
   }
+  // Pairs of levels (l, l + 1) whose pre-additions run as one two-level pass
+  // (and post-additions too, except at the top of an accumulating plan):
+  // the default form at both levels, every block entirely valid, sizes that
+  // split into whole 16-byte chunks at the lower level (ew2.hip).
+  const bool pairs_allowed =
+      !strassen && !leaf_u && !b.P.spl && !b.P.trans_b && !b.P.fuse && !overlap_req && !b.P.level_passes;
+  auto pair_ok = [&](const std::vector<Sub>& v) {
+    if (v.empty()) return false;
+    for (const Sub& s : v) {
+      const MView &A = s.A, &B = s.B, &C = s.C;
+      if (s.akind != OK_PLAIN || s.bkind != OK_PLAIN || s.spl) return false;
+      if (A.vrows != A.rows || A.vcols != A.cols || B.vrows != B.rows || B.vcols != B.cols ||
+          C.vrows != C.rows || C.vcols != C.cols)
+        return false;
+      if (A.rows % 4 || A.cols % 4 || B.cols % 4 || (A.cols / 4) % b.E || (B.cols / 4) % b.E) return false;
+    }
+    return true;
+  };
+  std::vector<char> pair_top(std::max(L, 1), 0), upair_top(std::max(L, 1), 0);
+  // upper level of a pair: its sums, kept for the pass that forms both levels
+  std::vector<std::array<MView, 4>> up_s, up_t, lo_s, lo_t;
+  std::vector<std::pair<MView, MView>> up_x;
   for (int l = 0; l < L; ++l) {
+    const bool fuse_low = l > 0 && pair_top[l - 1];
+    const bool fuse_top = pairs_allowed && !fuse_low && l + 1 < L && pair_ok(subs);
+    pair_top[l] = fuse_top;
+    upair_top[l] = fuse_top && !(l == 0 && b.P.accumulate);
     std::vector<Sub> next;
     next.reserve(subs.size() * 7);
     std::vector<std::array<MView, 11>> uargs;
@@ -1199,8 +1267,17 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
       for (auto& v : S) v = b.temp(hm, hk);
       for (auto& v : T) v = b.temp(hk, hn);
       for (auto& v : Pt) v = b.temp(hm, hn);
-      b.ew_part(EW_WINO_S, hm, hk, {A11, A12, A21, A22}, {S[0], S[1], S[2], S[3]});
-      b.ew_part(EW_WINO_T, hk, hn, {B11, B12, B21, B22}, {T[0], T[1], T[2], T[3]});
+      if (fuse_top) {
+        up_s.push_back({S[0], S[1], S[2], S[3]});
+        up_t.push_back({T[0], T[1], T[2], T[3]});
+        up_x.push_back({s.A, s.B});
+      } else if (fuse_low) {
+        lo_s.push_back({S[0], S[1], S[2], S[3]});
+        lo_t.push_back({T[0], T[1], T[2], T[3]});
+      } else {
+        b.ew_part(EW_WINO_S, hm, hk, {A11, A12, A21, A22}, {S[0], S[1], S[2], S[3]});
+        b.ew_part(EW_WINO_T, hk, hn, {B11, B12, B21, B22}, {T[0], T[1], T[2], T[3]});
+      }
       next.push_back({A11, B11, Pt[0]});
       next.push_back({A12, B21, Pt[1]});
       next.push_back({S[3], B22, Pt[2]});
@@ -1210,6 +1287,30 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
       next.push_back({S[2], T[2], Pt[6]});
       uargs.push_back({Pt[0], Pt[1], Pt[2], Pt[3], Pt[4], Pt[5], Pt[6], b.quad(s.C, 0, 0),
                        b.quad(s.C, 0, 1), b.quad(s.C, 1, 0), b.quad(s.C, 1, 1)});
+    }
+    if (fuse_low) {
+      // the pair's pre-additions: one part per upper-level block, the lower
+      // level's sums of its seven operands (children 7 j .. 7 j + 6)
+      for (size_t j = 0; j < up_x.size(); ++j) {
+        std::vector<std::vector<MView>> ls(7), lt(7);
+        for (int o = 0; o < 7; ++o) {
+          ls[o].assign(lo_s[7 * j + o].begin(), lo_s[7 * j + o].end());
+          lt[o].assign(lo_t[7 * j + o].begin(), lo_t[7 * j + o].end());
+        }
+        const MView &XA = up_x[j].first, &XB = up_x[j].second;
+        MView ts[4], tt[4];
+        for (int q = 0; q < 4; ++q) {
+          ts[q] = up_s[j][q];
+          tt[q] = up_t[j][q];
+        }
+        b.ew2_part(EW2_S, XA.rows / 4, XA.cols / 4, XA, ts, ls);
+        b.ew2_part(EW2_T, XB.rows / 4, XB.cols / 4, XB, tt, lt);
+      }
+      up_s.clear();
+      up_t.clear();
+      up_x.clear();
+      lo_s.clear();
+      lo_t.clear();
     }
     b.flush();
     // U parts of this level are emitted after the deeper levels finish.
@@ -1266,6 +1367,21 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
   }
   b.flush();
   for (int l = L - 1; l >= 0; --l) {
+    if (l > 0 && upair_top[l - 1]) continue;  // formed by the pair's two-level pass
+    if (upair_top[l]) {
+      // one part per upper-level block: its C quadrants from the 49 lower
+      // products of its seven products
+      const std::vector<EwPart>& up = u_levels[l];
+      const std::vector<EwPart>& lo = u_levels[l + 1];
+      for (size_t j = 0; j < up.size(); ++j) {
+        std::vector<std::vector<MView>> low(7);
+        for (int q = 0; q < 7; ++q) low[q].assign(lo[7 * j + q].in, lo[7 * j + q].in + 7);
+        const MView top[4] = {up[j].out[0], up[j].out[1], up[j].out[2], up[j].out[3]};
+        b.ew2_part(EW2_U, top[0].rows / 2, top[0].cols / 2, b.none(), top, low);
+      }
+      b.flush();
+      continue;
+    }
     for (const EwPart& p : u_levels[l]) {
       if (l == 0 && b.P.accumulate)  // C = beta C + U at the top level
         b.ew_part(strassen ? EW_STR_U_ACC : EW_WINO_U_ACC, p.rows, p.cols,
@@ -1713,6 +1829,8 @@ int enqueue(Plan& P, void* A, void* B, void* C, void* ws, hipStream_t s, hipEven
       const void* d = (const char*)dtab + op.off;
       if (op.type == OP_EW)
         e = launch_ew(op.kdtype, kb, (const EwPart*)d, op.count, op.grid, st);
+      else if (op.type == OP_EW2)
+        e = launch_ew2(op.kdtype, kb, (const Ew2Part*)d, op.count, op.grid, st);
       else if (op.type == OP_WINO)
         e = launch_gemm_wino(op.cfg, op.fused, kb, (const WinoLeafDesc*)d, op.count, op.grid, op.remap, st);
       else if (op.type == OP_SPLIT)
@@ -1847,6 +1965,7 @@ int make_plan(int algo, int sched, int64_t m, int64_t n, int64_t k, int64_t lda,
   P->overlap = (flags & MM_PLAN_OVERLAP) != 0;
   P->accumulate = (flags & MM_PLAN_ACCUMULATE) != 0;
   P->peel = (flags & MM_PLAN_PEEL) != 0;
+  P->level_passes = (flags & MM_PLAN_LEVEL_PASSES) != 0;
   P->trans_b = (flags & MM_PLAN_TRANS_B) != 0 && dtype == MM_F32 && algo == MM_ALGO_WINOGRAD &&
                resolve_sched(algo, sched) == MM_SCHED_GROUPED;
   P->split_k = (int)((flags >> 16) & 0xf);

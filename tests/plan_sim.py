@@ -24,6 +24,7 @@ EW_SPLIT, EW_WINO_S_SPL, EW_WINO_T_SPL, EW_WINO_U_ACC, EW_AXPBY = 12, 13, 14, 15
 EW_STR_S, EW_STR_T, EW_STR_U, EW_STR_U_ACC = 17, 18, 19, 20
 EW_WINO_T_TR = 21
 EW_SUM, EW_SUM_ACC = 22, 23
+EW2_S, EW2_T, EW2_U = 0, 1, 2
 OK_TRANS = 9
 GM_STORE, GM_ADD, GM_AXPBY = 1, 2, 3
 MB_A, MB_B, MB_C, MB_WS, MB_ABS = 0, 1, 2, 3, 4
@@ -99,6 +100,16 @@ def parse(text):
             a, b, c = [_view(t) for t in rest[0].split()]
             cur.append(("BASE", dict(order=int(h[1]), a=a, b=b, c=c)))
             continue
+        if h[0] == "EW2":
+            kind, rows, cols = map(int, h[1:])
+            x = _view(rest[0].split()[0])
+            top = [_view(t) for t in rest[1].split()]
+            low = [_view(t) for t in rest[2].split()]
+            per = 7 if kind == EW2_U else 4
+            assert len(top) == 4 and len(low) == 7 * per
+            cur.append(("EW2", dict(kind=kind, rows=rows, cols=cols, x=x, top=top,
+                                    low=[low[per * q:per * q + per] for q in range(7)])))
+            continue
         if h[0] == "TRANS":
             kind, rows, cols = map(int, h[1:])
             ins = [_view(t) for t in rest[0].split()]
@@ -166,10 +177,43 @@ def check_streams(launches):
     assert not inside, "listing ends inside a fork window"
 
 
+def _sub_view(v, sa, sc):
+    """Sub-block (sa, sc) of the 2 x 2 split of view v."""
+    r, c = v.rows // 2, v.cols // 2
+    return View([v.base, v.off + sa * r * v.ld + sc * c, v.ld, r, c,
+                 max(0, min(r, v.vrows - sa * r)), max(0, min(c, v.vcols - sc * c))])
+
+
+def _ew2_written_top(it):
+    """The parts of an EW2 pass's top views it writes: all of a U pass's C
+    quadrants; three of the four sub-blocks of each upper-level sum (the one
+    the lower level never reads plainly is skipped)."""
+    if it["kind"] == EW2_U:
+        return [(v, None, k) for k, v in enumerate(it["top"])]
+    skip = (1, 0) if it["kind"] == EW2_S else (0, 1)
+    return [(_sub_view(v, sa, sc), (sa, sc), k) for k, v in enumerate(it["top"]) for sa in (0, 1)
+            for sc in (0, 1) if (sa, sc) != skip]
+
+
+def _ew2_footprint(it):
+    if it["kind"] == EW2_U:
+        reads = set().union(*[_footprint(v) for row in it["low"] for v in row])
+        writes = set().union(*[_footprint(v) for v in it["top"]])
+    else:
+        reads = _footprint(it["x"])
+        writes = set().union(*[_footprint(v) for v, _, _ in _ew2_written_top(it)])
+        writes |= set().union(*[_footprint(v) for row in it["low"] for v in row])
+    return reads, writes
+
+
 def _launch_footprint(kind, items):
     reads, writes = set(), set()
     for _, it in items:
-        if kind in ("EW", "TRANS"):
+        if kind == "EW2":
+            r, w = _ew2_footprint(it)
+            reads |= r
+            writes |= w
+        elif kind in ("EW", "TRANS"):
             for v in it["ins"]:
                 reads |= _footprint(v)
             for v in it["outs"]:
@@ -342,6 +386,18 @@ def check_hazards(launch):
                         for x in common.tolist():
                             pi, po = pos_in[x], pos_out[x]
                             assert (pi // ci, pi % ci) == (po // co, po % co), "EW cross-element alias"
+        elif kind == "EW2":
+            r, w = _ew2_footprint(it)
+            assert not (w & r), "EW2 writes its own inputs"
+            outs = [v for v, _, _ in _ew2_written_top(it)] + ([] if it["kind"] == EW2_U else
+                                                            [v for row in it["low"] for v in row])
+            assert sum(len(_footprint(v)) for v in outs) == len(w), "EW2 outputs overlap"
+            R, C = it["rows"], it["cols"]
+            for v in it["top"]:
+                assert (v.rows, v.cols) == (2 * R, 2 * C), "EW2 upper block of another shape"
+            for row in it["low"]:
+                for v in row:
+                    assert (v.rows, v.cols) == (R, C), "EW2 lower block of another shape"
         elif kind == "BASE":
             r, w = _footprint(it["a"]) | _footprint(it["b"]), _footprint(it["c"])
             assert not (w & r), "BASE writes its own operands"
@@ -434,6 +490,53 @@ def unrolled_winograd(a, b):
     return c
 
 
+def _quads(m):
+    r, c = m.shape[0] // 2, m.shape[1] // 2
+    return m[:r, :c], m[:r, c:], m[r:, :c], m[r:, c:]
+
+
+def _ew2_run(mem, it):
+    """Two recursion levels of Section 2.3's pre- or post-additions (an EW2
+    part), level by level, as the two separate passes compute them."""
+    outs = []
+    if it["kind"] == EW2_U:
+        def u(p):  # U1 U5 U6 U7 of P1..P7, assembled into one block
+            u2 = p[0] + p[5]
+            u3 = u2 + p[6]
+            return np.block([[p[0] + p[1], (u2 + p[4]) + p[2]], [u3 - p[3], u3 + p[4]]])
+        upper = [u([mem.read(v) for v in row]) for row in it["low"]]
+        c = u(upper)
+        for v, q in zip(it["top"], _quads(c)):
+            outs.append((v, q))
+        return outs
+    x = mem.read(it["x"])
+    q11, q12, q21, q22 = _quads(x)
+    if it["kind"] == EW2_S:
+        s1 = q21 + q22
+        s2 = s1 - q11
+        sums = [s1, s2, q11 - q21, q12 - s2]
+        ops = [q11, q12, sums[3], q22, sums[0], sums[1], sums[2]]
+    else:
+        t1 = q12 - q11
+        t2 = q22 - t1
+        sums = [t1, t2, q22 - q12, t2 - q21]
+        ops = [q11, q21, q22, sums[3], sums[0], sums[1], sums[2]]
+    for v, (sa, sc), k in _ew2_written_top(it):
+        outs.append((v, _quads(sums[k])[2 * sa + sc]))
+    for o, row in zip(ops, it["low"]):
+        o11, o12, o21, o22 = _quads(o)
+        if it["kind"] == EW2_S:
+            z1 = o21 + o22
+            z2 = z1 - o11
+            z = [z1, z2, o11 - o21, o12 - z2]
+        else:
+            z1 = o12 - o11
+            z2 = o22 - z1
+            z = [z1, z2, o22 - o12, z2 - o21]
+        outs.extend(zip(row, z))
+    return outs
+
+
 def run(text, bufs, hazards=True, beta=1):
     mem = Memory(bufs)
     for launch in parse(text):
@@ -464,6 +567,8 @@ def run(text, bufs, hazards=True, beta=1):
                 else:
                     y = _recipe(it["kind"], x, it["mode"])
                 results.append(list(zip(it["outs"], y)))
+            elif kind == "EW2":
+                results.append(_ew2_run(mem, it))
             elif kind == "BASE":
                 results.append([(it["c"], unrolled_winograd(mem.read(it["a"]), mem.read(it["b"])))])
             elif kind == "TRANS":

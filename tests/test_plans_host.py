@@ -122,11 +122,12 @@ def test_grouped_launch_count_and_leaves(lib):
     for L_ in (1, 2, 3):
         text, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_)
         assert info["levels"] == L_
-        # L S/T passes, the leaf products (one launch, or two that each fill
-        # whole rounds of workgroups), L U passes
+        # S/T passes, the leaf products (one launch, or two that each fill
+        # whole rounds of workgroups), U passes: levels 0 and 1 (2 and 3, ...)
+        # as one two-level pass each, an unpaired last level on its own
         g = count(text, "GEMM")
-        assert count(text, "EW") == 2 * L_ and g in (1, 2)
-        assert info["launches"] == 2 * L_ + g
+        assert count(text, "EW2") == 2 * (L_ // 2) and count(text, "EW ") == 2 * (L_ % 2) and g in (1, 2)
+        assert info["launches"] == 2 * (L_ // 2) + 2 * (L_ % 2) + g
         assert info["leaves"] == 7 ** L_ and info["fused"] == 0
         # with MM_PLAN_OVERLAP: fork, L S/T passes (auxiliary stream), the
         # products of blocks of A and B, join, the other products, L U passes
@@ -475,7 +476,15 @@ def test_peel_launch_structure(lib):
     _, info0 = L.describe("winograd", "grouped", 3000, 3000, 3000, cutoff=1, levels=3)
     assert (info["M"], info["N"], info["K"]) == (2976, 2976, 2976)
     assert (info0["M"], info0["N"], info0["K"]) == (3008, 3008, 3008)
-    assert info["launches"] == info0["launches"] + 1
+    # the peeled recursion is entirely valid, so levels 0 and 1 pair into
+    # two-level passes (2 launches for both levels' S/T and U) while the
+    # zero-padded one keeps a pass per level: one launch per level fewer,
+    # one more for the thin products
+    kinds = [l.split()[1] for l in text.splitlines() if l.startswith("LAUNCH")]
+    kinds0 = [l.split()[1] for l in L.describe("winograd", "grouped", 3000, 3000, 3000, cutoff=1,
+                                                levels=3)[0].splitlines() if l.startswith("LAUNCH")]
+    assert kinds.count("EW2") == 2 and kinds.count("EW") == 2 and kinds0.count("EW") == 6
+    assert info["launches"] == info0["launches"] - 2 + 1
     last = [l for l in text.splitlines() if l.startswith("LAUNCH")][-1].split()
     assert last[1] == "GEMM" and int(last[2]) == 3
     # nothing to peel: the same plan
@@ -520,7 +529,9 @@ def test_transposed_b_plan_is_exact(lib, m, n, k, levels):
 
 def test_transposed_b_plan_shape(lib):
     for lv in (1, 2):
-        _, ref = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=lv)
+        # (the transposing pass replaces a level's own T pass: compared with
+        # the level-by-level passes)
+        _, ref = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=lv, level_passes=True)
         text, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=lv, trans_b=True)
         launches = [l.split() for l in text.splitlines() if l.startswith("LAUNCH")]
         # the last level's S pass and transposing T pass are two launches
@@ -790,3 +801,52 @@ def test_pad_to_a_multiple_is_exact(lib, sched):
     C = np.full(m * n, -(10**9), dtype=np.int64)
     plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws})
     assert np.array_equal(C.reshape(m, n), A @ B)
+
+
+PAIR_CASES = [(64, 64, 64, 2, "f32", {}), (128, 96, 64, 2, "f32", {}), (64, 64, 64, 3, "f32", {}),
+              (128, 128, 128, 4, "f32", {}), (64, 64, 64, 2, "f64", {}), (96, 64, 128, 2, "f32",
+                                                                          {"unroll_base": False}),
+              (64, 64, 64, 2, "f32", {"accumulate": True}), (256, 128, 192, 3, "f32", {"tile": 8})]
+
+
+@pytest.mark.parametrize("m,n,k,levels,dtype,opts", PAIR_CASES)
+def test_two_level_passes_are_exact(lib, m, n, k, levels, dtype, opts):
+    """Levels 0 and 1 (and 2 and 3) of the grouped Winograd schedule share one
+    S/T pass and one U pass (EW2); exact on integers, and the same values as
+    the level-by-level passes (MM_PLAN_LEVEL_PASSES), which the listing then
+    has instead."""
+    A = inputs.integers((m, k), 61, dtype=np.int64)
+    B = inputs.integers((k, n), 62, dtype=np.int64)
+    C0 = inputs.integers((m, n), 63, dtype=np.int64)
+    results = []
+    for lp in (False, True):
+        text, info = L.describe("winograd", "grouped", m, n, k, cutoff=1, levels=levels, dtype=dtype,
+                                level_passes=lp, **opts)
+        kinds = [l.split()[1] for l in text.splitlines() if l.startswith("LAUNCH")]
+        pairs = levels // 2
+        if lp:
+            assert "EW2" not in kinds and kinds.count("EW") == 2 * levels
+        else:
+            # the U pair at the top of an accumulating plan stays two passes
+            u_pairs = pairs - (1 if opts.get("accumulate") else 0)
+            assert kinds.count("EW2") == pairs + u_pairs
+        ws = np.full(max(info["ws_bytes"] // (8 if dtype == "f64" else 4), 1), 10**9, dtype=np.int64)
+        C = C0.ravel().copy()
+        plan_sim.run(text, {0: A.ravel().copy(), 1: B.ravel().copy(), 2: C, 3: ws}, beta=2)
+        want = A @ B + (2 * C0 if opts.get("accumulate") else 0)
+        assert np.array_equal(C.reshape(m, n), want)
+        results.append(C)
+    assert np.array_equal(results[0], results[1])
+
+
+def test_two_level_passes_need_whole_blocks(lib):
+    # zero-padded operands (3000 -> 3008 at three levels) and the options that
+    # change a level's form keep one pass per level
+    for args, opts in (((3000, 3000, 3000, 3), {}), ((4096, 4096, 4096, 2), {"overlap": True}),
+                       ((4096, 4096, 4096, 2), {"leaf_u": True}), ((4096, 4096, 4096, 2), {"trans_b": True}),
+                       ((4096, 4096, 4096, 2), {"fuse": True}), ((4096, 4096, 4096, 2), {"level_passes": True})):
+        m, n, k, lv = args
+        text, _ = L.describe("winograd", "grouped", m, n, k, cutoff=1, levels=lv, **opts)
+        assert "EW2" not in text, (args, opts)
+    text, _ = L.describe("strassen", "grouped", 4096, 4096, 4096, cutoff=1, levels=2)
+    assert "EW2" not in text
