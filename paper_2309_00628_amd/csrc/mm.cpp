@@ -1097,8 +1097,7 @@ void sched_grouped(Builder& b, std::vector<Sub> subs) {
   // (and post-additions too, except at the top of an accumulating plan):
   // the default form at both levels, every block entirely valid, sizes that
   // split into whole 16-byte chunks at the lower level (ew2.hip).
-  const bool pairs_allowed =
-      !strassen && !leaf_u && !b.P.spl && !b.P.trans_b && !b.P.fuse && !overlap_req && !b.P.level_passes;
+  const bool pairs_allowed = !strassen && !leaf_u && !b.P.spl && !b.P.trans_b && !b.P.fuse && !b.P.level_passes;
   auto pair_ok = [&](const std::vector<Sub>& v) {
     if (v.empty()) return false;
     for (const Sub& s : v) {

@@ -129,12 +129,12 @@ def test_grouped_launch_count_and_leaves(lib):
         assert count(text, "EW2") == 2 * (L_ // 2) and count(text, "EW ") == 2 * (L_ % 2) and g in (1, 2)
         assert info["launches"] == 2 * (L_ // 2) + 2 * (L_ % 2) + g
         assert info["leaves"] == 7 ** L_ and info["fused"] == 0
-        # with MM_PLAN_OVERLAP: fork, L S/T passes (auxiliary stream), the
-        # products of blocks of A and B, join, the other products, L U passes
+        # with MM_PLAN_OVERLAP: fork, the S/T passes (auxiliary stream), the
+        # products of blocks of A and B, join, the other products, the U passes
         text, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_, overlap=True)
         g = count(text, "GEMM")
         assert "FORK" in text and "JOIN" in text and g >= 2
-        assert info["launches"] == 2 * L_ + g + 2
+        assert info["launches"] == 2 * (L_ // 2) + 2 * (L_ % 2) + g + 2
         # with MM_PLAN_FUSE the last level's S/T pass is formed in the leaf loader
         text, info = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=L_, fuse=True)
         assert count(text, "EW") == 2 * L_ - 1 and info["fused"] == 1
@@ -804,6 +804,7 @@ def test_pad_to_a_multiple_is_exact(lib, sched):
 
 
 PAIR_CASES = [(64, 64, 64, 2, "f32", {}), (128, 96, 64, 2, "f32", {}), (64, 64, 64, 3, "f32", {}),
+              (128, 64, 96, 2, "f32", {"overlap": True}), (128, 128, 128, 3, "f32", {"overlap": True}),
               (128, 128, 128, 4, "f32", {}), (64, 64, 64, 2, "f64", {}), (96, 64, 128, 2, "f32",
                                                                           {"unroll_base": False}),
               (64, 64, 64, 2, "f32", {"accumulate": True}), (256, 128, 192, 3, "f32", {"tile": 8})]
@@ -842,7 +843,7 @@ def test_two_level_passes_are_exact(lib, m, n, k, levels, dtype, opts):
 def test_two_level_passes_need_whole_blocks(lib):
     # zero-padded operands (3000 -> 3008 at three levels) and the options that
     # change a level's form keep one pass per level
-    for args, opts in (((3000, 3000, 3000, 3), {}), ((4096, 4096, 4096, 2), {"overlap": True}),
+    for args, opts in (((3000, 3000, 3000, 3), {}),
                        ((4096, 4096, 4096, 2), {"leaf_u": True}), ((4096, 4096, 4096, 2), {"trans_b": True}),
                        ((4096, 4096, 4096, 2), {"fuse": True}), ((4096, 4096, 4096, 2), {"level_passes": True})):
         m, n, k, lv = args
