@@ -316,24 +316,28 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
 }
 
 // The same products on a 256 x 256 tile with eight waves (two per SIMD, each
-// 128 x 64), software-pipelined so that the split's vector work runs under
-// the MFMAs of the same wave.  Each thread stages one 8-float chunk of A
-// and one 8-row column of B per stage (EBB = 1 column per block), so the
-// split work is the same in every wave.  During stage t the registers hold
-// stage t+1 (loaded during stage t-1): it is split into the other LDS
-// buffer between the MFMAs of the first two rows of 32 x 32 tiles, after
-// which the loads of stage t+2 are issued into the same registers, to
-// arrive while the last two rows and the next stage's first rows compute.
-// The steady-state loop (stages that both split and load) is one basic
-// block, so the compiler can interleave the split with the MFMAs; the last
-// two stages are peeled.  A stage holds 16 k (one MFMA k-step); the six
-// products of a tile are issued in the order of the kernel above and the
-// LDS layout is the same (swz_b depends only on the column), so both
-// kernels give the same bits.  Tiles that are not entirely inside both
-// operands (and products whose k is not a multiple of 16) take a plain
-// masked loop.
-template <int BM, int BN, int WGM, int WGN, int EBB>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(KernelBases kb,
+// 128 x 64), software-pipelined over a ring of three LDS stages of 16 k (one
+// MFMA k-step; 48 MFMAs per wave and stage).  Each thread stages one 8-float
+// chunk of A and one 8-row column of B per stage, so the split work is the
+// same in every wave.  During stage t:
+//  * the registers hold the raw float32 data of stage t+2 (loaded during
+//    stage t-1); it is split into hi, lo and residual and stored to the
+//    third LDS buffer between the MFMAs of the first two rows of 32 x 32
+//    tiles, after which the loads of stage t+3 are issued into the same
+//    registers (buffer loads: per-lane 32-bit offsets fixed for the whole
+//    loop, the stage's position in scalar registers);
+//  * the buffer of stage t+1 was written during stage t-1 and published by
+//    the barrier that began stage t, so each wave reads stage t+1's B
+//    fragments and first-row A fragments during the last row of MFMAs, and
+//    the barrier that ends the stage (a wait for this wave's LDS accesses,
+//    not for the global loads in flight) is followed by MFMAs at once;
+//  * the A fragments of the next row are read during the current row.
+// The last three stages are peeled (no loads, then no split); tiles at the
+// matrix edge, small k and leading dimensions of 2^21 or more take a
+// one-buffer loop with bounds-checked loads.  The six products of a tile are
+// issued in the order of the kernel above: the same bits.
+template <int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16r_kernel(KernelBases kb,
                                                                     const GemmDesc* __restrict__ descs,
                                                                     int ndesc, int remap) {
   constexpr int NT = 64 * WGM * WGN;
@@ -342,16 +346,16 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(KernelBases 
   constexpr int FM = WM / TM, FN = WN / TM;
   constexpr int BKC = 2;
   constexpr int BK = BKC * KC;
-  constexpr int NCH_A = BM * BKC;           // 8-float chunks of A per stage
+  constexpr int NCH_A = BM * BKC;   // 8-float chunks of A per stage
   constexpr int NA = NCH_A / NT;
-  constexpr int NBLK_B = BKC * (BN / EBB);  // 8 x EBB blocks of B per stage
+  constexpr int NBLK_B = BKC * BN;  // 8 x 1 columns of B per stage
   constexpr int NB = NBLK_B / NT;
-  constexpr int NPART = NA + NB * EBB;      // split calls per thread and stage
+  constexpr int NPART = NA + NB;    // split calls per thread and stage
   static_assert(NCH_A % NT == 0 && NBLK_B % NT == 0 && NA >= 1 && NB >= 1, "whole chunks per thread");
-  static_assert(FM >= 2 * NPART / 2 && FM % 2 == 0, "split spread over the first half of the tile rows");
+  static_assert(FM >= 2 && FM % 2 == 0 && NPART <= FM / 2, "split spread over the first half of the rows");
 
-  __shared__ bf16x8 As[2][3][BKC][BM];
-  __shared__ bf16x8 Bs[2][3][BKC][BN];
+  __shared__ bf16x8 As[3][3][BKC][BM];
+  __shared__ bf16x8 Bs[3][3][BKC][BN];
 
   const TileRef tr = locate_tile<BM, BN>(descs, ndesc, remap);
   const GemmDesc& D = descs[tr.desc];
@@ -369,18 +373,35 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(KernelBases 
   const int wm = wave / WGN, wn = wave % WGN;
   const int g = lane / TM, t = lane % TM;
 
-  float sa[NA][8];          // staged A chunks of one stage
-  float sb[NB][8][EBB];     // staged B blocks of one stage
+  float sa[NA][8];  // staged A chunks of one stage
+  float sb[NB][8];  // staged B columns of one stage
 
+  // buffer-load offsets: bytes from the stage's first element (A row i0,
+  // column k0; B row k0, column j0); they fit in 32 bits for leading
+  // dimensions below 2^21 (checked with the interior test)
+  uint32_t oa[NA], ob[NB];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    const int q = tid + NT * i;
+    oa[i] = (uint32_t)(((q / BKC) * lda + (q % BKC) * KC) * (int64_t)sizeof(float));
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int q = tid + NT * i;
+    ob[i] = (uint32_t)(((q / BN) * KC * ldb + q % BN) * (int64_t)sizeof(float));
+  }
+  const uint32_t brow = (uint32_t)(ldb * (int64_t)sizeof(float));
+  auto rsrc = [](const float* p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), 0, -1, 0x00020000);
+  };
   auto load_full = [&](int kt) {
-    const int k0 = kt * BK;
+    const int64_t k0 = (int64_t)kt * BK;
+    const __amdgpu_buffer_rsrc_t ra = rsrc(Ap + (int64_t)i0 * lda + k0);
+    const __amdgpu_buffer_rsrc_t rb = rsrc(Bp + k0 * ldb + j0);
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int q = tid + NT * i;
-      const int row = q / BKC, kc = q % BKC;
-      const float* p = Ap + (int64_t)(i0 + row) * lda + k0 + kc * KC;
-      const f32x4 u = *reinterpret_cast<const f32x4*>(p);
-      const f32x4 w = *reinterpret_cast<const f32x4*>(p + 4);
+      const f32x4 u = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, oa[i], 0, 0));
+      const f32x4 w = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, oa[i] + 16, 0, 0));
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         sa[i][e] = u[e];
@@ -388,21 +409,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(KernelBases 
       }
     }
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int q = tid + NT * i;
-      const int kc = q / (BN / EBB), cb = q % (BN / EBB);
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-      for (int rr = 0; rr < KC; ++rr) {
-        const float* p = Bp + (int64_t)(k0 + kc * KC + rr) * ldb + j0 + cb * EBB;
-        if constexpr (EBB == 2) {
-          const f32x2 u = *reinterpret_cast<const f32x2*>(p);
-          sb[i][rr][0] = u[0];
-          sb[i][rr][1] = u[1];
-        } else {
-          sb[i][rr][0] = *p;
-        }
-      }
-    }
+      for (int rr = 0; rr < KC; ++rr)
+        sb[i][rr] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, ob[i], rr * brow, 0));
   };
   auto load_masked = [&](int kt) {
     const int k0 = kt * BK;
@@ -418,15 +428,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(KernelBases 
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int q = tid + NT * i;
-      const int kc = q / (BN / EBB), cb = q % (BN / EBB);
+      const int kc = q / BN, cb = q % BN;
+      const int gc = j0 + cb;
 #pragma unroll
       for (int rr = 0; rr < KC; ++rr) {
         const int gr = k0 + kc * KC + rr;
-#pragma unroll
-        for (int c = 0; c < EBB; ++c) {
-          const int gc = j0 + cb * EBB + c;
-          sb[i][rr][c] = (gr < bv.vrows && gc < bv.vcols) ? Bp[(int64_t)gr * ldb + gc] : 0.f;
-        }
+        sb[i][rr] = (gr < bv.vrows && gc < bv.vcols) ? Bp[(int64_t)gr * ldb + gc] : 0.f;
       }
     }
   };
@@ -443,14 +450,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(KernelBases 
       As[buf][1][kc][sr] = l;
       As[buf][2][kc][sr] = r;
     } else {
-      const int i = (j - NA) / EBB, c = (j - NA) % EBB;
-      const int q = tid + NT * i;
-      const int kc = q / (BN / EBB), cb = q % (BN / EBB);
-      float col[8];
-#pragma unroll
-      for (int rr = 0; rr < KC; ++rr) col[rr] = sb[i][rr][c];
-      split8(col, h, l, r);
-      const int sc = swz_b<EB>(cb * EBB + c);
+      const int q = tid + NT * (j - NA);
+      const int kc = q / BN, cb = q % BN;
+      split8(sb[j - NA], h, l, r);
+      const int sc = swz_b<EB>(cb);
       Bs[buf][0][kc][sc] = h;
       Bs[buf][1][kc][sc] = l;
       Bs[buf][2][kc][sc] = r;
@@ -465,73 +468,122 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(KernelBases 
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-  // The MFMAs of one stage from LDS buffer buf.  SPLIT: the staged stage is
-  // split into buffer nbuf between the first FM/2 rows of tiles; LOAD: then
-  // stage kt_next is loaded into the staging registers.
-  auto stage = [&](auto split_tag, auto load_tag, int buf, int nbuf, int kt_next) {
-    constexpr bool SPLIT = decltype(split_tag)::value;
-    constexpr bool LOAD = decltype(load_tag)::value;
-    bf16x8 fb[3][FN];
+  bf16x8 fb[3][FN], nfb[3][FN], fa[2][3];
+  auto read_b = [&](int buf, bf16x8 (&x)[3][FN]) {
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
-      for (int b = 0; b < FN; ++b) fb[p][b] = Bs[buf][p][g][swz_b<EB>(wn * WN + b * TM + t)];
+      for (int b = 0; b < FN; ++b) x[p][b] = Bs[buf][p][g][swz_b<EB>(wn * WN + b * TM + t)];
+  };
+  auto read_a = [&](int buf, int a, bf16x8 (&x)[3]) {
+#pragma unroll
+    for (int p = 0; p < 3; ++p) x[p] = As[buf][p][g][swz_a<BKC>(wm * WM + a * TM + t, g)];
+  };
+  // LDS accesses of this wave done, then the workgroup barrier (the global
+  // loads in flight are not waited for: vmcnt left at its maximum)
+  auto lds_barrier = [&]() {
+    __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4));
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+
+  // Stage kt from buffer kt % 3 (its B fragments and first-row A fragments
+  // in registers).  SPLIT: the staged stage kt+2 goes into buffer (kt+2) % 3
+  // between the first FM/2 rows; LOAD: then stage kt+3 is loaded into the
+  // staging registers; NEXT: the last row also reads stage kt+1's fragments.
+  auto stage = [&](auto split_tag, auto load_tag, auto next_tag, int kt) {
+    constexpr bool SPLIT = decltype(split_tag)::value;
+    constexpr bool LOAD = decltype(load_tag)::value;
+    constexpr bool NEXT = decltype(next_tag)::value;
+    const int buf = kt % 3, nbuf = (kt + 1) % 3, sbuf = (kt + 2) % 3;
 #pragma unroll
     for (int a = 0; a < FM; ++a) {
-      bf16x8 fa[3];
+      const int ca = a & 1;
+      __builtin_amdgcn_sched_barrier(0);
+      if (a + 1 < FM) {
+        read_a(buf, a + 1, fa[ca ^ 1]);
+      } else if (NEXT) {
+        read_a(nbuf, 0, fa[ca ^ 1]);
+        read_b(nbuf, nfb);
+      }
 #pragma unroll
-      for (int p = 0; p < 3; ++p) fa[p] = As[buf][p][g][swz_a<BKC>(wm * WM + a * TM + t, g)];
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[ca][1], fb[1][b], acc[a][b]);  // lo  * lo
 #pragma unroll
-      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[1], fb[1][b], acc[a][b]);  // lo  * lo
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[ca][2], fb[0][b], acc[a][b]);  // res * hi
 #pragma unroll
-      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[2], fb[0][b], acc[a][b]);  // res * hi
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[ca][0], fb[2][b], acc[a][b]);  // hi  * res
 #pragma unroll
-      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[0], fb[2][b], acc[a][b]);  // hi  * res
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[ca][1], fb[0][b], acc[a][b]);  // lo  * hi
 #pragma unroll
-      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[1], fb[0][b], acc[a][b]);  // lo  * hi
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[ca][0], fb[1][b], acc[a][b]);  // hi  * lo
 #pragma unroll
-      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[0], fb[1][b], acc[a][b]);  // hi  * lo
-#pragma unroll
-      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[0], fb[0][b], acc[a][b]);  // hi  * hi
+      for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[ca][0], fb[0][b], acc[a][b]);  // hi  * hi
       if constexpr (SPLIT) {
 #pragma unroll
         for (int j = 0; j < NPART; ++j)
-          if (j * (FM / 2) / NPART == a) split_part(nbuf, j);
+          if (j * (FM / 2) / NPART == a) split_part(sbuf, j);
       }
       if constexpr (LOAD) {
-        if (a == FM / 2 - 1) load_full(kt_next);
+        if (a == FM / 2 - 1) load_full(kt + 3);
       }
+      // one MFMA, then a share of the row's other work: an LDS read of the
+      // next fragments, six vector instructions of the split, its LDS
+      // stores and the global loads (measured 2 % faster than leaving the
+      // order to the compiler, which gathers the reads before the barrier)
+#pragma unroll
+      for (int i = 0; i < 6 * FN; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+        __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // VALU
+        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS write
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // global load
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (NEXT) {
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) fb[p][b] = nfb[p][b];
     }
   };
   typedef std::integral_constant<bool, true> yes;
   typedef std::integral_constant<bool, false> no;
 
   const bool interior = avec && bvec && (i0 + BM <= av.vrows) && (j0 + BN <= bv.vcols) && (K % BK == 0) &&
-                        (K <= av.vcols) && (K <= bv.vrows);
-  if (ktiles > 0 && interior) {
+                        (K <= av.vcols) && (K <= bv.vrows) && lda < (int64_t(1) << 21) &&
+                        ldb < (int64_t(1) << 21);
+  if (ktiles >= 3 && interior) {
     load_full(0);
 #pragma unroll
     for (int j = 0; j < NPART; ++j) split_part(0, j);
-    if (ktiles > 1) load_full(1);
-    __syncthreads();
+    load_full(1);
+#pragma unroll
+    for (int j = 0; j < NPART; ++j) split_part(1, j);
+    load_full(2);
+    lds_barrier();
+    read_b(0, fb);
+    read_a(0, 0, fa[0]);
     int kt = 0;
-    for (; kt + 2 < ktiles; ++kt) {
-      stage(yes{}, yes{}, kt & 1, (kt & 1) ^ 1, kt + 2);
-      __syncthreads();
+    for (; kt + 3 < ktiles; ++kt) {
+      stage(yes{}, yes{}, yes{}, kt);
+      lds_barrier();
     }
-    if (kt + 1 < ktiles) {
-      stage(yes{}, no{}, kt & 1, (kt & 1) ^ 1, 0);
-      __syncthreads();
-      ++kt;
-    }
-    stage(no{}, no{}, kt & 1, 0, 0);
+    stage(yes{}, no{}, yes{}, kt);  // kt = ktiles - 3
+    lds_barrier();
+    stage(no{}, no{}, yes{}, kt + 1);
+    lds_barrier();
+    stage(no{}, no{}, no{}, kt + 2);
   } else if (ktiles > 0) {
     for (int kt = 0; kt < ktiles; ++kt) {
       load_masked(kt);
 #pragma unroll
       for (int j = 0; j < NPART; ++j) split_part(0, j);
       __syncthreads();
-      stage(no{}, no{}, 0, 0, 0);
+      read_b(0, fb);
+      read_a(0, 0, fa[0]);
+      stage(no{}, no{}, no{}, 0);
       __syncthreads();
     }
   }
@@ -728,10 +780,10 @@ hipError_t launch_spl(const KernelBases& kb, const GemmDesc* d, int n, int tiles
   return hipGetLastError();
 }
 
-template <int BM, int BN, int WGM, int WGN, int EBB>
-hipError_t launch_pipe(const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_bf16p_kernel<BM, BN, WGM, WGN, EBB>), dim3(tiles), dim3(64 * WGM * WGN), 0, s, kb, d,
-                     n, remap);
+template <int BM, int BN, int WGM, int WGN>
+hipError_t launch_ring(const KernelBases& kb, const GemmDesc* d, int n, int tiles, int remap, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_bf16r_kernel<BM, BN, WGM, WGN>), dim3(tiles), dim3(64 * WGM * WGN), 0, s, kb, d, n,
+                     remap);
   return hipGetLastError();
 }
 
@@ -778,8 +830,9 @@ hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d,
     case 1: return launch_cfg<256, 128, 4, 4, 2, true>(kb, d, n, tiles, remap, s);
     case 3: return launch_cfg<256, 256, 2, 4, 2, true>(kb, d, n, tiles, remap, s);
     case 4: return launch_cfg<64, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
-    // eight waves of 128 x 64, split pipelined under the MFMAs
-    case 6: return launch_pipe<256, 256, 2, 4, 1>(kb, d, n, tiles, remap, s);
+    // eight waves of 128 x 64, split pipelined under the MFMAs, three LDS
+    // stages
+    case 6: return launch_ring<256, 256, 2, 4>(kb, d, n, tiles, remap, s);
     // small products: one 32x32 tile per wave
     case 8: return launch_cfg<64, 64, 4, 2, 2>(kb, d, n, tiles, remap, s);
     default: return launch_cfg<128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);

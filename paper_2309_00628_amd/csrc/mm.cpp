@@ -184,8 +184,9 @@ int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
       t128 += ceil_div(g.m, 128) * ceil_div(g.n, 128);
       t64x128 += ceil_div(g.m, 64) * ceil_div(g.n, 128);
     }
-    // (the in-loader split's 256x256 tile: the pipelined eight-wave kernel,
-    // measured 9 % faster than the other 256x256 kernel at n = 8192)
+    // (the in-loader split's 256x256 tile: the pipelined eight-wave kernel;
+    // with two LDS stages it measured 9 % faster than the other 256x256
+    // kernel at n = 8192, with three 1.5 to 4 % faster again)
     if (kdtype == DT_BF16X3 && t2x2 >= 512) return 6;
     if (t256 >= 256) return 1;
     if (t128 >= 256) return 0;
@@ -769,8 +770,8 @@ struct Builder {
     }
     if (P.tile_cfg < 0 && equal && kd == DT_BF16X3 && cfg == 6) {
       // split-bfloat16: the pipelined 256x256 tile and the 128x128 tile
-      // (measured MFMA fractions 0.54 and about 0.45)
-      const int p6 = split_for_rounds(group, 0.54, 0.45);
+      // (measured MFMA fractions 0.53 to 0.55 and about 0.45)
+      const int p6 = split_for_rounds(group, 0.55, 0.45);
       if (p6 > 0 && p6 < (int)group.size()) {
         std::vector<GemmDesc> big(group.begin(), group.begin() + p6), small(group.begin() + p6, group.end());
         emit_gemm_cfg(big, false, 6, true, kd);
