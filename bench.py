@@ -27,6 +27,7 @@ loop) timed on the host on samples of output rows.
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -465,7 +466,31 @@ def profile_set(torch, api, L, inputs, tuner, args):
             r = run_product(torch, api, L, algo, "grouped" if lv else "auto", n, lv, A, B, args.steps,
                             args.warmup, dtype="bf16x3")
             out[name] = round(r["tflops"], 2)
+        out["hipblaslt_bf16"] = bf16_library_rate(torch, A, B, args.steps, args.warmup)["tflops"]
     print(json.dumps(out), flush=True)
+
+
+def bf16_library_rate(torch, A, B, steps=10, warmup=5):
+    """hipBLASLt's bfloat16 GEMM (torch.matmul, one bfloat16 product per
+    output, float32 accumulation) on the same operands rounded to bfloat16:
+    the MFMA rate the library sustains on this chip with the bfloat16
+    matrix cores busy, beside the split-bfloat16 leaves' six products."""
+    n = A.shape[0]
+    Ab, Bb = A.to(torch.bfloat16).contiguous(), B.to(torch.bfloat16).contiguous()
+    Cb = torch.empty((n, n), dtype=torch.bfloat16, device=A.device)
+    for _ in range(warmup):
+        torch.matmul(Ab, Bb, out=Cb)
+    ts = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.matmul(Ab, Bb, out=Cb)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = statistics.median(ts)
+    tf = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+    return {"tflops": round(tf, 2), "p50_ms": round(ms, 4), "frac_of_bf16_peak": round(tf / PEAK_BF16_TFLOPS, 4)}
 
 
 def leaf_roofline(res, dt):
@@ -515,6 +540,8 @@ def bench_precision(torch, api, L, inputs, tuner, n=8192, steps=10, warmup=10, r
         del r
     out["speedup_bf16x3_winograd_vs_f32_plain"] = round(out["bf16x3_winograd_L2"]["tflops"] /
                                                         out["f32_plain"]["tflops"], 4)
+    out["hipblaslt_bf16"] = bf16_library_rate(torch, A, B)
+    print(f"# precision hipblaslt_bf16: {out['hipblaslt_bf16']}", file=sys.stderr, flush=True)
     return out
 
 
