@@ -112,3 +112,21 @@ def test_split_pass_bitwise_equal_to_split_pass(api, naive, algo, m, n, k, level
         assert torch.equal(C, ref), tile
     rows = np.arange(0, m, max(1, m // 16))
     assert rel_fro(ref[torch.from_numpy(rows).cuda()].cpu().numpy(), naive.gemm_rows(A, B, rows)) < 1e-5
+
+
+@pytest.mark.parametrize("k", [16, 32, 48, 64, 80, 96])
+def test_ring_tile_short_k_bitwise(api, naive, k):
+    # the 256x256 tile on a ring of three LDS stages peels its last three
+    # stages (16 k each) and runs products of fewer than three stages, and
+    # tiles at the matrix edge, through a one-buffer loop: every count of
+    # stages around the peel gives the bits of the 128x128 tile
+    for m, n in ((512, 512), (520, 300)):
+        A, B = inputs.pair("gauss_rowscaled", m, n, k, 9, np.float32)
+        At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        print(f"ring tile {m}x{n}x{k}", flush=True)
+        ref = api.mm(At, Bt, algo="naive", dtype="bf16x3", tile=0)
+        C = torch.full((m, n), float("nan"), device="cuda")
+        api.mm(At, Bt, algo="naive", dtype="bf16x3", tile=6, out=C)
+        torch.cuda.synchronize()
+        assert torch.equal(C, ref)
+        assert rel_fro(C.cpu().numpy(), naive.gemm(A, B)) < 1e-5
