@@ -260,9 +260,9 @@ int mm_set_workspace(void* ws, size_t bytes, hipStream_t stream);
  * 1 256x128 (8 waves), 2 128x256 (8 waves), 3 256x256 (BK 32, 8 waves),
  * 4 64x128, 5 128x64, 6 256x128 (BK 16, 4 waves), 7 128x128 (BK 16,
  * 4 waves), 8 64x64 (BK 32, 4 waves); float64: 0 128x128, 5 128x64 (others fall back to 0);
- * MM_BF16X3_REFINED: 0 128x128, 1 256x128 (8 waves), 3 256x256 (8 waves),
- * 4 64x128, 6 256x256 (8 waves, three LDS stages, the split pipelined under
- * the MFMAs), 8 64x64
+ * MM_BF16X3_REFINED: 0 128x128 (4 waves, three LDS stages, two workgroups
+ * per CU), 1 256x128 (8 waves), 3 256x256 (8 waves), 4 64x128, 6 256x256
+ * (8 waves, three LDS stages, the split pipelined under the MFMAs), 8 64x64
  * (others fall back to 0), and with MM_PLAN_SPLIT_PASS 0, 1, 3
  * 256x256 (4 waves), 4, 5 256x128 (4 waves), 6 256x256 (8 waves).  With
  * MM_PLAN_LEAF_U in effect c picks the fused leaf-level kernel's tile

@@ -315,6 +315,16 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
                                                [](int l, int r) { return row32(l, r); });
 }
 
+// f(integral_constant<int, I>) for I = I0 .. N-1, unrolled by construction
+// (a loop whose body indexes register arrays must not be left rolled).
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
 // The same products on a 256 x 256 tile with eight waves (two per SIMD, each
 // 128 x 64), software-pipelined over a ring of three LDS stages of 16 k (one
 // MFMA k-step; 48 MFMAs per wave and stage).  Each thread stages one 8-float
@@ -352,7 +362,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16r_kernel(KernelBases 
   constexpr int NB = NBLK_B / NT;
   constexpr int NPART = NA + NB;    // split calls per thread and stage
   static_assert(NCH_A % NT == 0 && NBLK_B % NT == 0 && NA >= 1 && NB >= 1, "whole chunks per thread");
-  static_assert(FM >= 2 && FM % 2 == 0 && NPART <= FM / 2, "split spread over the first half of the rows");
+  static_assert(FM >= 2 && FM % 2 == 0, "rows of MFMA tiles in pairs (A fragments alternate)");
 
   __shared__ bf16x8 As[3][3][BKC][BM];
   __shared__ bf16x8 Bs[3][3][BKC][BN];
@@ -364,7 +374,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16r_kernel(KernelBases 
   const float* __restrict__ Ap = resolve<float>(kb, av);
   const float* __restrict__ Bp = resolve<float>(kb, bv);
   const int64_t lda = av.ld, ldb = bv.ld;
-  const bool avec = view_vec(kb, av), bvec = view_vec(kb, bv);
+  const bool avec = view_vec(kb, av);
   const int K = D.k;
   const int ktiles = (K + BK - 1) / BK;
 
@@ -378,17 +388,22 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16r_kernel(KernelBases 
 
   // buffer-load offsets: bytes from the stage's first element (A row i0,
   // column k0; B row k0, column j0); they fit in 32 bits for leading
-  // dimensions below 2^21 (checked with the interior test)
+  // dimensions below 2^21 (checked with the interior test).  In a tile at a
+  // matrix edge, rows of A past its valid rows and columns of B past its
+  // valid columns are read as copies of the last valid one: an output
+  // element depends only on its own row of A and column of B, so these
+  // reach only outputs past the edge, which are not stored (checked below).
+  const int rlast = min(BM, av.vrows - i0) - 1, clast = min(BN, bv.vcols - j0) - 1;
   uint32_t oa[NA], ob[NB];
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
     const int q = tid + NT * i;
-    oa[i] = (uint32_t)(((q / BKC) * lda + (q % BKC) * KC) * (int64_t)sizeof(float));
+    oa[i] = (uint32_t)((min(q / BKC, rlast) * lda + (q % BKC) * KC) * (int64_t)sizeof(float));
   }
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int q = tid + NT * i;
-    ob[i] = (uint32_t)(((q / BN) * KC * ldb + q % BN) * (int64_t)sizeof(float));
+    ob[i] = (uint32_t)(((q / BN) * KC * ldb + min(q % BN, clast)) * (int64_t)sizeof(float));
   }
   const uint32_t brow = (uint32_t)(ldb * (int64_t)sizeof(float));
   auto rsrc = [](const float* p) {
@@ -434,6 +449,40 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16r_kernel(KernelBases 
       for (int rr = 0; rr < KC; ++rr) {
         const int gr = k0 + kc * KC + rr;
         sb[i][rr] = (gr < bv.vrows && gc < bv.vcols) ? Bp[(int64_t)gr * ldb + gc] : 0.f;
+      }
+    }
+  };
+  // Stage kt of a tile at a matrix edge, without branches: every load reads
+  // a valid element (indices clamped into the operand) and is replaced by
+  // zero past the edges (the values of load_masked).
+  auto load_edge = [&](int kt) {
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + NT * i;
+      const int row = q / BKC, kc = q % BKC;
+      const int gr = i0 + row, gc = k0 + kc * KC;
+      const bool rok = gr < av.vrows;
+      const float* p = Ap + (int64_t)(rok ? gr : 0) * lda;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool ok = rok && gc + e < av.vcols;
+        const float v = p[ok ? gc + e : 0];
+        sa[i][e] = ok ? v : 0.f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + NT * i;
+      const int kc = q / BN, cb = q % BN;
+      const int gc = j0 + cb;
+      const bool cok = gc < bv.vcols;
+#pragma unroll
+      for (int rr = 0; rr < KC; ++rr) {
+        const int gr = k0 + kc * KC + rr;
+        const bool ok = cok && gr < bv.vrows;
+        const float v = Bp[(int64_t)(ok ? gr : 0) * ldb + (ok ? gc : 0)];
+        sb[i][rr] = ok ? v : 0.f;
       }
     }
   };
@@ -488,18 +537,29 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16r_kernel(KernelBases 
     asm volatile("" ::: "memory");
   };
 
+  // With k not a multiple of 16 the last stage is loaded with bounds checks
+  // (zeros past k, as in the one-buffer loop: the same bits).
+  const bool ragged = K % BK != 0;
+  auto load_last = [&](int kt) {
+    if (ragged)
+      load_masked(kt);
+    else
+      load_full(kt);
+  };
+
   // Stage kt from buffer kt % 3 (its B fragments and first-row A fragments
   // in registers).  SPLIT: the staged stage kt+2 goes into buffer (kt+2) % 3
-  // between the first FM/2 rows; LOAD: then stage kt+3 is loaded into the
-  // staging registers; NEXT: the last row also reads stage kt+1's fragments.
-  auto stage = [&](auto split_tag, auto load_tag, auto next_tag, int kt) {
+  // between the first FM/2 rows; LOAD (1, or 2 when stage kt+3 is the last):
+  // then stage kt+3 is loaded into the staging registers; NEXT: the last row
+  // also reads stage kt+1's fragments.
+  auto stage = [&](auto split_tag, auto load_tag, auto next_tag, int kt) __attribute__((always_inline)) {
     constexpr bool SPLIT = decltype(split_tag)::value;
-    constexpr bool LOAD = decltype(load_tag)::value;
+    constexpr int LOAD = decltype(load_tag)::value;
     constexpr bool NEXT = decltype(next_tag)::value;
     const int buf = kt % 3, nbuf = (kt + 1) % 3, sbuf = (kt + 2) % 3;
-#pragma unroll
-    for (int a = 0; a < FM; ++a) {
-      const int ca = a & 1;
+    static_for<0, FM>([&](auto a_tag) {
+      constexpr int a = decltype(a_tag)::value;
+      constexpr int ca = a & 1;
       __builtin_amdgcn_sched_barrier(0);
       if (a + 1 < FM) {
         read_a(buf, a + 1, fa[ca ^ 1]);
@@ -524,8 +584,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16r_kernel(KernelBases 
         for (int j = 0; j < NPART; ++j)
           if (j * (FM / 2) / NPART == a) split_part(sbuf, j);
       }
-      if constexpr (LOAD) {
+      if constexpr (LOAD == 1) {
         if (a == FM / 2 - 1) load_full(kt + 3);
+      } else if constexpr (LOAD == 2) {
+        if (a == FM / 2 - 1) load_last(kt + 3);
+      } else if constexpr (LOAD == 3) {
+        if (a == FM / 2 - 1) load_edge(kt + 3);
       }
       // one MFMA, then a share of the row's other work: an LDS read of the
       // next fragments, six vector instructions of the split, its LDS
@@ -540,7 +604,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16r_kernel(KernelBases 
         __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // global load
       }
       __builtin_amdgcn_sched_barrier(0);
-    }
+    });
     if constexpr (NEXT) {
 #pragma unroll
       for (int p = 0; p < 3; ++p)
@@ -550,31 +614,67 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16r_kernel(KernelBases 
   };
   typedef std::integral_constant<bool, true> yes;
   typedef std::integral_constant<bool, false> no;
+  typedef std::integral_constant<int, 0> load_none;
 
-  const bool interior = avec && bvec && (i0 + BM <= av.vrows) && (j0 + BN <= bv.vcols) && (K % BK == 0) &&
-                        (K <= av.vcols) && (K <= bv.vrows) && lda < (int64_t(1) << 21) &&
-                        ldb < (int64_t(1) << 21);
-  if (ktiles >= 3 && interior) {
-    load_full(0);
+  // The ring over all stages.  Tiles inside both operands (16-byte rows, k
+  // within them, leading dimensions that fit the 32-bit offsets) load with
+  // buffer loads (the last stage bounds-checked when k is ragged); tiles at
+  // a matrix edge run the same loop with bounds-checked loads (zeros past
+  // the edges, as in the one-buffer loop).
+  auto ring = [&](auto masked_tag) __attribute__((always_inline)) {
+    constexpr bool MASKED = decltype(masked_tag)::value;
+    typedef std::integral_constant<int, MASKED ? 3 : 1> load_next;
+    typedef std::integral_constant<int, MASKED ? 3 : 2> load_final;
+    auto first = [&](int kt) __attribute__((always_inline)) {
+      if constexpr (MASKED)
+        load_edge(kt);
+      else if (kt == ktiles - 1)
+        load_last(kt);
+      else
+        load_full(kt);
+    };
+    first(0);
 #pragma unroll
     for (int j = 0; j < NPART; ++j) split_part(0, j);
-    load_full(1);
+    first(1);
 #pragma unroll
     for (int j = 0; j < NPART; ++j) split_part(1, j);
-    load_full(2);
+    first(2);
     lds_barrier();
     read_b(0, fb);
     read_a(0, 0, fa[0]);
     int kt = 0;
-    for (; kt + 3 < ktiles; ++kt) {
-      stage(yes{}, yes{}, yes{}, kt);
+    for (; kt + 4 < ktiles; ++kt) {
+      stage(yes{}, load_next{}, yes{}, kt);
       lds_barrier();
     }
-    stage(yes{}, no{}, yes{}, kt);  // kt = ktiles - 3
+    if (kt + 3 < ktiles) {  // kt = ktiles - 4: loads the last stage
+      stage(yes{}, load_final{}, yes{}, kt);
+      lds_barrier();
+      ++kt;
+    }
+    stage(yes{}, load_none{}, yes{}, kt);  // kt = ktiles - 3
     lds_barrier();
-    stage(no{}, no{}, yes{}, kt + 1);
+    stage(no{}, load_none{}, yes{}, kt + 1);
     lds_barrier();
-    stage(no{}, no{}, no{}, kt + 2);
+    stage(no{}, load_none{}, no{}, kt + 2);
+  };
+
+  // The buffer-load loop: A in 16-byte chunks, k within both operands,
+  // offsets in 32 bits, and at a matrix edge every stored output inside the
+  // operands' valid rows and columns (outputs past A's valid rows would be
+  // zero rows of the padded product, not copies).
+  bool edge_ok = rlast >= 0 && clast >= 0;
+  for (int o = 0; o < D.nout; ++o)
+    edge_ok = edge_ok && D.out[o].c.vrows <= av.vrows && D.out[o].c.vcols <= bv.vcols;
+  const bool interior = avec && (K <= av.vcols) && (K <= bv.vrows) && lda < (int64_t(1) << 21) &&
+                        ldb < (int64_t(1) << 21) &&
+                        (((i0 + BM <= av.vrows) && (j0 + BN <= bv.vcols)) || edge_ok);
+  if (ktiles >= 3) {
+    if (interior)
+      ring(no{});
+    else
+      ring(yes{});
   } else if (ktiles > 0) {
     for (int kt = 0; kt < ktiles; ++kt) {
       load_masked(kt);
@@ -583,7 +683,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16r_kernel(KernelBases 
       __syncthreads();
       read_b(0, fb);
       read_a(0, 0, fa[0]);
-      stage(no{}, no{}, no{}, 0);
+      stage(no{}, load_none{}, no{}, 0);
       __syncthreads();
     }
   }
@@ -835,7 +935,9 @@ hipError_t launch_gemm_bf16x3(int cfg, const KernelBases& kb, const GemmDesc* d,
     case 6: return launch_ring<256, 256, 2, 4>(kb, d, n, tiles, remap, s);
     // small products: one 32x32 tile per wave
     case 8: return launch_cfg<64, 64, 4, 2, 2>(kb, d, n, tiles, remap, s);
-    default: return launch_cfg<128, 128, 4, 2, 2>(kb, d, n, tiles, remap, s);
+    // 128x128: four waves of 64 x 64 on the same three-stage ring (two
+    // workgroups per CU)
+    default: return launch_ring<128, 128, 2, 2>(kb, d, n, tiles, remap, s);
   }
 }
 

@@ -184,10 +184,18 @@ int choose_gemm_cfg(int kdtype, const std::vector<GemmDesc>& group) {
       t128 += ceil_div(g.m, 128) * ceil_div(g.n, 128);
       t64x128 += ceil_div(g.m, 64) * ceil_div(g.n, 128);
     }
-    // (the in-loader split's 256x256 tile: the pipelined eight-wave kernel;
-    // with two LDS stages it measured 9 % faster than the other 256x256
-    // kernel at n = 8192, with three 1.5 to 4 % faster again)
-    if (kdtype == DT_BF16X3 && t2x2 >= 512) return 6;
+    if (kdtype == DT_BF16X3) {
+      // the in-loader split's ring tiles (256x256 eight waves, 128x128 four
+      // waves, both with three LDS stages and full-speed edge tiles):
+      // measured best from half a round of 256x256 tiles up (n = 3000:
+      // 329 us against 378 on 128x128 and 776 on the 256x128 tile), the
+      // 128x128 ring below (n = 2048: 110 us against 159 and 221; n = 2560:
+      // 206 us against 277 on 256x256); the 64-row tiles for small products
+      // (n = 1024: 37 us on 64x64, 57 on the 128x128 ring)
+      if (t2x2 >= 128) return 6;
+      if (t128 >= 96) return 0;
+      return t64x128 < 256 ? 8 : 4;
+    }
     if (t256 >= 256) return 1;
     if (t128 >= 256) return 0;
     // (the in-loader split kernel also has 64x64 tiles for small products)
@@ -778,9 +786,9 @@ struct Builder {
       }
     }
     if (P.tile_cfg < 0 && equal && kd == DT_BF16X3 && cfg == 6) {
-      // split-bfloat16: the pipelined 256x256 tile and the 128x128 tile
-      // (measured MFMA fractions 0.53 to 0.55 and about 0.45)
-      const int p6 = split_for_rounds(group, 0.55, 0.45);
+      // split-bfloat16: the 256x256 and 128x128 ring tiles (measured MFMA
+      // fractions 0.53 to 0.56 and about 0.47)
+      const int p6 = split_for_rounds(group, 0.55, 0.47, 2);
       if (p6 > 0 && p6 < (int)group.size()) {
         std::vector<GemmDesc> big(group.begin(), group.begin() + p6), small(group.begin() + p6, group.end());
         emit_gemm_cfg(big, false, 6, true, kd);
@@ -791,27 +799,32 @@ struct Builder {
     emit_gemm_cfg(group, fused, cfg, equal, kd);
   }
 
-  // Equal problems on the eight-wave tiles (one workgroup per CU): how many
-  // of them to give 256x256 tiles, the rest 128x128, so that both launches
-  // fill whole rounds of 256 workgroups.  Time model per problem class:
-  // rounds x tile work / measured tile efficiency (e256 for 256x256, e128
-  // for 128x128; float32: 0.87 and 0.84).  Returns the count, or -1 when one
-  // tile shape for all is as good.
-  static int split_for_rounds(const std::vector<GemmDesc>& group, double e256, double e128) {
+  // Equal problems on the large tiles: how many of them to give 256x256
+  // tiles (one workgroup per CU), the rest 128x128 (w128 workgroups per CU:
+  // float32 1, the split-bfloat16 ring 2), so that both launches fill whole
+  // rounds.  Time model per problem class: rounds x tile work / measured
+  // tile efficiency (e256 for 256x256, e128 for 128x128; float32: 0.87 and
+  // 0.84), w128 tiles sharing a CU taking w128 times as long.  Returns the
+  // count, or -1 when one tile shape for all is as good.
+  static int split_for_rounds(const std::vector<GemmDesc>& group, double e256, double e128, int64_t w128 = 1) {
     const int64_t P = (int64_t)group.size();
     const int64_t m = group[0].m, n = group[0].n;
     const int64_t T3 = ceil_div(m, 256) * ceil_div(n, 256), T0 = ceil_div(m, 128) * ceil_div(n, 128);
     const double t3 = 256.0 * 256.0 / e256, t0 = 128.0 * 128.0 / e128;
     auto cost = [&](int64_t p) {
-      return (double)ceil_div(p * T3, 256) * t3 + (double)ceil_div((P - p) * T0, 256) * t0;
+      return (double)ceil_div(p * T3, 256) * t3 + (double)ceil_div((P - p) * T0, 256 * w128) * t0 * (double)w128;
     };
+    // (with w128 > 1 ties go to more 256x256 tiles: a partial round of
+    // 128x128 tiles runs fewer workgroups per CU, faster than modelled)
     int64_t best = -1;
     double best_cost = 0.99 * std::min(cost(0), cost(P));
-    for (int64_t p = 1; p < P; ++p)
+    for (int64_t i = 1; i < P; ++i) {
+      const int64_t p = w128 > 1 ? P - i : i;
       if (cost(p) < best_cost) {
         best_cost = cost(p);
         best = p;
       }
+    }
     return (int)best;
   }
 

@@ -132,7 +132,7 @@ def _time_plan(plan, A, B, C, reps, warmup):
     return ts[len(ts) // 2]
 
 
-TILES = {"f32": (None, 0, 3, 4, 8), "bf16x3": (None, 0, 1, 3, 4, 6, 8), "f64": (None,)}
+TILES = {"f32": (None, 0, 3, 4, 8), "bf16x3": (None, 0, 1, 4, 6, 8), "f64": (None,)}
 LEAF_U_TILES = (None, 0, 1, 2)  # tiles of the fused last-level kernel (float32)
 
 
