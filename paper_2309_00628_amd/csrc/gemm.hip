@@ -42,8 +42,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
 
   typename TL::Acc acc;
   TL::zero(acc);
+  // edge tiles may read past the operands' valid extents when no output
+  // stores there (TileLoop::product)
+  bool clamp_ok = !BT;
+  for (int o = 0; o < D.nout; ++o)
+    clamp_ok = clamp_ok && D.out[o].c.vrows <= D.a.vrows && D.out[o].c.vcols <= D.b.vcols;
   TL::template product<OK_PLAIN, BT ? OK_TRANS : OK_PLAIN>(sm, operand<T>(kb, D.a), operand<T>(kb, D.b), tr.i0,
-                                                         tr.j0, D.k, acc);
+                                                         tr.j0, D.k, acc, clamp_ok);
 
   store_outputs<T, TL::TM, M::NACC, TL::FM, TL::FN, TL::WM, TL::WN, TL::NATF && !BT>(
       kb, D, tr.i0, tr.j0, wave / WGN, wave % WGN, lane, acc, [](int l, int r) { return M::row(l, r); });

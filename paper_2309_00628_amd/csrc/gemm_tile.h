@@ -590,8 +590,12 @@ struct TileLoop {
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
   }
+  // rlast / clast: the last row of A and the last 16-byte column chunk of B
+  // the tile may read (a tile at a matrix edge reads the rows and chunks
+  // past them as copies of these; see product).
   static __device__ __forceinline__ void main_loop_direct(Smem& sm, const Operand<T>& A, const Operand<T>& B,
-                                                          int i0, int j0, int ktiles, Acc& acc) {
+                                                          int i0, int j0, int ktiles, Acc& acc,
+                                                          int rlast = BM - 1, int clast = BN / E - 1) {
     static_assert(direct_kind<OK_PLAIN, OK_PLAIN>(),
                   "float32, whole loads per lane, even k-blocks per stage, a stage's loads spread over all but "
                   "its last step");
@@ -610,12 +614,12 @@ struct TileLoop {
       const int p = (wave * DPA + i) * 64 + lane;
       const int row = p / BKC, slot = p % BKC;
       const int kc = slot ^ ((row / (16 / BKC)) & (BKC - 1));
-      oa[i] = (uint32_t)(((int64_t)row * A.ld + kc * E) * (int64_t)sizeof(T));
+      oa[i] = (uint32_t)(((int64_t)min(row, rlast) * A.ld + kc * E) * (int64_t)sizeof(T));
     }
 #pragma unroll
     for (int i = 0; i < DPB; ++i) {
       const int p = (wave * DPB + i) * 64 + lane;
-      ob[i] = (uint32_t)(((int64_t)(p / CPR) * B.ld + (p % CPR) * E) * (int64_t)sizeof(T));
+      ob[i] = (uint32_t)(((int64_t)(p / CPR) * B.ld + min(p % CPR, clast) * E) * (int64_t)sizeof(T));
     }
     // load i (0 <= i < DPA + DPB: A's first) of this lane's share of stage
     // kt, into LDS buffer kt & 1
@@ -749,9 +753,16 @@ struct TileLoop {
   }
 
   // acc += A[i0 : i0 + BM, 0 : K] B[0 : K, j0 : j0 + BN] (A and B of kinds KA, KB2).
+  // clamp_ok: the caller stores no output row past A's valid rows and no
+  // output column past B's valid columns.  A tile at a matrix edge may then
+  // take the direct loop, reading the rows of A and the column chunks of B
+  // past the edge as copies of the last valid ones: an output depends only
+  // on its own row of A and column of B, so the copies reach only outputs
+  // that are not stored (B's valid width a multiple of E, so that no chunk
+  // straddles the edge).
   template <int KA = OK_PLAIN, int KB2 = OK_PLAIN>
   static __device__ __forceinline__ void product(Smem& sm, const Operand<T>& A, const Operand<T>& B, int i0,
-                                                 int j0, int K, Acc& acc) {
+                                                 int j0, int K, Acc& acc, bool clamp_ok = false) {
     const int ktiles = (K + BK - 1) / BK;
     if (ktiles <= 0) return;
     // an operand with no valid element is zero: nothing to add (and the
@@ -764,6 +775,13 @@ struct TileLoop {
                           (K <= A.vcols) && (K <= bk);
     const bool edge_vec = A.vec && B.vec && A.vrows > 0 && A.vcols > 0 && B.vrows > 0 && B.vcols > 0 &&
                           A.vcols % E == 0 && B.vcols % E == 0;
+    if constexpr (direct_kind<KA, KB2>()) {
+      if (!interior && clamp_ok && i0 < A.vrows && j0 < bn && A.vec && B.vec && (K % BK == 0) && (K <= A.vcols) &&
+          (K <= bk) && B.vcols % E == 0 && A.ld < kDirectLdMax && B.ld < kDirectLdMax) {
+        main_loop_direct(sm, A, B, i0, j0, ktiles, acc, min(BM, A.vrows - i0) - 1, min(BN, bn - j0) / E - 1);
+        return;
+      }
+    }
     if (interior)
       main_loop<LOAD_FULL, KA, KB2>(sm, A, B, i0, j0, ktiles, acc);
     else if (edge_vec)
