@@ -326,10 +326,11 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // The same products on a 256 x 256 tile with eight waves (two per SIMD, each
-// 128 x 64), software-pipelined over a ring of three LDS stages of 16 k (one
-// MFMA k-step; 48 MFMAs per wave and stage).  Each thread stages one 8-float
-// chunk of A and one 8-row column of B per stage, so the split work is the
-// same in every wave.  During stage t:
+// 128 x 64; also instantiated as 128 x 128 with four waves of 64 x 64, two
+// workgroups per CU), software-pipelined over a ring of three LDS stages of
+// 16 k (one MFMA k-step; 48 MFMAs per wave and stage on the large tile).
+// Each thread stages one 8-float chunk of A and one 8-row column of B per
+// stage, so the split work is the same in every wave.  During stage t:
 //  * the registers hold the raw float32 data of stage t+2 (loaded during
 //    stage t-1); it is split into hi, lo and residual and stored to the
 //    third LDS buffer between the MFMAs of the first two rows of 32 x 32
@@ -342,10 +343,13 @@ __device__ __forceinline__ void static_for(F&& f) {
 //    the barrier that ends the stage (a wait for this wave's LDS accesses,
 //    not for the global loads in flight) is followed by MFMAs at once;
 //  * the A fragments of the next row are read during the current row.
-// The last three stages are peeled (no loads, then no split); tiles at the
-// matrix edge, small k and leading dimensions of 2^21 or more take a
-// one-buffer loop with bounds-checked loads.  The six products of a tile are
-// issued in the order of the kernel above: the same bits.
+// The last three stages are peeled (no loads, then no split).  A k that is
+// not a multiple of 16 is bounds-checked in its last stage; tiles at a
+// matrix edge read clamped rows and columns (see the offsets below), or,
+// where that is not allowed, run the ring with branch-free bounds-checked
+// loads; products of fewer than three stages take a one-buffer loop.  The
+// six products of a tile are issued in the order of the kernel above: the
+// same bits.
 template <int BM, int BN, int WGM, int WGN>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16r_kernel(KernelBases kb,
                                                                     const GemmDesc* __restrict__ descs,
