@@ -3,7 +3,7 @@
 The hot path (naive MFMA GEMM, Strassen, Winograd and the paper's memory
 schedules) lives in ``libmm.so`` (HIP kernels behind the C ABI of
 ``include/mm.h``).  This package holds its Python binding (``api``, ``_lib``),
-the build script, the autotuner, the batched driver and the serving loop.
+the build script, the autotuner, the batched plans and the serving loop.
 Importing the package loads nothing; the library is loaded on first use and
 a missing library raises.
 """
