@@ -852,3 +852,25 @@ def test_two_level_passes_need_whole_blocks(lib):
         assert "EW2" not in text, (args, opts)
     text, _ = L.describe("strassen", "grouped", 4096, 4096, 4096, cutoff=1, levels=2)
     assert "EW2" not in text
+
+
+def gemm_launches(text):
+    """(count, workgroups, tile) of every GEMM launch in a plan listing."""
+    return [tuple(int(x) for x in l.split()[2:5]) for l in text.splitlines() if l.startswith("LAUNCH GEMM")]
+
+
+def test_split_bf16_tile_choice(lib):
+    # the planner's split-bfloat16 tiles: the 256x256 ring (6) from half a
+    # round of its tiles up, the 128x128 ring (0) below, 64-row tiles for
+    # small products
+    for n, tile in ((1024, 8), (1536, 0), (2048, 0), (2560, 0), (3000, 6), (4096, 6), (8000, 6)):
+        text, _ = L.describe("naive", "auto", n, n, n, cutoff=1, levels=0, dtype="bf16x3")
+        assert [t for _, _, t in gemm_launches(text)] == [tile], (n, text)
+    # leaves of two Winograd levels at n = 8192: 48 on the 256x256 ring (12
+    # whole rounds) and one on the 128x128 ring; the model's tie between
+    # 48 + 1 and 47 + 2 goes to more 256x256 tiles
+    text, _ = L.describe("winograd", "grouped", 8192, 8192, 8192, cutoff=1, levels=2, dtype="bf16x3")
+    assert gemm_launches(text) == [(48, 3072, 6), (1, 256, 0)]
+    # float32 keeps its own split (4096, two levels: 45 + 4)
+    text, _ = L.describe("winograd", "grouped", 4096, 4096, 4096, cutoff=1, levels=2, dtype="f32")
+    assert gemm_launches(text) == [(45, 720, 3), (4, 256, 0)]
