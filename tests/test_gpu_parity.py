@@ -506,7 +506,12 @@ ACC_GPU = [("naive", "auto", 300, 200, 100, 0, "f32", {}), ("naive", "auto", 257
            ("naive", "auto", 640, 384, 200, 0, "bf16x3", {"split_pass": True}),
            ("strassen", "grouped", 640, 384, 512, 2, "f32", {}),
            ("winograd", "grouped", 1000, 777, 555, 2, "f32", {"peel": True}),
-           ("strassen", "grouped", 301, 290, 257, 2, "f64", {"peel": True})]
+           ("strassen", "grouped", 301, 290, 257, 2, "f64", {"peel": True}),
+           # edge tiles and a ragged k on the split-bf16 ring tiles and on the
+           # float32 direct loop, each epilogue reading the C it adds to
+           ("naive", "auto", 1000, 777, 520, 0, "bf16x3", {"tile": 6}),
+           ("winograd", "grouped", 1000, 777, 555, 2, "bf16x3", {"tile": 0}),
+           ("naive", "auto", 1000, 776, 512, 0, "f32", {"tile": 3})]
 
 
 PEEL_GPU = [("winograd", 1000, 777, 555, 2, "f32"), ("winograd", 1200, 1300, 1100, 3, "f32"),
