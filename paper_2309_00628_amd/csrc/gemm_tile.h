@@ -593,9 +593,14 @@ struct TileLoop {
   // rlast / clast: the last row of A and the last 16-byte column chunk of B
   // the tile may read (a tile at a matrix edge reads the rows and chunks
   // past them as copies of these; see product).
+  // kvalid: k past which A's columns and B's rows are zero (a k that is not
+  // a multiple of BK, but of E): the last two stages load through a checked
+  // copy of the stage that skips the chunks past it and zeroes their LDS
+  // slots instead (they lie past the operands, so they are never read).
   static __device__ __forceinline__ void main_loop_direct(Smem& sm, const Operand<T>& A, const Operand<T>& B,
                                                           int i0, int j0, int ktiles, Acc& acc,
-                                                          int rlast = BM - 1, int clast = BN / E - 1) {
+                                                          int rlast = BM - 1, int clast = BN / E - 1,
+                                                          int kvalid = 0x7fffffff) {
     static_assert(direct_kind<OK_PLAIN, OK_PLAIN>(),
                   "float32, whole loads per lane, even k-blocks per stage, a stage's loads spread over all but "
                   "its last step");
@@ -634,6 +639,33 @@ struct TileLoop {
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, lds(&sm.Bs[buf][(wave * DPB + j) * 64]), 16, ob[j], 0, 0, 0);
       }
     };
+    // load_part, with the chunks at or past kvalid zeroed in LDS instead of
+    // loaded
+    auto load_part_checked = [&](int kt, int i) __attribute__((always_inline)) {
+      const int buf = kt & 1;
+      if (i < DPA) {
+        const int p = (wave * DPA + i) * 64 + lane;
+        const int row = p / BKC, slot = p % BKC;
+        const int kc = slot ^ ((row / (16 / BKC)) & (BKC - 1));
+        if (kt * BK + kc * E < kvalid) {
+          const __amdgpu_buffer_rsrc_t ra = rsrc(A.p + (int64_t)i0 * A.ld + (int64_t)kt * BK);
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, lds(&sm.As[buf][(wave * DPA + i) * 64]), 16, oa[i], 0, 0,
+                                                   0);
+        } else {
+          sm.As[buf][p] = chunk_t{};
+        }
+      } else {
+        const int j = i - DPA;
+        const int p = (wave * DPB + j) * 64 + lane;
+        if (kt * BK + p / CPR < kvalid) {
+          const __amdgpu_buffer_rsrc_t rb = rsrc(B.p + (int64_t)kt * BK * B.ld + j0);
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, lds(&sm.Bs[buf][(wave * DPB + j) * 64]), 16, ob[j], 0, 0,
+                                                   0);
+        } else {
+          sm.Bs[buf][p] = chunk_t{};
+        }
+      }
+    };
     chunk_t fa[2][FM];
     bv_t fb[2];
     auto read_a = [&](int buf, int kb2, chunk_t (&xa)[FM]) {
@@ -647,12 +679,19 @@ struct TileLoop {
       xb = *reinterpret_cast<const bv_t*>(Bf + (plane * E + step % E) * BN);
     };
 #pragma unroll
-    for (int i = 0; i < DPA + DPB; ++i) load_part(0, i);
+    for (int i = 0; i < DPA + DPB; ++i) {
+      if (ktiles == 1)
+        load_part_checked(0, i);
+      else
+        load_part(0, i);
+    }
     __builtin_amdgcn_s_waitcnt(0);  // this wave's part of stage 0 has landed
     bare_barrier();
     read_a(0, 0, fa[0]);
     read_b(0, 0, fb[0]);
-    for (int kt = 0; kt < ktiles; ++kt) {
+    // stage kt; CHECKED: its loads of stage kt+1 go through load_part_checked
+    auto stage = [&](int kt, auto checked_tag) __attribute__((always_inline)) {
+      constexpr bool CHECKED = decltype(checked_tag)::value;
       const int buf = kt & 1;
       const bool more = kt + 1 < ktiles;
 #pragma unroll
@@ -676,7 +715,12 @@ struct TileLoop {
             if (more) {
 #pragma unroll
               for (int j = 0; j < kLoadsPerStep; ++j)
-                if (step * kLoadsPerStep + j < DPA + DPB) load_part(kt + 1, step * kLoadsPerStep + j);
+                if (step * kLoadsPerStep + j < DPA + DPB) {
+                  if constexpr (CHECKED)
+                    load_part_checked(kt + 1, step * kLoadsPerStep + j);
+                  else
+                    load_part(kt + 1, step * kLoadsPerStep + j);
+                }
             }
             __builtin_amdgcn_sched_barrier(0);
             mfmas((FM * FN) / 2, FM * FN);
@@ -700,7 +744,12 @@ struct TileLoop {
         }
         __builtin_amdgcn_sched_barrier(0);
       }
-    }
+    };
+    typedef std::integral_constant<bool, false> plain_loads;
+    typedef std::integral_constant<bool, true> checked_loads;
+    int kt = 0;
+    for (; kt + 2 < ktiles; ++kt) stage(kt, plain_loads{});
+    for (; kt < ktiles; ++kt) stage(kt, checked_loads{});  // loads the last stage
     // Every wave read its last fragments before the last stage's barrier,
     // and no load is in flight: the LDS may be reused at once.
   }
@@ -775,10 +824,13 @@ struct TileLoop {
                           (K <= A.vcols) && (K <= bk);
     const bool edge_vec = A.vec && B.vec && A.vrows > 0 && A.vcols > 0 && B.vrows > 0 && B.vcols > 0 &&
                           A.vcols % E == 0 && B.vcols % E == 0;
+    // The direct loop also takes a k that is a multiple of E but not of BK
+    // (the chunks past k zeroed in LDS, see main_loop_direct).
     if constexpr (direct_kind<KA, KB2>()) {
-      if (!interior && clamp_ok && i0 < A.vrows && j0 < bn && A.vec && B.vec && (K % BK == 0) && (K <= A.vcols) &&
-          (K <= bk) && B.vcols % E == 0 && A.ld < kDirectLdMax && B.ld < kDirectLdMax) {
-        main_loop_direct(sm, A, B, i0, j0, ktiles, acc, min(BM, A.vrows - i0) - 1, min(BN, bn - j0) / E - 1);
+      const bool mn_in = (i0 + BM <= A.vrows) && (j0 + BN <= bn);
+      if (!interior && (mn_in || (clamp_ok && i0 < A.vrows && j0 < bn && B.vcols % E == 0)) && A.vec && B.vec &&
+          K % E == 0 && (K <= A.vcols) && (K <= bk) && A.ld < kDirectLdMax && B.ld < kDirectLdMax) {
+        main_loop_direct(sm, A, B, i0, j0, ktiles, acc, min(BM, A.vrows - i0) - 1, min(BN, bn - j0) / E - 1, K);
         return;
       }
     }
