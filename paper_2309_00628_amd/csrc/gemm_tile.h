@@ -608,7 +608,9 @@ struct TileLoop {
     constexpr int CPR = BN / E;
     typedef FVec<FN> FV;
     typedef typename FV::type bv_t;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index in a scalar register: the LDS destinations of the
+    // direct loads (M0) are then computed without vector instructions
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = wave / WGN, wn = wave % WGN;
     const int g = lane / TM, t = lane % TM;
     // byte offsets of this lane's chunks in a stage (A in a_idx order, B as
