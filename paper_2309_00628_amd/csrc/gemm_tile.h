@@ -180,7 +180,9 @@ struct TileLoop {
   template <int R, bool IS_B>
   static __device__ __forceinline__ void dma_rows(Smem& sm, int buf, const Operand<T>& X, int r0, int k0) {
     constexpr int PER = (R * BKC) / NT;  // instructions per thread
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // (the wave index in a scalar register: the LDS destinations, M0, are
+    // then computed without vector instructions)
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int base = (wave * PER + i) * 64;
@@ -206,7 +208,7 @@ struct TileLoop {
     if constexpr (DMA_B) {
       constexpr int PER = NCH_B / NT;
       constexpr int CPR = BN / E;  // chunks per row
-      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
       const int k0 = kt * BK;
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
