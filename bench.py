@@ -795,7 +795,7 @@ def bench_serving(torch, inputs, count=160, budget_gib=32, slots=4, seed=11, che
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU only (the library runs one process per GPU and has no multi-GPU path); run with --gpus 1"}))
         sys.exit(2)
     import numpy as np
     import torch
