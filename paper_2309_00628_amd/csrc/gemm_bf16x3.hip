@@ -311,8 +311,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(KernelBases
       main_loop(std::integral_constant<int, LOAD_MASKED>{});
   }
 
-  store_outputs<float, TM, 16, FM, FN, WM, WN>(kb, D, i0, j0, wm, wn, lane, acc,
-                                               [](int l, int r) { return row32(l, r); });
+  // (the checked epilogue: this kernel has no registers to spare)
+  store_outputs<float, TM, 16, FM, FN, WM, WN, false, false>(kb, D, i0, j0, wm, wn, lane, acc,
+                                                             [](int l, int r) { return row32(l, r); });
 }
 
 // f(integral_constant<int, I>) for I = I0 .. N-1, unrolled by construction
