@@ -50,7 +50,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(KernelBases kb,
   TL::template product<OK_PLAIN, BT ? OK_TRANS : OK_PLAIN>(sm, operand<T>(kb, D.a), operand<T>(kb, D.b), tr.i0,
                                                          tr.j0, D.k, acc, clamp_ok);
 
-  store_outputs<T, TL::TM, M::NACC, TL::FM, TL::FN, TL::WM, TL::WN, TL::NATF && !BT>(
+  // (the epilogue's interior path costs the smaller tiles a wave per SIMD)
+  store_outputs<T, TL::TM, M::NACC, TL::FM, TL::FN, TL::WM, TL::WN, TL::NATF && !BT, (BM >= 128 && BN >= 128)>(
       kb, D, tr.i0, tr.j0, wave / WGN, wave % WGN, lane, acc, [](int l, int r) { return M::row(l, r); });
 }
 

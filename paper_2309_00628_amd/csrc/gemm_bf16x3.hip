@@ -693,8 +693,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16r_kernel(KernelBases 
     }
   }
 
-  store_outputs<float, TM, 16, FM, FN, WM, WN>(kb, D, i0, j0, wm, wn, lane, acc,
-                                               [](int l, int r) { return row32(l, r); });
+  // (the epilogue's interior path only on the 256 x 256 tile: it would take the
+  // 128 x 128 tile past the registers of two workgroups per CU)
+  store_outputs<float, TM, 16, FM, FN, WM, WN, false, (BM == 256)>(kb, D, i0, j0, wm, wn, lane, acc,
+                                                                    [](int l, int r) { return row32(l, r); });
 }
 
 // The same products from operands already split by the split pass (SPL
@@ -874,8 +876,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16s_kernel(KernelBases 
       main_loop(std::integral_constant<bool, false>{});
   }
 
-  store_outputs<float, TM, 16, FM, FN, WM, WN>(kb, D, i0, j0, wm, wn, lane, acc,
-                                               [](int l, int r) { return row32(l, r); });
+  // (the checked epilogue: its interior path costs the smaller tiles a wave per SIMD)
+  store_outputs<float, TM, 16, FM, FN, WM, WN, false, false>(kb, D, i0, j0, wm, wn, lane, acc,
+                                                             [](int l, int r) { return row32(l, r); });
 }
 
 template <int BM, int BN, int BKC, int WGM, int WGN>

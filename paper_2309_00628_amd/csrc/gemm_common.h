@@ -171,72 +171,50 @@ __device__ __forceinline__ TileRef locate_tile(const Desc* __restrict__ descs, i
   return tile_in_problem<BM, BN>(lo, rb - D.tile_start, D.tiles_m, D.tiles_n);
 }
 
-// Raw buffer accesses of the epilogue's interior path: a resource over a
+// Raw buffer stores of the epilogue's interior path: a resource over a
 // base address (no range limit), a per-lane byte offset and a scalar one.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, -1, 0x00020000);
 }
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-template <typename T>
-struct BufIO;
-template <>
-struct BufIO<float> {
-  static __device__ __forceinline__ void st(float x, __amdgpu_buffer_rsrc_t r, int v, int s) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
-  }
-  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int v, int s) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
-  }
-};
-template <>
-struct BufIO<double> {
-  static __device__ __forceinline__ void st(double x, __amdgpu_buffer_rsrc_t r, int v, int s) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, v, s, 0);
-  }
-  static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, int v, int s) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
-  }
-};
+__device__ __forceinline__ void buf_store(float x, __amdgpu_buffer_rsrc_t r, int v, int s) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
+}
+__device__ __forceinline__ void buf_store(double x, __amdgpu_buffer_rsrc_t r, int v, int s) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, v, s, 0);
+}
 
-// store_group through buffer accesses: N consecutive floats of one row at
-// byte offsets (v, s) of rc, with D read at (dv, ds) of rd when ADD; one
-// vector access when the views allow 16-byte ones (VEC).  A 16-byte store
-// takes its whole offset in the vector register and a constant scalar
-// offset: a vector instruction that overwrites the data registers of a
-// store of more than 8 bytes right after it needs a wait state, which the
-// compiler inserts for that form (and for global stores) but not when the
-// scalar offset is a register, where gfx950 needs it as well (measured: the
-// first dword of such stores was sometimes the overwritten value).
-template <int N, bool ADD, bool VEC>
-__device__ __forceinline__ void buf_store_group(__amdgpu_buffer_rsrc_t rc, int v, int s, __amdgpu_buffer_rsrc_t rd,
-                                                int dv, int ds, float dscale, const float (&x)[N]) {
+// N consecutive floats of one row at byte offsets (v, s) of rc: one vector
+// store when the view allows 16-byte accesses (VEC).  A store of more than
+// 8 bytes takes its whole offset in the vector register and a constant
+// scalar offset: a vector instruction that overwrites the data registers
+// of such a store right after it needs a wait state, which the compiler
+// inserts for that form (and for global stores) but not when the scalar
+// offset is a register, where gfx950 needs it as well (measured: the first
+// dword of such stores was sometimes the overwritten value).
+template <int N, bool VEC>
+__device__ __forceinline__ void buf_store_group(__amdgpu_buffer_rsrc_t rc, int v, int s, const float (&x)[N]) {
   typedef FVec<N> FV;
-  if constexpr (VEC && N > 1) {
-    typename FV::type y, d;
-    if constexpr (ADD) {
-      if constexpr (N == 4)
-        d = __builtin_bit_cast(typename FV::type, __builtin_amdgcn_raw_buffer_load_b128(rd, dv, ds, 0));
-      else if constexpr (N == 2)
-        d = __builtin_bit_cast(typename FV::type, __builtin_amdgcn_raw_buffer_load_b64(rd, dv, ds, 0));
-    }
+  if constexpr (VEC && N == 4) {
+    typename FV::type y;
 #pragma unroll
-    for (int b = 0; b < N; ++b) FV::set(y, b, ADD ? fma(dscale, FV::get(d, b), x[b]) : x[b]);
-    if constexpr (N == 4) {
-      int vs = v + s;
-      asm("" : "+v"(vs));  // (opaque: the compiler would move s back to the scalar offset)
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, y), rc, vs, 0, 0);
-    }
-    else if constexpr (N == 2)
-      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, y), rc, v, s, 0);
+    for (int b = 0; b < N; ++b) FV::set(y, b, x[b]);
+    int vs = v + s;
+    asm("" : "+v"(vs));  // (opaque: the compiler would move s back to the scalar offset)
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, y), rc, vs, 0, 0);
+  } else if constexpr (VEC && N == 2) {
+    typename FV::type y;
+#pragma unroll
+    for (int b = 0; b < N; ++b) FV::set(y, b, x[b]);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, y), rc, v, s, 0);
   } else {
-    // (the N single stores may be merged into one wide store: the same
+    // (the single stores may be merged into one wide store: the same
     // constant scalar offset)
     int vs = v + s;
     asm("" : "+v"(vs));
 #pragma unroll
-    for (int b = 0; b < N; ++b)
-      BufIO<float>::st(ADD ? fma(dscale, BufIO<float>::ld(rd, dv + 4 * b, ds), x[b]) : x[b], rc, vs + 4 * b, 0);
+    for (int b = 0; b < N; ++b) buf_store(x[b], rc, vs + 4 * b, 0);
   }
 }
 
@@ -274,62 +252,44 @@ __device__ __forceinline__ void store_outputs(const KernelBases& kb, const GemmD
     const int64_t ldc = cv.ld, ldd = add ? dv.ld : 0;
     const int crows = cv.vrows, ccols = cv.vcols;
     const bool vec = PERM && view_vec(kb, cv) && (!add || view_vec(kb, dv));
-    // The wave's FM TM x FN TM outputs all inside C: no per-element
-    // checks, and buffer accesses over the wave's first output with the
-    // lane's byte offset (computed once) and each row's offset in a scalar
-    // register, so a store costs no vector address arithmetic (the 64-bit
-    // row arithmetic of the checked loops below costs more vector
-    // instructions than the stores themselves).  Offsets are 32-bit: the
-    // leading dimensions are bounded accordingly.  The same values go to
-    // the same places as in the checked loops.  Tiles whose accumulators
-    // take more than 128 registers per lane keep the checked loops (there
-    // the extra registers of this path spill), as do callers passing FAST =
-    // false.
+    // Plain stores of a wave whose FM TM x FN TM outputs all lie inside C:
+    // no per-element checks, and buffer stores over the wave's first
+    // output with the lane's byte offset (computed once) and each row's
+    // offset in a scalar register, so a store costs no vector address
+    // arithmetic (the 64-bit row arithmetic of the checked loops below costs
+    // more vector instructions than the stores themselves).  Offsets are
+    // 32-bit: the leading dimension is bounded accordingly.  The same values
+    // go to the same places as in the checked loops.  Tiles whose
+    // accumulators take more than 128 registers per lane keep the checked
+    // loops (there the extra registers of this path spill), as do callers
+    // passing FAST = false.
     constexpr int64_t kMaxLd = (int64_t(1) << 31) / (FM * TM * (int64_t)sizeof(T));
     constexpr bool kFast = FAST && FM * FN * NACC * sizeof(T) / 4 <= 128;
-    if (kFast && r0 + FM * TM <= crows && c0 + FN * TM <= ccols && ldc < kMaxLd && ldd < kMaxLd) {
+    if (kFast && !add && r0 + FM * TM <= crows && c0 + FN * TM <= ccols && ldc < kMaxLd) {
       const __amdgpu_buffer_rsrc_t rc = buf_rsrc(Cp + (int64_t)r0 * ldc + c0);
-      const __amdgpu_buffer_rsrc_t rd = buf_rsrc(add ? Dp + (int64_t)r0 * ldd + c0 : Cp);
       const int cl = (int)(((int64_t)lr * ldc + lc) * (int64_t)sizeof(T));
-      const int dl = add ? (int)(((int64_t)lr * ldd + lc) * (int64_t)sizeof(T)) : 0;
-      auto rows = [&](auto add_tag, auto vec_tag) __attribute__((always_inline)) {
-        constexpr bool ADD = decltype(add_tag)::value;
+      auto rows = [&](auto vec_tag) __attribute__((always_inline)) {
         constexpr bool VEC = decltype(vec_tag)::value;
 #pragma unroll
         for (int a = 0; a < FM; ++a)
 #pragma unroll
           for (int r = 0; r < NACC; ++r) {
-            const int row = a * TM + rowfn(0, r);
-            const int sc = (int)(row * ldc * (int64_t)sizeof(T));
-            const int sd = ADD ? (int)(row * ldd * (int64_t)sizeof(T)) : 0;
+            const int sc = (int)((a * TM + rowfn(0, r)) * ldc * (int64_t)sizeof(T));
             if constexpr (PERM) {
               float x[FN];
 #pragma unroll
               for (int b = 0; b < FN; ++b) x[b] = sg * acc[a][b][r];
-              buf_store_group<FN, ADD, VEC>(rc, cl, sc, rd, dl, sd, dscale, x);
+              buf_store_group<FN, VEC>(rc, cl, sc, x);
             } else {
 #pragma unroll
-              for (int b = 0; b < FN; ++b) {
-                const T v = sg * acc[a][b][r];
-                const int cb = b * TM * (int)sizeof(T);
-                BufIO<T>::st(ADD ? fma(dscale, BufIO<T>::ld(rd, dl + cb, sd), v) : v, rc, cl + cb, sc);
-              }
+              for (int b = 0; b < FN; ++b) buf_store(T(sg * acc[a][b][r]), rc, cl + b * TM * (int)sizeof(T), sc);
             }
           }
       };
-      typedef std::integral_constant<bool, true> yes;
-      typedef std::integral_constant<bool, false> no;
-      if (add) {
-        if (vec)
-          rows(yes{}, yes{});
-        else
-          rows(yes{}, no{});
-      } else {
-        if (vec)
-          rows(no{}, yes{});
-        else
-          rows(no{}, no{});
-      }
+      if (vec)
+        rows(std::integral_constant<bool, true>{});
+      else
+        rows(std::integral_constant<bool, false>{});
       continue;
     }
     if constexpr (PERM) {
