@@ -58,3 +58,22 @@ def test_edge_tiles_same_bits_on_every_tile(api, oracle_built, dtype, tiles, alg
     rows = np.unique(np.r_[0, np.linspace(0, m - 1, 12).astype(np.int64), m - 1])
     err = rel_fro(outs[0][torch.from_numpy(rows).cuda()].cpu().numpy(), naive.gemm_rows(A_np, B_np, rows))
     assert err < 1e-5, err
+
+
+@pytest.mark.parametrize("dtype,tile", [("f32", 3), ("f32", 0), ("bf16x3", 6)])
+@pytest.mark.parametrize("m,n,k", [(600, 520, 256), (1000, 777, 96)])
+def test_unaligned_output_rows_same_bits(api, oracle_built, dtype, tile, m, n, k):
+    # the epilogue stores interior waves with one buffer store per row (or
+    # per element when C's rows are not 16-byte aligned): an output whose
+    # leading dimension is odd must get the bits of a compact one, and
+    # nothing outside it may be written
+    A_np, B_np = inputs.pair("uniform", m, n, k, 96, np.float32)
+    A, B = torch.from_numpy(A_np).cuda(), torch.from_numpy(B_np).cuda()
+    print(f"unaligned C {dtype} tile {tile} {m}x{n}x{k}", flush=True)
+    ref = torch.full((m, n), float("nan"), device="cuda")
+    api.mm(A, B, algo="naive", dtype=dtype, tile=tile, out=ref)
+    wide = torch.full((m, n + 3), 7.0, device="cuda")
+    api.mm(A, B, algo="naive", dtype=dtype, tile=tile, out=wide[:, 1:n + 1])
+    torch.cuda.synchronize()
+    assert torch.equal(wide[:, 1:n + 1], ref)
+    assert bool((wide[:, 0] == 7.0).all()) and bool((wide[:, n + 1:] == 7.0).all())
